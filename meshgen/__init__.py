@@ -1,0 +1,265 @@
+"""Seeded synthetic meshes and nodal fields.
+
+This module is the one place that both the product path and the oracle take
+their inputs from.  It builds meshes (a jittered unit cube of HEX08 cells, or
+the same cube split into TET04 cells), random renumberings, Dirichlet node
+lists and the nodal fields (velocity, density, viscosity, species).  It holds
+none of the finite-element arithmetic: no shape function, quadrature rule,
+Jacobian, elemental matrix or solver lives here.
+
+The paper's test case is a swirl burner on a 64 M-cell mixed tet/pyramid/hex
+mesh (Section 5.1) with a flamelet database; neither is available, so these
+synthetic cubes stand in for it.  Recipes (all stated in the design doc):
+
+* geometry: unit cube, n cells per side, h = 1/n.  Nodes are jittered by an
+  i.i.d. uniform offset in [-j*h, +j*h] per coordinate; nodes on the boundary
+  move only tangentially (faces stay planar, corners stay put), so the domain
+  stays exactly [0,1]^3.
+* HEX08 node order: 0:(-,-,-) 1:(+,-,-) 2:(+,+,-) 3:(-,+,-) 4:(-,-,+)
+  5:(+,-,+) 6:(+,+,+) 7:(-,+,+).
+* TET04: each cube split into six tetrahedra around the 0-6 diagonal,
+  (0,1,2,6) (0,2,3,6) (0,3,7,6) (0,7,4,6) (0,4,5,6) (0,5,1,6), all positively
+  oriented and conforming across cubes.
+* velocity: Taylor-Green u = sin2πx cos2πy cos2πz, v = -cos2πx sin2πy cos2πz,
+  w = 0, plus i.i.d. N(0, 0.01^2) per component.
+* density U[0.2, 1.2] i.i.d. per node; viscosity 1.8e-5 (air).
+* flame-kernel temperature T = 300 + 1700 * (1 - tanh((r - 0.25)/0.03))/2
+  around the cube centre; density p0/(R T), Sutherland viscosity.
+* species Y_k ~ U[0,1], diffusivities D_k = 10^U(-6,-4).
+* time step dt = 0.5 h / U0 with U0 = 1.
+
+Random sub-streams come from numpy.random.SeedSequence(case_id).spawn(9) in
+the fixed order: jitter, u-noise, rho, node permutation, element permutation,
+Y, D, arrivals, sizes.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+HEX08 = 8
+TET04 = 4
+
+# Six positively oriented tetrahedra per hexahedron, local HEX08 node ids.
+KUHN_TETS = np.array(
+    [[0, 1, 2, 6], [0, 2, 3, 6], [0, 3, 7, 6], [0, 7, 4, 6], [0, 4, 5, 6], [0, 5, 1, 6]],
+    dtype=np.int64,
+)
+
+AIR_P0 = 101325.0        # Pa
+AIR_R = 287.05           # J/(kg K)
+SUTH_MU_REF = 1.716e-5   # Pa s
+SUTH_T_REF = 273.15      # K
+SUTH_S = 110.4           # K
+MU_AIR = 1.8e-5
+
+_STREAMS = ("jitter", "unoise", "rho", "nperm", "eperm", "Y", "D", "arrivals", "sizes")
+
+
+def streams(case_id: int, sub=None) -> dict:
+    """Named numpy Generators for a case (and optional sub-case id)."""
+    key = [int(case_id)] if sub is None else [int(case_id), int(sub)]
+    ss = np.random.SeedSequence(key)
+    return {name: np.random.Generator(np.random.PCG64(s))
+            for name, s in zip(_STREAMS, ss.spawn(len(_STREAMS)))}
+
+
+@dataclass
+class Case:
+    """A mesh plus its nodal fields, all in the user's numbering.
+
+    coords [N,3] float64; conn [E,nen] int32; dirichlet int32 node ids;
+    u [3,N]; rho [N]; mu [N]; Y [k,N]; D [k]; dt scalar.
+    """
+    elem_type: int
+    n: int
+    coords: np.ndarray
+    conn: np.ndarray
+    dirichlet: np.ndarray
+    u: np.ndarray
+    rho: np.ndarray
+    mu: np.ndarray
+    dt: float
+    Y: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+    D: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    name: str = ""
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.coords.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.conn.shape[0])
+
+    @property
+    def nen(self) -> int:
+        return int(self.conn.shape[1])
+
+
+def node_id(n: int, i, j, k):
+    return i + (n + 1) * (j + (n + 1) * k)
+
+
+def cube_nodes(n: int, jitter: float = 0.0, rng=None) -> np.ndarray:
+    """Nodes of an n^3 grid on [0,1]^3, id = i + (n+1)(j + (n+1)k).
+
+    Jitter is uniform in [-jitter*h, jitter*h] per coordinate; a boundary node
+    keeps the coordinate normal to each boundary face it lies on.
+    """
+    h = 1.0 / n
+    g = np.arange(n + 1, dtype=np.float64) * h
+    kk, jj, ii = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    idx = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    x = g[idx]
+    if jitter > 0.0:
+        if rng is None:
+            raise ValueError("jitter needs an rng")
+        d = rng.uniform(-jitter * h, jitter * h, size=x.shape)
+        on_bnd = (idx == 0) | (idx == n)
+        d[on_bnd] = 0.0
+        x = x + d
+    return np.ascontiguousarray(x)
+
+
+def hex_conn(n: int) -> np.ndarray:
+    """HEX08 connectivity of the n^3 grid, elements i-fastest."""
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    i, j, k = ii.ravel(), jj.ravel(), kk.ravel()
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+               (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    conn = np.stack([node_id(n, i + a, j + b, k + c) for a, b, c in corners], axis=1)
+    return np.ascontiguousarray(conn.astype(np.int32))
+
+
+def kuhn_split(hconn: np.ndarray) -> np.ndarray:
+    """Split every HEX08 into six TET04 (hex order kept, tets consecutive)."""
+    t = hconn[:, KUHN_TETS]                      # [E, 6, 4]
+    return np.ascontiguousarray(t.reshape(-1, 4).astype(np.int32))
+
+
+def boundary_nodes(n: int) -> np.ndarray:
+    kk, jj, ii = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    m = (ii == 0) | (ii == n) | (jj == 0) | (jj == n) | (kk == 0) | (kk == n)
+    return np.flatnonzero(m.ravel()).astype(np.int32)
+
+
+def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems):
+    """Random renumbering: new id of old node i is pn[i]; elements shuffled.
+
+    node_fields: list of arrays whose LAST axis is the node axis.
+    """
+    N = coords.shape[0]
+    E = conn.shape[0]
+    pn = rng_nodes.permutation(N)
+    pe = rng_elems.permutation(E)
+    inv = np.empty(N, dtype=np.int64)
+    inv[pn] = np.arange(N)
+    coords2 = np.ascontiguousarray(coords[inv])
+    conn2 = np.ascontiguousarray(pn[conn[pe]].astype(np.int32))
+    dir2 = np.sort(pn[dirichlet]).astype(np.int32)
+    f2 = [np.ascontiguousarray(f[..., inv]) for f in node_fields]
+    return coords2, conn2, dir2, f2
+
+
+def taylor_green(coords, rng=None, noise=0.01) -> np.ndarray:
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    tp = 2.0 * math.pi
+    u = np.stack([np.sin(tp * x) * np.cos(tp * y) * np.cos(tp * z),
+                  -np.cos(tp * x) * np.sin(tp * y) * np.cos(tp * z),
+                  np.zeros_like(x)])
+    if noise > 0.0:
+        u = u + rng.normal(0.0, noise, size=u.shape)
+    return np.ascontiguousarray(u)
+
+
+def flame_temperature(coords) -> np.ndarray:
+    r = np.linalg.norm(coords - 0.5, axis=1)
+    return 300.0 + 1700.0 * 0.5 * (1.0 - np.tanh((r - 0.25) / 0.03))
+
+
+def ideal_gas_density(T) -> np.ndarray:
+    return AIR_P0 / (AIR_R * T)
+
+
+def sutherland(T) -> np.ndarray:
+    return SUTH_MU_REF * (T / SUTH_T_REF) ** 1.5 * (SUTH_T_REF + SUTH_S) / (T + SUTH_S)
+
+
+def time_step(n: int, u0: float = 1.0) -> float:
+    return 0.5 * (1.0 / n) / u0
+
+
+def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int = 0,
+              sub=None, shuffle: bool = False, temperature: bool = False,
+              n_scalars: int = 0, noise: float = 0.01, name: str = "") -> Case:
+    """Build one synthetic case (see the module docstring for the recipe)."""
+    rs = streams(case_id, sub)
+    coords = cube_nodes(n, jitter, rs["jitter"])
+    hconn = hex_conn(n)
+    conn = hconn if elem_type == HEX08 else kuhn_split(hconn)
+    dirichlet = boundary_nodes(n)
+    N = coords.shape[0]
+    u = taylor_green(coords, rs["unoise"], noise)
+    if temperature:
+        T = flame_temperature(coords)
+        rho = ideal_gas_density(T)
+        mu = sutherland(T)
+    else:
+        rho = rs["rho"].uniform(0.2, 1.2, size=N)
+        mu = np.full(N, MU_AIR)
+    Y = rs["Y"].uniform(0.0, 1.0, size=(n_scalars, N)) if n_scalars else np.zeros((0, N))
+    D = 10.0 ** rs["D"].uniform(-6.0, -4.0, size=n_scalars) if n_scalars else np.zeros(0)
+    if shuffle:
+        coords, conn, dirichlet, (u, rho, mu, Y) = permute(
+            coords, conn, dirichlet, [u, rho, mu, Y], rs["nperm"], rs["eperm"])
+    return Case(elem_type, n, coords, conn.astype(np.int32), dirichlet, u, rho, mu,
+                time_step(n), Y, D, name)
+
+
+# --- the five workloads -----------------------------------------------------
+
+def cfg0() -> Case:
+    """10^3 HEX08, jitter 10 %, Taylor-Green + noise, rho U[0.2,1.2]."""
+    return make_case(10, HEX08, 0.10, case_id=0, name="hex08-10^3")
+
+
+def cfg1(n: int = 128) -> Case:
+    """128^3 HEX08, jitter 15 %, node and element ids shuffled."""
+    return make_case(n, HEX08, 0.15, case_id=1, shuffle=True, name=f"hex08-{n}^3-shuffled")
+
+
+def cfg2(n: int = 128) -> Case:
+    """128^3 cubes x 6 Kuhn TET04, jitter 10 %, flame-kernel T, shuffled."""
+    return make_case(n, TET04, 0.10, case_id=2, shuffle=True, temperature=True,
+                     name=f"tet04-6x{n}^3-flame")
+
+
+def cfg4(n: int = 256) -> Case:
+    """256^3 HEX08, jitter 15 %, plus 5 species and diffusivities."""
+    return make_case(n, HEX08, 0.15, case_id=4, n_scalars=5, name=f"hex08-{n}^3-5species")
+
+
+def serving_stream(n_requests: int = 2000, qps: float = 1.0, lo: int = 8, hi: int = 96):
+    """Arrival times (s) and cube sides of the serving workload."""
+    rs = streams(3)
+    gaps = rs["arrivals"].exponential(1.0 / qps, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    sides = np.rint(np.exp(rs["sizes"].uniform(math.log(lo), math.log(hi), size=n_requests)))
+    return t, sides.astype(np.int64)
+
+
+def serving_case(req: int, n: int) -> Case:
+    """Request `req` of the serving workload: a jittered HEX08 cube as cfg0."""
+    return make_case(int(n), HEX08, 0.10, case_id=3, sub=req, name=f"req{req}-hex08-{n}^3")
+
+
+def hex_pattern_nnz(n: int) -> int:
+    return (3 * n + 1) ** 3
+
+
+def kuhn_pattern_nnz(n: int) -> int:
+    edges = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
+    return (n + 1) ** 3 + 2 * edges

@@ -1,0 +1,186 @@
+"""Python access to the FP64 CPU oracle (feoracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product library never does.
+It shares no code with the GPU path.  The shared object is built with plain
+gcc and no FMA contraction (see build()).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "feoracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OP_MOMENTUM, OP_SCALAR, OP_POISSON = 0, 1, 2
+OK, EINVAL, ENOMEM, EBADELEM, ENOCONV, EBREAKDOWN = 0, 1, 2, 4, 5, 6
+
+_lib = None
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (serial, -ffp-contract=off)."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                           "-std=c99", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        L.or_pattern.restype = i64
+        L.or_pattern.argtypes = [i32, i64, i64, P, P, P]
+        L.or_assemble.restype = i32
+        L.or_assemble.argtypes = [i32, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
+                                  i32, C.POINTER(i64), C.POINTER(dbl)]
+        L.or_dirichlet.restype = i32
+        L.or_dirichlet.argtypes = [i64, P, P, P, P, i64, P, P]
+        L.or_spmv.restype = None
+        L.or_spmv.argtypes = [i64, P, P, P, P, P]
+        L.or_dot.restype = dbl
+        L.or_dot.argtypes = [i64, P, P]
+        L.or_pcg.restype = i32
+        L.or_pcg.argtypes = [i64, P, P, P, P, P, dbl, i32, P]
+        for name in ("or_hex08_shape", "or_tet04_shape"):
+            getattr(L, name).restype = None
+            getattr(L, name).argtypes = [P, P, P]
+        for name in ("or_hex08_gauss", "or_tet04_gauss"):
+            getattr(L, name).restype = None
+            getattr(L, name).argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# --- reference element -------------------------------------------------------
+
+def shape(nen: int, xi):
+    xi = _f64(xi)
+    N = np.zeros(nen)
+    dN = np.zeros((nen, 3))
+    fn = lib().or_hex08_shape if nen == 8 else lib().or_tet04_shape
+    fn(_p(xi), _p(N), _p(dN))
+    return N, dN
+
+
+def gauss(nen: int):
+    ng = 8 if nen == 8 else 4
+    pts = np.zeros((ng, 3))
+    w = np.zeros(ng)
+    fn = lib().or_hex08_gauss if nen == 8 else lib().or_tet04_gauss
+    fn(_p(pts), _p(w))
+    return pts, w
+
+
+# --- assembly ----------------------------------------------------------------
+
+def pattern(conn, n_nodes: int):
+    conn = _i32(conn)
+    nen = conn.shape[1]
+    rowptr = np.zeros(n_nodes + 1, dtype=np.int32)
+    nnz = lib().or_pattern(nen, n_nodes, conn.shape[0], _p(conn), _p(rowptr), None)
+    if nnz < 0:
+        raise ValueError("invalid connectivity")
+    colidx = np.zeros(max(nnz, 1), dtype=np.int32)[:nnz]
+    lib().or_pattern(nen, n_nodes, conn.shape[0], _p(conn), _p(rowptr), _p(colidx))
+    return rowptr, colidx
+
+
+class AssembleError(RuntimeError):
+    def __init__(self, status, bad_elem, min_det):
+        super().__init__(f"oracle assembly failed: status {status}, element {bad_elem}, min detJ {min_det}")
+        self.status, self.bad_elem, self.min_det = status, bad_elem, min_det
+
+
+def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None, D=None,
+             pattern_=None, mixed: bool = False):
+    """Return (rowptr, colidx, values[n_mat, nnz], rhs[n_rhs, N])."""
+    coords = _f64(coords)
+    conn = _i32(conn)
+    N = coords.shape[0]
+    nen = conn.shape[1]
+    rowptr, colidx = pattern_ if pattern_ is not None else pattern(conn, N)
+    nnz = int(rowptr[-1])
+    ns = 0 if Y is None else int(np.asarray(Y).shape[0])
+    n_mat = ns if op == OP_SCALAR else 1
+    n_rhs = 3 if op == OP_MOMENTUM else (ns if op == OP_SCALAR else 1)
+    u = _f64(u if u is not None else np.zeros((3, N)))
+    rho = _f64(rho if rho is not None else np.ones(N))
+    mu = _f64(mu if mu is not None else np.ones(N))
+    Yp = _f64(Y) if ns else None
+    Dp = _f64(D) if ns else None
+    values = np.zeros((n_mat, nnz))
+    rhs = np.zeros((n_rhs, N))
+    bad = C.c_int64(-1)
+    mdet = C.c_double(0.0)
+    st = lib().or_assemble(nen, N, _p(coords), conn.shape[0], _p(conn), op, dt, _p(u), _p(rho), _p(mu),
+                           ns, _p(Yp), _p(Dp), _p(rowptr), _p(colidx), _p(values), _p(rhs),
+                           1 if mixed else 0, C.byref(bad), C.byref(mdet))
+    if st != OK:
+        raise AssembleError(st, bad.value, mdet.value)
+    return rowptr, colidx, values, rhs
+
+
+def dirichlet(rowptr, colidx, values, rhs, dnodes, g=None):
+    """Apply symmetric elimination in place (values [nnz], rhs [N])."""
+    N = rowptr.shape[0] - 1
+    dn = _i32(dnodes)
+    gp = _f64(g) if g is not None else None
+    assert values.flags.c_contiguous and rhs.flags.c_contiguous
+    st = lib().or_dirichlet(N, _p(rowptr), _p(colidx), _p(values), _p(rhs), dn.shape[0], _p(dn), _p(gp))
+    if st != OK:
+        raise ValueError(f"oracle dirichlet failed: {st}")
+
+
+def spmv(rowptr, colidx, values, x):
+    N = rowptr.shape[0] - 1
+    x = _f64(x)
+    y = np.zeros(N)
+    lib().or_spmv(N, _p(rowptr), _p(colidx), _p(_f64(values)), _p(x), _p(y))
+    return y
+
+
+def dot(x, y):
+    x, y = _f64(x), _f64(y)
+    return lib().or_dot(x.shape[0], _p(x), _p(y))
+
+
+def pcg(rowptr, colidx, values, b, x0=None, rtol=1e-10, max_iter=10000):
+    """Jacobi-PCG; returns (x, status, iterations, rel_res, true_rel_res)."""
+    N = rowptr.shape[0] - 1
+    b = _f64(b)
+    x = np.zeros(N) if x0 is None else _f64(x0).copy()
+    info = np.zeros(3)
+    values = _f64(values)
+    st = lib().or_pcg(N, _p(rowptr), _p(colidx), _p(values), _p(b), _p(x), rtol, max_iter, _p(info))
+    return x, st, int(info[0]), float(info[1]), float(info[2])
+
+
+def time_call(fn, *a, **k):
+    t0 = time.perf_counter()
+    r = fn(*a, **k)
+    return r, time.perf_counter() - t0

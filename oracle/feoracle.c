@@ -1,0 +1,523 @@
+/*
+ * feoracle.c -- plain, serial FP64 reference of the finite-element hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the GPU
+ * path.  Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction,
+ * so every product and sum is rounded as written).
+ *
+ * What it computes (paper: Oyarzun, Mira, Houzeaux, "Performance assessment
+ * of CUDA and OpenACC in large scale combustion simulations"):
+ *
+ *  - Element-by-element Galerkin assembly (Section 4.2, Listing 1: an outer
+ *    loop over elements, an inner loop over Gauss points and node pairs that
+ *    accumulates Ae(a,b) from shape functions N and the Jacobian weight).
+ *    The operator is the momentum operator of Eq. (1) in the reduced form
+ *    fixed in the design doc: density-weighted mass / dt + advective convection
+ *    + Laplacian-form viscous term, and its right-hand side M_rho u / dt;
+ *    a scalar-transport variant with coefficient rho*D_k; and the
+ *    constant-coefficient pressure Laplacian assembled once before the time
+ *    loop (Algorithm 1, first step).
+ *  - Scatter of the elemental matrices into CSR (Section 4.2), in element
+ *    order: A = sum_e P_e^T A_e P_e.
+ *  - Symmetric Dirichlet elimination for the pressure system.
+ *  - Jacobi-preconditioned conjugate gradients for the pressure equation
+ *    (Algorithm 1, last step; Section 5.2 names its SpMV, AXPY and dot
+ *    kernels).
+ *
+ * Reference elements: HEX08 trilinear with the 2x2x2 Gauss rule at +-1/sqrt3
+ * (weights 1, xi fastest); TET04 linear with the 4-point rule at the
+ * barycentric permutations of (b,a,a,a), a = (5-sqrt5)/20, b = 1-3a,
+ * weights 1/24.  Jacobian J_ij = d x_i / d xi_j; grad N = J^-T grad_ref N.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL 1
+#define OR_ENOMEM 2
+#define OR_EBADELEM 4
+#define OR_ENOCONV 5
+#define OR_EBREAKDOWN 6
+
+#define OP_MOMENTUM 0
+#define OP_SCALAR 1
+#define OP_POISSON 2
+
+#define MAXN 8
+#define MAXG 8
+#define MAXS 8
+
+/* ------------------------------------------------------------------ */
+/* Reference elements                                                 */
+/* ------------------------------------------------------------------ */
+
+static const double HEX_CORNER[8][3] = {
+    {-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+    {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+/* Trilinear shape functions N_a(xi) = 1/8 (1+xa xi)(1+ya eta)(1+za zeta)
+ * and their reference gradients dN[a][j] = dN_a / dxi_j. */
+void or_hex08_shape(const double *xi, double *N, double *dN)
+{
+    for (int a = 0; a < 8; ++a) {
+        double sx = HEX_CORNER[a][0], sy = HEX_CORNER[a][1], sz = HEX_CORNER[a][2];
+        double fx = 1.0 + sx * xi[0], fy = 1.0 + sy * xi[1], fz = 1.0 + sz * xi[2];
+        N[a] = 0.125 * fx * fy * fz;
+        dN[a * 3 + 0] = 0.125 * sx * fy * fz;
+        dN[a * 3 + 1] = 0.125 * fx * sy * fz;
+        dN[a * 3 + 2] = 0.125 * fx * fy * sz;
+    }
+}
+
+/* 2x2x2 Gauss-Legendre points (xi fastest, then eta, then zeta), weight 1. */
+void or_hex08_gauss(double *pts, double *w)
+{
+    double g = 1.0 / sqrt(3.0);
+    int q = 0;
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) {
+                pts[q * 3 + 0] = i ? g : -g;
+                pts[q * 3 + 1] = j ? g : -g;
+                pts[q * 3 + 2] = k ? g : -g;
+                w[q] = 1.0;
+                ++q;
+            }
+}
+
+/* Linear tetrahedron on (0,0,0),(1,0,0),(0,1,0),(0,0,1). */
+void or_tet04_shape(const double *xi, double *N, double *dN)
+{
+    N[0] = 1.0 - xi[0] - xi[1] - xi[2];
+    N[1] = xi[0];
+    N[2] = xi[1];
+    N[3] = xi[2];
+    static const double g[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int a = 0; a < 4; ++a)
+        for (int j = 0; j < 3; ++j) dN[a * 3 + j] = g[a][j];
+}
+
+/* Degree-2 four-point rule: point q has barycentric coordinate b at vertex q
+ * and a at the other three; weights 1/24 (reference volume 1/6). */
+void or_tet04_gauss(double *pts, double *w)
+{
+    double a = (5.0 - sqrt(5.0)) / 20.0;
+    double b = 1.0 - 3.0 * a;
+    for (int q = 0; q < 4; ++q) {
+        /* (xi,eta,zeta) are the barycentric coordinates of vertices 1..3 */
+        for (int j = 0; j < 3; ++j) pts[q * 3 + j] = (q == j + 1) ? b : a;
+        w[q] = 1.0 / 24.0;
+    }
+}
+
+static int ref_element(int nen, double pts[MAXG][3], double w[MAXG],
+                       double N[MAXG][MAXN], double dN[MAXG][MAXN][3])
+{
+    int ng;
+    if (nen == 8) {
+        or_hex08_gauss(&pts[0][0], w);
+        ng = 8;
+        for (int g = 0; g < ng; ++g) or_hex08_shape(pts[g], N[g], &dN[g][0][0]);
+    } else if (nen == 4) {
+        or_tet04_gauss(&pts[0][0], w);
+        ng = 4;
+        for (int g = 0; g < ng; ++g) or_tet04_shape(pts[g], N[g], &dN[g][0][0]);
+    } else {
+        return -1;
+    }
+    return ng;
+}
+
+/* ------------------------------------------------------------------ */
+/* CSR pattern: row i holds every node that shares an element with i,   */
+/* columns sorted ascending.                                            */
+/* ------------------------------------------------------------------ */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Pass colidx == NULL to get nnz and rowptr; call again to fill colidx.
+ * Returns nnz, or -1 on an invalid connectivity entry. */
+int64_t or_pattern(int nen, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
+                   int32_t *rowptr, int32_t *colidx)
+{
+    int64_t *cnt = calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    if (!cnt) return -1;
+    for (int64_t e = 0; e < n_elems; ++e)
+        for (int a = 0; a < nen; ++a) {
+            int32_t v = conn[e * nen + a];
+            if (v < 0 || v >= n_nodes) { free(cnt); return -1; }
+            cnt[v + 1]++;
+        }
+    for (int64_t i = 0; i < n_nodes; ++i) cnt[i + 1] += cnt[i];
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
+    int64_t *inc = malloc(sizeof(int64_t) * (size_t)(cnt[n_nodes] + 1));
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n_nodes + 1));
+    for (int64_t e = 0; e < n_elems; ++e)
+        for (int a = 0; a < nen; ++a) inc[fill[conn[e * nen + a]]++] = e;
+    int32_t *buf = malloc(sizeof(int32_t) * 4096);
+    size_t cap = 4096;
+    int64_t nnz = 0;
+    rowptr[0] = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        size_t m = 0;
+        for (int64_t k = cnt[i]; k < cnt[i + 1]; ++k) {
+            int64_t e = inc[k];
+            if (m + (size_t)nen > cap) {
+                cap *= 2;
+                buf = realloc(buf, sizeof(int32_t) * cap);
+            }
+            for (int a = 0; a < nen; ++a) buf[m++] = conn[e * nen + a];
+        }
+        qsort(buf, m, sizeof(int32_t), cmp_i32);
+        size_t u = 0;
+        for (size_t k = 0; k < m; ++k)
+            if (k == 0 || buf[k] != buf[k - 1]) buf[u++] = buf[k];
+        if (colidx)
+            for (size_t k = 0; k < u; ++k) colidx[nnz + (int64_t)k] = buf[k];
+        nnz += (int64_t)u;
+        rowptr[i + 1] = (int32_t)nnz;
+    }
+    free(buf);
+    free(inc);
+    free(fill);
+    free(cnt);
+    return nnz;
+}
+
+static int64_t find_col(const int32_t *rowptr, const int32_t *colidx, int32_t i, int32_t j)
+{
+    int64_t lo = rowptr[i], hi = rowptr[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (colidx[mid] == j) return mid;
+        if (colidx[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Assembly                                                            */
+/* ------------------------------------------------------------------ */
+
+/* Geometry at one Gauss point: J, det J, J^-1 and physical gradients. */
+static double geometry(int nen, double X[MAXN][3], double dNr[MAXN][3], double dNx[MAXN][3])
+{
+    double J[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < nen; ++a) s += X[a][i] * dNr[a][j];
+            J[i][j] = s;
+        }
+    double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    if (!(det > 0.0)) return det;
+    double Ji[3][3]; /* inverse of J */
+    Ji[0][0] = c00 / det;
+    Ji[1][0] = c01 / det;
+    Ji[2][0] = c02 / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    /* grad_x N_a = J^-T grad_xi N_a :  (grad N_a)_i = sum_j Ji[j][i] dNr[a][j] */
+    for (int a = 0; a < nen; ++a)
+        for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += Ji[j][i] * dNr[a][j];
+            dNx[a][i] = s;
+        }
+    return det;
+}
+
+/*
+ * Assemble one operator into a CSR pattern produced by or_pattern.
+ *
+ *   op = 0 MOMENTUM: values[1][nnz] = M/dt + C + K_mu ; rhs[3][N], b_i = M_rho u_i / dt
+ *   op = 1 SCALAR  : values[k][nnz] = M/dt + C + K_{rho D_k} ; rhs[k][N] = M_rho Y_k / dt
+ *   op = 2 POISSON : values[1][nnz] = L ; rhs[1][N], f_a = (1/dt) int grad N_a . (rho u)
+ *
+ * with, at each Gauss point, dV = w det J, rho_g, mu_g, u_g the nodal
+ * interpolants, and
+ *   M_ab = sum dV rho_g N_a N_b
+ *   C_ab = sum dV rho_g N_a (u_g . grad N_b)
+ *   K_ab = sum dV coef_g grad N_a . grad N_b.
+ * mixed != 0 reproduces, for characterisation only, FP32 quadrature: the
+ * Gauss-point inputs are rounded to float, the products and the elemental
+ * sums are float, the elemental matrix is widened to double and assembled in
+ * double.  Inputs: coords [N][3]; conn [E][nen]; u [3][N]; rho, mu [N];
+ * Y [k][N]; D [k].  Outputs are overwritten.  Returns OR_EBADELEM (with the
+ * first element index and the smallest det J) for det J <= 0.
+ */
+int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
+                const int32_t *conn, int op, double dt, const double *u, const double *rho,
+                const double *mu, int n_scalars, const double *Y, const double *D,
+                const int32_t *rowptr, const int32_t *colidx, double *values, double *rhs,
+                int mixed, int64_t *bad_elem, double *min_det)
+{
+    double pts[MAXG][3], w[MAXG], Ng[MAXG][MAXN], dNr[MAXG][MAXN][3];
+    int ng = ref_element(nen, pts, w, Ng, dNr);
+    if (ng < 0) return OR_EINVAL;
+    if (op == OP_SCALAR && (n_scalars < 1 || n_scalars > MAXS)) return OR_EINVAL;
+    int n_mat = (op == OP_SCALAR) ? n_scalars : 1;
+    int n_rhs = (op == OP_MOMENTUM) ? 3 : (op == OP_SCALAR ? n_scalars : 1);
+    int64_t nnz = rowptr[n_nodes];
+    memset(values, 0, sizeof(double) * (size_t)(nnz * n_mat));
+    memset(rhs, 0, sizeof(double) * (size_t)(n_nodes * n_rhs));
+    *bad_elem = -1;
+    *min_det = INFINITY;
+    int status = OR_OK;
+
+    for (int64_t e = 0; e < n_elems; ++e) {
+        const int32_t *c = conn + e * nen;
+        double X[MAXN][3];
+        for (int a = 0; a < nen; ++a)
+            for (int i = 0; i < 3; ++i) X[a][i] = coords[(int64_t)c[a] * 3 + i];
+
+        double M[MAXN][MAXN] = {{0}}, C[MAXN][MAXN] = {{0}}, K[MAXS][MAXN][MAXN] = {{{0}}};
+        double B[MAXS][MAXN] = {{0}};
+        float Mf[MAXN][MAXN] = {{0}}, Cf[MAXN][MAXN] = {{0}}, Kf[MAXS][MAXN][MAXN] = {{{0}}};
+        float Bf[MAXS][MAXN] = {{0}};
+
+        for (int g = 0; g < ng; ++g) {
+            double dNx[MAXN][3];
+            double det = geometry(nen, X, dNr[g], dNx);
+            if (det < *min_det) *min_det = det;
+            if (!(det > 0.0)) {
+                if (*bad_elem < 0) *bad_elem = e;
+                status = OR_EBADELEM;
+                break;
+            }
+            double dV = w[g] * det;
+            double rg = 0.0, mg = 0.0, ug[3] = {0.0, 0.0, 0.0}, yg[MAXS] = {0};
+            for (int a = 0; a < nen; ++a) {
+                double Na = Ng[g][a];
+                rg += Na * rho[c[a]];
+                if (op == OP_MOMENTUM) mg += Na * mu[c[a]];
+                for (int i = 0; i < 3; ++i) ug[i] += Na * u[(int64_t)i * n_nodes + c[a]];
+                if (op == OP_SCALAR)
+                    for (int k = 0; k < n_scalars; ++k) yg[k] += Na * Y[(int64_t)k * n_nodes + c[a]];
+            }
+            if (!mixed) {
+                for (int a = 0; a < nen; ++a) {
+                    double Na = Ng[g][a];
+                    for (int b = 0; b < nen; ++b) {
+                        double Nb = Ng[g][b];
+                        double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
+                        double ugb = ug[0] * dNx[b][0] + ug[1] * dNx[b][1] + ug[2] * dNx[b][2];
+                        if (op == OP_POISSON) {
+                            K[0][a][b] += dV * gg;
+                        } else {
+                            M[a][b] += dV * rg * Na * Nb;
+                            C[a][b] += dV * rg * Na * ugb;
+                            if (op == OP_MOMENTUM)
+                                K[0][a][b] += dV * mg * gg;
+                            else
+                                for (int k = 0; k < n_scalars; ++k) K[k][a][b] += dV * (rg * D[k]) * gg;
+                        }
+                    }
+                    if (op == OP_MOMENTUM)
+                        for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ug[i] / dt;
+                    else if (op == OP_SCALAR)
+                        for (int k = 0; k < n_scalars; ++k) B[k][a] += dV * rg * Na * yg[k] / dt;
+                    else
+                        B[0][a] += (1.0 / dt) * dV *
+                                   (dNx[a][0] * (rg * ug[0]) + dNx[a][1] * (rg * ug[1]) + dNx[a][2] * (rg * ug[2]));
+                }
+            } else {
+                float fdV = (float)dV, frg = (float)rg, fmg = (float)mg, fdt = (float)dt;
+                float fug[3] = {(float)ug[0], (float)ug[1], (float)ug[2]};
+                float fyg[MAXS];
+                for (int k = 0; k < n_scalars; ++k) fyg[k] = (float)yg[k];
+                float fN[MAXN], fdN[MAXN][3];
+                for (int a = 0; a < nen; ++a) {
+                    fN[a] = (float)Ng[g][a];
+                    for (int i = 0; i < 3; ++i) fdN[a][i] = (float)dNx[a][i];
+                }
+                for (int a = 0; a < nen; ++a) {
+                    for (int b = 0; b < nen; ++b) {
+                        float gg = fdN[a][0] * fdN[b][0] + fdN[a][1] * fdN[b][1] + fdN[a][2] * fdN[b][2];
+                        float ugb = fug[0] * fdN[b][0] + fug[1] * fdN[b][1] + fug[2] * fdN[b][2];
+                        if (op == OP_POISSON) {
+                            Kf[0][a][b] += fdV * gg;
+                        } else {
+                            Mf[a][b] += fdV * frg * fN[a] * fN[b];
+                            Cf[a][b] += fdV * frg * fN[a] * ugb;
+                            if (op == OP_MOMENTUM)
+                                Kf[0][a][b] += fdV * fmg * gg;
+                            else
+                                for (int k = 0; k < n_scalars; ++k)
+                                    Kf[k][a][b] += fdV * (frg * (float)D[k]) * gg;
+                        }
+                    }
+                    if (op == OP_MOMENTUM)
+                        for (int i = 0; i < 3; ++i) Bf[i][a] += fdV * frg * fN[a] * fug[i] / fdt;
+                    else if (op == OP_SCALAR)
+                        for (int k = 0; k < n_scalars; ++k) Bf[k][a] += fdV * frg * fN[a] * fyg[k] / fdt;
+                    else
+                        Bf[0][a] += (1.0f / fdt) * fdV *
+                                    (fdN[a][0] * (frg * fug[0]) + fdN[a][1] * (frg * fug[1]) +
+                                     fdN[a][2] * (frg * fug[2]));
+                }
+            }
+        }
+        if (status != OR_OK) continue;
+        if (mixed) {
+            for (int a = 0; a < nen; ++a) {
+                for (int b = 0; b < nen; ++b) {
+                    M[a][b] = Mf[a][b];
+                    C[a][b] = Cf[a][b];
+                    for (int k = 0; k < n_mat; ++k) K[k][a][b] = Kf[k][a][b];
+                }
+                for (int k = 0; k < n_rhs; ++k) B[k][a] = Bf[k][a];
+            }
+        }
+        /* A_e = M/dt + C + K (momentum, scalar) or L (Poisson); scatter. */
+        for (int a = 0; a < nen; ++a) {
+            for (int b = 0; b < nen; ++b) {
+                int64_t pos = find_col(rowptr, colidx, c[a], c[b]);
+                if (pos < 0) return OR_EINVAL;
+                for (int k = 0; k < n_mat; ++k) {
+                    double v = (op == OP_POISSON) ? K[0][a][b] : (M[a][b] / dt + C[a][b] + K[k][a][b]);
+                    values[(int64_t)k * nnz + pos] += v;
+                }
+            }
+            for (int k = 0; k < n_rhs; ++k) rhs[(int64_t)k * n_nodes + c[a]] += B[k][a];
+        }
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dirichlet elimination (symmetric)                                   */
+/* ------------------------------------------------------------------ */
+
+/* For a free row i: f_i -= sum_{j in D} L_ij g_j and L_ij = 0 for j in D.
+ * For a Dirichlet row i: off-diagonals = 0, diagonal kept, f_i = L_ii g_i.
+ * g == NULL means g = 0. */
+int or_dirichlet(int64_t n_nodes, const int32_t *rowptr, const int32_t *colidx, double *values,
+                 double *rhs, int64_t n_dir, const int32_t *dnodes, const double *g)
+{
+    unsigned char *isd = calloc((size_t)n_nodes, 1);
+    if (!isd) return OR_ENOMEM;
+    for (int64_t k = 0; k < n_dir; ++k) {
+        if (dnodes[k] < 0 || dnodes[k] >= n_nodes) { free(isd); return OR_EINVAL; }
+        isd[dnodes[k]] = 1;
+    }
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        if (isd[i]) continue;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int32_t j = colidx[p];
+            if (isd[j]) {
+                double gj = g ? g[j] : 0.0;
+                rhs[i] -= values[p] * gj;
+                values[p] = 0.0;
+            }
+        }
+    }
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        if (!isd[i]) continue;
+        double diag = 0.0;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (colidx[p] == i) diag = values[p];
+            else values[p] = 0.0;
+        }
+        rhs[i] = diag * (g ? g[i] : 0.0);
+    }
+    free(isd);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Solver kernels and Jacobi-PCG                                       */
+/* ------------------------------------------------------------------ */
+
+void or_spmv(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+             const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s += vals[p] * x[colidx[p]];
+        y[i] = s;
+    }
+}
+
+double or_dot(int64_t n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+void or_axpy(int64_t n, double a, const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] += a * x[i];
+}
+
+/*
+ * Jacobi-preconditioned CG on an SPD CSR matrix.
+ * x holds x0 on entry and the iterate on return.  Stop when
+ * ||r_k||_2 <= rtol ||b||_2 (recursive residual).  rtol <= 0 runs exactly
+ * max_iter iterations.  info[0] = iterations, info[1] = ||r||/||b||
+ * (recursive), info[2] = ||b - A x||/||b|| recomputed.
+ * Returns OR_OK, OR_ENOCONV or OR_EBREAKDOWN (p.Ap <= 0 or not finite).
+ */
+int or_pcg(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+           const double *b, double *x, double rtol, int max_iter, double *info)
+{
+    double *r = malloc(sizeof(double) * (size_t)n), *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+    double *dinv = malloc(sizeof(double) * (size_t)n);
+    if (!r || !z || !p || !q || !dinv) return OR_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (colidx[k] == i) d = vals[k];
+        dinv[i] = 1.0 / d;
+    }
+    or_spmv(n, rowptr, colidx, vals, x, q);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    double bnorm = sqrt(or_dot(n, b, b));
+    for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double rho = or_dot(n, r, z);
+    int status = OR_ENOCONV, it = 0;
+    double rnorm = sqrt(or_dot(n, r, r));
+    if (rtol > 0.0 && rnorm <= rtol * bnorm) status = OR_OK;
+    while (status == OR_ENOCONV && it < max_iter) {
+        or_spmv(n, rowptr, colidx, vals, p, q);
+        double pq = or_dot(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = OR_EBREAKDOWN; break; }
+        double alpha = rho / pq;
+        or_axpy(n, alpha, p, x);
+        or_axpy(n, -alpha, q, r);
+        ++it;
+        rnorm = sqrt(or_dot(n, r, r));
+        if (rtol > 0.0 && rnorm <= rtol * bnorm) { status = OR_OK; break; }
+        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        double rho1 = or_dot(n, r, z);
+        double beta = rho1 / rho;
+        rho = rho1;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (rtol <= 0.0 && status == OR_ENOCONV && it == max_iter) status = OR_OK;
+    or_spmv(n, rowptr, colidx, vals, x, q);
+    for (int64_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
+    info[0] = it;
+    info[1] = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+    info[2] = bnorm > 0.0 ? sqrt(or_dot(n, q, q)) / bnorm : sqrt(or_dot(n, q, q));
+    free(r); free(z); free(p); free(q); free(dinv);
+    return status;
+}
