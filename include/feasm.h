@@ -1,0 +1,226 @@
+/*
+ * feasm.h -- C ABI of the MI355X finite-element assembly + PCG library.
+ *
+ * Scope (paper: Oyarzun, Mira, Houzeaux, "Performance assessment of CUDA and
+ * OpenACC in large scale combustion simulations"): the two operations that
+ * take 99.84 % of a time step (Section 2, Table 1) -- element-by-element
+ * matrix assembly into CSR (Section 4.2, Listing 1; Algorithm 1, first and
+ * fourth steps) and the preconditioned conjugate-gradient pressure solve with
+ * its SpMV, AXPY and dot kernels (Algorithm 1, last step; Section 5.2).
+ *
+ * General conventions
+ *  - Every function returns fe_status; no C++ exception crosses the ABI.  On
+ *    a non-OK status the outputs are unspecified unless stated, and
+ *    fe_ctx_last_error() holds a message.
+ *  - "device" pointers are HIP device memory on the context's device (for
+ *    instance torch tensors' data_ptr()); "host" pointers are ordinary host
+ *    memory, borrowed for the call only (never retained).
+ *  - All device work is ordered on the context's stream.  Calls that return
+ *    a result to the host (status words, CG scalars) synchronise that stream.
+ *  - Mesh numbering: fe_mesh_upload may renumber nodes and elements for
+ *    memory locality (the paper's renumbering by element type, Section 4.3,
+ *    generalised to a space-filling-curve order).  Every per-node device
+ *    array exchanged with the library (fields, values, rhs, x, g) is in MESH
+ *    numbering; fe_mesh_node_perm() gives mesh index -> user node id and
+ *    fe_mesh_to_mesh_order()/fe_mesh_to_user_order() convert device arrays.
+ *  - Node ids and row/column indices are int32 (< 2^31); counts are int64.
+ *  - A context is bound to one device and one stream; it and its meshes are
+ *    not thread-safe (one host thread at a time).
+ */
+#ifndef FEASM_H
+#define FEASM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FE_OK = 0,
+    FE_EINVAL = 1,      /* bad argument (null pointer, negative count, bad enum) */
+    FE_ENOMEM = 2,      /* device or host allocation failed, or budget exceeded */
+    FE_EBADMESH = 3,    /* connectivity out of range, node in no element, row too long */
+    FE_EBADELEM = 4,    /* det J <= 0 at a Gauss point (index in fe_asm_info) */
+    FE_ENOCONV = 5,     /* CG reached max_iter (x still written) */
+    FE_EBREAKDOWN = 6,  /* CG: p.Ap <= 0 or a non-finite scalar */
+    FE_EDEVICE = 7,     /* a HIP call failed */
+    FE_EBUSY = 8        /* serving: no slot free */
+} fe_status;
+
+typedef enum { FE_TET04 = 4, FE_HEX08 = 8 } fe_elem_type;   /* value = nodes per element */
+typedef enum { FE_FP64 = 0, FE_MIXED = 1 } fe_precision;
+typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_operator;
+
+/* fe_mesh_upload flags */
+#define FE_UPLOAD_RENUMBER 1u   /* reorder elements along a Morton curve, nodes by first touch */
+
+typedef struct fe_ctx_s *fe_ctx;
+typedef struct fe_mesh_s *fe_mesh;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL =
+ * the legacy default stream).  *out receives the context. */
+fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out);
+void fe_ctx_destroy(fe_ctx ctx);
+/* Message for the last non-OK status on this context (never NULL). */
+const char *fe_ctx_last_error(fe_ctx ctx);
+/* Re-bind the context (and its meshes) to another stream of the same device. */
+fe_status fe_ctx_set_stream(fe_ctx ctx, void *hip_stream);
+
+/* ---- mesh ----------------------------------------------------------------- */
+
+/*
+ * Preprocess and upload a single-type mesh (Section 4.2: unstructured mesh;
+ * Section 4.3: elements grouped and renumbered for SIMD/SIMT execution).
+ *   coords  host [n_nodes][3] float64 (user numbering)
+ *   conn    host [n_elems][nen] int32, 0-based, node order of the design doc
+ *           (HEX08: VTK hexahedron order; TET04: positively oriented)
+ *   dirichlet_nodes host [n_dirichlet] user node ids, or NULL if n_dirichlet = 0
+ * Builds the canonical CSR pattern (row i = every node sharing an element
+ * with node i, columns ascending, explicit zeros kept), the element blocks,
+ * their colouring and the scatter plan.  Errors: FE_EINVAL, FE_EBADMESH,
+ * FE_ENOMEM, FE_EDEVICE.  The mesh owns all its device memory.
+ */
+fe_status fe_mesh_upload(fe_ctx ctx, fe_elem_type type, int64_t n_nodes, const double *coords,
+                         int64_t n_elems, const int32_t *conn, int64_t n_dirichlet,
+                         const int32_t *dirichlet_nodes, uint32_t flags, fe_mesh *out);
+
+typedef struct {
+    int32_t nen;              /* nodes per element */
+    int64_t n_nodes, n_elems, nnz;
+    const int32_t *rowptr;    /* device [n_nodes+1], mesh numbering */
+    const int32_t *colidx;    /* device [nnz], ascending per row */
+    int64_t n_blocks;         /* element blocks (one wavefront each) */
+    int32_t n_colors;         /* block colours = assembly launches per operator */
+    int32_t max_row;          /* longest CSR row */
+    int64_t n_dirichlet;
+    size_t device_bytes;      /* device memory held by the mesh */
+} fe_mesh_desc;
+
+fe_status fe_mesh_info(fe_mesh mesh, fe_mesh_desc *out);
+/* host perm[n_nodes]: perm[mesh index] = user node id.  elem_perm likewise
+ * for elements (either pointer may be NULL). */
+fe_status fe_mesh_perm(fe_mesh mesh, int32_t *node_perm, int32_t *elem_perm);
+/* Copy the CSR pattern to host arrays rowptr[n_nodes+1], colidx[nnz]
+ * (mesh numbering; either pointer may be NULL).  Synchronises the stream. */
+fe_status fe_mesh_pattern_host(fe_mesh mesh, int32_t *rowptr, int32_t *colidx);
+/* Device permutation of ncomp node arrays stored [ncomp][n_nodes]. */
+fe_status fe_mesh_to_mesh_order(fe_mesh mesh, const double *user_in, double *mesh_out, int32_t ncomp);
+fe_status fe_mesh_to_user_order(fe_mesh mesh, const double *mesh_in, double *user_out, int32_t ncomp);
+void fe_mesh_free(fe_mesh mesh);
+
+/* ---- assembly --------------------------------------------------------------- */
+
+/* Nodal fields, device arrays in mesh numbering. */
+typedef struct {
+    fe_operator op;
+    double dt;            /* time step, > 0 */
+    const double *u;      /* [3][n_nodes] velocity */
+    const double *rho;    /* [n_nodes] density */
+    const double *mu;     /* [n_nodes] viscosity (MOMENTUM only) */
+    int32_t n_scalars;    /* SCALAR: 1..8 */
+    const double *Y;      /* SCALAR: [n_scalars][n_nodes] transported scalars */
+    const double *D;      /* SCALAR: HOST [n_scalars] diffusivities */
+} fe_fields;
+
+typedef struct {
+    double min_detJ;         /* smallest det J met (FP64) */
+    int64_t first_bad_elem;  /* user element id of the first det J <= 0, or -1 */
+} fe_asm_info;
+
+/*
+ * Element-by-element assembly (Section 4.2, Listing 1, generalised to the
+ * operators of Eq. (1) in the reduced form stated in the design doc):
+ *   MOMENTUM: values[1][nnz] = M_rho/dt + C(u) + K_mu,  rhs[3][n_nodes] = M_rho u_i/dt
+ *   SCALAR  : values[k][nnz] = M_rho/dt + C(u) + K_{rho D_k}, rhs[k][n_nodes] = M_rho Y_k/dt
+ *   POISSON : values[1][nnz] = L (constant coefficient), rhs[1][n_nodes] = (1/dt) int grad N . (rho u)
+ * values and rhs are caller-owned device arrays and are overwritten (not
+ * added to).  FE_FP64 does everything in FP64; FE_MIXED forms the Gauss-point
+ * products and elemental sums in FP32 while the Jacobian, its determinant
+ * and inverse and the CSR accumulation stay FP64.  The scatter is
+ * deterministic: the same inputs give bitwise the same outputs.  Returns
+ * after reading back a device status word; FE_EBADELEM reports the element
+ * in *info (info may be NULL).
+ */
+fe_status fe_assemble(fe_mesh mesh, const fe_fields *fields, fe_precision prec, double *values,
+                      double *rhs, fe_asm_info *info);
+
+/*
+ * Symmetric Dirichlet elimination on the mesh's Dirichlet nodes, in place:
+ * free rows i: rhs_i -= sum_{j in D} A_ij g_j, A_ij = 0 (j in D);
+ * Dirichlet rows: off-diagonals 0, diagonal kept, rhs_i = A_ii g_i.
+ * g: device [n_nodes] or NULL for g = 0.
+ */
+fe_status fe_apply_dirichlet(fe_mesh mesh, double *values, double *rhs, const double *g);
+
+/* ---- solver kernels (Section 5.2: SpMV, AXPY, dot) -------------------------- */
+
+/* y = A x on the mesh pattern (device arrays, FP64). */
+fe_status fe_spmv(fe_mesh mesh, const double *values, const double *x, double *y);
+/* *out (host) = x . y over n entries; deterministic two-stage reduction. */
+fe_status fe_dot(fe_ctx ctx, int64_t n, const double *x, const double *y, double *out);
+/* y += a x over n entries. */
+fe_status fe_axpy(fe_ctx ctx, int64_t n, double a, const double *x, double *y);
+
+typedef struct {
+    int32_t iterations;        /* inner (FP32 in mixed mode) CG iterations in total */
+    int32_t outer_iterations;  /* refinement steps (mixed); 1 for FE_FP64 */
+    double rel_residual;       /* ||r||/||b|| from the recurrence (FP64 outer residual in mixed) */
+    double true_rel_residual;  /* ||b - A x||/||b|| recomputed in FP64 */
+} fe_cg_info;
+
+/*
+ * Jacobi-preconditioned CG on the assembled SPD system (Algorithm 1, last
+ * step).  x: device [n_nodes], in = x0, out = solution.  Stops when
+ * ||r||_2 <= rtol ||b||_2; rtol <= 0 runs exactly max_iter iterations and
+ * returns FE_OK.  FE_MIXED runs FP32 Jacobi-PCG on an FP32 copy of the
+ * matrix inside FP64 iterative refinement (residual and norms in FP64).
+ * Returns FE_ENOCONV (x written) at max_iter, FE_EBREAKDOWN on p.Ap <= 0 or
+ * non-finite scalars.  info may be NULL.
+ */
+fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
+                      int32_t max_iter, fe_precision prec, fe_cg_info *info);
+
+/* ---- measurement hooks --------------------------------------------------------
+ * With profiling on, the library brackets its launches with HIP events on the
+ * context's stream: slot 0 = one PCG iteration's SpMV + vector updates,
+ * slot 1 = one fe_assemble call (all colours), slot 3 = fe_apply_dirichlet.
+ * fe_ctx_profile() clears the records; fe_ctx_profile_read() synchronises
+ * and returns the number of bracketed intervals and their summed duration. */
+fe_status fe_ctx_profile(fe_ctx ctx, int enable);
+fe_status fe_ctx_profile_read(fe_ctx ctx, int slot, int64_t *launches, double *total_ms);
+
+/* ---- host-only preprocessing (no device needed; used to test the planner) --- */
+
+typedef struct fe_plan_s *fe_plan;
+typedef struct {
+    int64_t n_nodes, n_elems, nnz, n_blocks;
+    int32_t n_colors, max_row, max_block_nodes, max_block_slots, max_phases;
+} fe_plan_desc;
+
+/* Same preprocessing as fe_mesh_upload, kept on the host. */
+fe_status fe_plan_create(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
+                         const int32_t *conn, uint32_t flags, fe_plan *out);
+fe_status fe_plan_info(fe_plan plan, fe_plan_desc *out);
+/* Copy host arrays out (any pointer may be NULL):
+ *   node_perm[n_nodes], elem_perm[n_elems], rowptr[n_nodes+1], colidx[nnz],
+ *   block_elem_ptr[n_blocks+1], block_color[n_blocks],
+ *   block_node_ptr[n_blocks+1] then block_nodes[block_node_ptr[n_blocks]]. */
+fe_status fe_plan_export(fe_plan plan, int32_t *node_perm, int32_t *elem_perm, int32_t *rowptr,
+                         int32_t *colidx, int32_t *block_elem_ptr, int32_t *block_color,
+                         int32_t *block_node_ptr, int32_t *block_nodes);
+void fe_plan_free(fe_plan plan);
+/* Message for the last failure of fe_plan_create on this thread. */
+const char *fe_plan_last_error(void);
+
+/* Pack layout of Section 4.3: n_elems elements of one type in packs of
+ * vector_size, the last pack zero-padded.  *packs, *padded receive counts. */
+fe_status fe_pack_layout(int64_t n_elems, int32_t vector_size, int64_t *packs, int64_t *padded);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEASM_H */

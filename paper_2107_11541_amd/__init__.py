@@ -1,0 +1,319 @@
+"""MI355X (gfx950) finite-element assembly + Jacobi-PCG, Python binding.
+
+Every step of the path runs in the HIP kernels of libfeasm.so; this module
+only marshals arguments through the C ABI (include/feasm.h).  PyTorch is used
+for device memory and the stream.  There is no CPU fallback: without the
+built library or a GPU the calls raise.
+
+    ctx  = Context()                                   # device 0, torch's current stream
+    mesh = Mesh(ctx, HEX08, coords, conn, dirichlet)   # host numpy arrays, user numbering
+    u_m  = mesh.to_mesh(u_user)                         # device arrays are in mesh numbering
+    values, rhs, info = assemble(mesh, MOMENTUM, dt, u=u_m, rho=rho_m, mu=mu_m)
+    apply_dirichlet(mesh, L, f)
+    x, cg = cg_solve(mesh, L, f, rtol=1e-8)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import capi
+from .capi import (FE_FP64, FE_HEX08, FE_MIXED, FE_OP_MOMENTUM, FE_OP_POISSON, FE_OP_SCALAR,
+                   FE_TET04, FE_UPLOAD_RENUMBER)
+
+HEX08, TET04 = FE_HEX08, FE_TET04
+MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
+FP64, MIXED = FE_FP64, FE_MIXED
+
+__all__ = ["Context", "Mesh", "Plan", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
+           "FeError", "HEX08", "TET04", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{capi.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name}: need a contiguous {dtype} tensor with >= {n} entries")
+
+
+class Context:
+    """One device and one stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = capi.load()
+        self.device = device
+        with torch.cuda.device(device):
+            s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = C.c_void_p()
+        st = self.lib.fe_ctx_create(device, C.c_void_p(s.cuda_stream), C.byref(h))
+        if st != capi.FE_OK:
+            raise FeError(st, "fe_ctx_create failed")
+        self.h = h
+
+    def error(self) -> str:
+        return self.lib.fe_ctx_last_error(self.h).decode()
+
+    def check(self, st: int):
+        if st != capi.FE_OK:
+            raise FeError(st, self.error())
+
+    def profile(self, enable: bool = True):
+        self.check(self.lib.fe_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, slot: int):
+        n = C.c_int64()
+        ms = C.c_double()
+        self.check(self.lib.fe_ctx_profile_read(self.h, slot, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fe_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """A preprocessed, device-resident mesh (fe_mesh_upload)."""
+
+    def __init__(self, ctx: Context, elem_type: int, coords, conn, dirichlet=None, renumber: bool = True):
+        self.ctx = ctx
+        lib = ctx.lib
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != elem_type:
+            raise ValueError("coords must be [N,3] and conn [E,nen]")
+        d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.int32)
+        h = C.c_void_p()
+        st = lib.fe_mesh_upload(ctx.h, elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                conn.ctypes.data, 0 if d is None else d.shape[0],
+                                None if d is None else d.ctypes.data,
+                                FE_UPLOAD_RENUMBER if renumber else 0, C.byref(h))
+        ctx.check(st)
+        self.h = h
+        desc = capi.MeshDesc()
+        ctx.check(lib.fe_mesh_info(h, C.byref(desc)))
+        self.desc = desc
+        self.nen = desc.nen
+        self.n_nodes = desc.n_nodes
+        self.n_elems = desc.n_elems
+        self.nnz = desc.nnz
+        self.node_perm = np.zeros(self.n_nodes, dtype=np.int32)
+        self.elem_perm = np.zeros(self.n_elems, dtype=np.int32)
+        ctx.check(lib.fe_mesh_perm(h, self.node_perm.ctypes.data, self.elem_perm.ctypes.data))
+
+    def info(self) -> dict:
+        d = capi.MeshDesc()
+        self.ctx.check(self.ctx.lib.fe_mesh_info(self.h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in capi.MeshDesc._fields_ if k not in ("rowptr", "colidx")}
+
+    def pattern_host(self):
+        """(rowptr, colidx) copied to host numpy arrays, mesh numbering."""
+        rp = np.empty(self.n_nodes + 1, dtype=np.int32)
+        ci = np.empty(self.nnz, dtype=np.int32)
+        self.ctx.check(self.ctx.lib.fe_mesh_pattern_host(self.h, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci
+
+    def to_mesh(self, t_user, ncomp: int = None):
+        """Device [ncomp][N] user-numbered array -> mesh numbering (new tensor)."""
+        torch = _torch()
+        t_user = t_user.contiguous()
+        nc = ncomp or max(1, t_user.numel() // self.n_nodes)
+        out = torch.empty_like(t_user)
+        self.ctx.check(self.ctx.lib.fe_mesh_to_mesh_order(self.h, _ptr(t_user), _ptr(out), nc))
+        return out
+
+    def to_user(self, t_mesh, ncomp: int = None):
+        torch = _torch()
+        t_mesh = t_mesh.contiguous()
+        nc = ncomp or max(1, t_mesh.numel() // self.n_nodes)
+        out = torch.empty_like(t_mesh)
+        self.ctx.check(self.ctx.lib.fe_mesh_to_user_order(self.h, _ptr(t_mesh), _ptr(out), nc))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.fe_mesh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def assemble(mesh: Mesh, op: int, dt: float, u, rho, mu=None, Y=None, D=None, precision: int = FP64,
+             values=None, rhs=None):
+    """fe_assemble.  Returns (values[n_mat, nnz], rhs[n_rhs, N], info dict)."""
+    torch = _torch()
+    N, nnz = mesh.n_nodes, mesh.nnz
+    dev = u.device
+    ns = 0
+    if op == SCALAR:
+        ns = int(Y.shape[0])
+        Dh = np.ascontiguousarray(np.asarray(D, dtype=np.float64))
+        if Dh.shape[0] != ns:
+            raise ValueError("D must have one entry per scalar")
+    n_mat = ns if op == SCALAR else 1
+    n_rhs = 3 if op == MOMENTUM else (ns if op == SCALAR else 1)
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    if op == MOMENTUM:
+        _check_dev(mu, torch.float64, N, "mu")
+    if op == SCALAR:
+        _check_dev(Y, torch.float64, ns * N, "Y")
+    if values is None:
+        values = torch.empty((n_mat, nnz), dtype=torch.float64, device=dev)
+    if rhs is None:
+        rhs = torch.empty((n_rhs, N), dtype=torch.float64, device=dev)
+    _check_dev(values, torch.float64, n_mat * nnz, "values")
+    _check_dev(rhs, torch.float64, n_rhs * N, "rhs")
+    f = capi.Fields()
+    f.op = op
+    f.dt = float(dt)
+    f.u = u.data_ptr()
+    f.rho = rho.data_ptr()
+    f.mu = mu.data_ptr() if mu is not None else None
+    f.n_scalars = ns
+    f.Y = Y.data_ptr() if Y is not None else None
+    f.D = Dh.ctypes.data if ns else None
+    info = capi.AsmInfo()
+    st = mesh.ctx.lib.fe_assemble(mesh.h, C.byref(f), precision, _ptr(values), _ptr(rhs), C.byref(info))
+    out = {"min_detJ": info.min_detJ, "first_bad_elem": info.first_bad_elem, "status": st}
+    if st != capi.FE_OK:
+        raise FeError(st, mesh.ctx.error())
+    return values, rhs, out
+
+
+def apply_dirichlet(mesh: Mesh, values, rhs, g=None):
+    torch = _torch()
+    _check_dev(values, torch.float64, mesh.nnz, "values")
+    _check_dev(rhs, torch.float64, mesh.n_nodes, "rhs")
+    if g is not None:
+        _check_dev(g, torch.float64, mesh.n_nodes, "g")
+    mesh.ctx.check(mesh.ctx.lib.fe_apply_dirichlet(mesh.h, _ptr(values), _ptr(rhs), _ptr(g)))
+
+
+def spmv(mesh: Mesh, values, x, y=None):
+    torch = _torch()
+    _check_dev(values, torch.float64, mesh.nnz, "values")
+    _check_dev(x, torch.float64, mesh.n_nodes, "x")
+    if y is None:
+        y = torch.empty(mesh.n_nodes, dtype=torch.float64, device=x.device)
+    mesh.ctx.check(mesh.ctx.lib.fe_spmv(mesh.h, _ptr(values), _ptr(x), _ptr(y)))
+    return y
+
+
+def dot(ctx: Context, x, y) -> float:
+    torch = _torch()
+    n = x.numel()
+    _check_dev(x, torch.float64, n, "x")
+    _check_dev(y, torch.float64, n, "y")
+    out = C.c_double()
+    ctx.check(ctx.lib.fe_dot(ctx.h, n, _ptr(x), _ptr(y), C.byref(out)))
+    return float(out.value)
+
+
+def axpy(ctx: Context, a: float, x, y):
+    torch = _torch()
+    n = x.numel()
+    _check_dev(x, torch.float64, n, "x")
+    _check_dev(y, torch.float64, n, "y")
+    ctx.check(ctx.lib.fe_axpy(ctx.h, n, float(a), _ptr(x), _ptr(y)))
+    return y
+
+
+def cg_solve(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_iter: int = 10000,
+             precision: int = FP64, raise_on_noconv: bool = True):
+    """fe_cg_solve.  Returns (x, info dict); info['status'] is the fe_status."""
+    torch = _torch()
+    _check_dev(values, torch.float64, mesh.nnz, "values")
+    _check_dev(rhs, torch.float64, mesh.n_nodes, "rhs")
+    if x is None:
+        x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=rhs.device)
+    _check_dev(x, torch.float64, mesh.n_nodes, "x")
+    info = capi.CGInfo()
+    st = mesh.ctx.lib.fe_cg_solve(mesh.h, _ptr(values), _ptr(rhs), _ptr(x), float(rtol), int(max_iter),
+                                  precision, C.byref(info))
+    out = {"status": st, "iterations": info.iterations, "outer_iterations": info.outer_iterations,
+           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual}
+    if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):
+        raise FeError(st, mesh.ctx.error())
+    return x, out
+
+
+class Plan:
+    """Host-only preprocessing (fe_plan_create): no device needed."""
+
+    def __init__(self, elem_type: int, coords, conn, renumber: bool = True):
+        self.lib = capi.load()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        h = C.c_void_p()
+        st = self.lib.fe_plan_create(elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                     conn.ctypes.data, FE_UPLOAD_RENUMBER if renumber else 0, C.byref(h))
+        if st != capi.FE_OK:
+            raise FeError(st, self.lib.fe_plan_last_error().decode())
+        self.h = h
+        d = capi.PlanDesc()
+        self.lib.fe_plan_info(h, C.byref(d))
+        self.desc = {k: getattr(d, k) for k, _ in capi.PlanDesc._fields_}
+
+    def export(self) -> dict:
+        d = self.desc
+        N, E, nnz, nb = d["n_nodes"], d["n_elems"], d["nnz"], d["n_blocks"]
+        out = {"node_perm": np.zeros(N, np.int32), "elem_perm": np.zeros(E, np.int32),
+               "rowptr": np.zeros(N + 1, np.int32), "colidx": np.zeros(nnz, np.int32),
+               "block_elem_ptr": np.zeros(nb + 1, np.int32), "block_color": np.zeros(nb, np.int32),
+               "block_node_ptr": np.zeros(nb + 1, np.int32)}
+        # first pass to size block_nodes
+        self.lib.fe_plan_export(self.h, None, None, None, None, None, None,
+                                out["block_node_ptr"].ctypes.data, None)
+        out["block_nodes"] = np.zeros(int(out["block_node_ptr"][-1]), np.int32)
+        a = [out[k].ctypes.data for k in ("node_perm", "elem_perm", "rowptr", "colidx", "block_elem_ptr",
+                                          "block_color", "block_node_ptr", "block_nodes")]
+        self.lib.fe_plan_export(self.h, *a)
+        return out
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.fe_plan_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def pack_layout(n_elems: int, vector_size: int):
+    lib = capi.load()
+    p = C.c_int64()
+    q = C.c_int64()
+    st = lib.fe_pack_layout(n_elems, vector_size, C.byref(p), C.byref(q))
+    if st != capi.FE_OK:
+        raise FeError(st, "bad pack layout arguments")
+    return int(p.value), int(q.value)

@@ -1,0 +1,95 @@
+"""ctypes declarations of the C ABI in include/feasm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfeasm.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EBADMESH, FE_EBADELEM, FE_ENOCONV, FE_EBREAKDOWN, FE_EDEVICE, FE_EBUSY = range(9)
+STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EBADMESH", 4: "FE_EBADELEM",
+                5: "FE_ENOCONV", 6: "FE_EBREAKDOWN", 7: "FE_EDEVICE", 8: "FE_EBUSY"}
+FE_TET04, FE_HEX08 = 4, 8
+FE_FP64, FE_MIXED = 0, 1
+FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON = 0, 1, 2
+FE_UPLOAD_RENUMBER = 1
+
+P = C.c_void_p
+i32, i64, dbl, sz = C.c_int32, C.c_int64, C.c_double, C.c_size_t
+
+
+class Fields(C.Structure):
+    _fields_ = [("op", C.c_int), ("dt", dbl), ("u", P), ("rho", P), ("mu", P),
+                ("n_scalars", i32), ("Y", P), ("D", P)]
+
+
+class AsmInfo(C.Structure):
+    _fields_ = [("min_detJ", dbl), ("first_bad_elem", i64)]
+
+
+class CGInfo(C.Structure):
+    _fields_ = [("iterations", i32), ("outer_iterations", i32), ("rel_residual", dbl),
+                ("true_rel_residual", dbl)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("nen", i32), ("n_nodes", i64), ("n_elems", i64), ("nnz", i64), ("rowptr", P),
+                ("colidx", P), ("n_blocks", i64), ("n_colors", i32), ("max_row", i32),
+                ("n_dirichlet", i64), ("device_bytes", sz)]
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [("n_nodes", i64), ("n_elems", i64), ("nnz", i64), ("n_blocks", i64), ("n_colors", i32),
+                ("max_row", i32), ("max_block_nodes", i32), ("max_block_slots", i32), ("max_phases", i32)]
+
+
+# name -> (restype, argtypes); every symbol include/feasm.h declares
+SIGNATURES = {
+    "fe_ctx_create": (C.c_int, [C.c_int, P, C.POINTER(P)]),
+    "fe_ctx_destroy": (None, [P]),
+    "fe_ctx_last_error": (C.c_char_p, [P]),
+    "fe_ctx_set_stream": (C.c_int, [P, P]),
+    "fe_mesh_upload": (C.c_int, [P, C.c_int, i64, P, i64, P, i64, P, C.c_uint32, C.POINTER(P)]),
+    "fe_mesh_info": (C.c_int, [P, C.POINTER(MeshDesc)]),
+    "fe_mesh_perm": (C.c_int, [P, P, P]),
+    "fe_mesh_pattern_host": (C.c_int, [P, P, P]),
+    "fe_mesh_to_mesh_order": (C.c_int, [P, P, P, i32]),
+    "fe_mesh_to_user_order": (C.c_int, [P, P, P, i32]),
+    "fe_mesh_free": (None, [P]),
+    "fe_assemble": (C.c_int, [P, C.POINTER(Fields), C.c_int, P, P, C.POINTER(AsmInfo)]),
+    "fe_apply_dirichlet": (C.c_int, [P, P, P, P]),
+    "fe_spmv": (C.c_int, [P, P, P, P]),
+    "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
+    "fe_axpy": (C.c_int, [P, i64, dbl, P, P]),
+    "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
+    "fe_ctx_profile": (C.c_int, [P, C.c_int]),
+    "fe_ctx_profile_read": (C.c_int, [P, C.c_int, C.POINTER(i64), C.POINTER(dbl)]),
+    "fe_plan_create": (C.c_int, [C.c_int, i64, P, i64, P, C.c_uint32, C.POINTER(P)]),
+    "fe_plan_info": (C.c_int, [P, C.POINTER(PlanDesc)]),
+    "fe_plan_export": (C.c_int, [P, P, P, P, P, P, P, P, P]),
+    "fe_plan_free": (None, [P]),
+    "fe_plan_last_error": (C.c_char_p, []),
+    "fe_pack_layout": (C.c_int, [i64, i32, C.POINTER(i64), C.POINTER(i64)]),
+}
+
+_lib = None
+
+
+def load(build_if_missing: bool = True):
+    """Load libfeasm.so; build it first only if no library exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise ImportError(f"{LIB_PATH} is not built (python -m paper_2107_11541_amd.build)")
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,660 @@
+// feasm.cpp -- C ABI entry points: context, mesh upload, assembly, PCG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/feasm.h"
+#include "internal.h"
+#include "plan.h"
+
+using namespace feasm;
+
+struct ProfSlot {
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    size_t used = 0;
+};
+
+struct fe_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    double *scratch = nullptr;    // 1024 partials + 8 results
+    double *host = nullptr;       // pinned read-back area (64 doubles)
+    bool profiling = false;
+    ProfSlot prof[4];             // 0 CG SpMV, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
+};
+
+struct fe_mesh_s {
+    fe_ctx_s *ctx = nullptr;
+    DevMesh dm;
+    std::vector<int32_t> node_perm, elem_perm;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    AsmStatus *status = nullptr;  // + per-block scratch
+    CGWork cg;
+};
+
+namespace {
+
+fe_status fail(fe_ctx_s *c, fe_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCALL(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail((ctx), FE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+fe_status dev_alloc(fe_mesh_s *m, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(m->ctx, FE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    m->allocs.push_back(*p);
+    m->bytes += bytes;
+    return FE_OK;
+}
+
+template <class T>
+fe_status upload(fe_mesh_s *m, T **dst, const std::vector<T> &src)
+{
+    fe_status s = dev_alloc(m, (void **)dst, src.size() * sizeof(T));
+    if (s != FE_OK) return s;
+    if (!src.empty()) HIPCALL(m->ctx, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice,
+                                                     m->ctx->stream));
+    return FE_OK;
+}
+
+hipEvent_t prof_event(fe_ctx_s *c, int slot)
+{
+    ProfSlot &p = c->prof[slot];
+    if (p.used == p.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p.ev.push_back(e);
+    }
+    return p.ev[p.used++];
+}
+
+struct ProfScope {
+    fe_ctx_s *c;
+    int slot;
+    ProfScope(fe_ctx_s *c_, int s_) : c(c_), slot(s_)
+    {
+        if (c->profiling) {
+            hipEvent_t e = prof_event(c, slot);
+            if (e) hipEventRecord(e, c->stream);
+        }
+    }
+    ~ProfScope()
+    {
+        if (c->profiling) {
+            hipEvent_t e = prof_event(c, slot);
+            if (e) hipEventRecord(e, c->stream);
+        }
+    }
+};
+
+fe_status sync(fe_ctx_s *c)
+{
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    return FE_OK;
+}
+
+fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed)
+{
+    CGWork &w = m->cg;
+    fe_ctx_s *c = m->ctx;
+    const int64_t n = m->dm.N;
+    if (!w.r) {
+        size_t vb = (size_t)n * sizeof(double);
+        double **v[] = {&w.r, &w.z, &w.p, &w.q, &w.dinv, &w.d64};
+        for (double **pp : v) {
+            HIPCALL(c, hipMalloc((void **)pp, vb));
+            w.bytes += vb;
+        }
+        HIPCALL(c, hipMalloc((void **)&w.part, 4 * 1024 * sizeof(double)));
+        HIPCALL(c, hipMalloc((void **)&w.flags, 4 * sizeof(int32_t)));
+        w.n = n;
+    }
+    if (w.hist_cap < max_iter + 2) {
+        if (w.hist) HIPCALL(c, hipFree(w.hist));
+        w.hist_cap = std::max(max_iter + 2, 256);
+        HIPCALL(c, hipMalloc((void **)&w.hist, (4 * (size_t)w.hist_cap + 4) * sizeof(double)));
+    }
+    if (mixed && !w.r32) {
+        size_t vb = (size_t)n * sizeof(float);
+        float **v[] = {&w.r32, &w.z32, &w.p32, &w.q32, &w.x32, &w.dinv32};
+        for (float **pp : v) {
+            HIPCALL(c, hipMalloc((void **)pp, vb));
+            w.bytes += vb;
+        }
+    }
+    if (mixed && w.v32_cap < m->dm.nnz) {
+        if (w.v32) HIPCALL(c, hipFree(w.v32));
+        HIPCALL(c, hipMalloc((void **)&w.v32, (size_t)m->dm.nnz * sizeof(float)));
+        w.v32_cap = m->dm.nnz;
+        w.bytes += (size_t)m->dm.nnz * sizeof(float);
+    }
+    return FE_OK;
+}
+
+void free_cg(CGWork &w)
+{
+    void *v[] = {w.r, w.z, w.p, w.q, w.dinv, w.d64, w.part, w.flags, w.hist,
+                 w.r32, w.z32, w.p32, w.q32, w.x32, w.dinv32, w.v32};
+    for (void *p : v)
+        if (p) (void)hipFree(p);
+    w = CGWork();
+}
+
+// Run FP64 or FP32 PCG iterations until the device flag says done or
+// max_iter is reached.  Returns the flags word (done, status, iterations).
+template <class T>
+fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, int max_iter, bool x_zero,
+                  int32_t flags_out[4])
+{
+    fe_ctx_s *c = m->ctx;
+    CGWork &w = m->cg;
+    HIPCALL(c, cg_setup<T>(m->dm, vals, b, x, w, rtol, c->stream, x_zero));
+    int k = 0;
+    int next_poll = 8;
+    int32_t *hf = (int32_t *)c->host;
+    while (k < max_iter) {
+        {
+            ProfScope ps(c, 0);
+            HIPCALL(c, cg_iteration<T>(m->dm, vals, x, w, k, c->stream));
+        }
+        ++k;
+        if (rtol > 0.0 && (k == next_poll || k == max_iter)) {
+            HIPCALL(c, hipMemcpyAsync(hf, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            fe_status s = sync(c);
+            if (s != FE_OK) return s;
+            if (hf[0]) break;
+            next_poll = k + std::max(8, k / 4);
+        }
+    }
+    HIPCALL(c, hipMemcpyAsync(hf, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    memcpy(flags_out, hf, 4 * sizeof(int32_t));
+    return FE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out)
+{
+    if (!out) return FE_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FE_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return FE_EDEVICE;
+    auto *c = new fe_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipMalloc((void **)&c->scratch, (1024 + 64) * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return FE_ENOMEM;
+    }
+    *out = c;
+    return FE_OK;
+}
+
+void fe_ctx_destroy(fe_ctx c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->host) (void)hipHostFree(c->host);
+    for (auto &p : c->prof)
+        for (auto e : p.ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char *fe_ctx_last_error(fe_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+fe_status fe_ctx_set_stream(fe_ctx c, void *hip_stream)
+{
+    if (!c) return FE_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return FE_OK;
+}
+
+fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
+                         const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, uint32_t flags,
+                         fe_mesh *out)
+{
+    if (!c || !out) return FE_EINVAL;
+    *out = nullptr;
+    if (type != FE_HEX08 && type != FE_TET04) return fail(c, FE_EINVAL, "unknown element type %d", (int)type);
+    if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet_nodes))
+        return fail(c, FE_EINVAL, "bad Dirichlet list");
+    HIPCALL(c, hipSetDevice(c->device));
+    Plan P;
+    std::string err;
+    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, (flags & FE_UPLOAD_RENUMBER) != 0, P, err);
+    if (st != FE_OK) return fail(c, (fe_status)st, "%s", err.c_str());
+    std::vector<uint8_t> isd(n_nodes, 0);
+    for (int64_t k = 0; k < n_dirichlet; ++k) {
+        int32_t v = dirichlet_nodes[k];
+        if (v < 0 || v >= n_nodes) return fail(c, FE_EINVAL, "Dirichlet node %d out of range", v);
+        isd[P.node_iperm[v]] = 1;
+    }
+    std::vector<int32_t> drows;
+    int64_t ndir = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        bool hit = isd[i] != 0;
+        ndir += hit;
+        for (int32_t p = P.rowptr[i]; !hit && p < P.rowptr[i + 1]; ++p) hit = isd[P.colidx[p]] != 0;
+        if (hit) drows.push_back((int32_t)i);
+    }
+
+    auto *m = new fe_mesh_s();
+    m->ctx = c;
+    DevMesh &d = m->dm;
+    d.nen = P.nen;
+    d.N = P.N;
+    d.E = P.E;
+    d.nnz = P.nnz;
+    d.nblk = P.n_blocks();
+    d.n_colors = P.n_colors;
+    d.max_T = P.max_T;
+    d.max_L = P.max_L;
+    d.max_row = P.max_row;
+    d.max_phase = P.max_phase;
+    d.color_ptr = P.color_ptr;
+    d.n_dir = ndir;
+    d.n_dir_rows = (int64_t)drows.size();
+    double mean = (double)P.nnz / (double)P.N;
+    int lpr = 2;
+    while (lpr * 4 < mean && lpr < 32) lpr <<= 1;
+    d.spmv_lpr = lpr;
+
+    fe_status s = FE_OK;
+#define UP(dst, src)                               \
+    if (s == FE_OK) s = upload(m, &d.dst, P.src);
+    UP(X, X);
+    UP(rowptr, rowptr);
+    UP(colidx, colidx);
+    UP(diagpos, diagpos);
+    UP(blk_elem_ptr, blk_elem_ptr);
+    UP(blk_node_ptr, blk_node_ptr);
+    UP(blk_nodes, blk_nodes);
+    UP(blk_lbase, blk_lbase);
+    UP(blk_nphase, blk_nphase);
+    UP(elem_lnode, elem_lnode);
+    UP(elem_off, elem_off);
+    UP(elem_phase, elem_phase);
+    UP(color_blk, color_blk);
+    UP(node_perm, node_perm);
+    UP(elem_perm, elem_perm);
+#undef UP
+    if (s == FE_OK) s = upload(m, &d.is_dir, isd);
+    if (s == FE_OK) s = upload(m, &d.dir_rows, drows);
+    if (s == FE_OK) s = dev_alloc(m, (void **)&m->status, sizeof(AsmStatus) + (size_t)d.nblk * 16);
+    if (s == FE_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(c, FE_EDEVICE, "upload sync failed");
+    if (s != FE_OK) {
+        fe_mesh_free(m);
+        return s;
+    }
+    m->node_perm = std::move(P.node_perm);
+    m->elem_perm = std::move(P.elem_perm);
+    *out = m;
+    return FE_OK;
+}
+
+fe_status fe_mesh_info(fe_mesh m, fe_mesh_desc *o)
+{
+    if (!m || !o) return FE_EINVAL;
+    const DevMesh &d = m->dm;
+    o->nen = d.nen;
+    o->n_nodes = d.N;
+    o->n_elems = d.E;
+    o->nnz = d.nnz;
+    o->rowptr = d.rowptr;
+    o->colidx = d.colidx;
+    o->n_blocks = d.nblk;
+    o->n_colors = d.n_colors;
+    o->max_row = d.max_row;
+    o->n_dirichlet = d.n_dir;
+    o->device_bytes = m->bytes + m->cg.bytes;
+    return FE_OK;
+}
+
+fe_status fe_mesh_perm(fe_mesh m, int32_t *node_perm, int32_t *elem_perm)
+{
+    if (!m) return FE_EINVAL;
+    if (node_perm) memcpy(node_perm, m->node_perm.data(), m->node_perm.size() * sizeof(int32_t));
+    if (elem_perm) memcpy(elem_perm, m->elem_perm.data(), m->elem_perm.size() * sizeof(int32_t));
+    return FE_OK;
+}
+
+fe_status fe_mesh_pattern_host(fe_mesh m, int32_t *rowptr, int32_t *colidx)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (rowptr)
+        HIPCALL(c, hipMemcpyAsync(rowptr, m->dm.rowptr, (m->dm.N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c->stream));
+    if (colidx)
+        HIPCALL(c, hipMemcpyAsync(colidx, m->dm.colidx, m->dm.nnz * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c->stream));
+    return sync(c);
+}
+
+fe_status fe_mesh_to_mesh_order(fe_mesh m, const double *in, double *out, int32_t ncomp)
+{
+    if (!m || !in || !out || ncomp < 1 || in == out) return m ? fail(m->ctx, FE_EINVAL, "bad permute args") : FE_EINVAL;
+    HIPCALL(m->ctx, launch_permute(m->dm.N, ncomp, m->dm.node_perm, in, out, true, m->ctx->stream));
+    return FE_OK;
+}
+
+fe_status fe_mesh_to_user_order(fe_mesh m, const double *in, double *out, int32_t ncomp)
+{
+    if (!m || !in || !out || ncomp < 1 || in == out) return m ? fail(m->ctx, FE_EINVAL, "bad permute args") : FE_EINVAL;
+    HIPCALL(m->ctx, launch_permute(m->dm.N, ncomp, m->dm.node_perm, in, out, false, m->ctx->stream));
+    return FE_OK;
+}
+
+void fe_mesh_free(fe_mesh m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    for (void *p : m->allocs) (void)hipFree(p);
+    free_cg(m->cg);
+    delete m;
+}
+
+fe_status fe_assemble(fe_mesh m, const fe_fields *f, fe_precision prec, double *values, double *rhs,
+                      fe_asm_info *info)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (!f || !values || !rhs) return fail(c, FE_EINVAL, "null fields/values/rhs");
+    if (prec != FE_FP64 && prec != FE_MIXED) return fail(c, FE_EINVAL, "bad precision %d", (int)prec);
+    if (!(f->dt > 0.0) || !std::isfinite(f->dt)) return fail(c, FE_EINVAL, "dt must be > 0");
+    if (!f->u || !f->rho) return fail(c, FE_EINVAL, "u and rho are required");
+    if (f->op == FE_OP_MOMENTUM && !f->mu) return fail(c, FE_EINVAL, "MOMENTUM needs mu");
+    if (f->op == FE_OP_SCALAR && (f->n_scalars < 1 || f->n_scalars > 8 || !f->Y || !f->D))
+        return fail(c, FE_EINVAL, "SCALAR needs 1..8 scalars, Y and D");
+    if (f->op != FE_OP_MOMENTUM && f->op != FE_OP_SCALAR && f->op != FE_OP_POISSON)
+        return fail(c, FE_EINVAL, "bad operator %d", (int)f->op);
+    HIPCALL(c, hipSetDevice(c->device));
+    const DevMesh &d = m->dm;
+    AsmArgs a{};
+    a.m = &d;
+    a.op = f->op;
+    a.dt = f->dt;
+    a.u = f->u;
+    a.rho = f->rho;
+    a.mu = f->mu;
+    a.status = m->status;
+    const int passes = f->op == FE_OP_SCALAR ? f->n_scalars : 1;
+    {
+        ProfScope ps(c, 1);
+        for (int k = 0; k < passes; ++k) {
+            a.values = values + (int64_t)k * d.nnz;
+            a.rhs = rhs + (int64_t)k * d.N;
+            if (f->op == FE_OP_SCALAR) {
+                a.Y = f->Y + (int64_t)k * d.N;
+                a.Dk = f->D[k];
+            }
+            HIPCALL(c, launch_assemble(a, prec == FE_MIXED, c->stream));
+        }
+    }
+    AsmStatus *hs = (AsmStatus *)c->host;
+    HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    double md;
+    memcpy(&md, &hs->min_det_key, 8);
+    long long bad = hs->first_bad;
+    if (info) {
+        info->min_detJ = md;
+        info->first_bad_elem = bad >= 0 ? m->elem_perm[bad] : -1;
+    }
+    if (bad >= 0) return fail(c, FE_EBADELEM, "det J <= 0 in element %d (user id)", m->elem_perm[bad]);
+    return FE_OK;
+}
+
+fe_status fe_apply_dirichlet(fe_mesh m, double *values, double *rhs, const double *g)
+{
+    if (!m) return FE_EINVAL;
+    if (!values || !rhs) return fail(m->ctx, FE_EINVAL, "null values/rhs");
+    ProfScope ps(m->ctx, 3);
+    HIPCALL(m->ctx, launch_dirichlet(m->dm, values, rhs, g, m->ctx->stream));
+    return FE_OK;
+}
+
+fe_status fe_spmv(fe_mesh m, const double *values, const double *x, double *y)
+{
+    if (!m) return FE_EINVAL;
+    if (!values || !x || !y || x == y) return fail(m->ctx, FE_EINVAL, "bad spmv args");
+    HIPCALL(m->ctx, launch_spmv(m->dm, values, x, y, m->ctx->stream));
+    return FE_OK;
+}
+
+fe_status fe_dot(fe_ctx c, int64_t n, const double *x, const double *y, double *out)
+{
+    if (!c) return FE_EINVAL;
+    if (n < 0 || !out || (n > 0 && (!x || !y))) return fail(c, FE_EINVAL, "bad dot args");
+    if (n == 0) {
+        *out = 0.0;
+        return FE_OK;
+    }
+    HIPCALL(c, launch_dot(n, x, y, c->scratch, c->scratch + 1024, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    *out = c->host[0];
+    return FE_OK;
+}
+
+fe_status fe_axpy(fe_ctx c, int64_t n, double a, const double *x, double *y)
+{
+    if (!c) return FE_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(c, FE_EINVAL, "bad axpy args");
+    if (n == 0) return FE_OK;
+    HIPCALL(c, launch_axpy(n, a, x, y, c->stream));
+    return FE_OK;
+}
+
+fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double *x, double rtol, int32_t max_iter,
+                      fe_precision prec, fe_cg_info *info)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (!values || !rhs || !x) return fail(c, FE_EINVAL, "null values/rhs/x");
+    if (max_iter < 0) return fail(c, FE_EINVAL, "max_iter < 0");
+    if (prec != FE_FP64 && prec != FE_MIXED) return fail(c, FE_EINVAL, "bad precision");
+    if (!std::isfinite(rtol)) return fail(c, FE_EINVAL, "rtol not finite");
+    HIPCALL(c, hipSetDevice(c->device));
+    fe_status s = ensure_cg(m, max_iter, prec == FE_MIXED);
+    if (s != FE_OK) return s;
+    CGWork &w = m->cg;
+    const DevMesh &d = m->dm;
+    fe_cg_info inf{};
+    fe_status result = FE_OK;
+    if (prec == FE_FP64) {
+        int32_t fl[4];
+        s = run_pcg<double>(m, values, rhs, x, rtol, max_iter, false, fl);
+        if (s != FE_OK) return s;
+        const int it = fl[2];
+        double hv[2];
+        HIPCALL(c, hipMemcpy(hv, w.hist + 4 * (size_t)it, 2 * sizeof(double), hipMemcpyDeviceToHost));
+        double bb;
+        HIPCALL(c, hipMemcpy(&bb, w.hist + 4 * (size_t)w.hist_cap, sizeof(double), hipMemcpyDeviceToHost));
+        inf.iterations = it;
+        inf.outer_iterations = 1;
+        inf.rel_residual = bb > 0 ? std::sqrt(hv[1] / bb) : std::sqrt(hv[1]);
+        if (fl[1] == FE_EBREAKDOWN) result = FE_EBREAKDOWN;
+        else if (rtol > 0.0 && !fl[0]) result = FE_ENOCONV;
+    } else {
+        HIPCALL(c, cast_f64_f32(d.nnz, values, w.v32, c->stream));
+        int used = 0, outer = 0;
+        double rel = 0.0;
+        result = FE_ENOCONV;
+        for (outer = 0; outer < 64; ++outer) {
+            HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 1024, c->stream));
+            HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                      c->stream));
+            if ((s = sync(c)) != FE_OK) return s;
+            const double rr = c->host[0], bb = c->host[1];
+            rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            if (!std::isfinite(rel)) {
+                result = FE_EBREAKDOWN;
+                break;
+            }
+            if (rtol > 0.0 ? rel <= rtol : used >= max_iter) {
+                result = FE_OK;
+                break;
+            }
+            if (used >= max_iter || rr == 0.0) break;
+            const double rn = std::sqrt(rr);
+            const double need = rtol > 0.0 ? rtol * std::sqrt(bb) / rn : 0.0;
+            const double tol_in = std::max(0.5 * need, 1e-5);
+            HIPCALL(c, scale_f64_to_f32(d.N, 1.0 / rn, w.d64, w.r32, c->stream));
+            int32_t fl[4];
+            s = run_pcg<float>(m, w.v32, w.r32, w.x32, tol_in, max_iter - used, true, fl);
+            if (s != FE_OK) return s;
+            used += fl[2];
+            HIPCALL(c, add_f32_to_f64(d.N, rn, w.x32, x, c->stream));
+            if (fl[2] == 0) break;   // no progress possible (e.g. immediate breakdown)
+        }
+        inf.iterations = used;
+        inf.outer_iterations = outer + (result == FE_OK ? 0 : 1);
+        inf.rel_residual = rel;
+    }
+    // true residual in FP64
+    HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 1024, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c)) != FE_OK) return s;
+    inf.true_rel_residual = c->host[1] > 0 ? std::sqrt(c->host[0] / c->host[1]) : std::sqrt(c->host[0]);
+    if (info) *info = inf;
+    if (result == FE_EBREAKDOWN) return fail(c, FE_EBREAKDOWN, "CG breakdown (p.Ap <= 0 or non-finite)");
+    if (result == FE_ENOCONV) return fail(c, FE_ENOCONV, "CG did not reach rtol in %d iterations", max_iter);
+    return FE_OK;
+}
+
+// ---- profiling hooks (not part of the numerical API) -------------------------
+
+fe_status fe_ctx_profile(fe_ctx c, int enable)
+{
+    if (!c) return FE_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    c->profiling = enable != 0;
+    for (auto &p : c->prof) p.used = 0;
+    return FE_OK;
+}
+
+fe_status fe_ctx_profile_read(fe_ctx c, int slot, int64_t *launches, double *total_ms)
+{
+    if (!c || slot < 0 || slot >= 4 || !launches || !total_ms) return FE_EINVAL;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    ProfSlot &p = c->prof[slot];
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < p.used; i += 2) {
+        float ms = 0.f;
+        HIPCALL(c, hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+        tot += ms;
+    }
+    *launches = (int64_t)(p.used / 2);
+    *total_ms = tot;
+    return FE_OK;
+}
+
+// ---- host-only planner access -------------------------------------------------
+
+struct fe_plan_s {
+    Plan P;
+};
+
+static thread_local std::string g_plan_err;
+
+fe_status fe_plan_create(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
+                         const int32_t *conn, uint32_t flags, fe_plan *out)
+{
+    if (!out) return FE_EINVAL;
+    *out = nullptr;
+    auto *p = new fe_plan_s();
+    std::string err;
+    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, (flags & FE_UPLOAD_RENUMBER) != 0, p->P, err);
+    if (st != FE_OK) {
+        g_plan_err = err;
+        delete p;
+        return (fe_status)st;
+    }
+    *out = p;
+    return FE_OK;
+}
+
+fe_status fe_plan_info(fe_plan p, fe_plan_desc *o)
+{
+    if (!p || !o) return FE_EINVAL;
+    const Plan &P = p->P;
+    o->n_nodes = P.N;
+    o->n_elems = P.E;
+    o->nnz = P.nnz;
+    o->n_blocks = P.n_blocks();
+    o->n_colors = P.n_colors;
+    o->max_row = P.max_row;
+    o->max_block_nodes = P.max_T;
+    o->max_block_slots = P.max_L;
+    o->max_phases = P.max_phase;
+    return FE_OK;
+}
+
+fe_status fe_plan_export(fe_plan p, int32_t *node_perm, int32_t *elem_perm, int32_t *rowptr, int32_t *colidx,
+                         int32_t *block_elem_ptr, int32_t *block_color, int32_t *block_node_ptr, int32_t *block_nodes)
+{
+    if (!p) return FE_EINVAL;
+    const Plan &P = p->P;
+    auto cp = [](int32_t *dst, const std::vector<int32_t> &v) {
+        if (dst && !v.empty()) memcpy(dst, v.data(), v.size() * sizeof(int32_t));
+    };
+    cp(node_perm, P.node_perm);
+    cp(elem_perm, P.elem_perm);
+    cp(rowptr, P.rowptr);
+    cp(colidx, P.colidx);
+    cp(block_elem_ptr, P.blk_elem_ptr);
+    cp(block_color, P.blk_color);
+    cp(block_node_ptr, P.blk_node_ptr);
+    cp(block_nodes, P.blk_nodes);
+    return FE_OK;
+}
+
+void fe_plan_free(fe_plan p) { delete p; }
+
+const char *fe_plan_last_error(void) { return g_plan_err.c_str(); }
+
+fe_status fe_pack_layout(int64_t n_elems, int32_t vector_size, int64_t *packs, int64_t *padded)
+{
+    if (n_elems < 0 || vector_size < 1 || !packs || !padded) return FE_EINVAL;
+    *packs = (n_elems + vector_size - 1) / vector_size;
+    *padded = *packs * vector_size - n_elems;
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// internal.h -- structures shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/feasm.h"
+
+namespace feasm {
+
+// Device-resident mesh: geometry, CSR pattern and the block scatter plan.
+struct DevMesh {
+    int nen = 0;
+    int64_t N = 0, E = 0, nnz = 0, nblk = 0;
+    int n_colors = 0, max_T = 0, max_L = 0, max_row = 0, max_phase = 0;
+    std::vector<int32_t> color_ptr;     // host copy: blocks of colour c are color_blk[color_ptr[c]..]
+
+    double *X = nullptr;                // [3][N]
+    int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
+    int32_t *blk_elem_ptr = nullptr, *blk_node_ptr = nullptr, *blk_nodes = nullptr, *blk_lbase = nullptr;
+    uint8_t *blk_nphase = nullptr;
+    uint16_t *elem_lnode = nullptr;     // [nen][E]
+    uint8_t *elem_off = nullptr;        // [E][nen*nen]
+    uint8_t *elem_phase = nullptr;      // [E]
+    int32_t *color_blk = nullptr;
+    int32_t *node_perm = nullptr;       // mesh -> user
+    int32_t *elem_perm = nullptr;       // mesh -> user
+    uint8_t *is_dir = nullptr;          // [N]
+    int32_t *dir_rows = nullptr;        // rows touched by the Dirichlet elimination
+    int64_t n_dir = 0, n_dir_rows = 0;
+    int spmv_lpr = 8;                   // lanes per row of the SpMV kernels
+};
+
+// Device status word of an assembly launch sequence.
+struct AsmStatus {
+    unsigned long long min_det_key;     // order-preserving key of the smallest det J
+    long long first_bad;                // smallest mesh element index with det J <= 0
+};
+
+struct AsmArgs {
+    const DevMesh *m;
+    int op;                  // fe_operator
+    double dt, Dk;
+    const double *u, *rho, *mu, *Y;   // Y: the scalar of this pass
+    double *values;          // operator's value array [nnz]
+    double *rhs;             // first rhs row [N] (momentum: 3 rows of N)
+    AsmStatus *status;
+};
+
+// Launchers (asm_kernels.hip).
+hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s);
+
+// Solver launchers (solver_kernels.hip).
+struct CGWork {
+    int64_t n = 0;
+    int nb = 0;                          // work-groups of the streaming kernels
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    double *part = nullptr;              // [4][nb] partial sums
+    double *hist = nullptr;              // [cap][4] per-iteration scalars
+    int32_t *flags = nullptr;            // [4]: done, status, iterations, spare
+    int hist_cap = 0;
+    // mixed precision buffers
+    float *v32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *x32 = nullptr,
+          *dinv32 = nullptr;
+    int64_t v32_cap = 0;
+    double *d64 = nullptr;               // FP64 outer residual
+    size_t bytes = 0;
+};
+
+int stream_blocks(int64_t n);
+hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s);
+hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s);
+hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+hipError_t launch_dirichlet(const DevMesh &m, double *vals, double *rhs, const double *g, hipStream_t s);
+hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const double *in, double *out, bool gather,
+                          hipStream_t s);
+
+// PCG building blocks (see solver_kernels.hip for the iteration scheme).
+template <class T>
+hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w, double rtol, hipStream_t s,
+                    bool x_zero);
+template <class T>
+hipError_t cg_iteration(const DevMesh &m, const T *vals, T *x, CGWork &w, int k, hipStream_t s);
+hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s);
+hipError_t residual_f64(const DevMesh &m, const double *vals, const double *b, const double *x, double *r,
+                        double *part, double *out_rr_bb, hipStream_t s);
+hipError_t add_f32_to_f64(int64_t n, double scale, const float *d, double *x, hipStream_t s);
+hipError_t scale_f64_to_f32(int64_t n, double scale, const double *in, float *out, hipStream_t s);
+
+}  // namespace feasm

@@ -1,0 +1,71 @@
+// plan.h -- host-side mesh preprocessing for the block-LDS assembly.
+//
+// Section 4.3 of the paper groups elements by geometric type, renumbers them
+// and packs them so that a SIMD/SIMT unit processes a pack at once.  The gfx950
+// form of that idea built here:
+//   * elements are reordered along a Morton curve of their centroids and nodes
+//     renumbered by first touch, so that a block of consecutive elements is
+//     spatially compact and touches few CSR rows;
+//   * a block is at most one wavefront (64) of elements, cut early when the
+//     LDS image of the rows it touches would exceed the budget;
+//   * blocks are coloured so that no two blocks of one colour share a node:
+//     one launch per colour runs without write conflicts (no atomics);
+//   * inside a block, elements are split into phases so that no two lanes of
+//     one phase hold the same node at the same local position, which makes
+//     every LDS accumulation instruction conflict-free and the summation
+//     order fixed;
+//   * for each touched row the first block (in launch order) that touches it
+//     overwrites it, later blocks read-modify-write it.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace feasm {
+
+// LDS budget of one assembly work-group (bytes).  The momentum kernel stages
+// 8 fields per touched node, 3 RHS images, 3 int tables and the row image.
+constexpr int kBlockElems = 64;
+constexpr int kLdsBudget = 40 * 1024;
+constexpr int kNodeFields = 8;
+constexpr int kMaxRhs = 3;
+constexpr int kMaxRow = 255;   // in-row offsets are stored as uint8
+constexpr uint32_t kFirstBit = 0x80000000u;
+
+struct Plan {
+    int nen = 0;
+    int64_t N = 0, E = 0, nnz = 0;
+    std::vector<int32_t> node_perm;   // mesh index -> user node id
+    std::vector<int32_t> node_iperm;  // user node id -> mesh index
+    std::vector<int32_t> elem_perm;   // mesh element -> user element id
+    std::vector<double> X;            // [3][N] coordinates, mesh numbering
+    std::vector<int32_t> conn;        // [E][nen] mesh numbering, mesh order
+    std::vector<int32_t> rowptr, colidx, diagpos;
+    int max_row = 0;
+
+    // element blocks
+    std::vector<int32_t> blk_elem_ptr;   // [nblk+1]
+    std::vector<int32_t> blk_node_ptr;   // [nblk+1]
+    std::vector<int32_t> blk_nodes;      // touched rows, ascending mesh ids
+    std::vector<int32_t> blk_lbase;      // image offset of each touched row | kFirstBit
+    std::vector<int32_t> blk_color;      // [nblk]
+    std::vector<uint8_t> blk_nphase;     // [nblk]
+    std::vector<uint16_t> elem_lnode;    // [nen][E] local row index of node a
+    std::vector<uint8_t> elem_off;       // [E][nen*nen] offset of col b in row a
+    std::vector<uint8_t> elem_phase;     // [E]
+    std::vector<int32_t> color_ptr;      // [ncolor+1]
+    std::vector<int32_t> color_blk;      // blocks ordered by colour
+    int n_colors = 0, max_T = 0, max_L = 0, max_phase = 0;
+
+    int64_t n_blocks() const { return (int64_t)blk_elem_ptr.size() - 1; }
+};
+
+// Returns 0 on success, else an fe_status code with a message in err.
+int build_plan(int nen, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
+               bool renumber, Plan &P, std::string &err);
+
+// Number of worker threads used by the host preprocessing.
+int host_threads();
+
+}  // namespace feasm

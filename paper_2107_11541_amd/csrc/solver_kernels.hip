@@ -1,0 +1,509 @@
+// solver_kernels.hip -- memory-bound kernels of the Jacobi-PCG pressure solve.
+//
+// Section 5.2 of the paper: the algebraic solver is vector operations (AXPY,
+// dot; no memory reuse) plus a CSR SpMV with indirect accesses.  gfx950 form:
+//
+//   * streaming kernels use a fixed grid of at most 1024 work-groups of 256
+//     threads, each thread walking a fixed strided subset, so every reduction
+//     has a fixed order and results are bitwise reproducible;
+//   * SpMV gives each row a group of 2..32 lanes (chosen from the mean row
+//     length) that read the row's values and column indices contiguously, and
+//     reduces the group with cross-lane shuffles in a fixed pattern;
+//   * one PCG iteration is three launches: SpMV fused with p.Ap; the x, r, z
+//     update fused with r.z and r.r; the p update.  Instead of a separate
+//     single-work-group reduction kernel, every work-group of the consuming
+//     kernel re-reduces the <= 1024 partial sums itself in the same fixed
+//     order (8 KB of L2 reads), so all work-groups hold bitwise the same
+//     alpha / beta without a grid-wide barrier;
+//   * CG scalars stay on the device; the host polls a flag word.
+#include "internal.h"
+
+namespace feasm {
+
+int stream_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+namespace {
+
+constexpr int kTB = 256;
+
+// Work-group sum with a fixed pattern: wave butterfly, then waves in order.
+__device__ inline double wg_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Every work-group computes the same total of part[0..nb) in the same order.
+__device__ inline double reduce_parts(const double *part, int nb, double *sh)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kTB) v += part[i];
+    return wg_sum(v, sh);
+}
+
+__device__ inline int load_flag(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The done flag, read once per work-group so that every thread of the group
+// takes the same branch (the flag may be set by another group meanwhile).
+__device__ inline bool wg_done(const int32_t *flags)
+{
+    __shared__ int f;
+    if (threadIdx.x == 0) f = load_flag(flags);
+    __syncthreads();
+    return f != 0;
+}
+
+__device__ inline void store_flag(int32_t *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// y = A x for rows handled by this thread's lane group; returns sum over the
+// group's rows of w_i * y_i on lane 0 of each group (w may be null).
+template <class T, int LPR>
+__device__ inline double spmv_rows(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                                   const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y,
+                                   const T *__restrict__ w, int64_t n)
+{
+    const int sub = threadIdx.x & (LPR - 1);
+    const int64_t gstride = (int64_t)gridDim.x * (kTB / LPR);
+    double acc = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * (kTB / LPR) + (threadIdx.x / LPR); r < n; r += gstride) {
+        const int p0 = rowptr[r], p1 = rowptr[r + 1];
+        T s = T(0);
+        for (int p = p0 + sub; p < p1; p += LPR) s += vals[p] * x[colidx[p]];
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+        if (sub == 0) {
+            y[r] = s;
+            if (w) acc += (double)w[r] * (double)s;
+        }
+    }
+    return acc;
+}
+
+template <class T, int LPR>
+__global__ void __launch_bounds__(kTB) k_spmv(const int32_t *rowptr, const int32_t *colidx, const T *vals,
+                                              const T *x, T *y, int64_t n)
+{
+    spmv_rows<T, LPR>(rowptr, colidx, vals, x, y, (const T *)nullptr, n);
+}
+
+template <class T>
+hipError_t spmv_dispatch(int lpr, int nb, hipStream_t s, const int32_t *rp, const int32_t *ci, const T *v,
+                         const T *x, T *y, int64_t n)
+{
+    switch (lpr) {
+    case 2: hipLaunchKernelGGL((k_spmv<T, 2>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
+    case 4: hipLaunchKernelGGL((k_spmv<T, 4>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
+    case 16: hipLaunchKernelGGL((k_spmv<T, 16>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
+    case 32: hipLaunchKernelGGL((k_spmv<T, 32>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
+    default: hipLaunchKernelGGL((k_spmv<T, 8>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
+    }
+    return hipGetLastError();
+}
+
+// Grid for the SpMV: enough groups to cover rows once, at most 1024.
+int spmv_blocks(int64_t n, int lpr)
+{
+    int64_t rows_per_wg = kTB / lpr;
+    int64_t b = (n + rows_per_wg - 1) / rows_per_wg;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+__global__ void __launch_bounds__(kTB) k_dot_part(int64_t n, const double *x, const double *y, double *part)
+{
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) v += x[i] * y[i];
+    v = wg_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void __launch_bounds__(kTB) k_reduce_final(const double *part, int nb, int nvec, double *out)
+{
+    __shared__ double sh[4];
+    for (int q = 0; q < nvec; ++q) {
+        const double v = reduce_parts(part + (int64_t)q * nb, nb, sh);
+        if (threadIdx.x == 0) out[q] = v;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kTB) k_axpy(int64_t n, double a, const double *x, double *y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) y[i] += a * x[i];
+}
+
+// Symmetric Dirichlet elimination on the affected rows, G lanes per row.
+template <int G>
+__global__ void __launch_bounds__(kTB) k_dirichlet(const int32_t *rowptr, const int32_t *colidx, const int32_t *rows,
+                                                   int64_t nrows, const uint8_t *is_dir, double *vals, double *rhs,
+                                                   const double *g)
+{
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t stride = (int64_t)gridDim.x * (kTB / G);
+    for (int64_t q = (int64_t)blockIdx.x * (kTB / G) + threadIdx.x / G; q < nrows; q += stride) {
+        const int i = rows[q];
+        const int p0 = rowptr[i], p1 = rowptr[i + 1];
+        double s = 0.0;
+        if (is_dir[i]) {
+            for (int p = p0 + sub; p < p1; p += G) {
+                if (colidx[p] == i) s += vals[p];
+                else vals[p] = 0.0;
+            }
+        } else {
+            for (int p = p0 + sub; p < p1; p += G) {
+                const int j = colidx[p];
+                if (is_dir[j]) {
+                    if (g) s += vals[p] * g[j];
+                    vals[p] = 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (sub == 0) {
+            if (is_dir[i]) rhs[i] = s * (g ? g[i] : 0.0);
+            else rhs[i] -= s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kTB) k_permute(int64_t n, int ncomp, const int32_t *perm, const double *in,
+                                                 double *out, int gather)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        const int64_t j = perm[i];
+        for (int c = 0; c < ncomp; ++c) {
+            if (gather) out[c * n + i] = in[c * n + j];
+            else out[c * n + j] = in[c * n + i];
+        }
+    }
+}
+
+// ---- PCG ---------------------------------------------------------------------
+// hist[k*4 + 0..3] = rz_k, rr_k, pq_k, alpha_k ;  flags = {done, status, iters, -}
+// part layout: [0] p.q, [1] r.z, [2] r.r, [3] b.b  (each nb doubles)
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_dinv(int64_t n, const int32_t *diagpos, const T *vals, T *dinv)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        dinv[i] = T(1) / vals[diagpos[i]];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_init(int64_t n, const T *b, const T *q, T *x, T *r, T *z, T *p,
+                                                 const T *dinv, double *part, int nb, int x_zero)
+{
+    __shared__ double sh[4];
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        const T bi = b[i];
+        T ri;
+        if (x_zero) {
+            x[i] = T(0);
+            ri = bi;
+        } else {
+            ri = bi - q[i];
+        }
+        const T zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+        bb += (double)bi * (double)bi;
+    }
+    rz = wg_sum(rz, sh);
+    rr = wg_sum(rr, sh);
+    bb = wg_sum(bb, sh);
+    if (threadIdx.x == 0) {
+        part[1 * 1024 + blockIdx.x] = rz;
+        part[2 * 1024 + blockIdx.x] = rr;
+        part[3 * 1024 + blockIdx.x] = bb;
+    }
+}
+
+__global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb, double rtol, double *hist,
+                                                     double *scal, int32_t *flags)
+{
+    __shared__ double sh[4];
+    const double rz = reduce_parts(part + 1 * 1024, nb, sh);
+    const double rr = reduce_parts(part + 2 * 1024, nb, sh);
+    const double bb = reduce_parts(part + 3 * 1024, nb, sh);
+    if (threadIdx.x == 0) {
+        hist[0] = rz;
+        hist[1] = rr;
+        scal[0] = bb;
+        const double thr2 = rtol > 0.0 ? rtol * rtol * bb : -1.0;
+        scal[1] = thr2;
+        flags[0] = (rr <= thr2) ? 1 : 0;
+        flags[1] = FE_OK;
+        flags[2] = 0;
+        flags[3] = 0;
+    }
+}
+
+template <class T, int LPR>
+__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
+                                                    const T *p, T *q, int64_t n, double *part, const int32_t *flags)
+{
+    __shared__ double sh[4];
+    if (wg_done(flags)) return;
+    double acc = spmv_rows<T, LPR>(rowptr, colidx, vals, p, q, p, n);
+    acc = wg_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q,
+                                                      const T *dinv, double *part, int nb_spmv, int nb,
+                                                      double *hist, int32_t *flags)
+{
+    __shared__ double sh[4];
+    if (wg_done(flags)) return;
+    const double pq = reduce_parts(part, nb_spmv, sh);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            store_flag(flags + 1, FE_EBREAKDOWN);
+            store_flag(flags + 0, 1);
+        }
+        return;
+    }
+    const double alpha = hist[(int64_t)k * 4 + 0] / pq;
+    const T a = T(alpha);
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        x[i] += a * p[i];
+        const T ri = r[i] - a * q[i];
+        const T zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+    rz = wg_sum(rz, sh);
+    rr = wg_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[1 * 1024 + blockIdx.x] = rz;
+        part[2 * 1024 + blockIdx.x] = rr;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hist[(int64_t)k * 4 + 2] = pq;
+        hist[(int64_t)k * 4 + 3] = alpha;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *z, T *p, double *part, int nb,
+                                                     double *hist, const double *scal, int32_t *flags)
+{
+    __shared__ double sh[4];
+    if (wg_done(flags)) return;
+    const double rz1 = reduce_parts(part + 1 * 1024, nb, sh);
+    const double rr = reduce_parts(part + 2 * 1024, nb, sh);
+    const bool conv = rr <= scal[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hist[(int64_t)(k + 1) * 4 + 0] = rz1;
+        hist[(int64_t)(k + 1) * 4 + 1] = rr;
+        store_flag(flags + 2, k + 1);
+        if (conv) store_flag(flags + 0, 1);
+    }
+    if (conv) return;
+    const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        p[i] = z[i] + beta * p[i];
+}
+
+__global__ void __launch_bounds__(kTB) k_cast(int64_t n, const double *in, float *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        out[i] = (float)in[i];
+}
+
+__global__ void __launch_bounds__(kTB) k_scale_cast(int64_t n, double s, const double *in, float *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        out[i] = (float)(in[i] * s);
+}
+
+__global__ void __launch_bounds__(kTB) k_add_scaled(int64_t n, double s, const float *d, double *x)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        x[i] += s * (double)d[i];
+}
+
+// r = b - q (q = A x on entry in r), partials of r.r and b.b
+__global__ void __launch_bounds__(kTB) k_resid(int64_t n, const double *b, double *r, double *part, int nb)
+{
+    __shared__ double sh[4];
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        const double ri = b[i] - r[i];
+        r[i] = ri;
+        rr += ri * ri;
+        bb += b[i] * b[i];
+    }
+    rr = wg_sum(rr, sh);
+    bb = wg_sum(bb, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rr;
+        part[nb + blockIdx.x] = bb;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s)
+{
+    return spmv_dispatch<double>(m.spmv_lpr, spmv_blocks(m.N, m.spmv_lpr), s, m.rowptr, m.colidx, vals, x, y, m.N);
+}
+
+hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s)
+{
+    const int nb = stream_blocks(n);
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(kTB), 0, s, n, x, y, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kTB), 0, s, part, nb, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, a, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_dirichlet(const DevMesh &m, double *vals, double *rhs, const double *g, hipStream_t s)
+{
+    if (m.n_dir_rows == 0) return hipSuccess;
+    int G = 2;
+    while (G < m.max_row && G < 64) G <<= 1;
+    int64_t rows_per_wg = kTB / G;
+    int64_t nb64 = (m.n_dir_rows + rows_per_wg - 1) / rows_per_wg;
+    const int nb = (int)(nb64 > 4096 ? 4096 : nb64);
+#define FE_DIR(GV)                                                                                       \
+    hipLaunchKernelGGL((k_dirichlet<GV>), dim3(nb), dim3(kTB), 0, s, m.rowptr, m.colidx, m.dir_rows,       \
+                       m.n_dir_rows, m.is_dir, vals, rhs, g)
+    switch (G) {
+    case 2: FE_DIR(2); break;
+    case 4: FE_DIR(4); break;
+    case 8: FE_DIR(8); break;
+    case 16: FE_DIR(16); break;
+    case 32: FE_DIR(32); break;
+    default: FE_DIR(64); break;
+    }
+#undef FE_DIR
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const double *in, double *out, bool gather,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_permute, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, ncomp, perm, in, out, gather ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w, double rtol, hipStream_t s,
+                    bool x_zero)
+{
+    const int64_t n = m.N;
+    const int nb = stream_blocks(n);
+    w.nb = nb;
+    T *r = sizeof(T) == 8 ? (T *)w.r : (T *)w.r32;
+    T *z = sizeof(T) == 8 ? (T *)w.z : (T *)w.z32;
+    T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
+    T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
+    T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
+    hipLaunchKernelGGL((k_dinv<T>), dim3(nb), dim3(kTB), 0, s, n, m.diagpos, vals, dinv);
+    if (!x_zero) spmv_dispatch<T>(m.spmv_lpr, spmv_blocks(n, m.spmv_lpr), s, m.rowptr, m.colidx, vals, x, q, n);
+    hipLaunchKernelGGL((k_cg_init<T>), dim3(nb), dim3(kTB), 0, s, n, b, q, x, r, z, p, dinv, w.part, nb,
+                       x_zero ? 1 : 0);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(kTB), 0, s, w.part, nb, rtol, w.hist, w.hist + 4 * w.hist_cap,
+                       w.flags);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_iteration(const DevMesh &m, const T *vals, T *x, CGWork &w, int k, hipStream_t s)
+{
+    const int64_t n = m.N;
+    const int nb = w.nb;
+    const int lpr = m.spmv_lpr;
+    const int nbs = spmv_blocks(n, lpr);
+    T *r = sizeof(T) == 8 ? (T *)w.r : (T *)w.r32;
+    T *z = sizeof(T) == 8 ? (T *)w.z : (T *)w.z32;
+    T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
+    T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
+    T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
+#define FE_SPQ(L)                                                                                            \
+    hipLaunchKernelGGL((k_cg_spmv_pq<T, L>), dim3(nbs), dim3(kTB), 0, s, m.rowptr, m.colidx, vals, p, q, n, w.part, \
+                       w.flags)
+    switch (lpr) {
+    case 2: FE_SPQ(2); break;
+    case 4: FE_SPQ(4); break;
+    case 16: FE_SPQ(16); break;
+    case 32: FE_SPQ(32); break;
+    default: FE_SPQ(8); break;
+    }
+#undef FE_SPQ
+    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(nb), dim3(kTB), 0, s, n, k, x, r, z, (const T *)p, (const T *)q,
+                       (const T *)dinv, w.part, nbs, nb, w.hist, w.flags);
+    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(nb), dim3(kTB), 0, s, n, k, (const T *)z, p, w.part, nb, w.hist,
+                       (const double *)(w.hist + 4 * w.hist_cap), w.flags);
+    return hipGetLastError();
+}
+
+template hipError_t cg_setup<double>(const DevMesh &, const double *, const double *, double *, CGWork &, double,
+                                     hipStream_t, bool);
+template hipError_t cg_setup<float>(const DevMesh &, const float *, const float *, float *, CGWork &, double,
+                                    hipStream_t, bool);
+template hipError_t cg_iteration<double>(const DevMesh &, const double *, double *, CGWork &, int, hipStream_t);
+template hipError_t cg_iteration<float>(const DevMesh &, const float *, float *, CGWork &, int, hipStream_t);
+
+hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cast, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, in, out);
+    return hipGetLastError();
+}
+
+hipError_t scale_f64_to_f32(int64_t n, double scale, const double *in, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_cast, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, scale, in, out);
+    return hipGetLastError();
+}
+
+hipError_t add_f32_to_f64(int64_t n, double scale, const float *d, double *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_scaled, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, scale, d, x);
+    return hipGetLastError();
+}
+
+hipError_t residual_f64(const DevMesh &m, const double *vals, const double *b, const double *x, double *r,
+                        double *part, double *out_rr_bb, hipStream_t s)
+{
+    const int64_t n = m.N;
+    const int nb = stream_blocks(n);
+    launch_spmv(m, vals, x, r, s);
+    hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kTB), 0, s, n, b, r, part, nb);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kTB), 0, s, part, nb, 2, out_rr_bb);
+    return hipGetLastError();
+}
+
+}  // namespace feasm
