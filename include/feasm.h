@@ -64,6 +64,7 @@ typedef struct fe_mesh_s *fe_mesh;
 /* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL =
  * the legacy default stream).  *out receives the context. */
 fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out);
+/* Frees the context and every mesh still alive on it. */
 void fe_ctx_destroy(fe_ctx ctx);
 /* Message for the last non-OK status on this context (never NULL). */
 const char *fe_ctx_last_error(fe_ctx ctx);
@@ -186,8 +187,9 @@ fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, dou
 
 /* ---- measurement hooks --------------------------------------------------------
  * With profiling on, the library brackets its launches with HIP events on the
- * context's stream: slot 0 = one PCG iteration's SpMV + vector updates,
- * slot 1 = one fe_assemble call (all colours), slot 3 = fe_apply_dirichlet.
+ * context's stream: slot 0 = the SpMV launch of one PCG iteration (fused with
+ * p.Ap), slot 1 = one fe_assemble call (all colours), slot 2 = the vector
+ * updates of one PCG iteration, slot 3 = fe_apply_dirichlet.
  * fe_ctx_profile() clears the records; fe_ctx_profile_read() synchronises
  * and returns the number of bracketed intervals and their summed duration. */
 fe_status fe_ctx_profile(fe_ctx ctx, int enable);

@@ -14,7 +14,10 @@ built library or a GPU the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 
 import numpy as np
 
@@ -53,6 +56,17 @@ def _check_dev(t, dtype, n, name):
         raise ValueError(f"{name}: need a contiguous {dtype} tensor with >= {n} entries")
 
 
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # Release device objects while the HIP runtime is still up (atexit runs
+    # before the runtime's own teardown); destroying a context frees its meshes.
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
+
+
 class Context:
     """One device and one stream (torch's current stream by default)."""
 
@@ -68,6 +82,8 @@ class Context:
         if st != capi.FE_OK:
             raise FeError(st, "fe_ctx_create failed")
         self.h = h
+        self._meshes = weakref.WeakSet()
+        _LIVE_CONTEXTS.add(self)
 
     def error(self) -> str:
         return self.lib.fe_ctx_last_error(self.h).decode()
@@ -87,10 +103,14 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for m in list(self._meshes):
+                m.h = None          # freed by fe_ctx_destroy
             self.lib.fe_ctx_destroy(self.h)
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -115,6 +135,7 @@ class Mesh:
                                 FE_UPLOAD_RENUMBER if renumber else 0, C.byref(h))
         ctx.check(st)
         self.h = h
+        ctx._meshes.add(self)
         desc = capi.MeshDesc()
         ctx.check(lib.fe_mesh_info(h, C.byref(desc)))
         self.desc = desc
@@ -156,11 +177,13 @@ class Mesh:
         return out
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx.lib.fe_mesh_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -28,7 +28,8 @@ struct fe_ctx_s {
     double *scratch = nullptr;    // 1024 partials + 8 results
     double *host = nullptr;       // pinned read-back area (64 doubles)
     bool profiling = false;
-    ProfSlot prof[4];             // 0 CG SpMV, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
+    std::vector<fe_mesh_s *> meshes;   // live meshes, freed by fe_ctx_destroy
+    ProfSlot prof[4];             // 0 CG SpMV + p.q, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
 };
 
 struct fe_mesh_s {
@@ -178,7 +179,11 @@ fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, in
     while (k < max_iter) {
         {
             ProfScope ps(c, 0);
-            HIPCALL(c, cg_iteration<T>(m->dm, vals, x, w, k, c->stream));
+            HIPCALL(c, cg_spmv_pq<T>(m->dm, vals, w, c->stream));
+        }
+        {
+            ProfScope ps(c, 2);
+            HIPCALL(c, cg_updates<T>(m->dm, x, w, k, c->stream));
         }
         ++k;
         if (rtol > 0.0 && (k == next_poll || k == max_iter)) {
@@ -228,6 +233,7 @@ void fe_ctx_destroy(fe_ctx c)
     (void)hipStreamSynchronize(c->stream);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->host) (void)hipHostFree(c->host);
+    while (!c->meshes.empty()) fe_mesh_free(c->meshes.back());
     for (auto &p : c->prof)
         for (auto e : p.ev) (void)hipEventDestroy(e);
     delete c;
@@ -321,6 +327,7 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     }
     m->node_perm = std::move(P.node_perm);
     m->elem_perm = std::move(P.elem_perm);
+    c->meshes.push_back(m);
     *out = m;
     return FE_OK;
 }
@@ -381,6 +388,8 @@ fe_status fe_mesh_to_user_order(fe_mesh m, const double *in, double *out, int32_
 void fe_mesh_free(fe_mesh m)
 {
     if (!m) return;
+    auto &v = m->ctx->meshes;
+    v.erase(std::remove(v.begin(), v.end(), m), v.end());
     (void)hipStreamSynchronize(m->ctx->stream);
     for (void *p : m->allocs) (void)hipFree(p);
     free_cg(m->cg);

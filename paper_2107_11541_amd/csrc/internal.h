@@ -82,8 +82,12 @@ hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const doubl
 template <class T>
 hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w, double rtol, hipStream_t s,
                     bool x_zero);
+// One PCG iteration = cg_spmv_pq (q = A p, partial p.q) + cg_updates (x, r, z,
+// p updates with r.z and r.r); k is the iteration index.
 template <class T>
-hipError_t cg_iteration(const DevMesh &m, const T *vals, T *x, CGWork &w, int k, hipStream_t s);
+hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, hipStream_t s);
+template <class T>
+hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s);
 hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s);
 hipError_t residual_f64(const DevMesh &m, const double *vals, const double *b, const double *x, double *r,
                         double *part, double *out_rr_bb, hipStream_t s);

@@ -441,17 +441,13 @@ hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w
 }
 
 template <class T>
-hipError_t cg_iteration(const DevMesh &m, const T *vals, T *x, CGWork &w, int k, hipStream_t s)
+hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, hipStream_t s)
 {
     const int64_t n = m.N;
-    const int nb = w.nb;
     const int lpr = m.spmv_lpr;
     const int nbs = spmv_blocks(n, lpr);
-    T *r = sizeof(T) == 8 ? (T *)w.r : (T *)w.r32;
-    T *z = sizeof(T) == 8 ? (T *)w.z : (T *)w.z32;
-    T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
+    const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
-    T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
 #define FE_SPQ(L)                                                                                            \
     hipLaunchKernelGGL((k_cg_spmv_pq<T, L>), dim3(nbs), dim3(kTB), 0, s, m.rowptr, m.colidx, vals, p, q, n, w.part, \
                        w.flags)
@@ -463,6 +459,20 @@ hipError_t cg_iteration(const DevMesh &m, const T *vals, T *x, CGWork &w, int k,
     default: FE_SPQ(8); break;
     }
 #undef FE_SPQ
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s)
+{
+    const int64_t n = m.N;
+    const int nb = w.nb;
+    const int nbs = spmv_blocks(n, m.spmv_lpr);
+    T *r = sizeof(T) == 8 ? (T *)w.r : (T *)w.r32;
+    T *z = sizeof(T) == 8 ? (T *)w.z : (T *)w.z32;
+    T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
+    T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
+    T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
     hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(nb), dim3(kTB), 0, s, n, k, x, r, z, (const T *)p, (const T *)q,
                        (const T *)dinv, w.part, nbs, nb, w.hist, w.flags);
     hipLaunchKernelGGL((k_cg_update_p<T>), dim3(nb), dim3(kTB), 0, s, n, k, (const T *)z, p, w.part, nb, w.hist,
@@ -474,8 +484,10 @@ template hipError_t cg_setup<double>(const DevMesh &, const double *, const doub
                                      hipStream_t, bool);
 template hipError_t cg_setup<float>(const DevMesh &, const float *, const float *, float *, CGWork &, double,
                                     hipStream_t, bool);
-template hipError_t cg_iteration<double>(const DevMesh &, const double *, double *, CGWork &, int, hipStream_t);
-template hipError_t cg_iteration<float>(const DevMesh &, const float *, float *, CGWork &, int, hipStream_t);
+template hipError_t cg_spmv_pq<double>(const DevMesh &, const double *, CGWork &, hipStream_t);
+template hipError_t cg_spmv_pq<float>(const DevMesh &, const float *, CGWork &, hipStream_t);
+template hipError_t cg_updates<double>(const DevMesh &, double *, CGWork &, int, hipStream_t);
+template hipError_t cg_updates<float>(const DevMesh &, float *, CGWork &, int, hipStream_t);
 
 hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s)
 {

@@ -335,7 +335,8 @@ def sampled_rows_check(ctx, case, ops, n_sample=64, seed=0):
             scale = np.abs(ovals).max()
             assert np.abs(gvals[o] - ovals).max() <= TOL * scale
             for r in range(B.shape[0]):
-                assert abs(b[r][im] - B[r][li]) <= TOL * max(abs(B[r][li]), np.abs(B[r]).max() * 1e-3)
+                rms = np.sqrt(np.mean(B[r] ** 2))
+                assert abs(b[r][im] - B[r][li]) <= TOL * max(abs(B[r][li]), rms)
     return mesh
 
 
