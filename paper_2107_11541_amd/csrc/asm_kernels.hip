@@ -6,9 +6,10 @@
 // CSR.  Section 4.3 packs elements so that a SIMD unit processes several at
 // once.  gfx950 form:
 //
-//   * one work-group = one wavefront = one block of <= 64 spatially compact
-//     elements; one lane computes one element (Gauss loop fully unrolled,
-//     reference-element tables folded to constants);
+//   * one work-group = one block of <= 64 spatially compact elements; a
+//     TET04 element is one lane, a HEX08 element two lanes in two waves
+//     (4 matrix rows each), which keeps a wave under 256 registers so that
+//     two blocks share each SIMD and hide each other's memory latency;
 //   * the block's nodal fields are staged in LDS (structure of arrays, so that
 //     lanes reading different nodes hit different banks);
 //   * the CSR rows the block touches live in an LDS image, initialised from
@@ -22,6 +23,8 @@
 //
 // Precision: FP64, or (mixed) FP32 Gauss-point products and elemental sums
 // with the Jacobian, det J, J^-1 and the CSR accumulation in FP64.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace feasm {
@@ -84,7 +87,7 @@ struct Tet {
 
 struct KArgs {
     const double *X;
-    const int32_t *rowptr, *blk_elem_ptr, *blk_node_ptr, *blk_nodes, *blk_lbase, *color_blk;
+    const int32_t *blk_elem_ptr, *blk_node_ptr, *blk_nodes, *blk_rdesc, *blk_rowstart, *color_blk;
     const uint8_t *blk_nphase, *elem_off, *elem_phase;
     const uint16_t *elem_lnode;
     int64_t N, E;
@@ -93,13 +96,18 @@ struct KArgs {
     double *values, *rhs;
     double *blk_mindet;       // [nblk] per-block smallest det J
     long long *blk_bad;       // [nblk] per-block first bad element (mesh index) or -1
-    int blk_offset, gshift;
+    int blk_offset;
 };
 
 template <int OP> struct OpTraits;
 template <> struct OpTraits<FE_OP_MOMENTUM> { static constexpr int NF = 8, NRHS = 3; };
 template <> struct OpTraits<FE_OP_SCALAR> { static constexpr int NF = 8, NRHS = 1; };
 template <> struct OpTraits<FE_OP_POISSON> { static constexpr int NF = 7, NRHS = 1; };
+
+// Waves per element block: a HEX08 element's 8 rows are split between two
+// waves (4 rows each) so that a wave needs <= 256 registers and two blocks'
+// waves share each SIMD; a TET04 element stays on one lane.
+template <class EL> struct Split { static constexpr int W = EL::NEN == 8 ? 2 : 1; };
 
 __device__ inline void lds_add(double *p, double v)
 {
@@ -113,31 +121,80 @@ template <> __device__ inline double RefdN<Hex>(int g, int a, int j) { return kH
 template <> __device__ inline double RefN<Tet>(int g, int a) { return Tet::N(g, a); }
 template <> __device__ inline double RefdN<Tet>(int g, int a, int j) { return Tet::dN(g, a, j); }
 
-// One Gauss point: geometry in FP64, quadrature products in Q.
+// One Gauss point for rows [a0, a0 + RA) of the elemental matrix.
+// Geometry in FP64 (from the LDS-staged nodal data), products in Q.
 //   MOM/SCA: A_ab += N_a s_b + wk grad N_a . grad N_b,
 //            s_b = rho dV (N_b / dt + u . grad N_b), wk = mu dV or rho D dV;
-//            rho dV / dt is stored in cgs for the rhs pass.
-//   POI    : A_ab += dV grad N_a . grad N_b (upper triangle),
+//            B_a += rho dV / dt N_a f, f = u (MOM) or Y (SCA).
+//   POI    : A_ab += dV grad N_a . grad N_b,
 //            B_a += dV / dt grad N_a . (rho u).
-template <class EL, int OP, class Q>
-__device__ __forceinline__ void gauss_point(int g, const double *nd, int T, const int (&ln)[EL::NEN],
-                                            Q (&A)[EL::NEN][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][EL::NEN],
-                                            double &mindet, double *cgs, double inv_dt, double Dk)
+// Geometry of one element kept in registers for the Gauss loop: HEX08 the
+// trilinear coefficients c1..c7 of x(xi), TET04 the vertex coordinates.
+template <class EL> struct Geo { double v[EL::NEN == 8 ? 7 : 4][3]; };
+
+template <class EL>
+__device__ __forceinline__ void load_geo(const double *nd, int T, const int (&ln)[EL::NEN], Geo<EL> &G)
 {
     constexpr int NEN = EL::NEN;
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
-    for (int a = 0; a < NEN; ++a) {
-        const double xa = nd[0 * T + ln[a]], ya = nd[1 * T + ln[a]], za = nd[2 * T + ln[a]];
+    for (int i = 0; i < 3; ++i) {
+        double x[NEN];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double d = RefdN<EL>(g, a, j);
-            if (!EL::kSparse || d != 0.0) {
-                J[0][j] += xa * d;
-                J[1][j] += ya * d;
-                J[2][j] += za * d;
+        for (int a = 0; a < NEN; ++a) x[a] = nd[i * T + ln[a]];
+        if (NEN == 8) {
+#pragma unroll
+            for (int m = 1; m < 8; ++m) {
+                double sum = 0.0;
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int sx = Hex::sx(a), sy = Hex::sy(a), sz = Hex::sz(a);
+                    const int sgn = m == 1 ? sx : m == 2 ? sy : m == 3 ? sz : m == 4 ? sx * sy
+                                  : m == 5 ? sy * sz : m == 6 ? sx * sz : sx * sy * sz;
+                    sum = sgn > 0 ? sum + x[a] : sum - x[a];
+                }
+                G.v[m - 1][i] = 0.125 * sum;
             }
+        } else {
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) G.v[a][i] = x[a];
         }
+    }
+}
+
+template <class EL, int OP, class Q, int RA, int A0>
+__device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, int T,
+                                            const int (&ln)[EL::NEN],
+                                            Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
+                                            double inv_dt, double Dk)
+{
+    constexpr int NEN = EL::NEN;
+    const auto &geo = GE.v;
+    double J[3][3];
+    if (NEN == 8) {
+        // x(xi) = c0 + c1 xi + c2 eta + c3 zeta + c4 xi eta + c5 eta zeta + c6 xi zeta
+        //         + c7 xi eta zeta (geo[m-1] = c_m): each Jacobian column is 3 FMAs.
+        const double xi = (g & 1) ? Hex::kG : -Hex::kG;
+        const double et = (g & 2) ? Hex::kG : -Hex::kG;
+        const double ze = (g & 4) ? Hex::kG : -Hex::kG;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            J[i][0] = geo[0][i] + et * geo[3][i] + ze * geo[5][i] + (et * ze) * geo[6][i];
+            J[i][1] = geo[1][i] + xi * geo[3][i] + ze * geo[4][i] + (xi * ze) * geo[6][i];
+            J[i][2] = geo[2][i] + et * geo[4][i] + xi * geo[5][i] + (xi * et) * geo[6][i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < NEN; ++a) {
+                    const double d = RefdN<EL>(g, a, j);
+                    if (d != 0.0) s += geo[a][i] * d;
+                }
+                J[i][j] = s;
+            }
     }
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
@@ -155,7 +212,7 @@ __device__ __forceinline__ void gauss_point(int g, const double *nd, int T, cons
     Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
     Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-    // physical gradients grad N_a = J^-T grad_ref N_a
+    // physical gradients grad N_a = J^-T grad_ref N_a (all nodes: needed for columns)
     Q dN[NEN][3];
 #pragma unroll
     for (int a = 0; a < NEN; ++a)
@@ -177,207 +234,209 @@ __device__ __forceinline__ void gauss_point(int g, const double *nd, int T, cons
         ug0 += Na * nd[3 * T + ln[a]];
         ug1 += Na * nd[4 * T + ln[a]];
         ug2 += Na * nd[5 * T + ln[a]];
-        if (OP == OP_MOM) fg += Na * nd[7 * T + ln[a]];
+        if (OP != OP_POI) fg += Na * nd[7 * T + ln[a]];
     }
     const double dV = EL::w(g) * det;
     if (OP == OP_POI) {
         const Q qdV = Q(dV), qi = Q(inv_dt);
         const Q f0 = Q(rg * ug0), f1 = Q(rg * ug1), f2 = Q(rg * ug2);
 #pragma unroll
-        for (int a = 0; a < NEN; ++a) {
+        for (int r = 0; r < RA; ++r) {
+            const int a = A0 + r;
+            const Q G0 = qdV * dN[a][0], G1 = qdV * dN[a][1], G2 = qdV * dN[a][2];
 #pragma unroll
-            for (int b = a; b < NEN; ++b)
-                A[a][b] += qdV * (dN[a][0] * dN[b][0] + dN[a][1] * dN[b][1] + dN[a][2] * dN[b][2]);
-            B[0][a] += qdV * qi * (dN[a][0] * f0 + dN[a][1] * f1 + dN[a][2] * f2);
+            for (int b = 0; b < NEN; ++b) A[r][b] += G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2];
+            B[0][r] += qi * (G0 * f0 + G1 * f1 + G2 * f2);
         }
     } else {
         const Q w1 = Q(dV) * Q(rg);
-        const Q wk = (OP == OP_MOM) ? Q(dV) * Q(fg) : Q(dV) * (Q(rg) * Q(Dk));
+        const Q wk = (OP == OP_MOM) ? Q(dV) * Q(fg) : Q(dV) * (Q(rg) * Q(Dk));   // fg = mu (MOM) or Y (SCA)
         const Q qi = Q(inv_dt);
-        cgs[g * 64 + threadIdx.x] = dV * rg * inv_dt;
         const Q qu0 = Q(ug0), qu1 = Q(ug1), qu2 = Q(ug2);
         Q s[NEN];
 #pragma unroll
         for (int b = 0; b < NEN; ++b)
             s[b] = w1 * (Q(RefN<EL>(g, b)) * qi + (qu0 * dN[b][0] + qu1 * dN[b][1] + qu2 * dN[b][2]));
 #pragma unroll
-        for (int a = 0; a < NEN; ++a) {
+        for (int r = 0; r < RA; ++r) {
+            const int a = A0 + r;
             const Q Na = Q(RefN<EL>(g, a));
             const Q G0 = wk * dN[a][0], G1 = wk * dN[a][1], G2 = wk * dN[a][2];
 #pragma unroll
-            for (int b = 0; b < NEN; ++b) A[a][b] += Na * s[b] + (G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2]);
+            for (int b = 0; b < NEN; ++b) A[r][b] += Na * s[b] + (G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2]);
+            const Q wn = w1 * Na * qi;
+            if (OP == OP_MOM) {
+                B[0][r] += wn * qu0;
+                B[1][r] += wn * qu1;
+                B[2][r] += wn * qu2;
+            } else {
+                B[0][r] += wn * Q(fg);
+            }
         }
     }
 }
 
-template <class EL, int OP, class Q>
-__global__ void __launch_bounds__(64) k_assemble(KArgs k)
+// All Gauss points of one element for rows [A0, A0 + RA).  ln is taken by
+// value: the loop makes its copy opaque at every point so that the nodal
+// field reads are re-issued from LDS instead of being hoisted into registers.
+template <class EL> struct Rows { int v[EL::NEN]; };
+
+template <class EL, int OP, class Q, int RA, int A0>
+__device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, int T, Rows<EL> rows,
+                                           Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
+                                           double inv_dt, double Dk)
 {
     constexpr int NEN = EL::NEN, NG = EL::NG;
+    int ln[NEN];
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) ln[a] = rows.v[a];
+    if (EL::kRolled) {
+#pragma unroll 1
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) asm volatile("" : "+v"(ln[a]));
+            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk);
+    }
+}
+
+// One work-group = one block of <= 64 elements = W waves.  Lane l computes
+// rows [a0, a0 + RA) of element l mod 64 with a0 = (l / 64) * RA.
+template <class EL, int OP, class Q>
+__global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
+{
+    constexpr int NEN = EL::NEN, NG = EL::NG, W = Split<EL>::W, RA = NEN / W, NT = 64 * W;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
     extern __shared__ double lds[];
 
     const int blk = k.color_blk[k.blk_offset + blockIdx.x];
     const int e0 = k.blk_elem_ptr[blk], ne = k.blk_elem_ptr[blk + 1] - e0;
     const int n0 = k.blk_node_ptr[blk], T = k.blk_node_ptr[blk + 1] - n0;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int el = tid & 63, wv = tid >> 6, a0 = wv * RA;
     const int64_t N = k.N;
 
     double *nd = lds;                        // [NF][T] nodal fields
     double *rimg = nd + NF * T;              // [NRHS][T] rhs image
-    double *cgs = rimg + NRHS * T;           // [NG][64] rho dV / dt per lane
-    int *lbs = (int *)(cgs + NG * 64);       // [T] image base | first flag
-    int *rs = lbs + T;                       // [T] CSR row start
-    int *rl = rs + T;                        // [T] CSR row length
-    double *img = (double *)(rl + T + ((3 * T) & 1));   // 8-byte aligned
+    int *rdesc = (int *)(rimg + NRHS * T);   // [T] row descriptors
+    double *img = (double *)(rdesc + T + (T & 1));   // 8-byte aligned row image
 
-    // 1. stage nodal fields, row descriptors and the rhs image
-    for (int t = lane; t < T; t += 64) {
-        const int g = k.blk_nodes[n0 + t];
-        nd[0 * T + t] = k.X[g];
-        nd[1 * T + t] = k.X[N + g];
-        nd[2 * T + t] = k.X[2 * N + g];
-        nd[3 * T + t] = k.u[g];
-        nd[4 * T + t] = k.u[N + g];
-        nd[5 * T + t] = k.u[2 * N + g];
-        nd[6 * T + t] = k.rho[g];
-        if (OP == OP_MOM) nd[7 * T + t] = k.mu[g];
-        if (OP == OP_SCA) nd[7 * T + t] = k.Y[g];
-        const int lb = k.blk_lbase[n0 + t];
-        const int r0 = k.rowptr[g];
-        lbs[t] = lb;
-        rs[t] = r0;
-        rl[t] = k.rowptr[g + 1] - r0;
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) rimg[r * T + t] = lb < 0 ? 0.0 : k.rhs[r * N + g];
-    }
-    __syncthreads();
-    // 2. row image: previous partial sums, or zero for the first writer
-    {
-        const int G = 1 << k.gshift, sub = lane & (G - 1);
-        for (int t = lane >> k.gshift; t < T; t += 64 >> k.gshift) {
-            const int lb = lbs[t], base = lb & 0x7fffffff, r0 = rs[t], len = rl[t];
-            if (lb < 0) {
-                for (int q = sub; q < len; q += G) img[base + q] = 0.0;
-            } else {
-                for (int q = sub; q < len; q += G) img[base + q] = k.values[r0 + q];
-            }
-        }
-    }
-    __syncthreads();
-
-    // 3. elemental matrix, one element per lane
-    const bool act = lane < ne;
-    const int e = e0 + (act ? lane : 0);
+    // Element data that depends only on the block: issue these loads first.
+    const bool act = el < ne;
+    const int e = e0 + (act ? el : 0);
     int ln[NEN];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) ln[a] = k.elem_lnode[(int64_t)a * k.E + e];
+    uint32_t offw[RA * NEN / 4];
+    {
+        const uint32_t *op = (const uint32_t *)(k.elem_off + (int64_t)e * (NEN * NEN) + a0 * NEN);
+#pragma unroll
+        for (int q = 0; q < RA * NEN / 4; ++q) offw[q] = op[q];
+    }
+    const int ph = act ? (int)k.elem_phase[e] : -1;
 
-    Q A[NEN][NEN];
-    Q B[NRHS][NEN];
+    // 1. stage, one touched row per lane: nodal fields, rhs and the row's
+    //    previous partial sums (zero for the first writer) into LDS.  Two
+    //    dependent load rounds: the block's row tables, then fields + values.
+    constexpr int kRowBatch = 32;   // columns loaded per batch (rows are <= 255)
+    for (int t = tid; t < T; t += NT) {
+        const int g = k.blk_nodes[n0 + t];
+        const int rd = k.blk_rdesc[n0 + t];
+        const int r0 = k.blk_rowstart[n0 + t];
+        const int len = (rd >> 16) & 0xff, base = rd & 0xffff;
+        const bool first = rd < 0;
+        double f[NF + NRHS];
+        f[0] = k.X[g];
+        f[1] = k.X[N + g];
+        f[2] = k.X[2 * N + g];
+        f[3] = k.u[g];
+        f[4] = k.u[N + g];
+        f[5] = k.u[2 * N + g];
+        f[6] = k.rho[g];
+        if (OP == OP_MOM) f[7] = k.mu[g];
+        if (OP == OP_SCA) f[7] = k.Y[g];
 #pragma unroll
-    for (int a = 0; a < NEN; ++a) {
+        for (int r = 0; r < NRHS; ++r) f[NF + r] = first ? 0.0 : k.rhs[r * N + g];
+        double v[kRowBatch];
 #pragma unroll
-        for (int b = 0; b < NEN; ++b) A[a][b] = Q(0);
+        for (int q = 0; q < kRowBatch; ++q) v[q] = (!first && q < len) ? k.values[r0 + q] : 0.0;
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) B[r][a] = Q(0);
+        for (int q = 0; q < NF; ++q) nd[q * T + t] = f[q];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) rimg[r * T + t] = f[NF + r];
+        rdesc[t] = rd;
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q)
+            if (q < len) img[base + q] = v[q];
+        for (int q = kRowBatch; q < len; ++q) img[base + q] = first ? 0.0 : k.values[r0 + q];
+    }
+    __syncthreads();
+
+    // 3. elemental matrix rows of this lane
+    Q A[RA][NEN];
+    Q B[NRHS][RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) A[r][b] = Q(0);
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) B[q][r] = Q(0);
     }
     double mindet = __builtin_huge_val();
     const double inv_dt = 1.0 / k.dt;
-    if (EL::kRolled) {
-#pragma unroll 1
-        for (int g = 0; g < NG; ++g) {
-            // opaque row indices: the nodal reads stay inside the loop
+    Geo<EL> GE;
+    load_geo<EL>(nd, T, ln, GE);
+    // the row range is a compile-time constant in each branch (wave-uniform)
+    {
+        Rows<EL> rows;
 #pragma unroll
-            for (int a = 0; a < NEN; ++a) asm volatile("" : "+v"(ln[a]));
-            gauss_point<EL, OP, Q>(g, nd, T, ln, A, B, mindet, cgs, inv_dt, k.Dk);
-        }
-    } else {
-#pragma unroll
-        for (int g = 0; g < NG; ++g) gauss_point<EL, OP, Q>(g, nd, T, ln, A, B, mindet, cgs, inv_dt, k.Dk);
+        for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
+        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk);
+        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk);
     }
-    if (OP == OP_POI) {
+    // this lane's rows of the element, selected without dynamic indexing
+    int lr[RA];
 #pragma unroll
-        for (int a = 0; a < NEN; ++a)
-#pragma unroll
-            for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
+    for (int r = 0; r < RA; ++r) {
+        // arithmetic blend (a select of two loads would become one load at a
+        // computed address and push ln[] to scratch)
+        const int hi = (W == 1) ? 0 : wv;
+        lr[r] = ln[r] + hi * (ln[(RA + r) % NEN] - ln[r]);
     }
 
-    // 4. scatter into the LDS images, phase by phase (fixed order, no conflicts)
-    int base[NEN];
+    // 4. scatter into the LDS images: wave by wave, then phase by phase, then
+    //    in (a, b) order -- no two lanes of one instruction hit one address.
+    int base[RA];
 #pragma unroll
-    for (int a = 0; a < NEN; ++a) base[a] = lbs[ln[a]] & 0x7fffffff;
-    uint32_t offw[NEN * NEN / 4];
-    {
-        const uint4 *op = (const uint4 *)(k.elem_off + (int64_t)e * (NEN * NEN));
-#pragma unroll
-        for (int q = 0; q < NEN * NEN / 16; ++q) {
-            const uint4 v = op[q];
-            offw[4 * q + 0] = v.x;
-            offw[4 * q + 1] = v.y;
-            offw[4 * q + 2] = v.z;
-            offw[4 * q + 3] = v.w;
-        }
-    }
-    const int ph = act ? (int)k.elem_phase[e] : -1;
+    for (int r = 0; r < RA; ++r) base[r] = rdesc[lr[r]] & 0xffff;
     const int nph = k.blk_nphase[blk];
-    for (int p = 0; p < nph; ++p) {
-        if (ph == p) {
 #pragma unroll
-            for (int a = 0; a < NEN; ++a) {
+    for (int w = 0; w < W; ++w) {
+        if (wv == w) {
+            for (int p = 0; p < nph; ++p) {
+                if (ph == p) {
 #pragma unroll
-                for (int b = 0; b < NEN; ++b) {
-                    const int idx = a * NEN + b;
-                    const int off = (offw[idx >> 2] >> (8 * (idx & 3))) & 0xff;
-                    lds_add(&img[base[a] + off], (double)A[a][b]);
+                    for (int r = 0; r < RA; ++r) {
+#pragma unroll
+                        for (int b = 0; b < NEN; ++b) {
+                            const int idx = r * NEN + b;
+                            const int off = (offw[idx >> 2] >> (8 * (idx & 3))) & 0xff;
+                            lds_add(&img[base[r] + off], (double)A[r][b]);
+                        }
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) lds_add(&rimg[q * T + lr[r]], (double)B[q][r]);
+                    }
                 }
-                if (OP == OP_POI) lds_add(&rimg[ln[a]], (double)B[0][a]);
             }
         }
-    }
-    if (OP != OP_POI) {
-        // rhs b_a = sum_g (rho dV / dt)_g N_a(g) f_g, f = u (MOM) or Y (SCA)
-        auto rhs_point = [&](int g) {
-            double f[NRHS];
-#pragma unroll
-            for (int r = 0; r < NRHS; ++r) f[r] = 0.0;
-#pragma unroll
-            for (int a = 0; a < NEN; ++a) {
-                const double Na = RefN<EL>(g, a);
-#pragma unroll
-                for (int r = 0; r < NRHS; ++r) f[r] += Na * nd[(OP == OP_MOM ? 3 + r : 7) * T + ln[a]];
-            }
-            const Q c = Q(cgs[g * 64 + lane]);
-#pragma unroll
-            for (int a = 0; a < NEN; ++a) {
-                const Q cn = c * Q(RefN<EL>(g, a));
-#pragma unroll
-                for (int r = 0; r < NRHS; ++r) B[r][a] += cn * Q(f[r]);
-            }
-        };
-        if (EL::kRolled) {
-#pragma unroll 1
-            for (int g = 0; g < NG; ++g) {
-#pragma unroll
-                for (int a = 0; a < NEN; ++a) asm volatile("" : "+v"(ln[a]));
-                rhs_point(g);
-            }
-        } else {
-#pragma unroll
-            for (int g = 0; g < NG; ++g) rhs_point(g);
-        }
-        for (int p = 0; p < nph; ++p) {
-            if (ph == p) {
-#pragma unroll
-                for (int a = 0; a < NEN; ++a)
-#pragma unroll
-                    for (int r = 0; r < NRHS; ++r) lds_add(&rimg[r * T + ln[a]], (double)B[r][a]);
-            }
-        }
+        if (W > 1) __syncthreads();
     }
 
     // status: per-block smallest det J and first non-positive element
-    {
+    if (wv == 0) {
         double md = act ? mindet : __builtin_huge_val();
         long long bad = (act && !(mindet > 0.0)) ? (long long)e : (long long)0x7fffffffffffffffLL;
 #pragma unroll
@@ -386,22 +445,29 @@ __global__ void __launch_bounds__(64) k_assemble(KArgs k)
             const long long ob = __shfl_xor(bad, o);
             bad = ob < bad ? ob : bad;
         }
-        if (lane == 0) {
+        if (el == 0) {
             k.blk_mindet[blk] = md;
             k.blk_bad[blk] = bad == 0x7fffffffffffffffLL ? -1 : bad;
         }
     }
     __syncthreads();
 
-    // 5. write the touched rows and rhs entries back
-    {
-        const int G = 1 << k.gshift, sub = lane & (G - 1);
-        for (int t = lane >> k.gshift; t < T; t += 64 >> k.gshift) {
-            const int base_t = lbs[t] & 0x7fffffff, r0 = rs[t], len = rl[t];
-            for (int q = sub; q < len; q += G) k.values[r0 + q] = img[base_t + q];
-        }
+    // 5. write back, one touched row per lane (LDS reads batched ahead of the
+    //    stores)
+    for (int t = tid; t < T; t += NT) {
+        const int rd = rdesc[t];
+        const int64_t r0 = k.blk_rowstart[n0 + t];
+        const int len = (rd >> 16) & 0xff, base = rd & 0xffff;
+        double v[kRowBatch];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q)
+            if (q < len) v[q] = img[base + q];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q)
+            if (q < len) k.values[r0 + q] = v[q];
+        for (int q = kRowBatch; q < len; ++q) k.values[r0 + q] = img[base + q];
     }
-    for (int t = lane; t < T; t += 64) {
+    for (int t = tid; t < T; t += NT) {
         const int g = k.blk_nodes[n0 + t];
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) k.rhs[r * N + g] = rimg[r * T + t];
@@ -445,14 +511,13 @@ hipError_t run(const AsmArgs &a, const KArgs &k0, hipStream_t s)
 {
     const DevMesh &m = *a.m;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
-    const size_t lds = (size_t)(NF + NRHS) * m.max_T * 8 + (size_t)EL::NG * 64 * 8 + (size_t)m.max_T * 12 + 8 +
-                       (size_t)m.max_L * 8;
+    const size_t lds = m.max_lds[OP];
     KArgs k = k0;
     for (int c = 0; c < m.n_colors; ++c) {
         const int nb = m.color_ptr[c + 1] - m.color_ptr[c];
         if (nb == 0) continue;
         k.blk_offset = m.color_ptr[c];
-        hipLaunchKernelGGL((k_assemble<EL, OP, Q>), dim3(nb), dim3(64), lds, s, k);
+        hipLaunchKernelGGL((k_assemble<EL, OP, Q>), dim3(nb), dim3(64 * Split<EL>::W), lds, s, k);
     }
     return hipGetLastError();
 }
@@ -464,11 +529,11 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     const DevMesh &m = *a.m;
     KArgs k{};
     k.X = m.X;
-    k.rowptr = m.rowptr;
     k.blk_elem_ptr = m.blk_elem_ptr;
     k.blk_node_ptr = m.blk_node_ptr;
     k.blk_nodes = m.blk_nodes;
-    k.blk_lbase = m.blk_lbase;
+    k.blk_rdesc = m.blk_rdesc;
+    k.blk_rowstart = m.blk_rowstart;
     k.color_blk = m.color_blk;
     k.blk_nphase = m.blk_nphase;
     k.elem_off = m.elem_off;
@@ -487,9 +552,6 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     // status scratch lives right after the AsmStatus word
     k.blk_mindet = (double *)(a.status + 1);
     k.blk_bad = (long long *)(k.blk_mindet + m.nblk);
-    int gs = 0;
-    while ((1 << gs) < m.max_row && gs < 6) ++gs;
-    k.gshift = gs;
     hipError_t err;
     const bool hex = m.nen == 8;
 #define FE_RUN(EL, OPV)                                                                     \

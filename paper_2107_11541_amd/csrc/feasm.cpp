@@ -129,7 +129,7 @@ fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed)
             HIPCALL(c, hipMalloc((void **)pp, vb));
             w.bytes += vb;
         }
-        HIPCALL(c, hipMalloc((void **)&w.part, 4 * 1024 * sizeof(double)));
+        HIPCALL(c, hipMalloc((void **)&w.part, kPartDoubles * sizeof(double)));
         HIPCALL(c, hipMalloc((void **)&w.flags, 4 * sizeof(int32_t)));
         w.n = n;
     }
@@ -179,7 +179,7 @@ fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, in
     while (k < max_iter) {
         {
             ProfScope ps(c, 0);
-            HIPCALL(c, cg_spmv_pq<T>(m->dm, vals, w, c->stream));
+            HIPCALL(c, cg_spmv_pq<T>(m->dm, vals, w, k, c->stream));
         }
         {
             ProfScope ps(c, 2);
@@ -214,6 +214,7 @@ fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FE_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return FE_EDEVICE;
+    if (init_spmv_grid(device) != hipSuccess) return FE_EDEVICE;
     auto *c = new fe_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -293,10 +294,31 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     d.color_ptr = P.color_ptr;
     d.n_dir = ndir;
     d.n_dir_rows = (int64_t)drows.size();
-    double mean = (double)P.nnz / (double)P.N;
-    int lpr = 2;
-    while (lpr * 4 < mean && lpr < 32) lpr <<= 1;
-    d.spmv_lpr = lpr;
+    // SpMV row blocks: consecutive rows, <= 64 rows (4 threads per row in a
+    // 256-thread group) and <= 2048 nonzeros each (the LDS product buffer)
+    std::vector<int32_t> rb{0};
+    for (int64_t r = 0; r < P.N;) {
+        int64_t r1 = r + 1;
+        while (r1 < P.N && r1 - r < 64 && P.rowptr[r1 + 1] - P.rowptr[r] <= 2048) ++r1;
+        rb.push_back((int32_t)r1);
+        r = r1;
+    }
+    d.spmv_nrb = (int64_t)rb.size() - 1;
+    // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int
+    // descriptor per row (+ alignment), then the row image
+    {
+        const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
+        for (int64_t b = 0; b < d.nblk; ++b) {
+            const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
+            int64_t L = 0;
+            for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
+                L += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
+            for (int op = 0; op < 3; ++op) {
+                size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)L * 8;
+                d.max_lds[op] = std::max(d.max_lds[op], by);
+            }
+        }
+    }
 
     fe_status s = FE_OK;
 #define UP(dst, src)                               \
@@ -308,7 +330,8 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     UP(blk_elem_ptr, blk_elem_ptr);
     UP(blk_node_ptr, blk_node_ptr);
     UP(blk_nodes, blk_nodes);
-    UP(blk_lbase, blk_lbase);
+    UP(blk_rdesc, blk_rdesc);
+    UP(blk_rowstart, blk_rowstart);
     UP(blk_nphase, blk_nphase);
     UP(elem_lnode, elem_lnode);
     UP(elem_off, elem_off);
@@ -317,6 +340,7 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     UP(node_perm, node_perm);
     UP(elem_perm, elem_perm);
 #undef UP
+    if (s == FE_OK) s = upload(m, &d.spmv_rb, rb);
     if (s == FE_OK) s = upload(m, &d.is_dir, isd);
     if (s == FE_OK) s = upload(m, &d.dir_rows, drows);
     if (s == FE_OK) s = dev_alloc(m, (void **)&m->status, sizeof(AsmStatus) + (size_t)d.nblk * 16);

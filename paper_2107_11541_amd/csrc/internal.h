@@ -16,11 +16,13 @@ struct DevMesh {
     int nen = 0;
     int64_t N = 0, E = 0, nnz = 0, nblk = 0;
     int n_colors = 0, max_T = 0, max_L = 0, max_row = 0, max_phase = 0;
+    size_t max_lds[3] = {0, 0, 0};      // assembly LDS bytes per operator (max over blocks)
     std::vector<int32_t> color_ptr;     // host copy: blocks of colour c are color_blk[color_ptr[c]..]
 
     double *X = nullptr;                // [3][N]
     int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
-    int32_t *blk_elem_ptr = nullptr, *blk_node_ptr = nullptr, *blk_nodes = nullptr, *blk_lbase = nullptr;
+    int32_t *blk_elem_ptr = nullptr, *blk_node_ptr = nullptr, *blk_nodes = nullptr;
+    int32_t *blk_rdesc = nullptr, *blk_rowstart = nullptr;   // per touched row
     uint8_t *blk_nphase = nullptr;
     uint16_t *elem_lnode = nullptr;     // [nen][E]
     uint8_t *elem_off = nullptr;        // [E][nen*nen]
@@ -31,7 +33,8 @@ struct DevMesh {
     uint8_t *is_dir = nullptr;          // [N]
     int32_t *dir_rows = nullptr;        // rows touched by the Dirichlet elimination
     int64_t n_dir = 0, n_dir_rows = 0;
-    int spmv_lpr = 8;                   // lanes per row of the SpMV kernels
+    int32_t *spmv_rb = nullptr;         // SpMV row blocks: rows [rb[i], rb[i+1]), <= 2048 nonzeros
+    int64_t spmv_nrb = 0;
 };
 
 // Device status word of an assembly launch sequence.
@@ -58,7 +61,7 @@ struct CGWork {
     int64_t n = 0;
     int nb = 0;                          // work-groups of the streaming kernels
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
-    double *part = nullptr;              // [4][nb] partial sums
+    double *part = nullptr;              // partial sums (kPartDoubles)
     double *hist = nullptr;              // [cap][4] per-iteration scalars
     int32_t *flags = nullptr;            // [4]: done, status, iterations, spare
     int hist_cap = 0;
@@ -70,7 +73,10 @@ struct CGWork {
     size_t bytes = 0;
 };
 
+constexpr int kPartDoubles = 8192;
 int stream_blocks(int64_t n);
+// Sizes the SpMV grid to the device's co-resident work-groups (context creation).
+hipError_t init_spmv_grid(int device);
 hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s);
 hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s);
 hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
@@ -82,10 +88,10 @@ hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const doubl
 template <class T>
 hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w, double rtol, hipStream_t s,
                     bool x_zero);
-// One PCG iteration = cg_spmv_pq (q = A p, partial p.q) + cg_updates (x, r, z,
-// p updates with r.z and r.r); k is the iteration index.
+// One PCG iteration k = cg_spmv_pq (q = A p, partial p.q) + cg_updates (x, r,
+// z with r.z and r.r, then the stop test and p = z + beta p).
 template <class T>
-hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, hipStream_t s);
+hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int k, hipStream_t s);
 template <class T>
 hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s);
 hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s);

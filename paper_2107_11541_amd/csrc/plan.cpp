@@ -225,7 +225,7 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         int64_t L = 0;
         int32_t bid = 0;
         auto lds_bytes = [&](int64_t T, int64_t Limg) {
-            return (T * (kNodeFields + kMaxRhs)) * 8 + T * 12 + Limg * 8;
+            return (T * (kNodeFields + kMaxRhs)) * 8 + T * 4 + 8 + Limg * 8;
         };
         auto close_block = [&](int64_t e_end) {
             std::sort(cur.begin(), cur.end());
@@ -370,8 +370,10 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         for (int64_t b = 0; b < nblk; ++b) P.color_blk[fill[P.blk_color[b]]++] = (int32_t)b;
     }
 
-    // 7. image offsets and first-writer flags (launch order = colour order)
-    P.blk_lbase.assign(P.blk_nodes.size(), 0);
+    // 7. row descriptors: image offset, length and first-writer flag (launch
+    //    order = colour order), and the CSR start of every touched row
+    P.blk_rdesc.assign(P.blk_nodes.size(), 0);
+    P.blk_rowstart.assign(P.blk_nodes.size(), 0);
     {
         std::vector<char> written(N, 0);
         for (int64_t q = 0; q < nblk; ++q) {
@@ -379,13 +381,19 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
             int32_t off = 0;
             for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k) {
                 int32_t v = P.blk_nodes[k];
-                uint32_t w = (uint32_t)off;
+                const int32_t len = P.rowptr[v + 1] - P.rowptr[v];
+                uint32_t w = (uint32_t)off | ((uint32_t)len << 16);
                 if (!written[v]) {
                     written[v] = 1;
                     w |= kFirstBit;
                 }
-                P.blk_lbase[k] = (int32_t)w;
-                off += P.rowptr[v + 1] - P.rowptr[v];
+                P.blk_rdesc[k] = (int32_t)w;
+                P.blk_rowstart[k] = P.rowptr[v];
+                off += len;
+            }
+            if (off >= (1 << 16)) {
+                err = "internal: block image exceeds 65536 entries";
+                return FE_EBADMESH;
             }
         }
     }

@@ -25,12 +25,14 @@
 namespace feasm {
 
 // LDS budget of one assembly work-group (bytes).  The momentum kernel stages
-// 8 fields per touched node, 3 RHS images, 3 int tables and the row image.
+// 8 fields per touched node, 3 RHS images, one int descriptor and the row image.
 constexpr int kBlockElems = 64;
 constexpr int kLdsBudget = 40 * 1024;
 constexpr int kNodeFields = 8;
 constexpr int kMaxRhs = 3;
 constexpr int kMaxRow = 255;   // in-row offsets are stored as uint8
+// Touched-row descriptor: image offset (bits 0-15) | row length (16-23) |
+// first-writer flag (bit 31).
 constexpr uint32_t kFirstBit = 0x80000000u;
 
 struct Plan {
@@ -48,7 +50,8 @@ struct Plan {
     std::vector<int32_t> blk_elem_ptr;   // [nblk+1]
     std::vector<int32_t> blk_node_ptr;   // [nblk+1]
     std::vector<int32_t> blk_nodes;      // touched rows, ascending mesh ids
-    std::vector<int32_t> blk_lbase;      // image offset of each touched row | kFirstBit
+    std::vector<int32_t> blk_rdesc;      // packed descriptor of each touched row (see kFirstBit)
+    std::vector<int32_t> blk_rowstart;   // CSR start of each touched row
     std::vector<int32_t> blk_color;      // [nblk]
     std::vector<uint8_t> blk_nphase;     // [nblk]
     std::vector<uint16_t> elem_lnode;    // [nen][E] local row index of node a

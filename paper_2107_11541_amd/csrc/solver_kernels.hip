@@ -3,17 +3,20 @@
 // Section 5.2 of the paper: the algebraic solver is vector operations (AXPY,
 // dot; no memory reuse) plus a CSR SpMV with indirect accesses.  gfx950 form:
 //
-//   * streaming kernels use a fixed grid of at most 1024 work-groups of 256
+//   * vector kernels use a fixed grid of at most 1024 work-groups of 256
 //     threads, each thread walking a fixed strided subset, so every reduction
 //     has a fixed order and results are bitwise reproducible;
-//   * SpMV gives each row a group of 2..32 lanes (chosen from the mean row
-//     length) that read the row's values and column indices contiguously, and
-//     reduces the group with cross-lane shuffles in a fixed pattern;
+//   * SpMV streams row blocks whose nonzeros are contiguous (fixed at
+//     upload): coalesced non-temporal loads of values and column indices, the
+//     products staged in LDS, one thread per row adding them in column order;
 //   * one PCG iteration is three launches: SpMV fused with p.Ap; the x, r, z
-//     update fused with r.z and r.r; the p update.  Instead of a separate
+//     update fused with r.z and r.r; the p update with the stop test.
+//     (Forming z + beta p inside the SpMV gather was measured slower: two
+//     gathered vectors cost more than the separate streaming update.)
+//     Instead of a separate
 //     single-work-group reduction kernel, every work-group of the consuming
-//     kernel re-reduces the <= 1024 partial sums itself in the same fixed
-//     order (8 KB of L2 reads), so all work-groups hold bitwise the same
+//     kernel re-reduces the <= 2048 partial sums itself in the same fixed
+//     order (<= 16 KB of L2 reads), so all work-groups hold bitwise the same
 //     alpha / beta without a grid-wide barrier;
 //   * CG scalars stay on the device; the host polls a flag word.
 #include "internal.h"
@@ -31,6 +34,9 @@ int stream_blocks(int64_t n)
 namespace {
 
 constexpr int kTB = 256;
+// Partial-sum buffer layout (doubles): SpMV p.q partials, then r.z, r.r, b.b.
+constexpr int kMaxParts = 2048;
+constexpr int kPartPQ = 0, kPartRZ = 2048, kPartRR = 3072, kPartBB = 4096;
 
 // Work-group sum with a fixed pattern: wave butterfly, then waves in order.
 __device__ inline double wg_sum(double v, double *sh)
@@ -72,57 +78,105 @@ __device__ inline void store_flag(int32_t *p, int v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// y = A x for rows handled by this thread's lane group; returns sum over the
-// group's rows of w_i * y_i on lane 0 of each group (w may be null).
-template <class T, int LPR>
-__device__ inline double spmv_rows(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                                   const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y,
-                                   const T *__restrict__ w, int64_t n)
+// CSR-stream SpMV: a work-group takes a row block whose nonzeros are
+// contiguous (<= kStreamNnz of them, <= kStreamRows rows), streams values and
+// column indices with coalesced non-temporal loads, forms the products in LDS
+// and lets kTPR threads per row add them (thread j takes entries j, j+kTPR,
+// ..., then a fixed shuffle combines the four).  The next block's values and
+// indices are requested before the current block's row sums, so the stream
+// keeps flowing through the LDS phase.  Row blocks are fixed at upload: the
+// summation order, and the result, do not depend on the grid.
+// X supplies the gathered vector entry for column c (lets the PCG fuse its
+// p update into the gather); the return value is this work-group's sum of
+// w_i y_i over its rows (w may be null).
+constexpr int kStreamNnz = 2048, kTPR = 4, kStreamRows = 256 / kTPR, kPer = kStreamNnz / 256;
+
+template <class T, class XF, class YF>
+__device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                                     const T *__restrict__ vals, XF xget, YF yput, const int32_t *__restrict__ rb,
+                                     int64_t nrb, T *prod, int *rps)
 {
-    const int sub = threadIdx.x & (LPR - 1);
-    const int64_t gstride = (int64_t)gridDim.x * (kTB / LPR);
+    const int tid = threadIdx.x;
     double acc = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * (kTB / LPR) + (threadIdx.x / LPR); r < n; r += gstride) {
-        const int p0 = rowptr[r], p1 = rowptr[r + 1];
-        T s = T(0);
-        for (int p = p0 + sub; p < p1; p += LPR) s += vals[p] * x[colidx[p]];
+    int c[kPer];
+    T v[kPer];
+    int64_t blk = blockIdx.x;
+    int r0 = 0, r1 = 0, p0 = 0, nz = 0;
+    auto fetch = [&](int64_t b) {
+        r0 = rb[b];
+        r1 = rb[b + 1];
+        p0 = rowptr[r0];
+        nz = rowptr[r1] - p0;
 #pragma unroll
-        for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-        if (sub == 0) {
-            y[r] = s;
-            if (w) acc += (double)w[r] * (double)s;
+        for (int j = 0; j < kPer; ++j) {
+            const int kk = tid + 256 * j;
+            if (kk < nz) {
+                c[j] = __builtin_nontemporal_load(colidx + p0 + kk);
+                v[j] = __builtin_nontemporal_load(vals + p0 + kk);
+            }
         }
+    };
+    if (blk < nrb) fetch(blk);
+    while (blk < nrb) {
+        const int cr0 = r0, cr1 = r1, cp0 = p0;
+        for (int t = tid; t <= cr1 - cr0; t += 256) rps[t] = rowptr[cr0 + t] - cp0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int kk = tid + 256 * j;
+            if (kk < nz) prod[kk] = v[j] * xget(c[j]);
+        }
+        const int64_t next = blk + gridDim.x;
+        if (next < nrb) fetch(next);
+        __syncthreads();
+        const int row = tid / kTPR, sub = tid % kTPR;
+        T s = T(0);
+        if (row < cr1 - cr0) {
+            const int q1 = rps[row + 1];
+            for (int q = rps[row] + sub; q < q1; q += kTPR) s += prod[q];
+        }
+        s += __shfl_xor(s, 1, kTPR);
+        s += __shfl_xor(s, 2, kTPR);
+        if (sub == 0 && row < cr1 - cr0) acc += yput(cr0 + row, s);
+        __syncthreads();
+        blk = next;
     }
     return acc;
 }
 
-template <class T, int LPR>
+template <class T>
 __global__ void __launch_bounds__(kTB) k_spmv(const int32_t *rowptr, const int32_t *colidx, const T *vals,
-                                              const T *x, T *y, int64_t n)
+                                              const T *x, T *y, const int32_t *rb, int64_t nrb)
 {
-    spmv_rows<T, LPR>(rowptr, colidx, vals, x, y, (const T *)nullptr, n);
+    __shared__ T prod[kStreamNnz];
+    __shared__ int rps[kStreamRows + 1];
+    spmv_stream<T>(
+        rowptr, colidx, vals, [&](int col) { return x[col]; },
+        [&](int row, T val) {
+            y[row] = val;
+            return 0.0;
+        },
+        rb, nrb, prod, rps);
+}
+
+// Work-groups of the stream SpMV: as many as are co-resident on the device
+// (a partial second round leaves the machine idle at the tail), at most
+// kMaxParts, at most one per row block.  Fixed per device, so reductions over
+// the per-group partials keep a fixed order.
+int g_spmv_resident = 0;
+
+int spmv_blocks(int64_t nrb)
+{
+    int cap = g_spmv_resident > 0 ? g_spmv_resident : kMaxParts;
+    if (cap > kMaxParts) cap = kMaxParts;
+    return (int)(nrb < 1 ? 1 : (nrb > cap ? cap : nrb));
 }
 
 template <class T>
-hipError_t spmv_dispatch(int lpr, int nb, hipStream_t s, const int32_t *rp, const int32_t *ci, const T *v,
-                         const T *x, T *y, int64_t n)
+hipError_t spmv_dispatch(const DevMesh &m, hipStream_t s, const T *v, const T *x, T *y)
 {
-    switch (lpr) {
-    case 2: hipLaunchKernelGGL((k_spmv<T, 2>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
-    case 4: hipLaunchKernelGGL((k_spmv<T, 4>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
-    case 16: hipLaunchKernelGGL((k_spmv<T, 16>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
-    case 32: hipLaunchKernelGGL((k_spmv<T, 32>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
-    default: hipLaunchKernelGGL((k_spmv<T, 8>), dim3(nb), dim3(kTB), 0, s, rp, ci, v, x, y, n); break;
-    }
+    hipLaunchKernelGGL((k_spmv<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.rowptr, m.colidx, v, x, y,
+                       m.spmv_rb, m.spmv_nrb);
     return hipGetLastError();
-}
-
-// Grid for the SpMV: enough groups to cover rows once, at most 1024.
-int spmv_blocks(int64_t n, int lpr)
-{
-    int64_t rows_per_wg = kTB / lpr;
-    int64_t b = (n + rows_per_wg - 1) / rows_per_wg;
-    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
 __global__ void __launch_bounds__(kTB) k_dot_part(int64_t n, const double *x, const double *y, double *part)
@@ -234,9 +288,9 @@ __global__ void __launch_bounds__(kTB) k_cg_init(int64_t n, const T *b, const T 
     rr = wg_sum(rr, sh);
     bb = wg_sum(bb, sh);
     if (threadIdx.x == 0) {
-        part[1 * 1024 + blockIdx.x] = rz;
-        part[2 * 1024 + blockIdx.x] = rr;
-        part[3 * 1024 + blockIdx.x] = bb;
+        part[kPartRZ + blockIdx.x] = rz;
+        part[kPartRR + blockIdx.x] = rr;
+        part[kPartBB + blockIdx.x] = bb;
     }
 }
 
@@ -244,9 +298,9 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
                                                      double *scal, int32_t *flags)
 {
     __shared__ double sh[4];
-    const double rz = reduce_parts(part + 1 * 1024, nb, sh);
-    const double rr = reduce_parts(part + 2 * 1024, nb, sh);
-    const double bb = reduce_parts(part + 3 * 1024, nb, sh);
+    const double rz = reduce_parts(part + kPartRZ, nb, sh);
+    const double rr = reduce_parts(part + kPartRR, nb, sh);
+    const double bb = reduce_parts(part + kPartBB, nb, sh);
     if (threadIdx.x == 0) {
         hist[0] = rz;
         hist[1] = rr;
@@ -260,28 +314,41 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
     }
 }
 
-template <class T, int LPR>
-__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
-                                                    const T *p, T *q, int64_t n, double *part, const int32_t *flags)
+// Iteration k, first launch: q = A p and the partial p . q.
+template <class T>
+__global__ void __launch_bounds__(kTB, 6) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
+                                                    const T *__restrict__ p, T *__restrict__ q, const int32_t *rb,
+                                                    int64_t nrb, double *part, const int32_t *flags)
 {
+    __shared__ T prod[kStreamNnz];
+    __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
     if (wg_done(flags)) return;
-    double acc = spmv_rows<T, LPR>(rowptr, colidx, vals, p, q, p, n);
+    double acc = spmv_stream<T>(
+        rowptr, colidx, vals, [&](int c) { return p[c]; },
+        [&](int row, T val) {
+            q[row] = val;
+            return (double)p[row] * (double)val;
+        },
+        rb, nrb, prod, rps);
     acc = wg_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[kPartPQ + blockIdx.x] = acc;
 }
 
+// Iteration k, second launch: alpha = rz_k / (p . q); x += alpha p;
+// r -= alpha q; z = D^-1 r; partials of r.z and r.r.
 template <class T>
 __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q,
-                                                      const T *dinv, double *part, int nb_spmv, int nb,
-                                                      double *hist, int32_t *flags)
+                                                      const T *dinv, double *part, int nb_spmv, double *hist,
+                                                      int32_t *flags)
 {
     __shared__ double sh[4];
     if (wg_done(flags)) return;
-    const double pq = reduce_parts(part, nb_spmv, sh);
+    const double pq = reduce_parts(part + kPartPQ, nb_spmv, sh);
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             store_flag(flags + 1, FE_EBREAKDOWN);
+            store_flag(flags + 2, k);
             store_flag(flags + 0, 1);
         }
         return;
@@ -301,8 +368,8 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
     rz = wg_sum(rz, sh);
     rr = wg_sum(rr, sh);
     if (threadIdx.x == 0) {
-        part[1 * 1024 + blockIdx.x] = rz;
-        part[2 * 1024 + blockIdx.x] = rr;
+        part[kPartRZ + blockIdx.x] = rz;
+        part[kPartRR + blockIdx.x] = rr;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hist[(int64_t)k * 4 + 2] = pq;
@@ -310,14 +377,17 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
     }
 }
 
+// Iteration k, third launch: every work-group reduces the r.z and r.r
+// partials (same order, same result); ||r||^2 <= rtol^2 ||b||^2 ends the
+// solve, else beta = rz_{k+1} / rz_k and p = z + beta p.
 template <class T>
 __global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *z, T *p, double *part, int nb,
                                                      double *hist, const double *scal, int32_t *flags)
 {
     __shared__ double sh[4];
     if (wg_done(flags)) return;
-    const double rz1 = reduce_parts(part + 1 * 1024, nb, sh);
-    const double rr = reduce_parts(part + 2 * 1024, nb, sh);
+    const double rz1 = reduce_parts(part + kPartRZ, nb, sh);
+    const double rr = reduce_parts(part + kPartRR, nb, sh);
     const bool conv = rr <= scal[1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hist[(int64_t)(k + 1) * 4 + 0] = rz1;
@@ -370,9 +440,23 @@ __global__ void __launch_bounds__(kTB) k_resid(int64_t n, const double *b, doubl
 
 }  // namespace
 
+hipError_t init_spmv_grid(int device)
+{
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_spmv_pq<double>),
+                                                     kTB, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    g_spmv_resident = per_cu * prop.multiProcessorCount;
+    return hipSuccess;
+}
+
 hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s)
 {
-    return spmv_dispatch<double>(m.spmv_lpr, spmv_blocks(m.N, m.spmv_lpr), s, m.rowptr, m.colidx, vals, x, y, m.N);
+    return spmv_dispatch<double>(m, s, vals, x, y);
 }
 
 hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s)
@@ -431,8 +515,11 @@ hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w
     T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
-    hipLaunchKernelGGL((k_dinv<T>), dim3(nb), dim3(kTB), 0, s, n, m.diagpos, vals, dinv);
-    if (!x_zero) spmv_dispatch<T>(m.spmv_lpr, spmv_blocks(n, m.spmv_lpr), s, m.rowptr, m.colidx, vals, x, q, n);
+    hipLaunchKernelGGL((k_dinv<T>), dim3((n + kTB - 1) / kTB), dim3(kTB), 0, s, n, m.diagpos, vals, dinv);
+    if (!x_zero) {
+        hipError_t e = spmv_dispatch<T>(m, s, vals, x, q);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_cg_init<T>), dim3(nb), dim3(kTB), 0, s, n, b, q, x, r, z, p, dinv, w.part, nb,
                        x_zero ? 1 : 0);
     hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(kTB), 0, s, w.part, nb, rtol, w.hist, w.hist + 4 * w.hist_cap,
@@ -441,24 +528,12 @@ hipError_t cg_setup(const DevMesh &m, const T *vals, const T *b, T *x, CGWork &w
 }
 
 template <class T>
-hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, hipStream_t s)
+hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream_t s)
 {
-    const int64_t n = m.N;
-    const int lpr = m.spmv_lpr;
-    const int nbs = spmv_blocks(n, lpr);
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
-#define FE_SPQ(L)                                                                                            \
-    hipLaunchKernelGGL((k_cg_spmv_pq<T, L>), dim3(nbs), dim3(kTB), 0, s, m.rowptr, m.colidx, vals, p, q, n, w.part, \
-                       w.flags)
-    switch (lpr) {
-    case 2: FE_SPQ(2); break;
-    case 4: FE_SPQ(4); break;
-    case 16: FE_SPQ(16); break;
-    case 32: FE_SPQ(32); break;
-    default: FE_SPQ(8); break;
-    }
-#undef FE_SPQ
+    hipLaunchKernelGGL((k_cg_spmv_pq<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.rowptr, m.colidx, vals,
+                       p, q, m.spmv_rb, m.spmv_nrb, w.part, w.flags);
     return hipGetLastError();
 }
 
@@ -466,16 +541,14 @@ template <class T>
 hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s)
 {
     const int64_t n = m.N;
-    const int nb = w.nb;
-    const int nbs = spmv_blocks(n, m.spmv_lpr);
     T *r = sizeof(T) == 8 ? (T *)w.r : (T *)w.r32;
     T *z = sizeof(T) == 8 ? (T *)w.z : (T *)w.z32;
     T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
-    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(nb), dim3(kTB), 0, s, n, k, x, r, z, (const T *)p, (const T *)q,
-                       (const T *)dinv, w.part, nbs, nb, w.hist, w.flags);
-    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(nb), dim3(kTB), 0, s, n, k, (const T *)z, p, w.part, nb, w.hist,
+    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, k, x, r, z, (const T *)p, (const T *)q,
+                       (const T *)dinv, w.part, spmv_blocks(m.spmv_nrb), w.hist, w.flags);
+    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, k, (const T *)z, p, w.part, w.nb, w.hist,
                        (const double *)(w.hist + 4 * w.hist_cap), w.flags);
     return hipGetLastError();
 }
@@ -484,8 +557,8 @@ template hipError_t cg_setup<double>(const DevMesh &, const double *, const doub
                                      hipStream_t, bool);
 template hipError_t cg_setup<float>(const DevMesh &, const float *, const float *, float *, CGWork &, double,
                                     hipStream_t, bool);
-template hipError_t cg_spmv_pq<double>(const DevMesh &, const double *, CGWork &, hipStream_t);
-template hipError_t cg_spmv_pq<float>(const DevMesh &, const float *, CGWork &, hipStream_t);
+template hipError_t cg_spmv_pq<double>(const DevMesh &, const double *, CGWork &, int, hipStream_t);
+template hipError_t cg_spmv_pq<float>(const DevMesh &, const float *, CGWork &, int, hipStream_t);
 template hipError_t cg_updates<double>(const DevMesh &, double *, CGWork &, int, hipStream_t);
 template hipError_t cg_updates<float>(const DevMesh &, float *, CGWork &, int, hipStream_t);
 
