@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--workload", default="hex128")
     ap.add_argument("--cpu-sample-n", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 512 MiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU domain decomposition is a design, "
@@ -107,6 +109,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3}))
+        return
     case, wl = make_workload(args.workload)
     log(f"workload {wl}: N={case.n_nodes} E={case.n_elems}")
     ctx = fe.Context(0)

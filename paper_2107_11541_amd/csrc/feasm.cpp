@@ -294,12 +294,14 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     d.color_ptr = P.color_ptr;
     d.n_dir = ndir;
     d.n_dir_rows = (int64_t)drows.size();
-    // SpMV row blocks: consecutive rows, <= 64 rows (4 threads per row in a
-    // 256-thread group) and <= 2048 nonzeros each (the LDS product buffer)
+    // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
+    // row in a 256-thread group) and <= kSpmvBlockNnz nonzeros (the LDS
+    // product buffer).  A single row longer than that cannot occur (rows are
+    // <= 255 entries).
     std::vector<int32_t> rb{0};
     for (int64_t r = 0; r < P.N;) {
         int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < 64 && P.rowptr[r1 + 1] - P.rowptr[r] <= 2048) ++r1;
+        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz) ++r1;
         rb.push_back((int32_t)r1);
         r = r1;
     }

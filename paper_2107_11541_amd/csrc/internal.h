@@ -74,6 +74,9 @@ struct CGWork {
 };
 
 constexpr int kPartDoubles = 8192;
+// SpMV row blocks (fixed at upload): <= kSpmvBlockRows rows and
+// <= kSpmvBlockNnz nonzeros, contiguous in CSR.
+constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024;
 int stream_blocks(int64_t n);
 // Sizes the SpMV grid to the device's co-resident work-groups (context creation).
 hipError_t init_spmv_grid(int device);

@@ -34,6 +34,9 @@ int stream_blocks(int64_t n)
 namespace {
 
 constexpr int kTB = 256;
+template <class T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
 // Partial-sum buffer layout (doubles): SpMV p.q partials, then r.z, r.r, b.b.
 constexpr int kMaxParts = 2048;
 constexpr int kPartPQ = 0, kPartRZ = 2048, kPartRR = 3072, kPartBB = 4096;
@@ -86,21 +89,31 @@ __device__ inline void store_flag(int32_t *p, int v)
 // indices are requested before the current block's row sums, so the stream
 // keeps flowing through the LDS phase.  Row blocks are fixed at upload: the
 // summation order, and the result, do not depend on the grid.
-// X supplies the gathered vector entry for column c (lets the PCG fuse its
-// p update into the gather); the return value is this work-group's sum of
-// w_i y_i over its rows (w may be null).
-constexpr int kStreamNnz = 2048, kTPR = 4, kStreamRows = 256 / kTPR, kPer = kStreamNnz / 256;
+// xget(c) supplies the gathered vector entry of column c; wget(i) a per-row
+// weight read before the row sums (so its latency overlaps them); yput(i, y,
+// w) stores row i and returns its contribution to this work-group's sum.
+constexpr int kStreamNnz = kSpmvBlockNnz, kTPR = 4, kStreamRows = kSpmvBlockRows, kPer = kStreamNnz / 256;
+static_assert(kStreamRows * kTPR == 256, "four threads per row in a 256-thread group");
+constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
-template <class T, class XF, class YF>
+template <class T, class XF, class WF, class YF>
 __device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                                     const T *__restrict__ vals, XF xget, YF yput, const int32_t *__restrict__ rb,
-                                     int64_t nrb, T *prod, int *rps)
+                                     const T *__restrict__ vals, XF xget, WF wget, YF yput,
+                                     const int32_t *__restrict__ rb, int64_t nrb, T *prod, int *rps)
 {
     const int tid = threadIdx.x;
     double acc = 0.0;
     int c[kPer];
     T v[kPer];
-    int64_t blk = blockIdx.x;
+    // XCD-aware walk: work-groups are dispatched round-robin over the XCDs,
+    // so group w runs on XCD w % kXcds.  Each XCD's groups stream one
+    // contiguous share of the row blocks, which keeps that share's slice of
+    // the gathered vector in the XCD's own L2.
+    const int ngrp = gridDim.x / kXcds;          // groups per XCD (grid is a multiple of kXcds)
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    const int64_t share = (nrb + kXcds - 1) / kXcds;
+    const int64_t lo = (int64_t)xcd * share, hi = lo + share < nrb ? lo + share : nrb;
+    int64_t blk = lo + slot;
     int r0 = 0, r1 = 0, p0 = 0, nz = 0;
     auto fetch = [&](int64_t b) {
         r0 = rb[b];
@@ -116,8 +129,8 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const i
             }
         }
     };
-    if (blk < nrb) fetch(blk);
-    while (blk < nrb) {
+    if (blk < hi) fetch(blk);
+    while (blk < hi) {
         const int cr0 = r0, cr1 = r1, cp0 = p0;
         for (int t = tid; t <= cr1 - cr0; t += 256) rps[t] = rowptr[cr0 + t] - cp0;
 #pragma unroll
@@ -125,10 +138,11 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const i
             const int kk = tid + 256 * j;
             if (kk < nz) prod[kk] = v[j] * xget(c[j]);
         }
-        const int64_t next = blk + gridDim.x;
-        if (next < nrb) fetch(next);
-        __syncthreads();
         const int row = tid / kTPR, sub = tid % kTPR;
+        const T wrow = (sub == 0 && row < cr1 - cr0) ? wget(cr0 + row) : T(0);
+        const int64_t next = blk + ngrp;
+        if (next < hi) fetch(next);
+        __syncthreads();
         T s = T(0);
         if (row < cr1 - cr0) {
             const int q1 = rps[row + 1];
@@ -136,7 +150,7 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const i
         }
         s += __shfl_xor(s, 1, kTPR);
         s += __shfl_xor(s, 2, kTPR);
-        if (sub == 0 && row < cr1 - cr0) acc += yput(cr0 + row, s);
+        if (sub == 0 && row < cr1 - cr0) acc += yput(cr0 + row, s, wrow);
         __syncthreads();
         blk = next;
     }
@@ -150,8 +164,8 @@ __global__ void __launch_bounds__(kTB) k_spmv(const int32_t *rowptr, const int32
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     spmv_stream<T>(
-        rowptr, colidx, vals, [&](int col) { return x[col]; },
-        [&](int row, T val) {
+        rowptr, colidx, vals, [&](int col) { return x[col]; }, [&](int) { return T(0); },
+        [&](int row, T val, T) {
             y[row] = val;
             return 0.0;
         },
@@ -168,7 +182,9 @@ int spmv_blocks(int64_t nrb)
 {
     int cap = g_spmv_resident > 0 ? g_spmv_resident : kMaxParts;
     if (cap > kMaxParts) cap = kMaxParts;
-    return (int)(nrb < 1 ? 1 : (nrb > cap ? cap : nrb));
+    int64_t g = nrb < cap ? nrb : cap;
+    g = (g + kXcds - 1) / kXcds * kXcds;    // a multiple of the XCD count
+    return (int)(g < kXcds ? kXcds : g);
 }
 
 template <class T>
@@ -316,7 +332,7 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
 
 // Iteration k, first launch: q = A p and the partial p . q.
 template <class T>
-__global__ void __launch_bounds__(kTB, 6) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
+__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
                                                     const T *__restrict__ p, T *__restrict__ q, const int32_t *rb,
                                                     int64_t nrb, double *part, const int32_t *flags)
 {
@@ -325,10 +341,10 @@ __global__ void __launch_bounds__(kTB, 6) k_cg_spmv_pq(const int32_t *rowptr, co
     __shared__ double sh[4];
     if (wg_done(flags)) return;
     double acc = spmv_stream<T>(
-        rowptr, colidx, vals, [&](int c) { return p[c]; },
-        [&](int row, T val) {
+        rowptr, colidx, vals, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
+        [&](int row, T val, T prow) {
             q[row] = val;
-            return (double)p[row] * (double)val;
+            return (double)prow * (double)val;
         },
         rb, nrb, prod, rps);
     acc = wg_sum(acc, sh);
@@ -356,7 +372,28 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
     const double alpha = hist[(int64_t)k * 4 + 0] / pq;
     const T a = T(alpha);
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+    // two entries per thread and step (16-byte accesses for FP64)
+    using T2 = typename Vec2<T>::type;
+    const int64_t n2 = n / 2, stride = (int64_t)gridDim.x * kTB;
+    for (int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x; j < n2; j += stride) {
+        T2 xv = ((T2 *)x)[j];
+        const T2 pv = ((const T2 *)p)[j], qv = ((const T2 *)q)[j], dv = ((const T2 *)dinv)[j];
+        T2 rv = ((T2 *)r)[j];
+        xv.x += a * pv.x;
+        xv.y += a * pv.y;
+        rv.x -= a * qv.x;
+        rv.y -= a * qv.y;
+        T2 zv;
+        zv.x = dv.x * rv.x;
+        zv.y = dv.y * rv.y;
+        ((T2 *)x)[j] = xv;
+        ((T2 *)r)[j] = rv;
+        ((T2 *)z)[j] = zv;
+        rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
+        rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t i = n - 1;
         x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
         const T zi = dinv[i] * ri;
@@ -397,8 +434,16 @@ __global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *
     }
     if (conv) return;
     const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
-    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
-        p[i] = z[i] + beta * p[i];
+    using T2 = typename Vec2<T>::type;
+    const int64_t n2 = n / 2, stride = (int64_t)gridDim.x * kTB;
+    for (int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x; j < n2; j += stride) {
+        const T2 zv = ((const T2 *)z)[j];
+        T2 pv = ((T2 *)p)[j];
+        pv.x = zv.x + beta * pv.x;
+        pv.y = zv.y + beta * pv.y;
+        ((T2 *)p)[j] = pv;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
 }
 
 __global__ void __launch_bounds__(kTB) k_cast(int64_t n, const double *in, float *out)
