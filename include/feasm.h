@@ -77,8 +77,10 @@ fe_status fe_ctx_set_stream(fe_ctx ctx, void *hip_stream);
  * Preprocess and upload a single-type mesh (Section 4.2: unstructured mesh;
  * Section 4.3: elements grouped and renumbered for SIMD/SIMT execution).
  *   coords  host [n_nodes][3] float64 (user numbering)
- *   conn    host [n_elems][nen] int32, 0-based, node order of the design doc
- *           (HEX08: VTK hexahedron order; TET04: positively oriented)
+ *   conn    host [n_elems][nen] int32, 0-based.  HEX08 node order
+ *           0:(-,-,-) 1:(+,-,-) 2:(+,+,-) 3:(-,+,-) 4:(-,-,+) 5:(+,-,+)
+ *           6:(+,+,+) 7:(-,+,+) in the reference cube; TET04 vertices
+ *           positively oriented (det J > 0)
  *   dirichlet_nodes host [n_dirichlet] user node ids, or NULL if n_dirichlet = 0
  * Builds the canonical CSR pattern (row i = every node sharing an element
  * with node i, columns ascending, explicit zeros kept), the element blocks,
@@ -134,7 +136,9 @@ typedef struct {
 
 /*
  * Element-by-element assembly (Section 4.2, Listing 1, generalised to the
- * operators of Eq. (1) in the reduced form stated in the design doc):
+ * operators of Eq. (1) in a reduced form: Galerkin advective convection
+ * linearised about the nodal velocity, Laplacian-form viscous term, one
+ * scalar operator shared by the three velocity components):
  *   MOMENTUM: values[1][nnz] = M_rho/dt + C(u) + K_mu,  rhs[3][n_nodes] = M_rho u_i/dt
  *   SCALAR  : values[k][nnz] = M_rho/dt + C(u) + K_{rho D_k}, rhs[k][n_nodes] = M_rho Y_k/dt
  *   POISSON : values[1][nnz] = L (constant coefficient), rhs[1][n_nodes] = (1/dt) int grad N . (rho u)
@@ -184,6 +188,83 @@ typedef struct {
  */
 fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
                       int32_t max_iter, fe_precision prec, fe_cg_info *info);
+
+/* ---- serving: continuous batching of assemble + solve requests -------------
+ * The time-step workload of the paper (Algorithm 1: momentum assembly, the
+ * pressure system's assembly and its PCG solve; Section 2) offered as a
+ * service for many independent meshes.  A server owns one device arena of
+ * hbm_budget bytes (allocated once at creation: requests never call
+ * hipMalloc), host planner threads and one dispatcher thread with its own
+ * HIP stream.  A request runs in four stages:
+ *   1. a planner thread validates and plans its mesh (the fe_mesh_upload
+ *      preprocessing, renumbering on) and computes its device footprint;
+ *   2. admission: when a slot is free and the footprint fits in the arena's
+ *      free space, the dispatcher uploads the mesh and fields and queues the
+ *      momentum assembly (M/dt + C + K with its 3 right-hand sides), the
+ *      Poisson assembly, the Dirichlet elimination and the PCG set-up;
+ *   3. batched PCG: every iteration advances all admitted requests with
+ *      three launches in total (SpMV with p.Ap, the x/r/z update, the
+ *      p update), each request keeping its own scalars and stop test;
+ *   4. completion: the FP64 true residual, copies back to the host, and the
+ *      request's arena space is returned for the next admission.
+ * A request's numbers do not depend on the other requests in flight: its
+ * work-group counts and summation orders are the ones of a request served
+ * alone (and of fe_cg_solve on the same system).
+ *
+ * Host arrays of a request are borrowed from fe_serve_submit until the
+ * request is reported done; they must stay valid and unchanged until then.
+ * The server functions may be called from any host thread. */
+typedef struct fe_server_s *fe_server;
+
+typedef struct {
+    fe_elem_type type;
+    int64_t n_nodes;
+    const double *coords;           /* host [n_nodes][3] */
+    int64_t n_elems;
+    const int32_t *conn;            /* host [n_elems][nen], user node ids */
+    int64_t n_dirichlet;
+    const int32_t *dirichlet_nodes; /* host [n_dirichlet]: homogeneous Dirichlet nodes of the Poisson system */
+    double dt;
+    const double *u;                /* host [3][n_nodes] velocity, user numbering */
+    const double *rho;              /* host [n_nodes] */
+    const double *mu;               /* host [n_nodes] */
+    double rtol;                    /* PCG stop: ||r||_2 <= rtol ||b||_2 (> 0) */
+    int32_t max_iter;
+    double *x;                      /* host [n_nodes] out: pressure solution, user numbering */
+    double *mom_rhs;                /* host [3][n_nodes] out (user numbering) or NULL */
+} fe_job;
+
+typedef struct {
+    fe_status status;               /* FE_OK, FE_ENOCONV (x written), FE_EBADELEM, FE_EBADMESH, ... */
+    int32_t iterations;
+    double rel_residual;            /* recursive ||r||/||b|| at the last iteration */
+    double true_rel_residual;       /* ||b - A x|| / ||b|| recomputed in FP64 */
+    double min_detJ;
+    int64_t first_bad_elem;         /* user element id with det J <= 0, or -1 */
+    double plan_ms;                 /* submit -> planned */
+    double wait_ms;                 /* planned -> admitted */
+    double run_ms;                  /* admitted -> results on the host */
+    double total_ms;                /* submit -> done */
+    char message[128];              /* detail for a non-OK status */
+} fe_job_result;
+
+/* max_slots: requests in flight on the device (1..32); host_threads:
+ * planner threads (>= 1).  hbm_budget: arena bytes. */
+fe_status fe_serve_create(fe_ctx ctx, size_t hbm_budget, int32_t max_slots, int32_t host_threads,
+                          fe_server *out);
+/* Queues a request; *ticket identifies it.  FE_ENOMEM (reported through the
+ * result) if its footprint exceeds the whole arena. */
+fe_status fe_serve_submit(fe_server server, const fe_job *job, int64_t *ticket);
+/* *done = 1 and *result filled once the request is complete (then the
+ * ticket is released); *done = 0 otherwise.  FE_EINVAL for an unknown ticket. */
+fe_status fe_serve_poll(fe_server server, int64_t ticket, int32_t *done, fe_job_result *result);
+/* Blocks until the request is complete, fills *result, releases the ticket. */
+fe_status fe_serve_wait(fe_server server, int64_t ticket, fe_job_result *result);
+/* Counters: requests completed, batched PCG iterations launched, sum over
+ * those launches of the requests they carried (occupancy = ratio). */
+fe_status fe_serve_stats(fe_server server, int64_t *completed, int64_t *batches, int64_t *batched_requests);
+/* Waits for every submitted request, then frees the server. */
+void fe_serve_destroy(fe_server server);
 
 /* ---- measurement hooks --------------------------------------------------------
  * With profiling on, the library brackets its launches with HIP events on the

@@ -9,7 +9,7 @@ Jacobian, elemental matrix or solver lives here.
 
 The paper's test case is a swirl burner on a 64 M-cell mixed tet/pyramid/hex
 mesh (Section 5.1) with a flamelet database; neither is available, so these
-synthetic cubes stand in for it.  Recipes (all stated in the design doc):
+synthetic cubes stand in for it.  Recipes:
 
 * geometry: unit cube, n cells per side, h = 1/n.  Nodes are jittered by an
   i.i.d. uniform offset in [-j*h, +j*h] per coordinate; nodes on the boundary

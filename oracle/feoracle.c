@@ -13,9 +13,11 @@
  *  - Element-by-element Galerkin assembly (Section 4.2, Listing 1: an outer
  *    loop over elements, an inner loop over Gauss points and node pairs that
  *    accumulates Ae(a,b) from shape functions N and the Jacobian weight).
- *    The operator is the momentum operator of Eq. (1) in the reduced form
- *    fixed in the design doc: density-weighted mass / dt + advective convection
- *    + Laplacian-form viscous term, and its right-hand side M_rho u / dt;
+ *    The operator is the momentum operator of Eq. (1) in a reduced form
+ *    (the paper gives no discretisation): density-weighted mass / dt +
+ *    Galerkin advective convection linearised about the nodal velocity +
+ *    Laplacian-form viscous term (one scalar operator shared by the three
+ *    components), and its right-hand side M_rho u / dt;
  *    a scalar-transport variant with coefficient rho*D_k; and the
  *    constant-coefficient pressure Laplacian assembled once before the time
  *    loop (Algorithm 1, first step).

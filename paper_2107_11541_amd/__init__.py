@@ -29,7 +29,7 @@ HEX08, TET04 = FE_HEX08, FE_TET04
 MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
-__all__ = ["Context", "Mesh", "Plan", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
+__all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
            "FeError", "HEX08", "TET04", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
@@ -83,6 +83,7 @@ class Context:
             raise FeError(st, "fe_ctx_create failed")
         self.h = h
         self._meshes = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
         _LIVE_CONTEXTS.add(self)
 
     def error(self) -> str:
@@ -103,6 +104,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for sv in list(self._servers):
+                sv.close()          # servers first: they use the context's device
             for m in list(self._meshes):
                 m.h = None          # freed by fe_ctx_destroy
             self.lib.fe_ctx_destroy(self.h)
@@ -288,6 +291,94 @@ def cg_solve(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_iter: int 
     if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):
         raise FeError(st, mesh.ctx.error())
     return x, out
+
+
+class Server:
+    """Continuous-batching service of assemble + solve requests (fe_serve_*).
+
+    A request is one mesh with its fields: momentum and Poisson assembly,
+    Dirichlet elimination and the Jacobi-PCG pressure solve, all on the GPU.
+    The host arrays of a request are kept alive here until it completes.
+    """
+
+    def __init__(self, ctx: Context, hbm_budget: int = 8 << 30, max_slots: int = 16, host_threads: int = 4):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = C.c_void_p()
+        ctx.check(self.lib.fe_serve_create(ctx.h, int(hbm_budget), int(max_slots), int(host_threads),
+                                           C.byref(h)))
+        self.h = h
+        self._pending = {}
+        ctx._servers.add(self)
+
+    def submit(self, elem_type: int, coords, conn, dirichlet, dt: float, u, rho, mu, rtol: float = 1e-8,
+               max_iter: int = 10000, want_mom_rhs: bool = False) -> int:
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        n = coords.shape[0]
+        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != elem_type:
+            raise ValueError("coords must be [N,3] and conn [E,nen]")
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, n)
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(n)
+        mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(n)
+        d = np.ascontiguousarray(dirichlet if dirichlet is not None else np.zeros(0), dtype=np.int32)
+        x = np.zeros(n, dtype=np.float64)
+        mr = np.zeros((3, n), dtype=np.float64) if want_mom_rhs else None
+        job = capi.Job(type=elem_type, n_nodes=n, coords=coords.ctypes.data, n_elems=conn.shape[0],
+                       conn=conn.ctypes.data, n_dirichlet=d.shape[0], dirichlet_nodes=d.ctypes.data if d.size else None,
+                       dt=float(dt), u=u.ctypes.data, rho=rho.ctypes.data, mu=mu.ctypes.data, rtol=float(rtol),
+                       max_iter=int(max_iter), x=x.ctypes.data, mom_rhs=None if mr is None else mr.ctypes.data)
+        t = C.c_int64()
+        st = self.lib.fe_serve_submit(self.h, C.byref(job), C.byref(t))
+        if st != capi.FE_OK:
+            raise FeError(st, "fe_serve_submit failed")
+        self._pending[t.value] = (job, coords, conn, d, u, rho, mu, x, mr)
+        return t.value
+
+    def _result(self, ticket, r):
+        keep = self._pending.pop(ticket)
+        return {"status": int(r.status), "status_name": capi.STATUS_NAMES.get(r.status, str(r.status)),
+                "iterations": int(r.iterations), "rel_residual": r.rel_residual,
+                "true_rel_residual": r.true_rel_residual, "min_detJ": r.min_detJ,
+                "first_bad_elem": int(r.first_bad_elem), "plan_ms": r.plan_ms, "wait_ms": r.wait_ms,
+                "run_ms": r.run_ms, "total_ms": r.total_ms, "message": r.message.decode(errors="replace"),
+                "x": keep[7], "mom_rhs": keep[8]}
+
+    def poll(self, ticket: int):
+        done = C.c_int32()
+        r = capi.JobResult()
+        st = self.lib.fe_serve_poll(self.h, ticket, C.byref(done), C.byref(r))
+        if st != capi.FE_OK:
+            raise FeError(st, "fe_serve_poll: unknown ticket")
+        return self._result(ticket, r) if done.value else None
+
+    def wait(self, ticket: int) -> dict:
+        r = capi.JobResult()
+        st = self.lib.fe_serve_wait(self.h, ticket, C.byref(r))
+        if st != capi.FE_OK:
+            raise FeError(st, "fe_serve_wait: unknown ticket")
+        return self._result(ticket, r)
+
+    def stats(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        if self.lib.fe_serve_stats(self.h, C.byref(a), C.byref(b), C.byref(c)) != capi.FE_OK:
+            raise FeError(capi.FE_EINVAL, "fe_serve_stats failed")
+        return {"completed": a.value, "batches": b.value, "batched_requests": c.value,
+                "mean_batch": c.value / b.value if b.value else 0.0}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fe_serve_destroy(self.h)
+            self.h = None
+            self._pending.clear()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -44,6 +44,18 @@ class PlanDesc(C.Structure):
                 ("max_row", i32), ("max_block_nodes", i32), ("max_block_slots", i32), ("max_phases", i32)]
 
 
+class Job(C.Structure):
+    _fields_ = [("type", C.c_int), ("n_nodes", i64), ("coords", P), ("n_elems", i64), ("conn", P),
+                ("n_dirichlet", i64), ("dirichlet_nodes", P), ("dt", dbl), ("u", P), ("rho", P), ("mu", P),
+                ("rtol", dbl), ("max_iter", i32), ("x", P), ("mom_rhs", P)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", i32), ("rel_residual", dbl), ("true_rel_residual", dbl),
+                ("min_detJ", dbl), ("first_bad_elem", i64), ("plan_ms", dbl), ("wait_ms", dbl),
+                ("run_ms", dbl), ("total_ms", dbl), ("message", C.c_char * 128)]
+
+
 # name -> (restype, argtypes); every symbol include/feasm.h declares
 SIGNATURES = {
     "fe_ctx_create": (C.c_int, [C.c_int, P, C.POINTER(P)]),
@@ -63,6 +75,12 @@ SIGNATURES = {
     "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
     "fe_axpy": (C.c_int, [P, i64, dbl, P, P]),
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
+    "fe_serve_create": (C.c_int, [P, sz, i32, i32, C.POINTER(P)]),
+    "fe_serve_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(i64)]),
+    "fe_serve_poll": (C.c_int, [P, i64, C.POINTER(i32), C.POINTER(JobResult)]),
+    "fe_serve_wait": (C.c_int, [P, i64, C.POINTER(JobResult)]),
+    "fe_serve_stats": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+    "fe_serve_destroy": (None, [P]),
     "fe_ctx_profile": (C.c_int, [P, C.c_int]),
     "fe_ctx_profile_read": (C.c_int, [P, C.c_int, C.POINTER(i64), C.POINTER(dbl)]),
     "fe_plan_create": (C.c_int, [C.c_int, i64, P, i64, P, C.c_uint32, C.POINTER(P)]),

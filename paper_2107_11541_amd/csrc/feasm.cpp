@@ -11,38 +11,13 @@
 #include <vector>
 
 #include "../../include/feasm.h"
+#include "host.h"
 #include "internal.h"
 #include "plan.h"
 
 using namespace feasm;
 
-struct ProfSlot {
-    std::vector<hipEvent_t> ev;   // start/stop pairs
-    size_t used = 0;
-};
-
-struct fe_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    double *scratch = nullptr;    // 1024 partials + 8 results
-    double *host = nullptr;       // pinned read-back area (64 doubles)
-    bool profiling = false;
-    std::vector<fe_mesh_s *> meshes;   // live meshes, freed by fe_ctx_destroy
-    ProfSlot prof[4];             // 0 CG SpMV + p.q, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
-};
-
-struct fe_mesh_s {
-    fe_ctx_s *ctx = nullptr;
-    DevMesh dm;
-    std::vector<int32_t> node_perm, elem_perm;
-    std::vector<void *> allocs;
-    size_t bytes = 0;
-    AsmStatus *status = nullptr;  // + per-block scratch
-    CGWork cg;
-};
-
-namespace {
+namespace feasm {
 
 fe_status fail(fe_ctx_s *c, fe_status s, const char *fmt, ...)
 {
@@ -55,31 +30,311 @@ fe_status fail(fe_ctx_s *c, fe_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIPCALL(ctx, expr)                                                                              \
-    do {                                                                                                \
-        hipError_t e_ = (expr);                                                                         \
-        if (e_ != hipSuccess) return fail((ctx), FE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+// ---- device arena (first fit over one allocation) ---------------------------
 
-fe_status dev_alloc(fe_mesh_s *m, void **p, size_t bytes)
+DevArena::DevArena(char *base, size_t bytes) : base_(base), cap_(bytes & ~(size_t)255), free_total_(cap_)
+{
+    if (cap_) holes_.push_back({0, cap_});
+}
+
+void *DevArena::alloc(size_t bytes)
+{
+    const size_t b = round(bytes ? bytes : 1);
+    for (size_t i = 0; i < holes_.size(); ++i) {
+        if (holes_[i].second < b) continue;
+        const size_t off = holes_[i].first;
+        holes_[i].first += b;
+        holes_[i].second -= b;
+        if (holes_[i].second == 0) holes_.erase(holes_.begin() + (long)i);
+        auto it = std::lower_bound(used_.begin(), used_.end(), std::make_pair(off, (size_t)0));
+        used_.insert(it, {off, b});
+        free_total_ -= b;
+        return base_ + off;
+    }
+    return nullptr;
+}
+
+void DevArena::release(void *p)
+{
+    if (!p) return;
+    const size_t off = (size_t)((char *)p - base_);
+    auto it = std::lower_bound(used_.begin(), used_.end(), std::make_pair(off, (size_t)0));
+    if (it == used_.end() || it->first != off) return;   // not ours
+    const size_t b = it->second;
+    used_.erase(it);
+    free_total_ += b;
+    auto h = std::lower_bound(holes_.begin(), holes_.end(), std::make_pair(off, (size_t)0));
+    h = holes_.insert(h, {off, b});
+    // merge with the next and the previous hole
+    if (h + 1 != holes_.end() && h->first + h->second == (h + 1)->first) {
+        h->second += (h + 1)->second;
+        holes_.erase(h + 1);
+    }
+    if (h != holes_.begin() && (h - 1)->first + (h - 1)->second == h->first) {
+        (h - 1)->second += h->second;
+        holes_.erase(h);
+    }
+}
+
+// ---- mesh image / device copy --------------------------------------------------
+
+namespace {
+
+// Visits every device array of a mesh: f(device pointer slot, host source or
+// nullptr, bytes).  The one list drives both the byte count and the upload.
+template <class F>
+void for_each_array(MeshImage &I, DevMesh &d, AsmStatus **status, F f)
+{
+    Plan &P = I.P;
+    auto v = [&](auto **dst, const auto &src) {
+        f((void **)dst, (const void *)src.data(), src.size() * sizeof(src[0]));
+    };
+    v(&d.X, P.X);
+    v(&d.rowptr, P.rowptr);
+    v(&d.colidx, P.colidx);
+    v(&d.diagpos, P.diagpos);
+    v(&d.blk_elem_ptr, P.blk_elem_ptr);
+    v(&d.blk_node_ptr, P.blk_node_ptr);
+    v(&d.blk_nodes, P.blk_nodes);
+    v(&d.blk_rdesc, P.blk_rdesc);
+    v(&d.blk_rowstart, P.blk_rowstart);
+    v(&d.blk_nphase, P.blk_nphase);
+    v(&d.elem_lnode, P.elem_lnode);
+    v(&d.elem_off, P.elem_off);
+    v(&d.elem_phase, P.elem_phase);
+    v(&d.color_blk, P.color_blk);
+    v(&d.node_perm, P.node_perm);
+    v(&d.elem_perm, P.elem_perm);
+    v(&d.spmv_desc, I.spmv_desc);
+    v(&d.spmv_roff, I.spmv_roff);
+    v(&d.is_dir, I.is_dir);
+    v(&d.dir_rows, I.dir_rows);
+    f((void **)status, nullptr, sizeof(AsmStatus) + (size_t)d.nblk * 16);
+}
+
+}  // namespace
+
+size_t MeshImage::device_bytes() const
+{
+    MeshImage &I = const_cast<MeshImage &>(*this);
+    DevMesh d = I.d;
+    AsmStatus *st = nullptr;
+    size_t total = 0;
+    for_each_array(I, d, &st, [&](void **, const void *, size_t b) { total += DevArena::round(b ? b : 1); });
+    return total;
+}
+
+int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
+                 int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber, MeshImage &I,
+                 std::string &err)
+{
+    if (type != FE_HEX08 && type != FE_TET04) {
+        err = "unknown element type " + std::to_string((int)type);
+        return FE_EINVAL;
+    }
+    if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet_nodes)) {
+        err = "bad Dirichlet list";
+        return FE_EINVAL;
+    }
+    Plan &P = I.P;
+    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, renumber, P, err);
+    if (st != FE_OK) return st;
+    I.is_dir.assign(n_nodes, 0);
+    for (int64_t k = 0; k < n_dirichlet; ++k) {
+        int32_t v = dirichlet_nodes[k];
+        if (v < 0 || v >= n_nodes) {
+            err = "Dirichlet node " + std::to_string(v) + " out of range";
+            return FE_EINVAL;
+        }
+        I.is_dir[P.node_iperm[v]] = 1;
+    }
+    int64_t ndir = 0;
+    I.dir_rows.clear();
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        bool hit = I.is_dir[i] != 0;
+        ndir += hit;
+        for (int32_t p = P.rowptr[i]; !hit && p < P.rowptr[i + 1]; ++p) hit = I.is_dir[P.colidx[p]] != 0;
+        if (hit) I.dir_rows.push_back((int32_t)i);
+    }
+    DevMesh &d = I.d;
+    d = DevMesh();
+    d.nen = P.nen;
+    d.N = P.N;
+    d.E = P.E;
+    d.nnz = P.nnz;
+    d.nblk = P.n_blocks();
+    d.n_colors = P.n_colors;
+    d.max_T = P.max_T;
+    d.max_L = P.max_L;
+    d.max_row = P.max_row;
+    d.max_phase = P.max_phase;
+    d.color_ptr = P.color_ptr;
+    d.n_dir = ndir;
+    d.n_dir_rows = (int64_t)I.dir_rows.size();
+    // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
+    // row in a 256-thread group) and <= kSpmvBlockNnz nonzeros (the LDS
+    // product buffer).  A single row longer than that cannot occur (rows are
+    // <= 255 entries).
+    std::vector<int32_t> rb{0};
+    for (int64_t r = 0; r < P.N;) {
+        int64_t r1 = r + 1;
+        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz) ++r1;
+        rb.push_back((int32_t)r1);
+        r = r1;
+    }
+    d.spmv_nrb = (int64_t)rb.size() - 1;
+    I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int2{0, 0});
+    I.spmv_roff.assign((size_t)(P.N + d.spmv_nrb), 0);
+    for (int64_t b = 0; b <= d.spmv_nrb; ++b) {
+        I.spmv_desc[b].x = rb[b];
+        I.spmv_desc[b].y = P.rowptr[rb[b]];
+        if (b == d.spmv_nrb) break;
+        for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
+            I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
+    }
+    // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int
+    // descriptor per row (+ alignment), then the row image
+    const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
+    for (int64_t b = 0; b < d.nblk; ++b) {
+        const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
+        int64_t L = 0;
+        for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
+            L += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
+        for (int op = 0; op < 3; ++op) {
+            size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)L * 8;
+            d.max_lds[op] = std::max(d.max_lds[op], by);
+        }
+    }
+    return FE_OK;
+}
+
+fe_status mesh_alloc(fe_mesh_s *m, void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(m->ctx, FE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (m->arena) {
+        *p = m->arena->alloc(bytes);
+        if (!*p) return fail(m->ctx, FE_ENOMEM, "arena: no room for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess)
+            return fail(m->ctx, FE_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
     m->allocs.push_back(*p);
-    m->bytes += bytes;
+    m->bytes += m->arena ? DevArena::round(bytes) : bytes;
     return FE_OK;
 }
 
-template <class T>
-fe_status upload(fe_mesh_s *m, T **dst, const std::vector<T> &src)
+static void mesh_free_ptr(fe_mesh_s *m, void *p)
 {
-    fe_status s = dev_alloc(m, (void **)dst, src.size() * sizeof(T));
-    if (s != FE_OK) return s;
-    if (!src.empty()) HIPCALL(m->ctx, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice,
-                                                     m->ctx->stream));
+    if (!p) return;
+    auto it = std::find(m->allocs.begin(), m->allocs.end(), p);
+    if (it != m->allocs.end()) m->allocs.erase(it);
+    if (m->arena) m->arena->release(p);
+    else (void)hipFree(p);
+}
+
+void mesh_release(fe_mesh_s *m)
+{
+    for (void *p : m->allocs) {
+        if (m->arena) m->arena->release(p);
+        else (void)hipFree(p);
+    }
+    m->allocs.clear();
+    m->cg = CGWork();
+}
+
+fe_status mesh_commit(fe_mesh_s *m, MeshImage &I, hipStream_t stream)
+{
+    m->dm = I.d;
+    fe_status s = FE_OK;
+    for_each_array(I, m->dm, &m->status, [&](void **dst, const void *src, size_t bytes) {
+        if (s != FE_OK) return;
+        s = mesh_alloc(m, dst, bytes);
+        if (s == FE_OK && src && bytes) {
+            hipError_t e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) s = fail(m->ctx, FE_EDEVICE, "mesh upload copy: %s", hipGetErrorString(e));
+        }
+    });
+    return s;
+}
+
+size_t cg_bytes(int64_t n, int max_iter)
+{
+    const int cap = std::max(max_iter + 2, 256);
+    return 6 * DevArena::round((size_t)n * sizeof(double)) + DevArena::round(kPartDoubles * sizeof(double)) +
+           DevArena::round(4 * sizeof(int32_t)) + DevArena::round((4 * (size_t)cap + 4) * sizeof(double));
+}
+
+fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed)
+{
+    CGWork &w = m->cg;
+    const int64_t n = m->dm.N;
+    fe_status s;
+    if (!w.r) {
+        size_t vb = (size_t)n * sizeof(double);
+        double **v[] = {&w.r, &w.z, &w.p, &w.q, &w.dinv, &w.d64};
+        for (double **pp : v) {
+            if ((s = mesh_alloc(m, (void **)pp, vb)) != FE_OK) return s;
+            w.bytes += vb;
+        }
+        if ((s = mesh_alloc(m, (void **)&w.part, kPartDoubles * sizeof(double))) != FE_OK) return s;
+        if ((s = mesh_alloc(m, (void **)&w.flags, 4 * sizeof(int32_t))) != FE_OK) return s;
+        w.n = n;
+    }
+    if (w.hist_cap < max_iter + 2) {
+        mesh_free_ptr(m, w.hist);
+        w.hist = nullptr;
+        w.hist_cap = std::max(max_iter + 2, 256);
+        if ((s = mesh_alloc(m, (void **)&w.hist, (4 * (size_t)w.hist_cap + 4) * sizeof(double))) != FE_OK)
+            return s;
+    }
+    if (mixed && !w.r32) {
+        size_t vb = (size_t)n * sizeof(float);
+        float **v[] = {&w.r32, &w.z32, &w.p32, &w.q32, &w.x32, &w.dinv32};
+        for (float **pp : v) {
+            if ((s = mesh_alloc(m, (void **)pp, vb)) != FE_OK) return s;
+            w.bytes += vb;
+        }
+    }
+    if (mixed && w.v32_cap < m->dm.nnz) {
+        mesh_free_ptr(m, w.v32);
+        w.v32 = nullptr;
+        if ((s = mesh_alloc(m, (void **)&w.v32, (size_t)m->dm.nnz * sizeof(float))) != FE_OK) return s;
+        w.v32_cap = m->dm.nnz;
+        w.bytes += (size_t)m->dm.nnz * sizeof(float);
+    }
     return FE_OK;
 }
+
+fe_status assemble_queue(fe_mesh_s *m, const fe_fields *f, fe_precision prec, double *values, double *rhs,
+                         hipStream_t stream)
+{
+    fe_ctx_s *c = m->ctx;
+    const DevMesh &d = m->dm;
+    AsmArgs a{};
+    a.m = &d;
+    a.op = f->op;
+    a.dt = f->dt;
+    a.u = f->u;
+    a.rho = f->rho;
+    a.mu = f->mu;
+    a.status = m->status;
+    const int passes = f->op == FE_OP_SCALAR ? f->n_scalars : 1;
+    for (int k = 0; k < passes; ++k) {
+        a.values = values + (int64_t)k * d.nnz;
+        a.rhs = rhs + (int64_t)k * d.N;
+        if (f->op == FE_OP_SCALAR) {
+            a.Y = f->Y + (int64_t)k * d.N;
+            a.Dk = f->D[k];
+        }
+        HIPCALL(c, launch_assemble(a, prec == FE_MIXED, stream));
+    }
+    return FE_OK;
+}
+
+}  // namespace feasm
+
+namespace {
 
 hipEvent_t prof_event(fe_ctx_s *c, int slot)
 {
@@ -115,53 +370,6 @@ fe_status sync(fe_ctx_s *c)
 {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     return FE_OK;
-}
-
-fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed)
-{
-    CGWork &w = m->cg;
-    fe_ctx_s *c = m->ctx;
-    const int64_t n = m->dm.N;
-    if (!w.r) {
-        size_t vb = (size_t)n * sizeof(double);
-        double **v[] = {&w.r, &w.z, &w.p, &w.q, &w.dinv, &w.d64};
-        for (double **pp : v) {
-            HIPCALL(c, hipMalloc((void **)pp, vb));
-            w.bytes += vb;
-        }
-        HIPCALL(c, hipMalloc((void **)&w.part, kPartDoubles * sizeof(double)));
-        HIPCALL(c, hipMalloc((void **)&w.flags, 4 * sizeof(int32_t)));
-        w.n = n;
-    }
-    if (w.hist_cap < max_iter + 2) {
-        if (w.hist) HIPCALL(c, hipFree(w.hist));
-        w.hist_cap = std::max(max_iter + 2, 256);
-        HIPCALL(c, hipMalloc((void **)&w.hist, (4 * (size_t)w.hist_cap + 4) * sizeof(double)));
-    }
-    if (mixed && !w.r32) {
-        size_t vb = (size_t)n * sizeof(float);
-        float **v[] = {&w.r32, &w.z32, &w.p32, &w.q32, &w.x32, &w.dinv32};
-        for (float **pp : v) {
-            HIPCALL(c, hipMalloc((void **)pp, vb));
-            w.bytes += vb;
-        }
-    }
-    if (mixed && w.v32_cap < m->dm.nnz) {
-        if (w.v32) HIPCALL(c, hipFree(w.v32));
-        HIPCALL(c, hipMalloc((void **)&w.v32, (size_t)m->dm.nnz * sizeof(float)));
-        w.v32_cap = m->dm.nnz;
-        w.bytes += (size_t)m->dm.nnz * sizeof(float);
-    }
-    return FE_OK;
-}
-
-void free_cg(CGWork &w)
-{
-    void *v[] = {w.r, w.z, w.p, w.q, w.dinv, w.d64, w.part, w.flags, w.hist,
-                 w.r32, w.z32, w.p32, w.q32, w.x32, w.dinv32, w.v32};
-    for (void *p : v)
-        if (p) (void)hipFree(p);
-    w = CGWork();
 }
 
 // Run FP64 or FP32 PCG iterations until the device flag says done or
@@ -255,104 +463,24 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
 {
     if (!c || !out) return FE_EINVAL;
     *out = nullptr;
-    if (type != FE_HEX08 && type != FE_TET04) return fail(c, FE_EINVAL, "unknown element type %d", (int)type);
-    if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet_nodes))
-        return fail(c, FE_EINVAL, "bad Dirichlet list");
     HIPCALL(c, hipSetDevice(c->device));
-    Plan P;
+    auto img = std::make_unique<MeshImage>();
     std::string err;
-    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, (flags & FE_UPLOAD_RENUMBER) != 0, P, err);
+    int st = mesh_prepare(type, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes,
+                          (flags & FE_UPLOAD_RENUMBER) != 0, *img, err);
     if (st != FE_OK) return fail(c, (fe_status)st, "%s", err.c_str());
-    std::vector<uint8_t> isd(n_nodes, 0);
-    for (int64_t k = 0; k < n_dirichlet; ++k) {
-        int32_t v = dirichlet_nodes[k];
-        if (v < 0 || v >= n_nodes) return fail(c, FE_EINVAL, "Dirichlet node %d out of range", v);
-        isd[P.node_iperm[v]] = 1;
-    }
-    std::vector<int32_t> drows;
-    int64_t ndir = 0;
-    for (int64_t i = 0; i < n_nodes; ++i) {
-        bool hit = isd[i] != 0;
-        ndir += hit;
-        for (int32_t p = P.rowptr[i]; !hit && p < P.rowptr[i + 1]; ++p) hit = isd[P.colidx[p]] != 0;
-        if (hit) drows.push_back((int32_t)i);
-    }
-
     auto *m = new fe_mesh_s();
     m->ctx = c;
-    DevMesh &d = m->dm;
-    d.nen = P.nen;
-    d.N = P.N;
-    d.E = P.E;
-    d.nnz = P.nnz;
-    d.nblk = P.n_blocks();
-    d.n_colors = P.n_colors;
-    d.max_T = P.max_T;
-    d.max_L = P.max_L;
-    d.max_row = P.max_row;
-    d.max_phase = P.max_phase;
-    d.color_ptr = P.color_ptr;
-    d.n_dir = ndir;
-    d.n_dir_rows = (int64_t)drows.size();
-    // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
-    // row in a 256-thread group) and <= kSpmvBlockNnz nonzeros (the LDS
-    // product buffer).  A single row longer than that cannot occur (rows are
-    // <= 255 entries).
-    std::vector<int32_t> rb{0};
-    for (int64_t r = 0; r < P.N;) {
-        int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz) ++r1;
-        rb.push_back((int32_t)r1);
-        r = r1;
-    }
-    d.spmv_nrb = (int64_t)rb.size() - 1;
-    // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int
-    // descriptor per row (+ alignment), then the row image
-    {
-        const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
-        for (int64_t b = 0; b < d.nblk; ++b) {
-            const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
-            int64_t L = 0;
-            for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
-                L += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
-            for (int op = 0; op < 3; ++op) {
-                size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)L * 8;
-                d.max_lds[op] = std::max(d.max_lds[op], by);
-            }
-        }
-    }
-
-    fe_status s = FE_OK;
-#define UP(dst, src)                               \
-    if (s == FE_OK) s = upload(m, &d.dst, P.src);
-    UP(X, X);
-    UP(rowptr, rowptr);
-    UP(colidx, colidx);
-    UP(diagpos, diagpos);
-    UP(blk_elem_ptr, blk_elem_ptr);
-    UP(blk_node_ptr, blk_node_ptr);
-    UP(blk_nodes, blk_nodes);
-    UP(blk_rdesc, blk_rdesc);
-    UP(blk_rowstart, blk_rowstart);
-    UP(blk_nphase, blk_nphase);
-    UP(elem_lnode, elem_lnode);
-    UP(elem_off, elem_off);
-    UP(elem_phase, elem_phase);
-    UP(color_blk, color_blk);
-    UP(node_perm, node_perm);
-    UP(elem_perm, elem_perm);
-#undef UP
-    if (s == FE_OK) s = upload(m, &d.spmv_rb, rb);
-    if (s == FE_OK) s = upload(m, &d.is_dir, isd);
-    if (s == FE_OK) s = upload(m, &d.dir_rows, drows);
-    if (s == FE_OK) s = dev_alloc(m, (void **)&m->status, sizeof(AsmStatus) + (size_t)d.nblk * 16);
+    fe_status s = mesh_commit(m, *img, c->stream);
     if (s == FE_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(c, FE_EDEVICE, "upload sync failed");
     if (s != FE_OK) {
-        fe_mesh_free(m);
+        (void)hipStreamSynchronize(c->stream);
+        mesh_release(m);
+        delete m;
         return s;
     }
-    m->node_perm = std::move(P.node_perm);
-    m->elem_perm = std::move(P.elem_perm);
+    m->node_perm = std::move(img->P.node_perm);
+    m->elem_perm = std::move(img->P.elem_perm);
     c->meshes.push_back(m);
     *out = m;
     return FE_OK;
@@ -417,8 +545,7 @@ void fe_mesh_free(fe_mesh m)
     auto &v = m->ctx->meshes;
     v.erase(std::remove(v.begin(), v.end(), m), v.end());
     (void)hipStreamSynchronize(m->ctx->stream);
-    for (void *p : m->allocs) (void)hipFree(p);
-    free_cg(m->cg);
+    mesh_release(m);
     delete m;
 }
 
@@ -437,27 +564,10 @@ fe_status fe_assemble(fe_mesh m, const fe_fields *f, fe_precision prec, double *
     if (f->op != FE_OP_MOMENTUM && f->op != FE_OP_SCALAR && f->op != FE_OP_POISSON)
         return fail(c, FE_EINVAL, "bad operator %d", (int)f->op);
     HIPCALL(c, hipSetDevice(c->device));
-    const DevMesh &d = m->dm;
-    AsmArgs a{};
-    a.m = &d;
-    a.op = f->op;
-    a.dt = f->dt;
-    a.u = f->u;
-    a.rho = f->rho;
-    a.mu = f->mu;
-    a.status = m->status;
-    const int passes = f->op == FE_OP_SCALAR ? f->n_scalars : 1;
     {
         ProfScope ps(c, 1);
-        for (int k = 0; k < passes; ++k) {
-            a.values = values + (int64_t)k * d.nnz;
-            a.rhs = rhs + (int64_t)k * d.N;
-            if (f->op == FE_OP_SCALAR) {
-                a.Y = f->Y + (int64_t)k * d.N;
-                a.Dk = f->D[k];
-            }
-            HIPCALL(c, launch_assemble(a, prec == FE_MIXED, c->stream));
-        }
+        fe_status s = assemble_queue(m, f, prec, values, rhs, c->stream);
+        if (s != FE_OK) return s;
     }
     AsmStatus *hs = (AsmStatus *)c->host;
     HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));

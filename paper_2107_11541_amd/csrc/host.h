@@ -1,0 +1,107 @@
+// host.h -- host-side objects shared by the C ABI (feasm.cpp) and the serving
+// runtime (serve.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/feasm.h"
+#include "internal.h"
+#include "plan.h"
+
+namespace feasm {
+
+// A region of device memory carved up by the serving runtime (first fit,
+// 256-byte granules).  Meshes placed in an arena never call hipMalloc.
+class DevArena {
+  public:
+    DevArena(char *base, size_t bytes);
+    void *alloc(size_t bytes);        // nullptr when no hole is large enough
+    void release(void *p);
+    size_t free_bytes() const { return free_total_; }
+    size_t capacity() const { return cap_; }
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+
+  private:
+    char *base_;
+    size_t cap_, free_total_;
+    std::vector<std::pair<size_t, size_t>> holes_;   // (offset, size), sorted by offset
+    std::vector<std::pair<size_t, size_t>> used_;    // (offset, size), sorted by offset
+};
+
+struct ProfSlot {
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    size_t used = 0;
+};
+
+}  // namespace feasm
+
+struct fe_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    double *scratch = nullptr;    // 1024 partials + 8 results
+    double *host = nullptr;       // pinned read-back area (64 doubles)
+    bool profiling = false;
+    std::vector<fe_mesh_s *> meshes;   // live meshes, freed by fe_ctx_destroy
+    feasm::ProfSlot prof[4];      // 0 CG SpMV + p.q, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
+};
+
+struct fe_mesh_s {
+    fe_ctx_s *ctx = nullptr;
+    feasm::DevMesh dm;
+    std::vector<int32_t> node_perm, elem_perm;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    feasm::AsmStatus *status = nullptr;  // + per-block scratch
+    feasm::CGWork cg;
+    feasm::DevArena *arena = nullptr;    // device memory source (nullptr: hipMalloc)
+    bool listed = true;                  // in ctx->meshes (freed with the context)
+};
+
+namespace feasm {
+
+fe_status fail(fe_ctx_s *c, fe_status s, const char *fmt, ...);
+
+#define HIPCALL(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail((ctx), FE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Host image of a device mesh: the plan plus every array the device copy
+// holds, built without touching the GPU (so planner threads can run it).
+struct MeshImage {
+    Plan P;
+    std::vector<uint8_t> is_dir;
+    std::vector<int32_t> dir_rows;
+    std::vector<int2> spmv_desc;
+    std::vector<uint16_t> spmv_roff;
+    DevMesh d;                 // sizes filled, device pointers null
+    // Device bytes of the mesh arrays (256-byte granules), without CG work.
+    size_t device_bytes() const;
+};
+
+// Validates and plans a mesh on the host (no device calls).  0 or an
+// fe_status code with a message in err.
+int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
+                 int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber, MeshImage &img,
+                 std::string &err);
+// Allocates (from m->arena or hipMalloc) and queues the copies of img on
+// `stream`.  img must stay alive until the copies have completed.
+fe_status mesh_commit(fe_mesh_s *m, MeshImage &img, hipStream_t stream);
+// Device memory of m (through the arena when it has one).
+fe_status mesh_alloc(fe_mesh_s *m, void **p, size_t bytes);
+void mesh_release(fe_mesh_s *m);
+// Device bytes of the FP64 PCG work buffers for n unknowns and max_iter.
+size_t cg_bytes(int64_t n, int max_iter);
+fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed);
+// Queues every assembly pass of one operator on `stream`; the status word
+// stays on the device (m->status).
+fe_status assemble_queue(fe_mesh_s *m, const fe_fields *f, fe_precision prec, double *values, double *rhs,
+                         hipStream_t stream);
+
+}  // namespace feasm

@@ -33,7 +33,12 @@ struct DevMesh {
     uint8_t *is_dir = nullptr;          // [N]
     int32_t *dir_rows = nullptr;        // rows touched by the Dirichlet elimination
     int64_t n_dir = 0, n_dir_rows = 0;
-    int32_t *spmv_rb = nullptr;         // SpMV row blocks: rows [rb[i], rb[i+1]), <= 2048 nonzeros
+    // SpMV row blocks (see kSpmvBlockRows): desc[b] = {first row, first
+    // nonzero}, b = 0..nrb (the last is the end sentinel); roff holds each
+    // block's row offsets relative to its first nonzero, rows + 1 entries at
+    // roff[first row + b].
+    int2 *spmv_desc = nullptr;
+    uint16_t *spmv_roff = nullptr;
     int64_t spmv_nrb = 0;
 };
 
@@ -98,6 +103,32 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int k, hipStre
 template <class T>
 hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s);
 hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s);
+
+// Batched FP64 PCG (serving): the device-resident description of one system
+// and the per-launch list of systems advanced together.  The work-group
+// counts are the ones a launch of its own would use (cg_spmv_groups and
+// stream_blocks), so a system's iterates do not depend on its neighbours.
+struct BatchJob {
+    const int32_t *colidx;
+    const double *vals;
+    const int2 *desc;
+    const uint16_t *roff;
+    int64_t nrb, n;
+    double *x, *r, *z, *p, *q, *dinv, *part, *hist;
+    const double *scal;
+    int32_t *flags;
+    int nb_spmv, nb_vec;
+};
+constexpr int kMaxBatch = 32;
+struct BatchList {
+    int n;                       // systems in this launch
+    int slot[kMaxBatch];         // index into the BatchJob table
+    int k[kMaxBatch];            // iteration index of each system
+    int wgs[kMaxBatch + 1];      // SpMV work-group prefix
+    int wgv[kMaxBatch + 1];      // vector-kernel work-group prefix
+};
+int cg_spmv_groups(const DevMesh &m);
+hipError_t batch_iteration(const BatchJob *jobs, const BatchList &L, hipStream_t s);
 hipError_t residual_f64(const DevMesh &m, const double *vals, const double *b, const double *x, double *r,
                         double *part, double *out_rr_bb, hipStream_t s);
 hipError_t add_f32_to_f64(int64_t n, double scale, const float *d, double *x, hipStream_t s);

@@ -12,8 +12,13 @@
 
 namespace feasm {
 
+static thread_local int t_thread_budget = 0;
+
+void set_thread_budget(int n) { t_thread_budget = n; }
+
 int host_threads()
 {
+    if (t_thread_budget > 0) return t_thread_budget;
     unsigned h = std::thread::hardware_concurrency();
     if (h == 0) h = 4;
     return (int)std::min(h, 16u);

@@ -70,5 +70,8 @@ int build_plan(int nen, int64_t n_nodes, const double *coords, int64_t n_elems, 
 
 // Number of worker threads used by the host preprocessing.
 int host_threads();
+// Caps host_threads() for the calling thread (0: no cap); planner threads
+// of the serving runtime plan one mesh each on a single thread.
+void set_thread_budget(int n);
 
 }  // namespace feasm

@@ -85,72 +85,103 @@ __device__ inline void store_flag(int32_t *p, int v)
 // contiguous (<= kStreamNnz of them, <= kStreamRows rows), streams values and
 // column indices with coalesced non-temporal loads, forms the products in LDS
 // and lets kTPR threads per row add them (thread j takes entries j, j+kTPR,
-// ..., then a fixed shuffle combines the four).  The next block's values and
-// indices are requested before the current block's row sums, so the stream
-// keeps flowing through the LDS phase.  Row blocks are fixed at upload: the
-// summation order, and the result, do not depend on the grid.
+// ..., then a fixed shuffle combines the four).  Row blocks are fixed at
+// upload: the summation order, and the result, do not depend on the grid.
+//
+// The upload stores, per block b, desc[b] = {first row, first nonzero} and
+// the in-block row offsets roff[first row + b + i] = rowptr[r0 + i] -
+// rowptr[r0] (i = 0..rows, uint16), so a block needs one level of address
+// computation: every load of a block depends only on its descriptor.  The
+// loads are branch-free (lanes past the block's end re-read its last entry
+// and weight it 0), and the next block's loads are issued before the
+// current block's products are formed, so the stream never waits behind the
+// gathers.
 // xget(c) supplies the gathered vector entry of column c; wget(i) a per-row
 // weight read before the row sums (so its latency overlaps them); yput(i, y,
 // w) stores row i and returns its contribution to this work-group's sum.
 constexpr int kStreamNnz = kSpmvBlockNnz, kTPR = 4, kStreamRows = kSpmvBlockRows, kPer = kStreamNnz / 256;
 static_assert(kStreamRows * kTPR == 256, "four threads per row in a 256-thread group");
+static_assert(kStreamRows < 256, "the row index of a block's rows must fit the thread count");
 constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
+// wg / G: this group's index and the number of groups working on the matrix
+// (G a multiple of kXcds, and wg % kXcds the group's XCD).
 template <class T, class XF, class WF, class YF>
-__device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                                     const T *__restrict__ vals, XF xget, WF wget, YF yput,
-                                     const int32_t *__restrict__ rb, int64_t nrb, T *prod, int *rps)
+__device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+                                     const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
+                                     int64_t nrb, int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps)
 {
     const int tid = threadIdx.x;
     double acc = 0.0;
-    int c[kPer];
-    T v[kPer];
     // XCD-aware walk: work-groups are dispatched round-robin over the XCDs,
     // so group w runs on XCD w % kXcds.  Each XCD's groups stream one
     // contiguous share of the row blocks, which keeps that share's slice of
     // the gathered vector in the XCD's own L2.
-    const int ngrp = gridDim.x / kXcds;          // groups per XCD (grid is a multiple of kXcds)
-    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    const int ngrp = G / kXcds;                  // groups per XCD
+    const int xcd = wg % kXcds, slot = wg / kXcds;
     const int64_t share = (nrb + kXcds - 1) / kXcds;
     const int64_t lo = (int64_t)xcd * share, hi = lo + share < nrb ? lo + share : nrb;
     int64_t blk = lo + slot;
-    int r0 = 0, r1 = 0, p0 = 0, nz = 0;
-    auto fetch = [&](int64_t b) {
-        r0 = rb[b];
-        r1 = rb[b + 1];
-        p0 = rowptr[r0];
-        nz = rowptr[r1] - p0;
+    if (blk >= hi) return acc;                    // uniform over the group
+    int c[kPer];
+    T v[kPer];
+    int r0 = 0, nrows = 0, nz = 0, ro = 0;
+    // fetch(b, real): load block b; with real == false only one entry is
+    // touched (the loop's last pass issues the same loads on both paths, so
+    // the wait counts of the gathers do not depend on the branch).
+    auto fetch = [&](int64_t b, bool real) {
+        const int2 d0 = desc[b], d1 = desc[b + 1];
+        r0 = d0.x;
+        nrows = d1.x - d0.x;
+        nz = d1.y - d0.y;
+        const int64_t p0 = d0.y;
+        const int span = real ? nz : 1;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int kk = tid + 256 * j;
-            if (kk < nz) {
-                c[j] = __builtin_nontemporal_load(colidx + p0 + kk);
-                v[j] = __builtin_nontemporal_load(vals + p0 + kk);
-            }
+            const int64_t idx = p0 + (kk < span ? kk : span - 1);
+            c[j] = __builtin_nontemporal_load(colidx + idx);
+            v[j] = __builtin_nontemporal_load(vals + idx);
         }
+        ro = roff[(int64_t)r0 + b + (tid < nrows ? tid : nrows)];
     };
-    if (blk < hi) fetch(blk);
-    while (blk < hi) {
-        const int cr0 = r0, cr1 = r1, cp0 = p0;
-        for (int t = tid; t <= cr1 - cr0; t += 256) rps[t] = rowptr[cr0 + t] - cp0;
+    fetch(blk, true);
+    const int row = tid / kTPR, sub = tid % kTPR;
+    for (;;) {
+        const int cr0 = r0, cn = nrows, cnz = nz;
+        if (tid <= cn) rps[tid] = ro;
+        T xv[kPer], vv[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int kk = tid + 256 * j;
-            if (kk < nz) prod[kk] = v[j] * xget(c[j]);
+            xv[j] = xget(c[j]);
+            vv[j] = tid + 256 * j < cnz ? v[j] : T(0);
         }
-        const int row = tid / kTPR, sub = tid % kTPR;
-        const T wrow = (sub == 0 && row < cr1 - cr0) ? wget(cr0 + row) : T(0);
+        const T wrow = wget(cr0 + (row < cn ? row : cn - 1));
         const int64_t next = blk + ngrp;
-        if (next < hi) fetch(next);
+        const bool more = next < hi;
+        fetch(more ? next : blk, more);
+        // keep every load of the next block ahead of the first wait on the gathers
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) prod[tid + 256 * j] = vv[j] * xv[j];
         __syncthreads();
-        T s = T(0);
-        if (row < cr1 - cr0) {
+        // two interleaved partial sums per thread: entries sub, sub + 8, ...
+        // and sub + 4, sub + 12, ... (a fixed order)
+        T s = T(0), s1 = T(0);
+        if (row < cn) {
             const int q1 = rps[row + 1];
-            for (int q = rps[row] + sub; q < q1; q += kTPR) s += prod[q];
+            int q = rps[row] + sub;
+            for (; q + kTPR < q1; q += 2 * kTPR) {
+                s += prod[q];
+                s1 += prod[q + kTPR];
+            }
+            if (q < q1) s += prod[q];
         }
+        s += s1;
         s += __shfl_xor(s, 1, kTPR);
         s += __shfl_xor(s, 2, kTPR);
-        if (sub == 0 && row < cr1 - cr0) acc += yput(cr0 + row, s, wrow);
+        if (sub == 0 && row < cn) acc += yput(cr0 + row, s, wrow);
+        if (!more) break;
         __syncthreads();
         blk = next;
     }
@@ -158,18 +189,20 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ rowptr, const i
 }
 
 template <class T>
-__global__ void __launch_bounds__(kTB) k_spmv(const int32_t *rowptr, const int32_t *colidx, const T *vals,
-                                              const T *x, T *y, const int32_t *rb, int64_t nrb)
+__global__ void __launch_bounds__(kTB) k_spmv(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+                                              const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
+                                              int64_t nrb, const T *__restrict__ x, T *__restrict__ y)
 {
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     spmv_stream<T>(
-        rowptr, colidx, vals, [&](int col) { return x[col]; }, [&](int) { return T(0); },
+        colidx, vals, desc, roff, nrb, blockIdx.x, gridDim.x, [&](int col) { return x[col]; },
+        [&](int) { return T(0); },
         [&](int row, T val, T) {
             y[row] = val;
             return 0.0;
         },
-        rb, nrb, prod, rps);
+        prod, rps);
 }
 
 // Work-groups of the stream SpMV: as many as are co-resident on the device
@@ -190,8 +223,8 @@ int spmv_blocks(int64_t nrb)
 template <class T>
 hipError_t spmv_dispatch(const DevMesh &m, hipStream_t s, const T *v, const T *x, T *y)
 {
-    hipLaunchKernelGGL((k_spmv<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.rowptr, m.colidx, v, x, y,
-                       m.spmv_rb, m.spmv_nrb);
+    hipLaunchKernelGGL((k_spmv<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.spmv_desc,
+                       m.spmv_roff, m.spmv_nrb, x, y);
     return hipGetLastError();
 }
 
@@ -330,39 +363,45 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
     }
 }
 
-// Iteration k, first launch: q = A p and the partial p . q.
+// One PCG iteration is three steps over one system; each is written for a
+// work-group wg of G groups, so that the same code runs as a launch of its
+// own (wg = blockIdx.x) or as one system's share of a batched launch that
+// advances many systems at once.  A system's result depends only on its own
+// G, never on what else shares the launch.
+
+// Iteration k, first step: q = A p and the partial p . q.
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *rowptr, const int32_t *colidx, const T *vals,
-                                                    const T *__restrict__ p, T *__restrict__ q, const int32_t *rb,
-                                                    int64_t nrb, double *part, const int32_t *flags)
+__device__ inline void cg_spmv_pq_step(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+                                       const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
+                                       int64_t nrb, const T *__restrict__ p, T *__restrict__ q,
+                                       double *__restrict__ part, const int32_t *flags, int wg, int G)
 {
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
     if (wg_done(flags)) return;
     double acc = spmv_stream<T>(
-        rowptr, colidx, vals, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
+        colidx, vals, desc, roff, nrb, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
         [&](int row, T val, T prow) {
             q[row] = val;
             return (double)prow * (double)val;
         },
-        rb, nrb, prod, rps);
+        prod, rps);
     acc = wg_sum(acc, sh);
-    if (threadIdx.x == 0) part[kPartPQ + blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[kPartPQ + wg] = acc;
 }
 
-// Iteration k, second launch: alpha = rz_k / (p . q); x += alpha p;
+// Iteration k, second step: alpha = rz_k / (p . q); x += alpha p;
 // r -= alpha q; z = D^-1 r; partials of r.z and r.r.
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q,
-                                                      const T *dinv, double *part, int nb_spmv, double *hist,
-                                                      int32_t *flags)
+__device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q, const T *dinv,
+                                         double *part, int nb_spmv, double *hist, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
     if (wg_done(flags)) return;
     const double pq = reduce_parts(part + kPartPQ, nb_spmv, sh);
     if (!(pq > 0.0) || !isfinite(pq)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (wg == 0 && threadIdx.x == 0) {
             store_flag(flags + 1, FE_EBREAKDOWN);
             store_flag(flags + 2, k);
             store_flag(flags + 0, 1);
@@ -374,8 +413,8 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
     double rz = 0.0, rr = 0.0;
     // two entries per thread and step (16-byte accesses for FP64)
     using T2 = typename Vec2<T>::type;
-    const int64_t n2 = n / 2, stride = (int64_t)gridDim.x * kTB;
-    for (int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x; j < n2; j += stride) {
+    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
+    for (int64_t j = (int64_t)wg * kTB + threadIdx.x; j < n2; j += stride) {
         T2 xv = ((T2 *)x)[j];
         const T2 pv = ((const T2 *)p)[j], qv = ((const T2 *)q)[j], dv = ((const T2 *)dinv)[j];
         T2 rv = ((T2 *)r)[j];
@@ -392,7 +431,7 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
         rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
         rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((n & 1) && wg == 0 && threadIdx.x == 0) {
         const int64_t i = n - 1;
         x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
@@ -405,28 +444,28 @@ __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T 
     rz = wg_sum(rz, sh);
     rr = wg_sum(rr, sh);
     if (threadIdx.x == 0) {
-        part[kPartRZ + blockIdx.x] = rz;
-        part[kPartRR + blockIdx.x] = rr;
+        part[kPartRZ + wg] = rz;
+        part[kPartRR + wg] = rr;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (wg == 0 && threadIdx.x == 0) {
         hist[(int64_t)k * 4 + 2] = pq;
         hist[(int64_t)k * 4 + 3] = alpha;
     }
 }
 
-// Iteration k, third launch: every work-group reduces the r.z and r.r
+// Iteration k, third step: every work-group reduces the r.z and r.r
 // partials (same order, same result); ||r||^2 <= rtol^2 ||b||^2 ends the
 // solve, else beta = rz_{k+1} / rz_k and p = z + beta p.
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *z, T *p, double *part, int nb,
-                                                     double *hist, const double *scal, int32_t *flags)
+__device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, double *part, int nb, double *hist,
+                                        const double *scal, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
     if (wg_done(flags)) return;
     const double rz1 = reduce_parts(part + kPartRZ, nb, sh);
     const double rr = reduce_parts(part + kPartRR, nb, sh);
     const bool conv = rr <= scal[1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (wg == 0 && threadIdx.x == 0) {
         hist[(int64_t)(k + 1) * 4 + 0] = rz1;
         hist[(int64_t)(k + 1) * 4 + 1] = rr;
         store_flag(flags + 2, k + 1);
@@ -435,15 +474,73 @@ __global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *
     if (conv) return;
     const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
     using T2 = typename Vec2<T>::type;
-    const int64_t n2 = n / 2, stride = (int64_t)gridDim.x * kTB;
-    for (int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x; j < n2; j += stride) {
+    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
+    for (int64_t j = (int64_t)wg * kTB + threadIdx.x; j < n2; j += stride) {
         const T2 zv = ((const T2 *)z)[j];
         T2 pv = ((T2 *)p)[j];
         pv.x = zv.x + beta * pv.x;
         pv.y = zv.y + beta * pv.y;
         ((T2 *)p)[j] = pv;
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
+    if ((n & 1) && wg == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+                                                    const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
+                                                    int64_t nrb, const T *__restrict__ p, T *__restrict__ q,
+                                                    double *__restrict__ part, const int32_t *flags)
+{
+    cg_spmv_pq_step<T>(colidx, vals, desc, roff, nrb, p, q, part, flags, blockIdx.x, gridDim.x);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q,
+                                                      const T *dinv, double *part, int nb_spmv, double *hist,
+                                                      int32_t *flags)
+{
+    cg_update_xr_step<T>(n, k, x, r, z, p, q, dinv, part, nb_spmv, hist, flags, blockIdx.x, gridDim.x);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *z, T *p, double *part, int nb,
+                                                     double *hist, const double *scal, int32_t *flags)
+{
+    cg_update_p_step<T>(n, k, z, p, part, nb, hist, scal, flags, blockIdx.x, gridDim.x);
+}
+
+// ---- batched PCG: one launch per step for every system of a BatchList ----
+// Work-group w belongs to the system j with start[j] <= w < start[j+1]
+// (a handful of entries: a linear scan).
+__device__ inline int batch_find(const int *start, int n, int w)
+{
+    int j = 0;
+    while (j + 1 < n && w >= start[j + 1]) ++j;
+    return j;
+}
+
+__global__ void __launch_bounds__(kTB) k_bat_spmv_pq(const BatchJob *__restrict__ jobs, BatchList L)
+{
+    const int j = batch_find(L.wgs, L.n, blockIdx.x);
+    const BatchJob &b = jobs[L.slot[j]];
+    cg_spmv_pq_step<double>(b.colidx, b.vals, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags,
+                            blockIdx.x - L.wgs[j], L.wgs[j + 1] - L.wgs[j]);
+}
+
+__global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restrict__ jobs, BatchList L)
+{
+    const int j = batch_find(L.wgv, L.n, blockIdx.x);
+    const BatchJob &b = jobs[L.slot[j]];
+    cg_update_xr_step<double>(b.n, L.k[j], b.x, b.r, b.z, b.p, b.q, b.dinv, b.part, b.nb_spmv, b.hist, b.flags,
+                              blockIdx.x - L.wgv[j], L.wgv[j + 1] - L.wgv[j]);
+}
+
+__global__ void __launch_bounds__(kTB) k_bat_update_p(const BatchJob *__restrict__ jobs, BatchList L)
+{
+    const int j = batch_find(L.wgv, L.n, blockIdx.x);
+    const BatchJob &b = jobs[L.slot[j]];
+    cg_update_p_step<double>(b.n, L.k[j], b.z, b.p, b.part, b.nb_vec, b.hist, b.scal, b.flags,
+                             blockIdx.x - L.wgv[j], L.wgv[j + 1] - L.wgv[j]);
 }
 
 __global__ void __launch_bounds__(kTB) k_cast(int64_t n, const double *in, float *out)
@@ -577,8 +674,8 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream
 {
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
-    hipLaunchKernelGGL((k_cg_spmv_pq<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.rowptr, m.colidx, vals,
-                       p, q, m.spmv_rb, m.spmv_nrb, w.part, w.flags);
+    hipLaunchKernelGGL((k_cg_spmv_pq<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, vals,
+                       m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
     return hipGetLastError();
 }
 
@@ -606,6 +703,17 @@ template hipError_t cg_spmv_pq<double>(const DevMesh &, const double *, CGWork &
 template hipError_t cg_spmv_pq<float>(const DevMesh &, const float *, CGWork &, int, hipStream_t);
 template hipError_t cg_updates<double>(const DevMesh &, double *, CGWork &, int, hipStream_t);
 template hipError_t cg_updates<float>(const DevMesh &, float *, CGWork &, int, hipStream_t);
+
+int cg_spmv_groups(const DevMesh &m) { return spmv_blocks(m.spmv_nrb); }
+
+hipError_t batch_iteration(const BatchJob *jobs, const BatchList &L, hipStream_t s)
+{
+    if (L.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bat_spmv_pq, dim3(L.wgs[L.n]), dim3(kTB), 0, s, jobs, L);
+    hipLaunchKernelGGL(k_bat_update_xr, dim3(L.wgv[L.n]), dim3(kTB), 0, s, jobs, L);
+    hipLaunchKernelGGL(k_bat_update_p, dim3(L.wgv[L.n]), dim3(kTB), 0, s, jobs, L);
+    return hipGetLastError();
+}
 
 hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s)
 {
