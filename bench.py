@@ -119,6 +119,199 @@ def cpu_baseline(sample_n: int):
     }
 
 
+def serve_bench(args):
+    """Serving workload: independent HEX08 cubes (side 8..96, log-uniform),
+    each a momentum + Poisson assembly and a Jacobi-PCG solve to a true
+    relative residual of 1e-8.  Sequential FP64 (FIFO, one request at a time
+    through the plain API) against the batching server, at an arrival rate
+    of 0.8x, 1.5x the sequential capacity and with everything queued at once."""
+    import threading
+    import torch
+    import meshgen
+    import paper_2107_11541_amd as fe
+
+    nreq = args.serve_requests
+    t_unit, sides = meshgen.serving_stream(nreq, qps=1.0)
+    log(f"serving: generating {nreq} requests (sides {sides.min()}..{sides.max()}, "
+        f"{int(np.sum(sides.astype(np.int64) ** 3))} elements)")
+    cases = [meshgen.serving_case(i, int(n)) for i, n in enumerate(sides)]
+    elems = np.array([c.n_elems for c in cases])
+    ctx = fe.Context(0)
+    RTOL = 1e-8
+
+    def run_plain(c):
+        mesh = fe.Mesh(ctx, c.elem_type, c.coords, c.conn, c.dirichlet, renumber=True)
+        u = mesh.to_mesh(torch.as_tensor(c.u, device="cuda"))
+        rho = mesh.to_mesh(torch.as_tensor(c.rho, device="cuda"))
+        mu = mesh.to_mesh(torch.as_tensor(c.mu, device="cuda"))
+        fe.assemble(mesh, fe.MOMENTUM, c.dt, u, rho, mu)
+        L, f, _ = fe.assemble(mesh, fe.POISSON, c.dt, u, rho)
+        fe.apply_dirichlet(mesh, L, f)
+        x, info = fe.cg_solve(mesh, L[0], f[0], rtol=RTOL, max_iter=20000)
+        xu = mesh.to_user(x).cpu().numpy()
+        mesh.close()
+        return xu, info
+
+    # warm-up (library, kernels, allocator)
+    run_plain(meshgen.serving_case(10**6, 12))
+    torch.cuda.synchronize()
+    seq_s = np.zeros(nreq)
+    seq_res = np.zeros(nreq)
+    t_all = time.perf_counter()
+    for i, c in enumerate(cases):
+        t0 = time.perf_counter()
+        _, info = run_plain(c)
+        seq_s[i] = time.perf_counter() - t0
+        seq_res[i] = info["true_rel_residual"]
+    seq_total = time.perf_counter() - t_all
+    mean_s = float(seq_s.mean())
+    log(f"sequential FP64: {nreq / seq_total:.2f} solves/s, mean service {mean_s * 1e3:.1f} ms, "
+        f"max true residual {seq_res.max():.2e}")
+
+    def fifo_latency(arr):
+        done, out = 0.0, np.zeros(nreq)
+        for i in range(nreq):
+            done = max(arr[i], done) + seq_s[i]
+            out[i] = done - arr[i]
+        return out
+
+    def run_served(qps, slots, threads):
+        srv = fe.Server(ctx, hbm_budget=args.serve_budget_gb << 30, max_slots=slots, host_threads=threads)
+        arr = t_unit / qps if qps else np.zeros(nreq)
+        tickets = [None] * nreq
+
+        def feeder():
+            t0 = time.perf_counter()
+            for i, c in enumerate(cases):
+                dt = arr[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(c.elem_type, c.coords, c.conn, c.dirichlet, c.dt, c.u, c.rho, c.mu,
+                                        rtol=RTOL, max_iter=20000)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=feeder)
+        th.start()
+        res = []
+        for i in range(nreq):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            res.append(srv.wait(tickets[i]))
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["total_ms"] for r in res])
+        bad = [r for r in res if r["status"] != 0 or not r["true_rel_residual"] <= RTOL * 1.0001]
+        return {"qps_offered": qps, "solves_per_s": nreq / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_batch": st["mean_batch"],
+                "max_true_rel_residual": float(max(r["true_rel_residual"] for r in res)), "failed": len(bad),
+                "plan_ms_mean": float(np.mean([r["plan_ms"] for r in res])),
+                "wait_ms_mean": float(np.mean([r["wait_ms"] for r in res])),
+                "run_ms_mean": float(np.mean([r["run_ms"] for r in res]))}
+
+    cap = 1.0 / mean_s
+    runs = {}
+    for name, q in (("saturated", None), ("load0.8", 0.8 * cap), ("load1.5", 1.5 * cap)):
+        runs[name] = run_served(q, args.serve_slots, args.serve_threads)
+        log(f"served {name}: {json.dumps(runs[name])}")
+    seq_lat = {k: fifo_latency(t_unit / (f * cap)) for k, f in (("load0.8", 0.8), ("load1.5", 1.5))}
+    line = {
+        "metric": "served solves/s and p99 at 1e-8 rel err",
+        "value": runs["saturated"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serve-hex08-cubes-8..96-log-uniform, {nreq} requests, momentum+Poisson assembly "
+                               f"+ PCG to true rel residual 1e-8", "requests": nreq,
+                   "elements_total": int(elems.sum()), "slots": args.serve_slots,
+                   "planner_threads": args.serve_threads, "arena_gb": args.serve_budget_gb},
+        "sequential_fp64": {"solves_per_s": nreq / seq_total, "mean_service_ms": mean_s * 1e3,
+                            "p50_ms_at_load0.8": float(np.percentile(seq_lat["load0.8"], 50)) * 1e3,
+                            "p99_ms_at_load0.8": float(np.percentile(seq_lat["load0.8"], 99)) * 1e3,
+                            "p50_ms_at_load1.5": float(np.percentile(seq_lat["load1.5"], 50)) * 1e3,
+                            "p99_ms_at_load1.5": float(np.percentile(seq_lat["load1.5"], 99)) * 1e3,
+                            "max_true_rel_residual": float(seq_res.max())},
+        "served": runs,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def cfg4_bench(args):
+    """256^3 HEX08 (jitter 15 %, 5 species): the momentum matrix with its 3
+    right-hand sides, 5 scalar-transport matrices with theirs and the Poisson
+    system, then the Poisson solve to a true relative residual of 1e-8 twice:
+    FP64 Jacobi-PCG, and FP32 Jacobi-PCG inside FP64 iterative refinement."""
+    import torch
+    import meshgen
+    import paper_2107_11541_amd as fe
+
+    n = args.cfg4_n
+    case = meshgen.cfg4(n)
+    log(f"cfg4 {n}^3: N={case.n_nodes} E={case.n_elems}")
+    ctx = fe.Context(0)
+    t0 = time.perf_counter()
+    mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=True)
+    upload_s = time.perf_counter() - t0
+    dev = "cuda"
+    u = mesh.to_mesh(torch.as_tensor(case.u, device=dev))
+    rho = mesh.to_mesh(torch.as_tensor(case.rho, device=dev))
+    mu = mesh.to_mesh(torch.as_tensor(case.mu, device=dev))
+    Y = mesh.to_mesh(torch.as_tensor(case.Y, device=dev))
+    N, nnz, E = mesh.n_nodes, mesh.nnz, mesh.n_elems
+    Vm = torch.empty((1, nnz), dtype=torch.float64, device=dev)
+    Bm = torch.empty((3, N), dtype=torch.float64, device=dev)
+    Vs = torch.empty((5, nnz), dtype=torch.float64, device=dev)
+    Bs = torch.empty((5, N), dtype=torch.float64, device=dev)
+    L = torch.empty((1, nnz), dtype=torch.float64, device=dev)
+    f = torch.empty((1, N), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    log(f"uploaded in {upload_s:.1f} s, nnz={nnz}, device memory {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+
+    def timed(fn, reps):
+        fn()
+        ctx.profile(True)
+        for _ in range(reps):
+            fn()
+        k, ms = ctx.profile_read(1)
+        ctx.profile(False)
+        return ms / k
+    reps = args.steps
+    ms = {
+        "momentum": timed(lambda: fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, values=Vm, rhs=Bm), reps),
+        "scalars5": timed(lambda: fe.assemble(mesh, fe.SCALAR, case.dt, u, rho, Y=Y, D=case.D, values=Vs,
+                                              rhs=Bs), reps) / 5,
+        "poisson": timed(lambda: fe.assemble(mesh, fe.POISSON, case.dt, u, rho, values=L, rhs=f), reps),
+    }
+    del Vs, Bs
+    total_ms = ms["momentum"] + 5 * ms["scalars5"] + ms["poisson"]
+    fe.apply_dirichlet(mesh, L, f)
+    torch.cuda.synchronize()
+    solves = {}
+    for name, prec in (("fp64_pcg", fe.FP64), ("mixed_ir", fe.MIXED)):
+        x = torch.zeros(N, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-8, max_iter=20000, precision=prec)
+        torch.cuda.synchronize()
+        solves[name] = dict(info, seconds=time.perf_counter() - t0)
+        log(f"{name}: {solves[name]}")
+    line = {
+        "metric": "Melem/s assembled (8 equations) and Poisson solve time to 1e-8: FP64 PCG vs FP32-in-FP64 IR",
+        "value": E / (total_ms * 1e-3) / 1e6, "unit": "Melem/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"hex08-{n}^3-jitter15-5species: 1 momentum + 5 scalar + 1 Poisson matrix, "
+                               f"Poisson solve to true rel residual 1e-8", "elements": E, "nodes": N, "nnz": nnz},
+        "assembly_ms": dict(ms, all_8_equations=total_ms),
+        "assembly_melem_s": {k: E / (v * 1e-3) / 1e6 for k, v in ms.items()},
+        "solve": solves,
+        "ir_speedup": solves["fp64_pcg"]["seconds"] / solves["mixed_ir"]["seconds"],
+        "upload_s": upload_s,
+    }
+    print(json.dumps(line), flush=True)
+    mesh.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +320,11 @@ def main():
     ap.add_argument("--workload", default="hex128")
     ap.add_argument("--cpu-sample-n", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cfg4-n", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-threads", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -147,6 +345,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3}))
+        return
+    if args.workload == "serve":
+        serve_bench(args)
+        return
+    if args.workload == "cfg4":
+        cfg4_bench(args)
         return
     case, wl = make_workload(args.workload)
     log(f"workload {wl}: N={case.n_nodes} E={case.n_elems}")
@@ -206,6 +410,17 @@ def main():
         return ms / n
     ms_mom = time_op(lambda: fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, values=Vm, rhs=Bm))
     ms_poi = time_op(lambda: fe.assemble(mesh, fe.POISSON, case.dt, u, rho, values=L, rhs=f))
+    # mixed-precision momentum assembly (FP32 quadrature, FP64 geometry and
+    # accumulation): its rate and its error against the FP64 assembly
+    Vx = torch.empty_like(Vm)
+    Bx = torch.empty_like(Bm)
+    ms_mix = time_op(lambda: fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, precision=fe.MIXED, values=Vx,
+                                         rhs=Bx))
+    fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, values=Vm, rhs=Bm)
+    torch.cuda.synchronize()
+    mixed_err = {"values_rel_frobenius": float(torch.linalg.norm(Vx - Vm) / torch.linalg.norm(Vm)),
+                 "rhs_rel": float(torch.linalg.norm(Bx - Bm) / torch.linalg.norm(Bm))}
+    del Vx, Bx
 
     spmv_us = ms_spmv / n_spmv * 1e3
     sb = spmv_bytes(nnz, N)
@@ -236,6 +451,8 @@ def main():
             "momentum_melem_s": E / (ms_mom * 1e-3) / 1e6, "poisson_melem_s": E / (ms_poi * 1e-3) / 1e6,
             "momentum_effective_gbs": momentum_bytes(nnz, N, E, mesh.nen) / (ms_mom * 1e-3) / 1e9,
             "poisson_effective_gbs": poisson_bytes(nnz, N, E, mesh.nen) / (ms_poi * 1e-3) / 1e9,
+            "momentum_mixed_assembly_ms": ms_mix, "momentum_mixed_melem_s": E / (ms_mix * 1e-3) / 1e6,
+            "momentum_mixed_vs_fp64": mixed_err,
             "dirichlet_ms": ms_dir / max(n_dir, 1),
             "cg_spmv_us": spmv_us, "cg_update_us": ms_upd / max(n_upd, 1) * 1e3,
             "cg_iteration_effective_gbs": (sb + 88 * N) / ((spmv_us + ms_upd / max(n_upd, 1) * 1e3) * 1e-6) / 1e9,

@@ -172,13 +172,13 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
     d.n_dir = ndir;
     d.n_dir_rows = (int64_t)I.dir_rows.size();
     // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
-    // row in a 256-thread group) and <= kSpmvBlockNnz nonzeros (the LDS
-    // product buffer).  A single row longer than that cannot occur (rows are
-    // <= 255 entries).
+    // row in a 256-thread group) and <= kSpmvBlockNnz - 3 nonzeros (a
+    // 4-aligned window of kSpmvBlockNnz entries in LDS).  A single row longer
+    // than that cannot occur (rows are <= 255 entries).
     std::vector<int32_t> rb{0};
     for (int64_t r = 0; r < P.N;) {
         int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz) ++r1;
+        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) ++r1;
         rb.push_back((int32_t)r1);
         r = r1;
     }
@@ -192,6 +192,8 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
         for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
             I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
     }
+    // the SpMV reads column indices in aligned groups of 4: pad the device copy
+    P.colidx.resize((size_t)P.nnz + kColPad, 0);
     // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int
     // descriptor per row (+ alignment), then the row image
     const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
@@ -299,7 +301,8 @@ fe_status ensure_cg(fe_mesh_s *m, int max_iter, bool mixed)
     if (mixed && w.v32_cap < m->dm.nnz) {
         mesh_free_ptr(m, w.v32);
         w.v32 = nullptr;
-        if ((s = mesh_alloc(m, (void **)&w.v32, (size_t)m->dm.nnz * sizeof(float))) != FE_OK) return s;
+        // padded like the column indices (the SpMV reads groups of 4)
+        if ((s = mesh_alloc(m, (void **)&w.v32, ((size_t)m->dm.nnz + kColPad) * sizeof(float))) != FE_OK) return s;
         w.v32_cap = m->dm.nnz;
         w.bytes += (size_t)m->dm.nnz * sizeof(float);
     }

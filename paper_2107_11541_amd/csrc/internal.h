@@ -80,8 +80,10 @@ struct CGWork {
 
 constexpr int kPartDoubles = 8192;
 // SpMV row blocks (fixed at upload): <= kSpmvBlockRows rows and
-// <= kSpmvBlockNnz nonzeros, contiguous in CSR.
-constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024;
+// <= kSpmvBlockNnz - 3 nonzeros, contiguous in CSR (a block read through a
+// 4-aligned window of kSpmvBlockNnz entries).  The device column-index array
+// is padded by kColPad zeros.
+constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024, kColPad = 4;
 int stream_blocks(int64_t n);
 // Sizes the SpMV grid to the device's co-resident work-groups (context creation).
 hipError_t init_spmv_grid(int device);
@@ -113,11 +115,12 @@ struct BatchJob {
     const double *vals;
     const int2 *desc;
     const uint16_t *roff;
-    int64_t nrb, n;
+    int64_t nrb, n, nnz;
     double *x, *r, *z, *p, *q, *dinv, *part, *hist;
     const double *scal;
     int32_t *flags;
     int nb_spmv, nb_vec;
+    int vec;                     // 16-byte SpMV loads (vals aligned, nnz >= 4)
 };
 constexpr int kMaxBatch = 32;
 struct BatchList {
@@ -128,6 +131,7 @@ struct BatchList {
     int wgv[kMaxBatch + 1];      // vector-kernel work-group prefix
 };
 int cg_spmv_groups(const DevMesh &m);
+bool spmv_vec_capable(const double *vals, int64_t nnz);
 hipError_t batch_iteration(const BatchJob *jobs, const BatchList &L, hipStream_t s);
 hipError_t residual_f64(const DevMesh &m, const double *vals, const double *b, const double *x, double *r,
                         double *part, double *out_rr_bb, hipStream_t s);

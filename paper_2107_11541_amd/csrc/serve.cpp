@@ -247,6 +247,8 @@ fe_status admit(fe_server_s *S, Job *j)
     b.roff = m->dm.spmv_roff;
     b.nrb = m->dm.spmv_nrb;
     b.n = N;
+    b.nnz = nnz;
+    b.vec = spmv_vec_capable(j->vals_p, nnz) ? 1 : 0;
     b.x = j->x_d;
     b.r = w.r;
     b.z = w.z;

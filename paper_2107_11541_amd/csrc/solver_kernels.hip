@@ -82,32 +82,69 @@ __device__ inline void store_flag(int32_t *p, int v)
 }
 
 // CSR-stream SpMV: a work-group takes a row block whose nonzeros are
-// contiguous (<= kStreamNnz of them, <= kStreamRows rows), streams values and
-// column indices with coalesced non-temporal loads, forms the products in LDS
+// contiguous (<= kSpmvBlockNnz - 3 of them, <= kStreamRows rows), streams
+// values and column indices with coalesced loads, forms the products in LDS
 // and lets kTPR threads per row add them (thread j takes entries j, j+kTPR,
 // ..., then a fixed shuffle combines the four).  Row blocks are fixed at
 // upload: the summation order, and the result, do not depend on the grid.
 //
 // The upload stores, per block b, desc[b] = {first row, first nonzero} and
 // the in-block row offsets roff[first row + b + i] = rowptr[r0 + i] -
-// rowptr[r0] (i = 0..rows, uint16), so a block needs one level of address
-// computation: every load of a block depends only on its descriptor.  The
-// loads are branch-free (lanes past the block's end re-read its last entry
-// and weight it 0), and the next block's loads are issued before the
-// current block's products are formed, so the stream never waits behind the
-// gathers.
+// rowptr[r0] (i = 0..rows, uint16), so every load of a block depends only on
+// its descriptor.
+//
+// Loads (VEC): the block is read through a window that starts at its first
+// nonzero rounded down to a multiple of 4; thread t owns window entries
+// 4t..4t+3 and reads them with one 16-byte column-index load and 16-byte
+// value loads (entries outside the block are weighted 0).  Column indices
+// are padded by 4 at upload.  FP64 values belong to the caller and are
+// never read past nnz - 1: a pair that would cross the end is re-based to
+// the last full pair and the final entry comes from one uniform load.  When
+// the caller's value array is not 16-byte aligned, the scalar form (one
+// entry per thread and pass, stride 256) is used instead.
+// The next block's loads are issued before the current block's products are
+// formed, and both paths of the loop's last pass issue the same loads, so
+// the stream never waits behind the gathers.
 // xget(c) supplies the gathered vector entry of column c; wget(i) a per-row
 // weight read before the row sums (so its latency overlaps them); yput(i, y,
 // w) stores row i and returns its contribution to this work-group's sum.
 constexpr int kStreamNnz = kSpmvBlockNnz, kTPR = 4, kStreamRows = kSpmvBlockRows, kPer = kStreamNnz / 256;
+static_assert(kPer == 4, "one 4-entry chunk per thread");
 static_assert(kStreamRows * kTPR == 256, "four threads per row in a 256-thread group");
 static_assert(kStreamRows < 256, "the row index of a block's rows must fit the thread count");
 constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Entries e..e+3 (e a multiple of 4) of a value array of n entries.
+__device__ inline void load_quad(const double *__restrict__ v, int64_t e, int64_t last_even, double last,
+                                 double out[4])
+{
+    const int64_t a = e < last_even ? e : last_even;
+    const int64_t b = e + 2 < last_even ? e + 2 : last_even;
+    const v2d pa = *(const v2d *)(v + a), pb = *(const v2d *)(v + b);
+    out[0] = a == e ? pa.x : last;
+    out[1] = pa.y;   // a != e only when entry e+1 is past the end (weighted 0)
+    out[2] = b == e + 2 ? pb.x : last;
+    out[3] = pb.y;
+}
+// The FP32 copy is the library's own, padded by 4: no re-basing needed.
+__device__ inline void load_quad(const float *__restrict__ v, int64_t e, int64_t, float, float out[4])
+{
+    const v4f q = *(const v4f *)(v + e);
+    out[0] = q.x;
+    out[1] = q.y;
+    out[2] = q.z;
+    out[3] = q.w;
+}
+
 // wg / G: this group's index and the number of groups working on the matrix
-// (G a multiple of kXcds, and wg % kXcds the group's XCD).
-template <class T, class XF, class WF, class YF>
-__device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+// (G a multiple of kXcds, and wg % kXcds the group's XCD).  nnz: entries of
+// vals (the 16-byte path needs nnz >= 4).
+template <class T, bool VEC, class XF, class WF, class YF>
+__device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T *__restrict__ vals, int64_t nnz,
                                      const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
                                      int64_t nrb, int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps)
 {
@@ -123,10 +160,12 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
     const int64_t lo = (int64_t)xcd * share, hi = lo + share < nrb ? lo + share : nrb;
     int64_t blk = lo + slot;
     if (blk >= hi) return acc;                    // uniform over the group
+    const int64_t last_even = (nnz - 2) & ~(int64_t)1;
+    const T last = VEC ? vals[nnz - 1] : T(0);
     int c[kPer];
     T v[kPer];
-    int r0 = 0, nrows = 0, nz = 0, ro = 0;
-    // fetch(b, real): load block b; with real == false only one entry is
+    int r0 = 0, nrows = 0, nz = 0, ro = 0, shift = 0;
+    // fetch(b, real): load block b; with real == false only one chunk is
     // touched (the loop's last pass issues the same loads on both paths, so
     // the wait counts of the gathers do not depend on the branch).
     auto fetch = [&](int64_t b, bool real) {
@@ -134,27 +173,43 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
         r0 = d0.x;
         nrows = d1.x - d0.x;
         nz = d1.y - d0.y;
-        const int64_t p0 = d0.y;
-        const int span = real ? nz : 1;
+        if (VEC) {
+            const int64_t a0 = (int64_t)d0.y & ~(int64_t)3;
+            shift = d0.y - (int)a0;
+            const int chunks = real ? (shift + nz + 3) / 4 : 1;
+            const int64_t e = a0 + 4 * (int64_t)(tid < chunks ? tid : chunks - 1);
+            const v4i cq = *(const v4i *)(colidx + e);
+            c[0] = cq.x;
+            c[1] = cq.y;
+            c[2] = cq.z;
+            c[3] = cq.w;
+            load_quad(vals, e, last_even, last, v);
+        } else {
+            const int64_t p0 = d0.y;
+            shift = 0;
+            const int span = real ? nz : 1;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int kk = tid + 256 * j;
-            const int64_t idx = p0 + (kk < span ? kk : span - 1);
-            c[j] = __builtin_nontemporal_load(colidx + idx);
-            v[j] = __builtin_nontemporal_load(vals + idx);
+            for (int j = 0; j < kPer; ++j) {
+                const int kk = tid + 256 * j;
+                const int64_t idx = p0 + (kk < span ? kk : span - 1);
+                c[j] = colidx[idx];
+                v[j] = vals[idx];
+            }
         }
         ro = roff[(int64_t)r0 + b + (tid < nrows ? tid : nrows)];
     };
+    auto pos = [&](int j) { return VEC ? 4 * tid + j : tid + 256 * j; };
     fetch(blk, true);
     const int row = tid / kTPR, sub = tid % kTPR;
     for (;;) {
-        const int cr0 = r0, cn = nrows, cnz = nz;
-        if (tid <= cn) rps[tid] = ro;
+        const int cr0 = r0, cn = nrows, cnz = nz, csh = shift;
+        if (tid <= cn) rps[tid] = ro + csh;
         T xv[kPer], vv[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             xv[j] = xget(c[j]);
-            vv[j] = tid + 256 * j < cnz ? v[j] : T(0);
+            const int w = pos(j);
+            vv[j] = (w >= csh && w < csh + cnz) ? v[j] : T(0);
         }
         const T wrow = wget(cr0 + (row < cn ? row : cn - 1));
         const int64_t next = blk + ngrp;
@@ -163,7 +218,7 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
         // keep every load of the next block ahead of the first wait on the gathers
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) prod[tid + 256 * j] = vv[j] * xv[j];
+        for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j] * xv[j];
         __syncthreads();
         // two interleaved partial sums per thread: entries sub, sub + 8, ...
         // and sub + 4, sub + 12, ... (a fixed order)
@@ -188,21 +243,29 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
     return acc;
 }
 
-template <class T>
+template <class T, bool VEC>
 __global__ void __launch_bounds__(kTB) k_spmv(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
-                                              const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
-                                              int64_t nrb, const T *__restrict__ x, T *__restrict__ y)
+                                              int64_t nnz, const int2 *__restrict__ desc,
+                                              const uint16_t *__restrict__ roff, int64_t nrb, const T *__restrict__ x,
+                                              T *__restrict__ y)
 {
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
-    spmv_stream<T>(
-        colidx, vals, desc, roff, nrb, blockIdx.x, gridDim.x, [&](int col) { return x[col]; },
+    spmv_stream<T, VEC>(
+        colidx, vals, nnz, desc, roff, nrb, blockIdx.x, gridDim.x, [&](int col) { return x[col]; },
         [&](int) { return T(0); },
         [&](int row, T val, T) {
             y[row] = val;
             return 0.0;
         },
         prod, rps);
+}
+
+// The 16-byte form needs the value array 16-byte aligned and nnz >= 4.
+template <class T>
+inline bool spmv_vec_ok(const T *vals, int64_t nnz)
+{
+    return ((uintptr_t)vals & 15) == 0 && nnz >= 4;
 }
 
 // Work-groups of the stream SpMV: as many as are co-resident on the device
@@ -223,8 +286,12 @@ int spmv_blocks(int64_t nrb)
 template <class T>
 hipError_t spmv_dispatch(const DevMesh &m, hipStream_t s, const T *v, const T *x, T *y)
 {
-    hipLaunchKernelGGL((k_spmv<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.spmv_desc,
-                       m.spmv_roff, m.spmv_nrb, x, y);
+    if (spmv_vec_ok(v, m.nnz))
+        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.nnz,
+                           m.spmv_desc, m.spmv_roff, m.spmv_nrb, x, y);
+    else
+        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.nnz,
+                           m.spmv_desc, m.spmv_roff, m.spmv_nrb, x, y);
     return hipGetLastError();
 }
 
@@ -370,8 +437,8 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
 // G, never on what else shares the launch.
 
 // Iteration k, first step: q = A p and the partial p . q.
-template <class T>
-__device__ inline void cg_spmv_pq_step(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
+template <class T, bool VEC>
+__device__ inline void cg_spmv_pq_step(const int32_t *__restrict__ colidx, const T *__restrict__ vals, int64_t nnz,
                                        const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
                                        int64_t nrb, const T *__restrict__ p, T *__restrict__ q,
                                        double *__restrict__ part, const int32_t *flags, int wg, int G)
@@ -380,8 +447,8 @@ __device__ inline void cg_spmv_pq_step(const int32_t *__restrict__ colidx, const
     __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
     if (wg_done(flags)) return;
-    double acc = spmv_stream<T>(
-        colidx, vals, desc, roff, nrb, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
+    double acc = spmv_stream<T, VEC>(
+        colidx, vals, nnz, desc, roff, nrb, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
         [&](int row, T val, T prow) {
             q[row] = val;
             return (double)prow * (double)val;
@@ -485,13 +552,14 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
     if ((n & 1) && wg == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
 }
 
-template <class T>
+template <class T, bool VEC>
 __global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
-                                                    const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
-                                                    int64_t nrb, const T *__restrict__ p, T *__restrict__ q,
+                                                    int64_t nnz, const int2 *__restrict__ desc,
+                                                    const uint16_t *__restrict__ roff, int64_t nrb,
+                                                    const T *__restrict__ p, T *__restrict__ q,
                                                     double *__restrict__ part, const int32_t *flags)
 {
-    cg_spmv_pq_step<T>(colidx, vals, desc, roff, nrb, p, q, part, flags, blockIdx.x, gridDim.x);
+    cg_spmv_pq_step<T, VEC>(colidx, vals, nnz, desc, roff, nrb, p, q, part, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
@@ -523,8 +591,13 @@ __global__ void __launch_bounds__(kTB) k_bat_spmv_pq(const BatchJob *__restrict_
 {
     const int j = batch_find(L.wgs, L.n, blockIdx.x);
     const BatchJob &b = jobs[L.slot[j]];
-    cg_spmv_pq_step<double>(b.colidx, b.vals, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags,
-                            blockIdx.x - L.wgs[j], L.wgs[j + 1] - L.wgs[j]);
+    const int wg = blockIdx.x - L.wgs[j], G = L.wgs[j + 1] - L.wgs[j];
+    if (b.vec)
+        cg_spmv_pq_step<double, true>(b.colidx, b.vals, b.nnz, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags, wg,
+                                      G);
+    else
+        cg_spmv_pq_step<double, false>(b.colidx, b.vals, b.nnz, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags,
+                                       wg, G);
 }
 
 __global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restrict__ jobs, BatchList L)
@@ -588,7 +661,7 @@ hipError_t init_spmv_grid(int device)
     hipError_t e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_spmv_pq<double>),
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_spmv_pq<double, true>),
                                                      kTB, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
@@ -674,8 +747,12 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream
 {
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
-    hipLaunchKernelGGL((k_cg_spmv_pq<T>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, vals,
-                       m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
+    if (spmv_vec_ok(vals, m.nnz))
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, vals,
+                           m.nnz, m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
+    else
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx,
+                           vals, m.nnz, m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
     return hipGetLastError();
 }
 
@@ -705,6 +782,8 @@ template hipError_t cg_updates<double>(const DevMesh &, double *, CGWork &, int,
 template hipError_t cg_updates<float>(const DevMesh &, float *, CGWork &, int, hipStream_t);
 
 int cg_spmv_groups(const DevMesh &m) { return spmv_blocks(m.spmv_nrb); }
+
+bool spmv_vec_capable(const double *vals, int64_t nnz) { return spmv_vec_ok(vals, nnz); }
 
 hipError_t batch_iteration(const BatchJob *jobs, const BatchList &L, hipStream_t s)
 {

@@ -238,6 +238,32 @@ def test_spmv_dot_axpy_parity(fe_ctx):
     assert fe.dot(fe_ctx, dev(np.zeros(0)), dev(np.zeros(0))) == 0.0
 
 
+@pytest.mark.parametrize("etype,n", [(meshgen.HEX08, 8), (meshgen.HEX08, 10), (meshgen.TET04, 3),
+                                     (meshgen.HEX08, 9)])
+def test_spmv_load_forms_agree(fe_ctx, etype, n):
+    """16-byte loads (aligned values) and one-entry loads (values offset by 8
+    bytes) give bitwise the same y; nnz % 4 = 1, 3, 2, 0 exercises the
+    end-of-array handling of the 16-byte form."""
+    fe = _fe()
+    import torch
+    case = meshgen.make_case(n, etype, 0.1, case_id=53, shuffle=True)
+    mesh, v, b, _ = gpu_assemble(fe_ctx, case, MOM)
+    nnz = mesh.nnz
+    va = dev(v[0])
+    buf = torch.empty(nnz + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = va
+    vm = buf[1:]
+    assert va.data_ptr() % 16 == 0 and vm.data_ptr() % 16 == 8
+    x = mesh.to_mesh(dev(np.random.default_rng(3).normal(0, 1, case.n_nodes)))
+    ya = fe.spmv(mesh, va, x)
+    ym = fe.spmv(mesh, vm, x)
+    assert torch.equal(ya, ym)
+    rp, ci, V, _ = oracle_assemble(case, MOM)
+    yr = oracle.spmv(rp, ci, V[0], rhs_user(mesh, host(x)))
+    print(etype, n, "nnz % 4 =", nnz % 4, flush=True)
+    assert rel(rhs_user(mesh, host(ya)), yr) <= 1e-13
+
+
 def test_pcg_cfg0_matches_direct_solve(fe_ctx):
     fe = _fe()
     case = meshgen.cfg0()
