@@ -323,7 +323,7 @@ def main():
     ap.add_argument("--cfg4-n", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--serve-threads", type=int, default=8)
+    ap.add_argument("--serve-threads", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device copy 3 times (calibrates HBM byte counters)")

@@ -86,7 +86,14 @@ static void morton_order(int nen, int64_t N, const double *coords, int64_t E, co
 }
 
 // CSR pattern in mesh numbering: row i = sorted unique nodes of the elements
-// containing i.  Two passes (count, fill), parallel over rows.
+// containing i.  One pass over the rows, parallel over row ranges: a row's
+// candidates (nen per incident element) are de-duplicated in a 512-slot
+// open-addressing table and the survivors (<= max row length) are sorted by
+// insertion; each range writes its rows to a buffer of its own, then the
+// buffers are concatenated behind the row pointers.  The same pass fills the
+// scatter offsets: with the row sorted, the table maps each column to its
+// position, and every incident element e (node i at local position a) gets
+// elem_off[e][a][c] = position of its node c in row i.
 static void build_pattern(Plan &P)
 {
     const int nen = P.nen;
@@ -102,22 +109,85 @@ static void build_pattern(Plan &P)
             for (int a = 0; a < nen; ++a) inc[fill[P.conn[e * nen + a]]++] = (int32_t)e;
     }
     std::vector<int32_t> len(N);
-    auto row = [&](int64_t i, std::vector<int32_t> &buf) {
-        buf.clear();
-        for (int64_t k = ip[i]; k < ip[i + 1]; ++k) {
-            const int32_t *c = &P.conn[(int64_t)inc[k] * nen];
-            buf.insert(buf.end(), c, c + nen);
+    const int nn2 = nen * nen;
+    P.elem_off.assign((size_t)E * nn2, 0);
+    const int nt = std::max(1, (int)std::min<int64_t>(host_threads(), (N + 4095) / 4096));
+    const int64_t chunk = (N + nt - 1) / nt;
+    std::vector<std::vector<int32_t>> cols(nt);
+    std::atomic<bool> overflow{false};
+    auto work = [&](int t) {
+        const int64_t lo = t * chunk, hi = std::min(N, lo + chunk);
+        std::vector<int32_t> &out = cols[t];
+        out.reserve((size_t)std::max<int64_t>(0, hi - lo) * 27);
+        constexpr int kSlots = 512;   // > 2 x the longest admissible row
+        int32_t table[kSlots];
+        uint16_t used[kSlots];
+        uint8_t posv[kSlots];
+        auto slot_of = [&](int32_t v) {
+            uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
+            while (table[h] != v) h = (h + 1) & (kSlots - 1);
+            return h;
+        };
+        for (int q = 0; q < kSlots; ++q) table[q] = -1;
+        for (int64_t i = lo; i < hi; ++i) {
+            const size_t start = out.size();
+            int nused = 0;
+            for (int64_t k = ip[i]; k < ip[i + 1]; ++k) {
+                const int32_t *c = &P.conn[(int64_t)inc[k] * nen];
+                for (int a = 0; a < nen; ++a) {
+                    const int32_t v = c[a];
+                    uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
+                    while (table[h] != -1 && table[h] != v) h = (h + 1) & (kSlots - 1);
+                    if (table[h] == -1) {
+                        if (nused == kSlots / 2) {   // row longer than any admissible one
+                            overflow = true;
+                            continue;
+                        }
+                        table[h] = v;
+                        used[nused++] = (uint16_t)h;
+                        out.push_back(v);
+                    }
+                }
+            }
+            int32_t *r = out.data() + start;
+            const int n = (int)(out.size() - start);
+            for (int x = 1; x < n; ++x) {
+                const int32_t key = r[x];
+                int y = x - 1;
+                while (y >= 0 && r[y] > key) {
+                    r[y + 1] = r[y];
+                    --y;
+                }
+                r[y + 1] = key;
+            }
+            len[i] = n;
+            if (n <= 255) {   // longer rows are rejected by the caller
+                for (int q = 0; q < n; ++q) posv[slot_of(r[q])] = (uint8_t)q;
+                int64_t prev_e = -1;
+                int prev_a = -1;
+                for (int64_t k = ip[i]; k < ip[i + 1]; ++k) {
+                    const int64_t e = inc[k];
+                    const int32_t *c = &P.conn[e * nen];
+                    // the k-th occurrence of i in e (an element may repeat a node)
+                    int a = e == prev_e ? prev_a + 1 : 0;
+                    while (a < nen && c[a] != (int32_t)i) ++a;
+                    prev_e = e;
+                    prev_a = a;
+                    if (a == nen) continue;
+                    uint8_t *off = &P.elem_off[(size_t)e * nn2 + (size_t)a * nen];
+                    for (int q = 0; q < nen; ++q) off[q] = posv[slot_of(c[q])];
+                }
+            }
+            for (int q = 0; q < nused; ++q) table[used[q]] = -1;
         }
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
     };
-    parallel_for(N, [&](int64_t a, int64_t b) {
-        std::vector<int32_t> buf;
-        for (int64_t i = a; i < b; ++i) {
-            row(i, buf);
-            len[i] = (int32_t)buf.size();
-        }
-    });
+    if (nt == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t) th.emplace_back(work, t);
+        for (auto &x : th) x.join();
+    }
     P.rowptr.assign(N + 1, 0);
     int64_t s = 0;
     int mx = 0;
@@ -128,24 +198,23 @@ static void build_pattern(Plan &P)
     }
     P.rowptr[N] = (int32_t)s;
     P.nnz = s;
-    P.max_row = mx;
-    P.colidx.assign(s, 0);
+    // a row reaching kSlots / 2 = 256 distinct nodes is over kMaxRow anyway
+    P.max_row = overflow ? (1 << 30) : mx;
+    P.colidx.resize(s);
     P.diagpos.assign(N, 0);
-    parallel_for(N, [&](int64_t a, int64_t b) {
-        std::vector<int32_t> buf;
-        for (int64_t i = a; i < b; ++i) {
-            row(i, buf);
-            std::copy(buf.begin(), buf.end(), P.colidx.begin() + P.rowptr[i]);
-            P.diagpos[i] = P.rowptr[i] + (int32_t)(std::lower_bound(buf.begin(), buf.end(), (int32_t)i) - buf.begin());
+    parallel_for(nt, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t lo = t * chunk;
+            if (lo >= N || cols[t].empty()) continue;
+            std::copy(cols[t].begin(), cols[t].end(), P.colidx.begin() + P.rowptr[lo]);
         }
     });
-}
-
-static inline int64_t slot_in_row(const Plan &P, int32_t i, int32_t j)
-{
-    const int32_t *b = P.colidx.data() + P.rowptr[i], *e = P.colidx.data() + P.rowptr[i + 1];
-    const int32_t *p = std::lower_bound(b, e, j);
-    return (p != e && *p == j) ? (p - b) : -1;
+    parallel_for(N, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+            const int32_t *r0 = P.colidx.data() + P.rowptr[i], *r1 = P.colidx.data() + P.rowptr[i + 1];
+            P.diagpos[i] = P.rowptr[i] + (int32_t)(std::lower_bound(r0, r1, (int32_t)i) - r0);
+        }
+    });
 }
 
 int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_t *conn, bool renumber,
@@ -290,23 +359,40 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
 
     // 5. per element: local rows, in-row offsets, phases
     P.elem_lnode.assign(nen * E, 0);
-    P.elem_off.assign(E * nn2, 0);
     P.elem_phase.assign(E, 0);
     P.blk_nphase.assign(nblk, 1);
     std::atomic<int> bad{0};
     std::atomic<int> maxph{1};
     parallel_for(nblk, [&](int64_t b0, int64_t b1) {
         std::vector<uint64_t> used;   // [T][nen] phase masks
+        // node -> local row of the current block: open addressing over
+        // 1024 slots (a block touches far fewer nodes, the LDS budget caps it)
+        constexpr int kSlots = 1024;
+        std::vector<int32_t> key(kSlots, -1);
+        std::vector<uint16_t> val(kSlots, 0);
+        auto hslot = [](int32_t v) { return ((uint32_t)v * 2654435761u) >> 22; };
         for (int64_t b = b0; b < b1; ++b) {
             const int32_t *nb = P.blk_nodes.data() + P.blk_node_ptr[b];
             const int T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
+            if (T >= kSlots) {
+                bad = 1;
+                continue;
+            }
+            for (int k = 0; k < T; ++k) {
+                uint32_t h = hslot(nb[k]);
+                while (key[h] != -1) h = (h + 1) & (kSlots - 1);
+                key[h] = nb[k];
+                val[h] = (uint16_t)k;
+            }
             used.assign((size_t)T * nen, 0);
             int nph = 1;
             for (int64_t e = P.blk_elem_ptr[b]; e < P.blk_elem_ptr[b + 1]; ++e) {
                 int ln[8];
                 for (int a = 0; a < nen; ++a) {
                     int32_t v = P.conn[e * nen + a];
-                    ln[a] = (int)(std::lower_bound(nb, nb + T, v) - nb);
+                    uint32_t h = hslot(v);
+                    while (key[h] != v) h = (h + 1) & (kSlots - 1);
+                    ln[a] = val[h];
                     P.elem_lnode[(int64_t)a * E + e] = (uint16_t)ln[a];
                 }
                 uint64_t m = 0;
@@ -317,14 +403,13 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
                 for (int a = 0; a < nen; ++a) used[(size_t)ln[a] * nen + a] |= (1ull << ph);
                 P.elem_phase[e] = (uint8_t)ph;
                 nph = std::max(nph, ph + 1);
-                for (int a = 0; a < nen; ++a)
-                    for (int c = 0; c < nen; ++c) {
-                        int64_t s = slot_in_row(P, P.conn[e * nen + a], P.conn[e * nen + c]);
-                        if (s < 0) bad = 1;
-                        P.elem_off[e * nn2 + a * nen + c] = (uint8_t)s;
-                    }
             }
             P.blk_nphase[b] = (uint8_t)nph;
+            for (int k = 0; k < T; ++k) {
+                uint32_t h = hslot(nb[k]);
+                while (key[h] != nb[k]) h = (h + 1) & (kSlots - 1);
+                key[h] = -1;
+            }
             int cur = maxph.load();
             while (nph > cur && !maxph.compare_exchange_weak(cur, nph)) {}
         }

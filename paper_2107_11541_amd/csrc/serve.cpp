@@ -6,7 +6,7 @@
 // elimination, then the PCG solve (Section 5.2).  Many small meshes give
 // kernels far too small to fill 256 compute units, so the runtime
 //   * plans meshes on host threads while the GPU works (the planner is the
-//     fe_mesh_upload preprocessing, run single-threaded per mesh);
+//     fe_mesh_upload preprocessing, on one to four threads per mesh);
 //   * places every admitted request in one pre-allocated device arena
 //     (admission by footprint; no hipMalloc per request);
 //   * advances all admitted requests' PCG iterations together, three
@@ -113,7 +113,9 @@ namespace {
 void plan_job(Job *j)
 {
     const fe_job &q = j->desc;
-    set_thread_budget(1);
+    // one thread per mesh keeps every planner busy; large meshes get a few
+    // more so that they do not set the latency tail alone
+    set_thread_budget((int)std::max<int64_t>(1, std::min<int64_t>(4, q.n_elems / 200000)));
     j->img = std::make_unique<MeshImage>();
     std::string err;
     int st = FE_OK;
