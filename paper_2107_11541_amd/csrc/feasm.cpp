@@ -107,6 +107,7 @@ void for_each_array(MeshImage &I, DevMesh &d, AsmStatus **status, F f)
     v(&d.elem_perm, P.elem_perm);
     v(&d.spmv_desc, I.spmv_desc);
     v(&d.spmv_roff, I.spmv_roff);
+    v(&d.spmv_cidx, I.spmv_cidx);
     v(&d.is_dir, I.is_dir);
     v(&d.dir_rows, I.dir_rows);
     f((void **)status, nullptr, sizeof(AsmStatus) + (size_t)d.nblk * 16);
@@ -183,15 +184,48 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
         r = r1;
     }
     d.spmv_nrb = (int64_t)rb.size() - 1;
-    I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int2{0, 0});
+    I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int4{0, 0, 0, 0});
     I.spmv_roff.assign((size_t)(P.N + d.spmv_nrb), 0);
-    for (int64_t b = 0; b <= d.spmv_nrb; ++b) {
-        I.spmv_desc[b].x = rb[b];
-        I.spmv_desc[b].y = P.rowptr[rb[b]];
-        if (b == d.spmv_nrb) break;
+    // packed column indices, block by block (16-byte aligned segments)
+    {
+        size_t bytes = 0;
+        std::vector<uint8_t> narrow((size_t)d.spmv_nrb, 0);
+        std::vector<int32_t> base((size_t)d.spmv_nrb, 0);
+        for (int64_t b = 0; b < d.spmv_nrb; ++b) {
+            const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]];
+            int32_t lo = P.colidx[p0], hi = P.colidx[p0];
+            for (int64_t q = p0; q < p1; ++q) {
+                lo = std::min(lo, P.colidx[q]);
+                hi = std::max(hi, P.colidx[q]);
+            }
+            narrow[b] = (int64_t)hi - lo <= 65535;
+            base[b] = lo;
+            const int64_t win = ((p0 & 3) + (p1 - p0) + 3) & ~(int64_t)3;
+            I.spmv_desc[b] = int4{rb[b], (int32_t)p0, (int32_t)(bytes / 16),
+                                  (int32_t)((uint32_t)lo | (narrow[b] ? 0u : 0x80000000u))};
+            bytes += (size_t)((narrow[b] ? 2 : 4) * win + 15) & ~(size_t)15;
+        }
+        I.spmv_desc[d.spmv_nrb] = int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)(bytes / 16), 0};
+        I.spmv_cidx.assign(bytes + 16, 0);
+        for (int64_t b = 0; b < d.spmv_nrb; ++b) {
+            const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]], a0 = p0 & ~(int64_t)3;
+            const int64_t win = ((p0 & 3) + (p1 - p0) + 3) & ~(int64_t)3;
+            uint8_t *seg = I.spmv_cidx.data() + (size_t)I.spmv_desc[b].z * 16;
+            for (int64_t w = 0; w < win; ++w) {
+                const int64_t q = a0 + w;
+                const int32_t col = (q >= p0 && q < p1) ? P.colidx[q] : base[b];
+                if (narrow[b]) {
+                    const uint16_t off = (uint16_t)(col - base[b]);
+                    memcpy(seg + 2 * w, &off, 2);
+                } else {
+                    memcpy(seg + 4 * w, &col, 4);
+                }
+            }
+        }
+    }
+    for (int64_t b = 0; b < d.spmv_nrb; ++b)
         for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
             I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
-    }
     // the SpMV reads column indices in aligned groups of 4: pad the device copy
     P.colidx.resize((size_t)P.nnz + kColPad, 0);
     // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int

@@ -78,8 +78,9 @@ struct MeshImage {
     Plan P;
     std::vector<uint8_t> is_dir;
     std::vector<int32_t> dir_rows;
-    std::vector<int2> spmv_desc;
+    std::vector<int4> spmv_desc;
     std::vector<uint16_t> spmv_roff;
+    std::vector<uint8_t> spmv_cidx;
     DevMesh d;                 // sizes filled, device pointers null
     // Device bytes of the mesh arrays (256-byte granules), without CG work.
     size_t device_bytes() const;

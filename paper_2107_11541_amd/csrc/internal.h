@@ -34,13 +34,33 @@ struct DevMesh {
     int32_t *dir_rows = nullptr;        // rows touched by the Dirichlet elimination
     int64_t n_dir = 0, n_dir_rows = 0;
     // SpMV row blocks (see kSpmvBlockRows): desc[b] = {first row, first
-    // nonzero}, b = 0..nrb (the last is the end sentinel); roff holds each
-    // block's row offsets relative to its first nonzero, rows + 1 entries at
-    // roff[first row + b].
-    int2 *spmv_desc = nullptr;
+    // nonzero, index segment offset in 16-byte units, base column | wide <<
+    // 31}, b = 0..nrb (the last is the end sentinel); roff holds each block's
+    // row offsets relative to its first nonzero, rows + 1 entries at
+    // roff[first row + b]; cidx the packed column indices (see SpmvMap).
+    int4 *spmv_desc = nullptr;
     uint16_t *spmv_roff = nullptr;
+    uint8_t *spmv_cidx = nullptr;
     int64_t spmv_nrb = 0;
 };
+
+// What the SpMV kernels read besides values and vectors.  A block's column
+// indices cover its 4-aligned window (first nonzero rounded down to a
+// multiple of 4, a multiple of 4 entries); a block whose columns span less
+// than 2^16 stores them as 16-bit offsets from its base column ("narrow"),
+// any other block as plain 32-bit indices ("wide").  Window entries outside
+// the block hold the base column (a valid index, weighted 0).
+struct SpmvMap {
+    const int4 *desc;
+    const uint16_t *roff;
+    const uint8_t *cidx;
+    const int32_t *colidx;   // canonical CSR columns (the one-entry form)
+    int64_t nrb, nnz;
+};
+inline SpmvMap spmv_map(const DevMesh &m)
+{
+    return SpmvMap{m.spmv_desc, m.spmv_roff, m.spmv_cidx, m.colidx, m.spmv_nrb, m.nnz};
+}
 
 // Device status word of an assembly launch sequence.
 struct AsmStatus {
@@ -111,11 +131,9 @@ hipError_t cast_f64_f32(int64_t n, const double *in, float *out, hipStream_t s);
 // counts are the ones a launch of its own would use (cg_spmv_groups and
 // stream_blocks), so a system's iterates do not depend on its neighbours.
 struct BatchJob {
-    const int32_t *colidx;
+    SpmvMap sm;
     const double *vals;
-    const int2 *desc;
-    const uint16_t *roff;
-    int64_t nrb, n, nnz;
+    int64_t n;
     double *x, *r, *z, *p, *q, *dinv, *part, *hist;
     const double *scal;
     int32_t *flags;

@@ -243,13 +243,9 @@ fe_status admit(fe_server_s *S, Job *j)
     HIPCALL(c, launch_dirichlet(m->dm, j->vals_p, j->rhs_p, nullptr, S->stream));
     HIPCALL(c, cg_setup<double>(m->dm, j->vals_p, j->rhs_p, j->x_d, w, q.rtol, S->stream, true));
     BatchJob &b = S->jobs_h[j->slot];
-    b.colidx = m->dm.colidx;
+    b.sm = spmv_map(m->dm);
     b.vals = j->vals_p;
-    b.desc = m->dm.spmv_desc;
-    b.roff = m->dm.spmv_roff;
-    b.nrb = m->dm.spmv_nrb;
     b.n = N;
-    b.nnz = nnz;
     b.vec = spmv_vec_capable(j->vals_p, nnz) ? 1 : 0;
     b.x = j->x_d;
     b.r = w.r;

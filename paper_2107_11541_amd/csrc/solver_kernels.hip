@@ -115,6 +115,7 @@ static_assert(kStreamRows < 256, "the row index of a block's rows must fit the t
 constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -144,10 +145,11 @@ __device__ inline void load_quad(const float *__restrict__ v, int64_t e, int64_t
 // (G a multiple of kXcds, and wg % kXcds the group's XCD).  nnz: entries of
 // vals (the 16-byte path needs nnz >= 4).
 template <class T, bool VEC, class XF, class WF, class YF>
-__device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T *__restrict__ vals, int64_t nnz,
-                                     const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
-                                     int64_t nrb, int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps)
+__device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
+                                     int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps)
 {
+    const uint16_t *__restrict__ roff = sm.roff;
+    const int64_t nrb = sm.nrb, nnz = sm.nnz;
     const int tid = threadIdx.x;
     double acc = 0.0;
     // XCD-aware walk: work-groups are dispatched round-robin over the XCDs,
@@ -168,8 +170,9 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
     // fetch(b, real): load block b; with real == false only one chunk is
     // touched (the loop's last pass issues the same loads on both paths, so
     // the wait counts of the gathers do not depend on the branch).
-    auto fetch = [&](int64_t b, bool real) {
-        const int2 d0 = desc[b], d1 = desc[b + 1];
+    // fetch(b, d0, d1, real): issue the loads of block b, whose descriptor
+    // pair (d0, d1) = (desc[b], desc[b + 1]) was read beforehand
+    auto fetch = [&](int64_t b, const int4 d0, const int4 d1, bool real) {
         r0 = d0.x;
         nrows = d1.x - d0.x;
         nz = d1.y - d0.y;
@@ -177,14 +180,22 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
             const int64_t a0 = (int64_t)d0.y & ~(int64_t)3;
             shift = d0.y - (int)a0;
             const int chunks = real ? (shift + nz + 3) / 4 : 1;
-            const int64_t e = a0 + 4 * (int64_t)(tid < chunks ? tid : chunks - 1);
-            const v4i cq = *(const v4i *)(colidx + e);
-            c[0] = cq.x;
-            c[1] = cq.y;
-            c[2] = cq.z;
-            c[3] = cq.w;
-            load_quad(vals, e, last_even, last, v);
+            const int t = tid < chunks ? tid : chunks - 1;
+            const uint8_t *seg = sm.cidx + (int64_t)d0.z * 16;
+            const int base = d0.w & 0x7fffffff;
+            const bool wide = d0.w < 0;
+            // the same two 8-byte loads for both kinds (no branch, so no wait
+            // is forced before the join): a wide block's 4 indices, or a
+            // narrow block's 4 offsets twice
+            const v2u q0 = *(const v2u *)(seg + (wide ? 16 * t : 8 * t));
+            const v2u q1 = *(const v2u *)(seg + (wide ? 16 * t + 8 : 8 * t));
+            c[0] = wide ? (int)q0.x : base + (int)(q0.x & 0xffffu);
+            c[1] = wide ? (int)q0.y : base + (int)(q0.x >> 16);
+            c[2] = wide ? (int)q1.x : base + (int)(q0.y & 0xffffu);
+            c[3] = wide ? (int)q1.y : base + (int)(q0.y >> 16);
+            load_quad(vals, a0 + 4 * (int64_t)t, last_even, last, v);
         } else {
+            const int32_t *__restrict__ colidx = sm.colidx;
             const int64_t p0 = d0.y;
             shift = 0;
             const int span = real ? nz : 1;
@@ -199,11 +210,17 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
         ro = roff[(int64_t)r0 + b + (tid < nrows ? tid : nrows)];
     };
     auto pos = [&](int j) { return VEC ? 4 * tid + j : tid + 256 * j; };
-    fetch(blk, true);
+    fetch(blk, desc[blk], desc[blk + 1], true);
     const int row = tid / kTPR, sub = tid % kTPR;
     for (;;) {
         const int cr0 = r0, cn = nrows, cnz = nz, csh = shift;
         if (tid <= cn) rps[tid] = ro + csh;
+        // the next block's descriptor is read before the gathers are issued,
+        // so that waiting for it never waits for them
+        const int64_t next = blk + ngrp;
+        const bool more = next < hi;
+        const int64_t nb = more ? next : blk;
+        const int4 n0 = desc[nb], n1 = desc[nb + 1];
         T xv[kPer], vv[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
@@ -212,9 +229,7 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
             vv[j] = (w >= csh && w < csh + cnz) ? v[j] : T(0);
         }
         const T wrow = wget(cr0 + (row < cn ? row : cn - 1));
-        const int64_t next = blk + ngrp;
-        const bool more = next < hi;
-        fetch(more ? next : blk, more);
+        fetch(nb, n0, n1, more);
         // keep every load of the next block ahead of the first wait on the gathers
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -244,16 +259,13 @@ __device__ inline double spmv_stream(const int32_t *__restrict__ colidx, const T
 }
 
 template <class T, bool VEC>
-__global__ void __launch_bounds__(kTB) k_spmv(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
-                                              int64_t nnz, const int2 *__restrict__ desc,
-                                              const uint16_t *__restrict__ roff, int64_t nrb, const T *__restrict__ x,
-                                              T *__restrict__ y)
+__global__ void __launch_bounds__(kTB) k_spmv(SpmvMap sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
+                                              const T *__restrict__ x, T *__restrict__ y)
 {
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     spmv_stream<T, VEC>(
-        colidx, vals, nnz, desc, roff, nrb, blockIdx.x, gridDim.x, [&](int col) { return x[col]; },
-        [&](int) { return T(0); },
+        sm, desc, vals, blockIdx.x, gridDim.x, [&](int col) { return x[col]; }, [&](int) { return T(0); },
         [&](int row, T val, T) {
             y[row] = val;
             return 0.0;
@@ -287,11 +299,11 @@ template <class T>
 hipError_t spmv_dispatch(const DevMesh &m, hipStream_t s, const T *v, const T *x, T *y)
 {
     if (spmv_vec_ok(v, m.nnz))
-        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.nnz,
-                           m.spmv_desc, m.spmv_roff, m.spmv_nrb, x, y);
+        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+                           (const int4 *)m.spmv_desc, v, x, y);
     else
-        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, v, m.nnz,
-                           m.spmv_desc, m.spmv_roff, m.spmv_nrb, x, y);
+        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+                           (const int4 *)m.spmv_desc, v, x, y);
     return hipGetLastError();
 }
 
@@ -438,17 +450,17 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
 
 // Iteration k, first step: q = A p and the partial p . q.
 template <class T, bool VEC>
-__device__ inline void cg_spmv_pq_step(const int32_t *__restrict__ colidx, const T *__restrict__ vals, int64_t nnz,
-                                       const int2 *__restrict__ desc, const uint16_t *__restrict__ roff,
-                                       int64_t nrb, const T *__restrict__ p, T *__restrict__ q,
-                                       double *__restrict__ part, const int32_t *flags, int wg, int G)
+__device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
+                                       const T *__restrict__ p,
+                                       T *__restrict__ q, double *__restrict__ part, const int32_t *flags, int wg,
+                                       int G)
 {
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
     if (wg_done(flags)) return;
     double acc = spmv_stream<T, VEC>(
-        colidx, vals, nnz, desc, roff, nrb, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
+        sm, desc, vals, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
         [&](int row, T val, T prow) {
             q[row] = val;
             return (double)prow * (double)val;
@@ -553,13 +565,11 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
 }
 
 template <class T, bool VEC>
-__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(const int32_t *__restrict__ colidx, const T *__restrict__ vals,
-                                                    int64_t nnz, const int2 *__restrict__ desc,
-                                                    const uint16_t *__restrict__ roff, int64_t nrb,
-                                                    const T *__restrict__ p, T *__restrict__ q,
-                                                    double *__restrict__ part, const int32_t *flags)
+__global__ void __launch_bounds__(kTB) k_cg_spmv_pq(SpmvMap sm, const int4 *__restrict__ desc,
+                                                    const T *__restrict__ vals, const T *__restrict__ p,
+                                                    T *__restrict__ q, double *__restrict__ part, const int32_t *flags)
 {
-    cg_spmv_pq_step<T, VEC>(colidx, vals, nnz, desc, roff, nrb, p, q, part, flags, blockIdx.x, gridDim.x);
+    cg_spmv_pq_step<T, VEC>(sm, desc, vals, p, q, part, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
@@ -593,11 +603,9 @@ __global__ void __launch_bounds__(kTB) k_bat_spmv_pq(const BatchJob *__restrict_
     const BatchJob &b = jobs[L.slot[j]];
     const int wg = blockIdx.x - L.wgs[j], G = L.wgs[j + 1] - L.wgs[j];
     if (b.vec)
-        cg_spmv_pq_step<double, true>(b.colidx, b.vals, b.nnz, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags, wg,
-                                      G);
+        cg_spmv_pq_step<double, true>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
     else
-        cg_spmv_pq_step<double, false>(b.colidx, b.vals, b.nnz, b.desc, b.roff, b.nrb, b.p, b.q, b.part, b.flags,
-                                       wg, G);
+        cg_spmv_pq_step<double, false>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
 }
 
 __global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restrict__ jobs, BatchList L)
@@ -748,11 +756,11 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     if (spmv_vec_ok(vals, m.nnz))
-        hipLaunchKernelGGL((k_cg_spmv_pq<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx, vals,
-                           m.nnz, m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+                           (const int4 *)m.spmv_desc, vals, p, q, w.part, w.flags);
     else
-        hipLaunchKernelGGL((k_cg_spmv_pq<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, m.colidx,
-                           vals, m.nnz, m.spmv_desc, m.spmv_roff, m.spmv_nrb, p, q, w.part, w.flags);
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+                           (const int4 *)m.spmv_desc, vals, p, q, w.part, w.flags);
     return hipGetLastError();
 }
 

@@ -238,12 +238,31 @@ def test_spmv_dot_axpy_parity(fe_ctx):
     assert fe.dot(fe_ctx, dev(np.zeros(0)), dev(np.zeros(0))) == 0.0
 
 
+def _spmv_block_spans(mesh):
+    """Column span of every SpMV row block (<= 64 rows, <= 1021 nonzeros),
+    computed from the pattern the library exposes."""
+    rp, ci = mesh.pattern_host()
+    rp = rp.astype(np.int64)
+    n = len(rp) - 1
+    spans, r = [], 0
+    while r < n:
+        r1 = r + 1
+        while r1 < n and r1 - r < 64 and rp[r1 + 1] - rp[r] <= 1021:
+            r1 += 1
+        c = ci[rp[r]:rp[r1]]
+        spans.append(int(c.max()) - int(c.min()))
+        r = r1
+    return np.array(spans)
+
+
 @pytest.mark.parametrize("etype,n", [(meshgen.HEX08, 8), (meshgen.HEX08, 10), (meshgen.TET04, 3),
-                                     (meshgen.HEX08, 9)])
+                                     (meshgen.HEX08, 9), (meshgen.HEX08, 48)])
 def test_spmv_load_forms_agree(fe_ctx, etype, n):
-    """16-byte loads (aligned values) and one-entry loads (values offset by 8
-    bytes) give bitwise the same y; nnz % 4 = 1, 3, 2, 0 exercises the
-    end-of-array handling of the 16-byte form."""
+    """16-byte loads (aligned values, packed column indices) and one-entry
+    loads (values offset by 8 bytes, plain column indices) give bitwise the
+    same y; nnz % 4 = 1, 3, 2, 0 exercises the end-of-array handling of the
+    16-byte form, and the 48^3 mesh has both 16-bit ("narrow") and 32-bit
+    ("wide") column-index blocks."""
     fe = _fe()
     import torch
     case = meshgen.make_case(n, etype, 0.1, case_id=53, shuffle=True)
@@ -260,7 +279,11 @@ def test_spmv_load_forms_agree(fe_ctx, etype, n):
     assert torch.equal(ya, ym)
     rp, ci, V, _ = oracle_assemble(case, MOM)
     yr = oracle.spmv(rp, ci, V[0], rhs_user(mesh, host(x)))
-    print(etype, n, "nnz % 4 =", nnz % 4, flush=True)
+    spans = _spmv_block_spans(mesh)
+    wide = float(np.mean(spans > 65535))
+    print(etype, n, "nnz % 4 =", nnz % 4, "wide blocks", wide, flush=True)
+    if n == 48:
+        assert 0.0 < wide < 1.0
     assert rel(rhs_user(mesh, host(ya)), yr) <= 1e-13
 
 
