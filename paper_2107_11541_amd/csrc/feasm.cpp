@@ -271,6 +271,10 @@ static void mesh_free_ptr(fe_mesh_s *m, void *p)
 
 void mesh_release(fe_mesh_s *m)
 {
+    for (auto &g : m->graph) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = fe_mesh_s::PcgGraph();
+    }
     for (void *p : m->allocs) {
         if (m->arena) m->arena->release(p);
         else (void)hipFree(p);
@@ -409,8 +413,47 @@ fe_status sync(fe_ctx_s *c)
     return FE_OK;
 }
 
+// Iterations recorded per PCG graph.  A graph replays them with no launch
+// argument depending on the iteration (the kernels keep the iteration index
+// on the device), so one recording serves every run of the same system.
+constexpr int kGraphIters = 8;
+
+template <class T>
+fe_status pcg_graph_launch(fe_mesh_s *m, const T *vals, T *x)
+{
+    fe_ctx_s *c = m->ctx;
+    fe_mesh_s::PcgGraph &g = m->graph[sizeof(T) == 4 ? 1 : 0];
+    if (!(g.exec && g.vals == vals && g.x == x && g.hist == m->cg.hist)) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = fe_mesh_s::PcgGraph();
+        hipGraph_t graph = nullptr;
+        HIPCALL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < kGraphIters && e == hipSuccess; ++i) {
+            e = cg_spmv_pq<T>(m->dm, vals, m->cg, 0, c->cap_stream);
+            if (e == hipSuccess) e = cg_updates<T>(m->dm, x, m->cg, 0, c->cap_stream);
+        }
+        const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g = fe_mesh_s::PcgGraph();
+            return fail(c, FE_EDEVICE, "recording the PCG graph: %s", hipGetErrorString(e));
+        }
+        g.vals = vals;
+        g.x = x;
+        g.hist = m->cg.hist;
+    }
+    HIPCALL(c, hipGraphLaunch(g.exec, c->stream));
+    return FE_OK;
+}
+
 // Run FP64 or FP32 PCG iterations until the device flag says done or
 // max_iter is reached.  Returns the flags word (done, status, iterations).
+// Unless the context is profiling (which brackets single launches with
+// events), runs of kGraphIters iterations go through a recorded graph; the
+// stop flag is polled on a growing schedule as before.
 template <class T>
 fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, int max_iter, bool x_zero,
                   int32_t flags_out[4])
@@ -418,25 +461,33 @@ fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, in
     fe_ctx_s *c = m->ctx;
     CGWork &w = m->cg;
     HIPCALL(c, cg_setup<T>(m->dm, vals, b, x, w, rtol, c->stream, x_zero));
+    const bool graphs = !c->profiling && c->cap_stream != nullptr;
     int k = 0;
     int next_poll = 8;
     int32_t *hf = (int32_t *)c->host;
     while (k < max_iter) {
-        {
-            ProfScope ps(c, 0);
-            HIPCALL(c, cg_spmv_pq<T>(m->dm, vals, w, k, c->stream));
+        if (graphs && k + kGraphIters <= max_iter && (rtol <= 0.0 || k + kGraphIters <= next_poll)) {
+            fe_status s = pcg_graph_launch<T>(m, vals, x);
+            if (s != FE_OK) return s;
+            k += kGraphIters;
+        } else {
+            {
+                ProfScope ps(c, 0);
+                HIPCALL(c, cg_spmv_pq<T>(m->dm, vals, w, k, c->stream));
+            }
+            {
+                ProfScope ps(c, 2);
+                HIPCALL(c, cg_updates<T>(m->dm, x, w, k, c->stream));
+            }
+            ++k;
         }
-        {
-            ProfScope ps(c, 2);
-            HIPCALL(c, cg_updates<T>(m->dm, x, w, k, c->stream));
-        }
-        ++k;
         if (rtol > 0.0 && (k == next_poll || k == max_iter)) {
             HIPCALL(c, hipMemcpyAsync(hf, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
             fe_status s = sync(c);
             if (s != FE_OK) return s;
             if (hf[0]) break;
             next_poll = k + std::max(8, k / 4);
+            if (graphs) next_poll = (next_poll + kGraphIters - 1) / kGraphIters * kGraphIters;
         }
     }
     HIPCALL(c, hipMemcpyAsync(hf, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -465,9 +516,11 @@ fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out)
     c->stream = (hipStream_t)hip_stream;
     if (hipMalloc((void **)&c->scratch, (1024 + 64) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (c->scratch) (void)hipFree(c->scratch);
         delete c;
         return FE_ENOMEM;
     }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->cap_stream = nullptr;
     *out = c;
     return FE_OK;
 }
@@ -480,6 +533,7 @@ void fe_ctx_destroy(fe_ctx c)
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->host) (void)hipHostFree(c->host);
     while (!c->meshes.empty()) fe_mesh_free(c->meshes.back());
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &p : c->prof)
         for (auto e : p.ev) (void)hipEventDestroy(e);
     delete c;

@@ -42,6 +42,7 @@ struct ProfSlot {
 struct fe_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream that PCG graphs are recorded on (never run on)
     std::string err;
     double *scratch = nullptr;    // 1024 partials + 8 results
     double *host = nullptr;       // pinned read-back area (64 doubles)
@@ -60,6 +61,12 @@ struct fe_mesh_s {
     feasm::CGWork cg;
     feasm::DevArena *arena = nullptr;    // device memory source (nullptr: hipMalloc)
     bool listed = true;                  // in ctx->meshes (freed with the context)
+    // recorded PCG iterations (FP64, FP32), valid for the pointers they were
+    // recorded with
+    struct PcgGraph {
+        hipGraphExec_t exec = nullptr;
+        const void *vals = nullptr, *x = nullptr, *hist = nullptr;
+    } graph[2];
 };
 
 namespace feasm {

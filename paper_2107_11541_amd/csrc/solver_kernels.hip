@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
         flags[0] = (rr <= thr2) ? 1 : 0;
         flags[1] = FE_OK;
         flags[2] = 0;
-        flags[3] = 0;
+        flags[3] = -1;   // iteration counter: each SpMV launch advances it
     }
 }
 
@@ -564,26 +564,34 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
     if ((n & 1) && wg == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
 }
 
+// The one-system kernels take the iteration index from the device
+// (flags[3]): the SpMV launch of iteration k advances it from k - 1 to k,
+// and the two updates, which run after it, read it.  No launch argument
+// changes from one iteration to the next, so a run of iterations can be
+// recorded once as a HIP graph and replayed.
 template <class T, bool VEC>
 __global__ void __launch_bounds__(kTB) k_cg_spmv_pq(SpmvMap sm, const int4 *__restrict__ desc,
                                                     const T *__restrict__ vals, const T *__restrict__ p,
-                                                    T *__restrict__ q, double *__restrict__ part, const int32_t *flags)
+                                                    T *__restrict__ q, double *__restrict__ part, int32_t *flags)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_flag(flags + 3, load_flag(flags + 3) + 1);
     cg_spmv_pq_step<T, VEC>(sm, desc, vals, p, q, part, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q,
+__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, T *x, T *r, T *z, const T *p, const T *q,
                                                       const T *dinv, double *part, int nb_spmv, double *hist,
                                                       int32_t *flags)
 {
+    const int k = load_flag(flags + 3);
     cg_update_xr_step<T>(n, k, x, r, z, p, q, dinv, part, nb_spmv, hist, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, int k, const T *z, T *p, double *part, int nb,
-                                                     double *hist, const double *scal, int32_t *flags)
+__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, const T *z, T *p, double *part, int nb, double *hist,
+                                                     const double *scal, int32_t *flags)
 {
+    const int k = load_flag(flags + 3);
     cg_update_p_step<T>(n, k, z, p, part, nb, hist, scal, flags, blockIdx.x, gridDim.x);
 }
 
@@ -773,9 +781,9 @@ hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s)
     T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
-    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, k, x, r, z, (const T *)p, (const T *)q,
+    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, x, r, z, (const T *)p, (const T *)q,
                        (const T *)dinv, w.part, spmv_blocks(m.spmv_nrb), w.hist, w.flags);
-    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, k, (const T *)z, p, w.part, w.nb, w.hist,
+    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, (const T *)z, p, w.part, w.nb, w.hist,
                        (const double *)(w.hist + 4 * w.hist_cap), w.flags);
     return hipGetLastError();
 }

@@ -287,6 +287,35 @@ def test_spmv_load_forms_agree(fe_ctx, etype, n):
     assert rel(rhs_user(mesh, host(ya)), yr) <= 1e-13
 
 
+def test_pcg_graph_replays_match_eager_launches(fe_ctx):
+    """Runs of 8 PCG iterations are replayed from a recorded HIP graph; with
+    profiling on, every kernel is launched on its own.  Each replayed solve,
+    with eager library work and synchronisations in between, must give
+    bitwise the eager result (fixed and converged iteration counts)."""
+    fe = _fe()
+    import torch
+    case = meshgen.make_case(11, meshgen.HEX08, 0.12, case_id=54, shuffle=True)
+    mesh, L, f = poisson_gpu(fe_ctx, case)
+    results = {}
+    for mode in ("eager", "graph", "graph", "graph"):
+        fe_ctx.profile(mode == "eager")
+        for rtol, iters in ((0.0, 40), (1e-9, 2000)):
+            x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+            x, info = fe.cg_solve(mesh, L, f, x=x, rtol=rtol, max_iter=iters)
+            key = (rtol, iters)
+            if mode == "eager":
+                results[key] = (host(x), info["iterations"])
+            else:
+                assert np.array_equal(host(x), results[key][0]), key
+                assert info["iterations"] == results[key][1], key
+        # unrelated eager work between replays
+        y = fe.spmv(mesh, L, f)
+        fe.dot(fe_ctx, y, y)
+        torch.cuda.synchronize()
+    fe_ctx.profile(False)
+    assert results[(0.0, 40)][1] == 40
+
+
 def test_pcg_cfg0_matches_direct_solve(fe_ctx):
     fe = _fe()
     case = meshgen.cfg0()
