@@ -111,8 +111,10 @@ class Context:
             self.lib.fe_ctx_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable while module globals
+        # are torn down at interpreter exit
+        if _finalizing():
             return
         try:
             self.close()
@@ -184,8 +186,10 @@ class Mesh:
             self.ctx.lib.fe_mesh_free(self.h)
         self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable while module globals
+        # are torn down at interpreter exit
+        if _finalizing():
             return
         try:
             self.close()
@@ -372,8 +376,10 @@ class Server:
             self.h = None
             self._pending.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable while module globals
+        # are torn down at interpreter exit
+        if _finalizing():
             return
         try:
             self.close()
