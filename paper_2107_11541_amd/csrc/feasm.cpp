@@ -514,7 +514,7 @@ fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out)
     auto *c = new fe_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    if (hipMalloc((void **)&c->scratch, (1024 + 64) * sizeof(double)) != hipSuccess ||
+    if (hipMalloc((void **)&c->scratch, (2048 + 64) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         if (c->scratch) (void)hipFree(c->scratch);
         delete c;
@@ -700,8 +700,8 @@ fe_status fe_dot(fe_ctx c, int64_t n, const double *x, const double *y, double *
         *out = 0.0;
         return FE_OK;
     }
-    HIPCALL(c, launch_dot(n, x, y, c->scratch, c->scratch + 1024, c->stream));
-    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(c, launch_dot(n, x, y, c->scratch, c->scratch + 2048, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 2048, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     fe_status s = sync(c);
     if (s != FE_OK) return s;
     *out = c->host[0];
@@ -753,8 +753,8 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
         double rel = 0.0;
         result = FE_ENOCONV;
         for (outer = 0; outer < 64; ++outer) {
-            HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 1024, c->stream));
-            HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, 2 * sizeof(double), hipMemcpyDeviceToHost,
+            HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 2048, c->stream));
+            HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 2048, 2 * sizeof(double), hipMemcpyDeviceToHost,
                                       c->stream));
             if ((s = sync(c)) != FE_OK) return s;
             const double rr = c->host[0], bb = c->host[1];
@@ -784,8 +784,8 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
         inf.rel_residual = rel;
     }
     // true residual in FP64
-    HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 1024, c->stream));
-    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 1024, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 2048, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 2048, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if ((s = sync(c)) != FE_OK) return s;
     inf.true_rel_residual = c->host[1] > 0 ? std::sqrt(c->host[0] / c->host[1]) : std::sqrt(c->host[0]);
     if (info) *info = inf;

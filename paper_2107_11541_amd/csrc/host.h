@@ -44,7 +44,7 @@ struct fe_ctx_s {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream that PCG graphs are recorded on (never run on)
     std::string err;
-    double *scratch = nullptr;    // 1024 partials + 8 results
+    double *scratch = nullptr;    // 2048 partials + 64 results
     double *host = nullptr;       // pinned read-back area (64 doubles)
     bool profiling = false;
     std::vector<fe_mesh_s *> meshes;   // live meshes, freed by fe_ctx_destroy

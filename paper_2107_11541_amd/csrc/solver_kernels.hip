@@ -27,7 +27,7 @@ int stream_blocks(int64_t n)
 {
     int64_t b = (n + 255) / 256;
     if (b < 1) b = 1;
-    if (b > 1024) b = 1024;
+    if (b > 1024) b = 1024;   // 2048 groups measured slower (re-reducing twice the partials)
     return (int)b;
 }
 
@@ -39,7 +39,7 @@ template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 // Partial-sum buffer layout (doubles): SpMV p.q partials, then r.z, r.r, b.b.
 constexpr int kMaxParts = 2048;
-constexpr int kPartPQ = 0, kPartRZ = 2048, kPartRR = 3072, kPartBB = 4096;
+constexpr int kPartPQ = 0, kPartRZ = 2048, kPartRR = 4096, kPartBB = 6144;
 
 // Work-group sum with a fixed pattern: wave butterfly, then waves in order.
 __device__ inline double wg_sum(double v, double *sh)
@@ -477,6 +477,21 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
                                          double *part, int nb_spmv, double *hist, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
+    // two entries per thread and item (16-byte accesses for FP64); each
+    // item's operands are requested one item ahead, the first ones before
+    // the scalar reduction, so that their latency overlaps it
+    using T2 = typename Vec2<T>::type;
+    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
+    int64_t j = (int64_t)wg * kTB + threadIdx.x;
+    T2 xv{}, pv{}, qv{}, dv{}, rv{};
+    auto load = [&](int64_t i, T2 &xo, T2 &po, T2 &qo, T2 &d_o, T2 &ro) {
+        xo = ((const T2 *)x)[i];
+        po = ((const T2 *)p)[i];
+        qo = ((const T2 *)q)[i];
+        d_o = ((const T2 *)dinv)[i];
+        ro = ((const T2 *)r)[i];
+    };
+    if (n2 > 0) load(j < n2 ? j : 0, xv, pv, qv, dv, rv);
     if (wg_done(flags)) return;
     const double pq = reduce_parts(part + kPartPQ, nb_spmv, sh);
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -490,13 +505,10 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
     const double alpha = hist[(int64_t)k * 4 + 0] / pq;
     const T a = T(alpha);
     double rz = 0.0, rr = 0.0;
-    // two entries per thread and step (16-byte accesses for FP64)
-    using T2 = typename Vec2<T>::type;
-    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
-    for (int64_t j = (int64_t)wg * kTB + threadIdx.x; j < n2; j += stride) {
-        T2 xv = ((T2 *)x)[j];
-        const T2 pv = ((const T2 *)p)[j], qv = ((const T2 *)q)[j], dv = ((const T2 *)dinv)[j];
-        T2 rv = ((T2 *)r)[j];
+    for (; j < n2; j += stride) {
+        const int64_t jn = j + stride < n2 ? j + stride : j;
+        T2 nx, np, nq, nd, nr;
+        load(jn, nx, np, nq, nd, nr);
         xv.x += a * pv.x;
         xv.y += a * pv.y;
         rv.x -= a * qv.x;
@@ -509,6 +521,11 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
         ((T2 *)z)[j] = zv;
         rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
         rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+        xv = nx;
+        pv = np;
+        qv = nq;
+        dv = nd;
+        rv = nr;
     }
     if ((n & 1) && wg == 0 && threadIdx.x == 0) {
         const int64_t i = n - 1;
@@ -540,6 +557,15 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
                                         const double *scal, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
+    using T2 = typename Vec2<T>::type;
+    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
+    int64_t j = (int64_t)wg * kTB + threadIdx.x;
+    T2 zv{}, pv{};
+    if (n2 > 0) {
+        const int64_t j0 = j < n2 ? j : 0;
+        zv = ((const T2 *)z)[j0];
+        pv = ((const T2 *)p)[j0];
+    }
     if (wg_done(flags)) return;
     const double rz1 = reduce_parts(part + kPartRZ, nb, sh);
     const double rr = reduce_parts(part + kPartRR, nb, sh);
@@ -552,14 +578,14 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
     }
     if (conv) return;
     const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
-    using T2 = typename Vec2<T>::type;
-    const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
-    for (int64_t j = (int64_t)wg * kTB + threadIdx.x; j < n2; j += stride) {
-        const T2 zv = ((const T2 *)z)[j];
-        T2 pv = ((T2 *)p)[j];
+    for (; j < n2; j += stride) {
+        const int64_t jn = j + stride < n2 ? j + stride : j;
+        const T2 nz = ((const T2 *)z)[jn], np = ((const T2 *)p)[jn];
         pv.x = zv.x + beta * pv.x;
         pv.y = zv.y + beta * pv.y;
         ((T2 *)p)[j] = pv;
+        zv = nz;
+        pv = np;
     }
     if ((n & 1) && wg == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
 }
