@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hex128")
-    ap.add_argument("--cpu-sample-n", type=int, default=80)
+    ap.add_argument("--cpu-sample-n", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cfg4-n", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=200)
