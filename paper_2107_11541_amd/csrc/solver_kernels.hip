@@ -144,9 +144,13 @@ __device__ inline void load_quad(const float *__restrict__ v, int64_t e, int64_t
 // wg / G: this group's index and the number of groups working on the matrix
 // (G a multiple of kXcds, and wg % kXcds the group's XCD).  nnz: entries of
 // vals (the 16-byte path needs nnz >= 4).
+// done_flags (may be null): a solve's flag word; a group returns right
+// after issuing its first block's loads when the solve has already stopped
+// (checked there so that the check's latency overlaps those loads).
 template <class T, bool VEC, class XF, class WF, class YF>
 __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
-                                     int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps)
+                                     int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps,
+                                     const int32_t *done_flags = nullptr)
 {
     const uint16_t *__restrict__ roff = sm.roff;
     const int64_t nrb = sm.nrb, nnz = sm.nnz;
@@ -211,6 +215,7 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
     };
     auto pos = [&](int j) { return VEC ? 4 * tid + j : tid + 256 * j; };
     fetch(blk, desc[blk], desc[blk + 1], true);
+    if (done_flags && wg_done(done_flags)) return acc;
     const int row = tid / kTPR, sub = tid % kTPR;
     for (;;) {
         const int cr0 = r0, cn = nrows, cnz = nz, csh = shift;
@@ -458,14 +463,13 @@ __device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict
     __shared__ T prod[kStreamNnz];
     __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
-    if (wg_done(flags)) return;
     double acc = spmv_stream<T, VEC>(
         sm, desc, vals, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
         [&](int row, T val, T prow) {
             q[row] = val;
             return (double)prow * (double)val;
         },
-        prod, rps);
+        prod, rps, flags);
     acc = wg_sum(acc, sh);
     if (threadIdx.x == 0) part[kPartPQ + wg] = acc;
 }
