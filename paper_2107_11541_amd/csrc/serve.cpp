@@ -247,6 +247,7 @@ fe_status admit(fe_server_s *S, Job *j)
     b.vals = j->vals_p;
     b.n = N;
     b.vec = spmv_vec_capable(j->vals_p, nnz) ? 1 : 0;
+    if (!b.vec) return fail(c, FE_EINVAL, "internal: arena value array not 16-byte aligned");
     b.x = j->x_d;
     b.r = w.r;
     b.z = w.z;

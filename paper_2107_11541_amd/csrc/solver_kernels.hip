@@ -640,10 +640,9 @@ __global__ void __launch_bounds__(kTB) k_bat_spmv_pq(const BatchJob *__restrict_
     const int j = batch_find(L.wgs, L.n, blockIdx.x);
     const BatchJob &b = jobs[L.slot[j]];
     const int wg = blockIdx.x - L.wgs[j], G = L.wgs[j + 1] - L.wgs[j];
-    if (b.vec)
-        cg_spmv_pq_step<double, true>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
-    else
-        cg_spmv_pq_step<double, false>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
+    // the serving arena keeps every value array 256-byte aligned (and every
+    // mesh has nnz >= 4): the 16-byte form only
+    cg_spmv_pq_step<double, true>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
 }
 
 __global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restrict__ jobs, BatchList L)
