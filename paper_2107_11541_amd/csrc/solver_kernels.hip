@@ -9,8 +9,8 @@
 //   * SpMV streams row blocks whose nonzeros are contiguous (fixed at
 //     upload): coalesced non-temporal loads of values and column indices, the
 //     products staged in LDS, one thread per row adding them in column order;
-//   * one PCG iteration is three launches: SpMV fused with p.Ap; the x, r, z
-//     update fused with r.z and r.r; the p update with the stop test.
+//   * one PCG iteration is three launches: SpMV fused with p.Ap; the r, z
+//     update fused with r.z and r.r; the x and p updates with the stop test.
 //     (Forming z + beta p inside the SpMV gather was measured slower: two
 //     gathered vectors cost more than the separate streaming update.)
 //     Instead of a separate
@@ -474,11 +474,12 @@ __device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict
     if (threadIdx.x == 0) part[kPartPQ + wg] = acc;
 }
 
-// Iteration k, second step: alpha = rz_k / (p . q); x += alpha p;
-// r -= alpha q; z = D^-1 r; partials of r.z and r.r.
+// Iteration k, second step: alpha = rz_k / (p . q); r -= alpha q;
+// z = D^-1 r; partials of r.z and r.r.  (x += alpha p is left to the third
+// step, which reads p anyway: the same arithmetic, one vector pass less.)
 template <class T>
-__device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, const T *p, const T *q, const T *dinv,
-                                         double *part, int nb_spmv, double *hist, int32_t *flags, int wg, int G)
+__device__ inline void cg_update_xr_step(int64_t n, int k, T *r, T *z, const T *q, const T *dinv, double *part,
+                                         int nb_spmv, double *hist, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
     // two entries per thread and item (16-byte accesses for FP64); each
@@ -487,15 +488,13 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
     using T2 = typename Vec2<T>::type;
     const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
     int64_t j = (int64_t)wg * kTB + threadIdx.x;
-    T2 xv{}, pv{}, qv{}, dv{}, rv{};
-    auto load = [&](int64_t i, T2 &xo, T2 &po, T2 &qo, T2 &d_o, T2 &ro) {
-        xo = ((const T2 *)x)[i];
-        po = ((const T2 *)p)[i];
-        qo = ((const T2 *)q)[i];
-        d_o = ((const T2 *)dinv)[i];
-        ro = ((const T2 *)r)[i];
-    };
-    if (n2 > 0) load(j < n2 ? j : 0, xv, pv, qv, dv, rv);
+    T2 qv{}, dv{}, rv{};
+    if (n2 > 0) {
+        const int64_t j0 = j < n2 ? j : 0;
+        qv = ((const T2 *)q)[j0];
+        dv = ((const T2 *)dinv)[j0];
+        rv = ((const T2 *)r)[j0];
+    }
     if (wg_done(flags)) return;
     const double pq = reduce_parts(part + kPartPQ, nb_spmv, sh);
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -511,29 +510,22 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
     double rz = 0.0, rr = 0.0;
     for (; j < n2; j += stride) {
         const int64_t jn = j + stride < n2 ? j + stride : j;
-        T2 nx, np, nq, nd, nr;
-        load(jn, nx, np, nq, nd, nr);
-        xv.x += a * pv.x;
-        xv.y += a * pv.y;
+        const T2 nq = ((const T2 *)q)[jn], nd = ((const T2 *)dinv)[jn], nr = ((const T2 *)r)[jn];
         rv.x -= a * qv.x;
         rv.y -= a * qv.y;
         T2 zv;
         zv.x = dv.x * rv.x;
         zv.y = dv.y * rv.y;
-        ((T2 *)x)[j] = xv;
         ((T2 *)r)[j] = rv;
         ((T2 *)z)[j] = zv;
         rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
         rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
-        xv = nx;
-        pv = np;
         qv = nq;
         dv = nd;
         rv = nr;
     }
     if ((n & 1) && wg == 0 && threadIdx.x == 0) {
         const int64_t i = n - 1;
-        x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
         const T zi = dinv[i] * ri;
         r[i] = ri;
@@ -554,21 +546,23 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *x, T *r, T *z, con
 }
 
 // Iteration k, third step: every work-group reduces the r.z and r.r
-// partials (same order, same result); ||r||^2 <= rtol^2 ||b||^2 ends the
-// solve, else beta = rz_{k+1} / rz_k and p = z + beta p.
+// partials (same order, same result); x += alpha_k p_k; then
+// ||r||^2 <= rtol^2 ||b||^2 ends the solve, else beta = rz_{k+1} / rz_k and
+// p = z + beta p.
 template <class T>
-__device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, double *part, int nb, double *hist,
+__device__ inline void cg_update_p_step(int64_t n, int k, T *x, const T *z, T *p, double *part, int nb, double *hist,
                                         const double *scal, int32_t *flags, int wg, int G)
 {
     __shared__ double sh[4];
     using T2 = typename Vec2<T>::type;
     const int64_t n2 = n / 2, stride = (int64_t)G * kTB;
     int64_t j = (int64_t)wg * kTB + threadIdx.x;
-    T2 zv{}, pv{};
+    T2 zv{}, pv{}, xv{};
     if (n2 > 0) {
         const int64_t j0 = j < n2 ? j : 0;
         zv = ((const T2 *)z)[j0];
         pv = ((const T2 *)p)[j0];
+        xv = ((const T2 *)x)[j0];
     }
     if (wg_done(flags)) return;
     const double rz1 = reduce_parts(part + kPartRZ, nb, sh);
@@ -580,18 +574,27 @@ __device__ inline void cg_update_p_step(int64_t n, int k, const T *z, T *p, doub
         store_flag(flags + 2, k + 1);
         if (conv) store_flag(flags + 0, 1);
     }
-    if (conv) return;
+    const T a = T(hist[(int64_t)k * 4 + 3]);
     const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
     for (; j < n2; j += stride) {
         const int64_t jn = j + stride < n2 ? j + stride : j;
-        const T2 nz = ((const T2 *)z)[jn], np = ((const T2 *)p)[jn];
-        pv.x = zv.x + beta * pv.x;
-        pv.y = zv.y + beta * pv.y;
-        ((T2 *)p)[j] = pv;
+        const T2 nz = ((const T2 *)z)[jn], np = ((const T2 *)p)[jn], nx = ((const T2 *)x)[jn];
+        xv.x += a * pv.x;
+        xv.y += a * pv.y;
+        ((T2 *)x)[j] = xv;
+        if (!conv) {
+            pv.x = zv.x + beta * pv.x;
+            pv.y = zv.y + beta * pv.y;
+            ((T2 *)p)[j] = pv;
+        }
         zv = nz;
         pv = np;
+        xv = nx;
     }
-    if ((n & 1) && wg == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];
+    if ((n & 1) && wg == 0 && threadIdx.x == 0) {
+        x[n - 1] += a * p[n - 1];
+        if (!conv) p[n - 1] = z[n - 1] + beta * p[n - 1];
+    }
 }
 
 // The one-system kernels take the iteration index from the device
@@ -609,20 +612,19 @@ __global__ void __launch_bounds__(kTB) k_cg_spmv_pq(SpmvMap sm, const int4 *__re
 }
 
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, T *x, T *r, T *z, const T *p, const T *q,
-                                                      const T *dinv, double *part, int nb_spmv, double *hist,
-                                                      int32_t *flags)
+__global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, T *r, T *z, const T *q, const T *dinv, double *part,
+                                                      int nb_spmv, double *hist, int32_t *flags)
 {
     const int k = load_flag(flags + 3);
-    cg_update_xr_step<T>(n, k, x, r, z, p, q, dinv, part, nb_spmv, hist, flags, blockIdx.x, gridDim.x);
+    cg_update_xr_step<T>(n, k, r, z, q, dinv, part, nb_spmv, hist, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
-__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, const T *z, T *p, double *part, int nb, double *hist,
-                                                     const double *scal, int32_t *flags)
+__global__ void __launch_bounds__(kTB) k_cg_update_p(int64_t n, T *x, const T *z, T *p, double *part, int nb,
+                                                     double *hist, const double *scal, int32_t *flags)
 {
     const int k = load_flag(flags + 3);
-    cg_update_p_step<T>(n, k, z, p, part, nb, hist, scal, flags, blockIdx.x, gridDim.x);
+    cg_update_p_step<T>(n, k, x, z, p, part, nb, hist, scal, flags, blockIdx.x, gridDim.x);
 }
 
 // ---- batched PCG: one launch per step for every system of a BatchList ----
@@ -649,7 +651,7 @@ __global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restric
 {
     const int j = batch_find(L.wgv, L.n, blockIdx.x);
     const BatchJob &b = jobs[L.slot[j]];
-    cg_update_xr_step<double>(b.n, L.k[j], b.x, b.r, b.z, b.p, b.q, b.dinv, b.part, b.nb_spmv, b.hist, b.flags,
+    cg_update_xr_step<double>(b.n, L.k[j], b.r, b.z, b.q, b.dinv, b.part, b.nb_spmv, b.hist, b.flags,
                               blockIdx.x - L.wgv[j], L.wgv[j + 1] - L.wgv[j]);
 }
 
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(kTB) k_bat_update_p(const BatchJob *__restrict
 {
     const int j = batch_find(L.wgv, L.n, blockIdx.x);
     const BatchJob &b = jobs[L.slot[j]];
-    cg_update_p_step<double>(b.n, L.k[j], b.z, b.p, b.part, b.nb_vec, b.hist, b.scal, b.flags,
+    cg_update_p_step<double>(b.n, L.k[j], b.x, b.z, b.p, b.part, b.nb_vec, b.hist, b.scal, b.flags,
                              blockIdx.x - L.wgv[j], L.wgv[j + 1] - L.wgv[j]);
 }
 
@@ -810,9 +812,9 @@ hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s)
     T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
-    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, x, r, z, (const T *)p, (const T *)q,
-                       (const T *)dinv, w.part, spmv_blocks(m.spmv_nrb), w.hist, w.flags);
-    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, (const T *)z, p, w.part, w.nb, w.hist,
+    hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, r, z, (const T *)q, (const T *)dinv,
+                       w.part, spmv_blocks(m.spmv_nrb), w.hist, w.flags);
+    hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, x, (const T *)z, p, w.part, w.nb, w.hist,
                        (const double *)(w.hist + 4 * w.hist_cap), w.flags);
     return hipGetLastError();
 }
