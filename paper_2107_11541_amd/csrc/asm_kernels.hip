@@ -474,30 +474,43 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     }
 }
 
-// Reduce the per-block status into (min det, first bad mesh element).
-__global__ void __launch_bounds__(256) k_asm_status(const double *mindet, const long long *bad, int64_t n,
-                                                    AsmStatus *out)
+// Reduce the per-block status into (min det, first bad mesh element): one
+// group of 1024 threads, four independent loads in flight per thread.
+constexpr int kStatusThreads = 1024;
+__global__ void __launch_bounds__(kStatusThreads) k_asm_status(const double *mindet, const long long *bad, int64_t n,
+                                                               AsmStatus *out)
 {
-    __shared__ double sd[256];
-    __shared__ long long sb[256];
+    __shared__ double sd[kStatusThreads];
+    __shared__ long long sb[kStatusThreads];
     double md = __builtin_huge_val();
     long long b = 0x7fffffffffffffffLL;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        md = fmin(md, mindet[i]);
-        const long long v = bad[i];
-        if (v >= 0 && v < b) b = v;
+    const int64_t t = threadIdx.x;
+    for (int64_t i = t; i < n; i += 4 * kStatusThreads) {
+        double m4[4];
+        long long b4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ii = i + u * kStatusThreads;
+            m4[u] = ii < n ? mindet[ii] : __builtin_huge_val();
+            b4[u] = ii < n ? bad[ii] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            md = fmin(md, m4[u]);
+            if (b4[u] >= 0 && b4[u] < b) b = b4[u];
+        }
     }
-    sd[threadIdx.x] = md;
-    sb[threadIdx.x] = b;
+    sd[t] = md;
+    sb[t] = b;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            sd[threadIdx.x] = fmin(sd[threadIdx.x], sd[threadIdx.x + s]);
-            if (sb[threadIdx.x + s] < sb[threadIdx.x]) sb[threadIdx.x] = sb[threadIdx.x + s];
+    for (int s = kStatusThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sd[t] = fmin(sd[t], sd[t + s]);
+            if (sb[t + s] < sb[t]) sb[t] = sb[t + s];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double d = sd[0];
         unsigned long long u;
         __builtin_memcpy(&u, &d, 8);
@@ -567,7 +580,7 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     }
 #undef FE_RUN
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(256), 0, s, k.blk_mindet, k.blk_bad, m.nblk, a.status);
+    hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.nblk, a.status);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -159,7 +160,14 @@ void planner_main(fe_server_s *S)
             S->submit_q.pop_front();
             ++S->planners_busy;
         }
-        plan_job(j);
+        try {
+            plan_job(j);
+        } catch (const std::bad_alloc &) {
+            j->img.reset();
+            j->fields = std::vector<double>();
+            j->res.status = FE_ENOMEM;
+            set_message(j->res, "host memory exhausted while planning the mesh");
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
             --S->planners_busy;
@@ -214,12 +222,19 @@ fe_status admit(fe_server_s *S, Job *j)
     j->mesh = m;
     const DevMesh &d = j->img->d;
     const int64_t N = d.N, nnz = d.nnz;
+    // pinned staging for the results first: its failure is not a lack of
+    // arena space and must fail the request rather than defer it
+    if (ensure_stage(S, j->slot, (size_t)4 * N) != FE_OK) {
+        delete m;
+        j->mesh = nullptr;
+        fail(c, FE_EDEVICE, "could not allocate pinned host staging for the results");
+        return FE_EDEVICE;
+    }
     fe_status s = mesh_commit(m, *j->img, S->stream);
     if (s == FE_OK) s = ensure_cg(m, q.max_iter, false);
     double **bufs[] = {&j->vals_m, &j->rhs_m, &j->vals_p, &j->rhs_p, &j->fields_d, &j->x_d};
     const size_t sizes[] = {(size_t)nnz, (size_t)3 * N, (size_t)nnz, (size_t)N, (size_t)5 * N, (size_t)N};
     for (int b = 0; b < 6 && s == FE_OK; ++b) s = mesh_alloc(m, (void **)bufs[b], sizes[b] * sizeof(double));
-    if (s == FE_OK) s = ensure_stage(S, j->slot, (size_t)4 * N);
     if (s != FE_OK) {
         mesh_release(m);
         delete m;
