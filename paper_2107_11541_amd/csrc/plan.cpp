@@ -123,60 +123,75 @@ static void build_pattern(Plan &P)
         int32_t table[kSlots];
         uint16_t used[kSlots];
         uint8_t posv[kSlots];
-        auto slot_of = [&](int32_t v) {
-            uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
-            while (table[h] != v) h = (h + 1) & (kSlots - 1);
-            return h;
-        };
+        int32_t tmp[kSlots / 2 + 1];   // columns in first-touch order (+1: a non-fresh store at the end)
+        int32_t rank[kSlots / 2];
+        std::vector<uint16_t> hs;     // table slot of every (incident element, node)
+        std::vector<uint8_t> where;   // per incident element: bit a set where node a is the row's node
         for (int q = 0; q < kSlots; ++q) table[q] = -1;
         for (int64_t i = lo; i < hi; ++i) {
             const size_t start = out.size();
+            const int64_t deg = ip[i + 1] - ip[i];
+            if ((int64_t)hs.size() < deg * nen) {
+                hs.resize(deg * nen);
+                where.resize(deg);
+            }
             int nused = 0;
-            for (int64_t k = ip[i]; k < ip[i + 1]; ++k) {
-                const int32_t *c = &P.conn[(int64_t)inc[k] * nen];
+            for (int64_t k = 0; k < deg; ++k) {
+                const int32_t *c = &P.conn[(int64_t)inc[ip[i] + k] * nen];
+                uint32_t mk = 0;
+                for (int a = 0; a < nen; ++a) mk |= (uint32_t)(c[a] == (int32_t)i) << a;
+                where[k] = (uint8_t)mk;
                 for (int a = 0; a < nen; ++a) {
                     const int32_t v = c[a];
                     uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
                     while (table[h] != -1 && table[h] != v) h = (h + 1) & (kSlots - 1);
-                    if (table[h] == -1) {
-                        if (nused == kSlots / 2) {   // row longer than any admissible one
-                            overflow = true;
-                            continue;
-                        }
-                        table[h] = v;
-                        used[nused++] = (uint16_t)h;
-                        out.push_back(v);
+                    hs[k * nen + a] = (uint16_t)h;
+                    // branch-free insert (whether a column is new is unpredictable)
+                    const bool fresh = table[h] == -1;
+                    if (fresh & (nused == kSlots / 2)) {   // row longer than any admissible one
+                        overflow = true;
+                        continue;
                     }
+                    table[h] = v;
+                    used[nused] = (uint16_t)h;
+                    tmp[nused] = v;
+                    nused += fresh;
                 }
             }
+            const int n = nused;
+            out.resize(start + n);
             int32_t *r = out.data() + start;
-            const int n = (int)(out.size() - start);
-            for (int x = 1; x < n; ++x) {
-                const int32_t key = r[x];
-                int y = x - 1;
-                while (y >= 0 && r[y] > key) {
-                    r[y + 1] = r[y];
-                    --y;
-                }
-                r[y + 1] = key;
-            }
             len[i] = n;
             if (n <= 255) {   // longer rows are rejected by the caller
-                for (int q = 0; q < n; ++q) posv[slot_of(r[q])] = (uint8_t)q;
-                int64_t prev_e = -1;
+                // sort by rank: the columns are distinct, so the number of
+                // smaller ones is each column's position (branch-free counting)
+                for (int x = 0; x < n; ++x) {
+                    const int32_t key = tmp[x];
+                    int cnt = 0;
+                    for (int y = 0; y < n; ++y) cnt += tmp[y] < key;
+                    rank[x] = cnt;
+                }
+                for (int x = 0; x < n; ++x) {
+                    r[rank[x]] = tmp[x];
+                    posv[used[x]] = (uint8_t)rank[x];
+                }
                 int prev_a = -1;
-                for (int64_t k = ip[i]; k < ip[i + 1]; ++k) {
-                    const int64_t e = inc[k];
-                    const int32_t *c = &P.conn[e * nen];
-                    // the k-th occurrence of i in e (an element may repeat a node)
-                    int a = e == prev_e ? prev_a + 1 : 0;
-                    while (a < nen && c[a] != (int32_t)i) ++a;
-                    prev_e = e;
+                for (int64_t k = 0; k < deg; ++k) {
+                    const int64_t e = inc[ip[i] + k];
+                    // the k-th occurrence of i in e (an element may repeat a
+                    // node; its repeats are consecutive in inc)
+                    uint32_t mk = where[k];
+                    if (k > 0 && inc[ip[i] + k - 1] == e) mk &= ~((2u << prev_a) - 1);
+                    const int a = mk ? __builtin_ctz(mk) : nen;
                     prev_a = a;
                     if (a == nen) continue;
                     uint8_t *off = &P.elem_off[(size_t)e * nn2 + (size_t)a * nen];
-                    for (int q = 0; q < nen; ++q) off[q] = posv[slot_of(c[q])];
+                    const uint16_t *hk = &hs[k * nen];
+                    for (int q = 0; q < nen; ++q) off[q] = posv[hk[q]];
                 }
+            } else {
+                std::copy(tmp, tmp + n, r);
+                std::sort(r, r + n);
             }
             for (int q = 0; q < nused; ++q) table[used[q]] = -1;
         }
