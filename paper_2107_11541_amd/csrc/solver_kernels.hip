@@ -285,10 +285,13 @@ inline bool spmv_vec_ok(const T *vals, int64_t nnz)
     return ((uintptr_t)vals & 15) == 0 && nnz >= 4;
 }
 
-// Work-groups of the stream SpMV: as many as are co-resident on the device
-// (a partial second round leaves the machine idle at the tail), at most
-// kMaxParts, at most one per row block.  Fixed per device, so reductions over
-// the per-group partials keep a fixed order.
+// Work-groups of the stream SpMV: four per CU (fewer than can be
+// co-resident: on the 128^3 HEX08 Poisson matrix, 8 groups per CU took
+// 155.8 us, 4 took 152.4 us and 3, 5, 6 or 7 took 156-158.5 us; eight
+// concurrent streams per CU contend in the memory system without hiding more
+// latency), at most kMaxParts, at most one per row block.  Fixed per device,
+// so reductions over the per-group partials keep a fixed order.
+constexpr int kSpmvGroupsPerCU = 4;
 int g_spmv_resident = 0;
 
 int spmv_blocks(int64_t nrb)
@@ -712,6 +715,7 @@ hipError_t init_spmv_grid(int device)
                                                      kTB, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
+    if (per_cu > kSpmvGroupsPerCU) per_cu = kSpmvGroupsPerCU;
     g_spmv_resident = per_cu * prop.multiProcessorCount;
     return hipSuccess;
 }
