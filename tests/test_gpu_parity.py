@@ -385,10 +385,11 @@ def test_tet_pcg(fe_ctx):
 
 # --- full-size workloads, sampled rows -----------------------------------------
 
-def sampled_rows_check(ctx, case, ops, n_sample=64, seed=0):
+def sampled_rows_check(ctx, case, ops, n_sample=64, seed=0, n_scalars=1):
     fe = _fe()
     mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet)
     f = mesh_fields(mesh, case)
+    ns = min(n_scalars, case.Y.shape[0])
     rp_m, ci_m = mesh.pattern_host()
     perm = mesh.node_perm
     iperm = np.empty_like(perm)
@@ -397,10 +398,14 @@ def sampled_rows_check(ctx, case, ops, n_sample=64, seed=0):
     nodes = np.unique(rng.integers(0, case.n_nodes, n_sample))
     sc, sconn, loc, glob = submesh_rows(case, nodes)
     for op in ops:
-        v, b, _ = fe.assemble(mesh, op, case.dt, f["u"], f["rho"], f["mu"])
+        kw, okw = {}, {}
+        if op == SCA:
+            kw = {"Y": f["Y"][:ns], "D": case.D[:ns]}
+            okw = {"Y": np.ascontiguousarray(case.Y[:ns, glob]), "D": case.D[:ns]}
+        v, b, _ = fe.assemble(mesh, op, case.dt, f["u"], f["rho"], f["mu"], **kw)
         v, b = host(v)[0], host(b)
         rp, ci, V, B = oracle.assemble(sc, sconn, op, case.dt, case.u[:, glob], case.rho[glob],
-                                       case.mu[glob])
+                                       case.mu[glob], **okw)
         for i in nodes:
             li = loc[i]
             ocols = glob[ci[rp[li]:rp[li + 1]]]
@@ -423,3 +428,62 @@ def test_full_size_sampled_rows(fe_ctx, which):
     case = meshgen.cfg1() if which == "cfg1" else meshgen.cfg2()
     print(f"full-size {which}: N={case.n_nodes} E={case.n_elems}", flush=True)
     sampled_rows_check(fe_ctx, case, [MOM, POI])
+
+
+def test_full_size_cfg4_sampled_rows(fe_ctx):
+    """256^3 HEX08 with 5 species: momentum, one scalar operator and the
+    Poisson operator at full size, sampled rows against the oracle."""
+    case = meshgen.cfg4()
+    print(f"full-size cfg4: N={case.n_nodes} E={case.n_elems}", flush=True)
+    mesh = sampled_rows_check(fe_ctx, case, [MOM, SCA, POI], n_sample=48, seed=4)
+    mesh.close()
+
+
+def _pair_values(rows, cols, n):
+    """A value for every (row, column) pair of user node ids, in [-1, 1):
+    the splitmix64 finaliser of the pair index row * n + col (a counter-based
+    generator, so either side can evaluate any entry on its own)."""
+    z = (rows.astype(np.uint64) * np.uint64(n) + cols.astype(np.uint64)) + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -52) - 1.0
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_full_size_spmv_sampled_rows(fe_ctx, which):
+    """y = A x at full size through the bench's SpMV launch configuration.
+    A has the mesh's pattern and, for entry (i, j), the value of a seeded
+    counter-based function of the user ids (i, j); x is seeded.  Sampled rows
+    are checked against the definition: row i's columns are the nodes of the
+    elements that contain i, and y_i is the exactly rounded sum of
+    A_ij x_j over them."""
+    import math
+    fe = _fe()
+    case = meshgen.cfg1() if which == "cfg1" else meshgen.cfg2()
+    N = case.n_nodes
+    mesh = fe.Mesh(fe_ctx, case.nen, case.coords, case.conn, case.dirichlet)
+    rp_m, ci_m = mesh.pattern_host()
+    perm = mesh.node_perm.astype(np.int64)
+    vals = _pair_values(np.repeat(perm, np.diff(rp_m)), perm[ci_m], N)
+    rng = np.random.default_rng(11)
+    xu = rng.uniform(-1.0, 1.0, N)
+    y = host(fe.spmv(mesh, dev(vals), dev(xu[perm])))
+    del vals
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(N)
+    nodes = np.unique(rng.integers(0, N, 96))
+    nodes = np.unique(np.concatenate([nodes, [0, N - 1]]))
+    mark = np.zeros(N, bool)
+    mark[nodes] = True
+    sub = case.conn[mark[case.conn].any(axis=1)]
+    worst = 0.0
+    for i in nodes:
+        cols = np.unique(sub[(sub == i).any(axis=1)])
+        terms = _pair_values(np.full(cols.size, i), cols, N) * xu[cols]
+        ref = math.fsum(terms)
+        err = abs(y[iperm[i]] - ref) / np.abs(terms).sum()
+        worst = max(worst, err)
+    print(f"{which}: {nodes.size} rows, worst error {worst:.2e} of sum |A_ij x_j|", flush=True)
+    assert worst <= 1e-13
+    mesh.close()
