@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 vector
+FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 vector
 CG_ITERS = 200
 
 
@@ -38,6 +40,63 @@ def log(msg):
 def spmv_bytes(nnz, n):
     # values 8 + colidx 4 per entry; rowptr 4 + x 8 + y 8 per row
     return 12 * nnz + 20 * n
+
+
+def measured_valu(workload):
+    """FP64/FP32 flops per element of the assembly kernels from the committed
+    VALU-counter summary, or None once the assembly sources have changed since
+    the counters were taken (or for another workload)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_assemble_hex128_valu.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = {}
+    for ln in text.splitlines():
+        ln = ln.strip()
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("valu_workload") != workload:
+        return None
+    h = hashlib.sha256()
+    for rel in ("asm_kernels.hip", "internal.h", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_2107_11541_amd", "csrc", rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != kv.get("valu_source_sha256"):
+        return None
+    keys = ("momentum_fp64_flops_per_element", "poisson_fp64_flops_per_element",
+            "mixed_momentum_fp64_flops_per_element", "mixed_momentum_fp32_flops_per_element",
+            "momentum_hbm_bytes_per_operator", "poisson_hbm_bytes_per_operator")
+    return {k: float(kv[k]) for k in keys}
+
+
+def assembly_roofline(workload, E, ms_mom, ms_poi, ms_mix):
+    """Assembly against both rooflines: FLOP rates against the FP64 / FP32
+    vector peaks and real HBM rates against 8 TB/s, from the counted flops
+    per element and HBM bytes per operator and this run's assembly times
+    (None when the counters do not describe the kernels as built)."""
+    f = measured_valu(workload)
+    if f is None:
+        return None
+    def rate(flops, ms):
+        return flops * E / (ms * 1e-3) / 1e12
+    mom = rate(f["momentum_fp64_flops_per_element"], ms_mom)
+    poi = rate(f["poisson_fp64_flops_per_element"], ms_poi)
+    m64 = rate(f["mixed_momentum_fp64_flops_per_element"], ms_mix)
+    m32 = rate(f["mixed_momentum_fp32_flops_per_element"], ms_mix)
+    return {"unit": "TFLOP/s", "fp64_peak": FP64_PEAK_TFLOPS, "fp32_peak": FP32_PEAK_TFLOPS,
+            "counted": f,
+            "momentum_fp64": mom, "momentum_fp64_frac": mom / FP64_PEAK_TFLOPS,
+            "poisson_fp64": poi, "poisson_fp64_frac": poi / FP64_PEAK_TFLOPS,
+            "mixed_momentum_fp64": m64, "mixed_momentum_fp32": m32,
+            "mixed_momentum_frac": m64 / FP64_PEAK_TFLOPS + m32 / FP32_PEAK_TFLOPS,
+            "hbm_unit": "GB/s", "hbm_peak": HBM_PEAK_GBS,
+            "momentum_hbm_real": f["momentum_hbm_bytes_per_operator"] / (ms_mom * 1e-3) / 1e9,
+            "momentum_hbm_frac": f["momentum_hbm_bytes_per_operator"] / (ms_mom * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "poisson_hbm_real": f["poisson_hbm_bytes_per_operator"] / (ms_poi * 1e-3) / 1e9,
+            "poisson_hbm_frac": f["poisson_hbm_bytes_per_operator"] / (ms_poi * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def momentum_bytes(nnz, n, e, nen):
@@ -460,6 +519,7 @@ def main():
             "poisson_effective_gbs": poisson_bytes(nnz, N, E, mesh.nen) / (ms_poi * 1e-3) / 1e9,
             "momentum_mixed_assembly_ms": ms_mix, "momentum_mixed_melem_s": E / (ms_mix * 1e-3) / 1e6,
             "momentum_mixed_vs_fp64": mixed_err,
+            "assembly_roofline": assembly_roofline(args.workload, E, ms_mom, ms_poi, ms_mix),
             "dirichlet_ms": ms_dir / max(n_dir, 1),
             "cg_spmv_us": spmv_us, "cg_update_us": ms_upd / max(n_upd, 1) * 1e3,
             "cg_iteration_effective_gbs": (sb + 88 * N) / ((spmv_us + ms_upd / max(n_upd, 1) * 1e3) * 1e-6) / 1e9,
