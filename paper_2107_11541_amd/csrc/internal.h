@@ -105,7 +105,8 @@ constexpr int kPartDoubles = 8192;
 // is padded by kColPad zeros.
 constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024, kColPad = 4;
 int stream_blocks(int64_t n);
-// Sizes the SpMV grid to the device's co-resident work-groups (context creation).
+// Sizes the SpMV grid for the device: four work-groups per CU, at most as many
+// as are co-resident (context creation).
 hipError_t init_spmv_grid(int device);
 hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s);
 hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s);

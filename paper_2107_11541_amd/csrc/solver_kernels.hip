@@ -3,12 +3,13 @@
 // Section 5.2 of the paper: the algebraic solver is vector operations (AXPY,
 // dot; no memory reuse) plus a CSR SpMV with indirect accesses.  gfx950 form:
 //
-//   * vector kernels use a fixed grid of at most 1024 work-groups of 256
+//   * vector kernels use a fixed grid of at most 512 work-groups of 256
 //     threads, each thread walking a fixed strided subset, so every reduction
 //     has a fixed order and results are bitwise reproducible;
 //   * SpMV streams row blocks whose nonzeros are contiguous (fixed at
-//     upload): coalesced non-temporal loads of values and column indices, the
-//     products staged in LDS, one thread per row adding them in column order;
+//     upload) on four work-groups per CU: 16-byte loads of values and packed
+//     column indices, the products staged in LDS, four threads per row adding
+//     them in a fixed order;
 //   * one PCG iteration is three launches: SpMV fused with p.Ap; the r, z
 //     update fused with r.z and r.r; the x and p updates with the stop test.
 //     (Forming z + beta p inside the SpMV gather was measured slower: two
