@@ -107,7 +107,8 @@ void for_each_array(MeshImage &I, DevMesh &d, AsmStatus **status, F f)
     v(&d.elem_perm, P.elem_perm);
     v(&d.spmv_desc, I.spmv_desc);
     v(&d.spmv_roff, I.spmv_roff);
-    v(&d.spmv_cidx, I.spmv_cidx);
+    v(&d.spmv_lidx, I.spmv_lidx);
+    v(&d.spmv_cols, I.spmv_cols);
     v(&d.is_dir, I.is_dir);
     v(&d.dir_rows, I.dir_rows);
     f((void **)status, nullptr, sizeof(AsmStatus) + (size_t)d.nblk * 16);
@@ -173,54 +174,60 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
     d.n_dir = ndir;
     d.n_dir_rows = (int64_t)I.dir_rows.size();
     // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
-    // row in a 256-thread group) and <= kSpmvBlockNnz - 3 nonzeros (a
-    // 4-aligned window of kSpmvBlockNnz entries in LDS).  A single row longer
-    // than that cannot occur (rows are <= 255 entries).
+    // row in a 256-thread group), <= kSpmvBlockNnz - 3 nonzeros (a 4-aligned
+    // window of kSpmvBlockNnz entries in LDS) and <= kSpmvBlockCols distinct
+    // columns.  A single row always fits (rows are <= 255 entries).
+    // stamp[c] = the block that last counted column c; loc[c] its local index
+    std::vector<int32_t> stamp((size_t)P.N, -1), loc((size_t)P.N, 0);
     std::vector<int32_t> rb{0};
     for (int64_t r = 0; r < P.N;) {
+        const int32_t bid = (int32_t)rb.size() - 1;
+        int ncol = 0;
+        auto add_row = [&](int64_t row, bool commit) {
+            int fresh = 0;
+            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) fresh += stamp[P.colidx[q]] != bid;
+            if (!commit) return fresh;
+            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) stamp[P.colidx[q]] = bid;
+            return fresh;
+        };
+        ncol += add_row(r, true);
         int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) ++r1;
+        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3 &&
+               ncol + add_row(r1, false) <= kSpmvBlockCols) {
+            ncol += add_row(r1, true);
+            ++r1;
+        }
         rb.push_back((int32_t)r1);
         r = r1;
     }
     d.spmv_nrb = (int64_t)rb.size() - 1;
     I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int4{0, 0, 0, 0});
     I.spmv_roff.assign((size_t)(P.N + d.spmv_nrb), 0);
-    // packed column indices, block by block (16-byte aligned segments)
+    // column sets (sorted distinct columns) and one-byte local indices, block
+    // by block; each block's local indices start on a 16-byte boundary
     {
+        I.spmv_cols.clear();
         size_t bytes = 0;
-        std::vector<uint8_t> narrow((size_t)d.spmv_nrb, 0);
-        std::vector<int32_t> base((size_t)d.spmv_nrb, 0);
+        std::vector<int32_t> set;
         for (int64_t b = 0; b < d.spmv_nrb; ++b) {
             const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]];
-            int32_t lo = P.colidx[p0], hi = P.colidx[p0];
-            for (int64_t q = p0; q < p1; ++q) {
-                lo = std::min(lo, P.colidx[q]);
-                hi = std::max(hi, P.colidx[q]);
-            }
-            narrow[b] = (int64_t)hi - lo <= 65535;
-            base[b] = lo;
             const int64_t win = ((p0 & 3) + (p1 - p0) + 3) & ~(int64_t)3;
-            I.spmv_desc[b] = int4{rb[b], (int32_t)p0, (int32_t)(bytes / 16),
-                                  (int32_t)((uint32_t)lo | (narrow[b] ? 0u : 0x80000000u))};
-            bytes += (size_t)((narrow[b] ? 2 : 4) * win + 15) & ~(size_t)15;
+            set.assign(P.colidx.begin() + p0, P.colidx.begin() + p1);
+            std::sort(set.begin(), set.end());
+            set.erase(std::unique(set.begin(), set.end()), set.end());
+            I.spmv_desc[b] = int4{rb[b], (int32_t)p0, (int32_t)(bytes / 16), (int32_t)I.spmv_cols.size()};
+            I.spmv_cols.insert(I.spmv_cols.end(), set.begin(), set.end());
+            bytes += (size_t)(win + 15) & ~(size_t)15;
         }
-        I.spmv_desc[d.spmv_nrb] = int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)(bytes / 16), 0};
-        I.spmv_cidx.assign(bytes + 16, 0);
+        I.spmv_desc[d.spmv_nrb] =
+            int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)(bytes / 16), (int32_t)I.spmv_cols.size()};
+        I.spmv_lidx.assign(bytes + 16, 0);
         for (int64_t b = 0; b < d.spmv_nrb; ++b) {
             const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]], a0 = p0 & ~(int64_t)3;
-            const int64_t win = ((p0 & 3) + (p1 - p0) + 3) & ~(int64_t)3;
-            uint8_t *seg = I.spmv_cidx.data() + (size_t)I.spmv_desc[b].z * 16;
-            for (int64_t w = 0; w < win; ++w) {
-                const int64_t q = a0 + w;
-                const int32_t col = (q >= p0 && q < p1) ? P.colidx[q] : base[b];
-                if (narrow[b]) {
-                    const uint16_t off = (uint16_t)(col - base[b]);
-                    memcpy(seg + 2 * w, &off, 2);
-                } else {
-                    memcpy(seg + 4 * w, &col, 4);
-                }
-            }
+            const int32_t c0 = I.spmv_desc[b].w, c1 = I.spmv_desc[b + 1].w;
+            for (int32_t k = c0; k < c1; ++k) loc[I.spmv_cols[k]] = k - c0;
+            uint8_t *seg = I.spmv_lidx.data() + (size_t)I.spmv_desc[b].z * 16;
+            for (int64_t q = p0; q < p1; ++q) seg[q - a0] = (uint8_t)loc[P.colidx[q]];
         }
     }
     for (int64_t b = 0; b < d.spmv_nrb; ++b)

@@ -87,7 +87,8 @@ struct MeshImage {
     std::vector<int32_t> dir_rows;
     std::vector<int4> spmv_desc;
     std::vector<uint16_t> spmv_roff;
-    std::vector<uint8_t> spmv_cidx;
+    std::vector<uint8_t> spmv_lidx;
+    std::vector<int32_t> spmv_cols;
     DevMesh d;                 // sizes filled, device pointers null
     // Device bytes of the mesh arrays (256-byte granules), without CG work.
     size_t device_bytes() const;

@@ -34,32 +34,36 @@ struct DevMesh {
     int32_t *dir_rows = nullptr;        // rows touched by the Dirichlet elimination
     int64_t n_dir = 0, n_dir_rows = 0;
     // SpMV row blocks (see kSpmvBlockRows): desc[b] = {first row, first
-    // nonzero, index segment offset in 16-byte units, base column | wide <<
-    // 31}, b = 0..nrb (the last is the end sentinel); roff holds each block's
-    // row offsets relative to its first nonzero, rows + 1 entries at
-    // roff[first row + b]; cidx the packed column indices (see SpmvMap).
+    // nonzero, local-index segment offset in 16-byte units, offset of the
+    // block's column set in cols}, b = 0..nrb (the last is the end
+    // sentinel); roff holds each block's row offsets relative to its first
+    // nonzero, rows + 1 entries at roff[first row + b]; lidx and cols the
+    // block-local column indices and column sets (see SpmvMap).
     int4 *spmv_desc = nullptr;
     uint16_t *spmv_roff = nullptr;
-    uint8_t *spmv_cidx = nullptr;
+    uint8_t *spmv_lidx = nullptr;
+    int32_t *spmv_cols = nullptr;
     int64_t spmv_nrb = 0;
 };
 
-// What the SpMV kernels read besides values and vectors.  A block's column
-// indices cover its 4-aligned window (first nonzero rounded down to a
-// multiple of 4, a multiple of 4 entries); a block whose columns span less
-// than 2^16 stores them as 16-bit offsets from its base column ("narrow"),
-// any other block as plain 32-bit indices ("wide").  Window entries outside
-// the block hold the base column (a valid index, weighted 0).
+// What the SpMV kernels read besides values and vectors.  Each row block has
+// a column set: its distinct columns, sorted (<= kSpmvBlockCols of them,
+// cols[desc[b].w .. desc[b + 1].w)), and one byte per entry that indexes it.
+// The local indices cover the block's 4-aligned window (first nonzero
+// rounded down to a multiple of 4, a multiple of 4 entries); window entries
+// outside the block hold 0 (a valid index, weighted 0).  The gathered
+// vector is read once per column of the set instead of once per entry.
 struct SpmvMap {
     const int4 *desc;
     const uint16_t *roff;
-    const uint8_t *cidx;
+    const uint8_t *lidx;
+    const int32_t *cols;
     const int32_t *colidx;   // canonical CSR columns (the one-entry form)
     int64_t nrb, nnz;
 };
 inline SpmvMap spmv_map(const DevMesh &m)
 {
-    return SpmvMap{m.spmv_desc, m.spmv_roff, m.spmv_cidx, m.colidx, m.spmv_nrb, m.nnz};
+    return SpmvMap{m.spmv_desc, m.spmv_roff, m.spmv_lidx, m.spmv_cols, m.colidx, m.spmv_nrb, m.nnz};
 }
 
 // Device status word of an assembly launch sequence.
@@ -99,11 +103,12 @@ struct CGWork {
 };
 
 constexpr int kPartDoubles = 8192;
-// SpMV row blocks (fixed at upload): <= kSpmvBlockRows rows and
+// SpMV row blocks (fixed at upload): <= kSpmvBlockRows rows,
 // <= kSpmvBlockNnz - 3 nonzeros, contiguous in CSR (a block read through a
-// 4-aligned window of kSpmvBlockNnz entries).  The device column-index array
-// is padded by kColPad zeros.
-constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024, kColPad = 4;
+// 4-aligned window of kSpmvBlockNnz entries), and <= kSpmvBlockCols distinct
+// columns (one-byte local indices).  The device column-index array is
+// padded by kColPad zeros.
+constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024, kSpmvBlockCols = 256, kColPad = 4;
 int stream_blocks(int64_t n);
 // Sizes the SpMV grid for the device: four work-groups per CU, at most as many
 // as are co-resident (context creation).

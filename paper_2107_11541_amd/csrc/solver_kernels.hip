@@ -145,6 +145,15 @@ __device__ inline void load_quad(const float *__restrict__ v, int64_t e, int64_t
     out[3] = q.w;
 }
 
+// a * b rounded on its own (never contracted into a fused multiply-add), as
+// a product stored and summed later would be
+template <class T>
+__device__ inline T mul_rn(T a, T b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 // wg / G: this group's index and the number of groups working on the matrix
 // (G a multiple of kXcds, and wg % kXcds the group's XCD).  nnz: entries of
 // vals (the 16-byte path needs nnz >= 4).
@@ -172,14 +181,19 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
     if (blk >= hi) return acc;                    // uniform over the group
     const int64_t last_even = (nnz - 2) & ~(int64_t)1;
     const T last = VEC ? vals[nnz - 1] : T(0);
-    int c[kPer];
+    // VEC: the block's column set and local indices, gathered once per column
+    __shared__ T xs[kSpmvBlockCols];
+    __shared__ uint32_t lw[kSpmvBlockNnz / 4];
+    uint32_t li = 0;   // VEC: local indices of this thread's 4 window entries
+    int cc = 0;        // VEC: this thread's column of the set
+    int c[kPer];       // one-entry form: column indices
     T v[kPer];
     int r0 = 0, nrows = 0, nz = 0, ro = 0, shift = 0;
-    // fetch(b, real): load block b; with real == false only one chunk is
-    // touched (the loop's last pass issues the same loads on both paths, so
-    // the wait counts of the gathers do not depend on the branch).
     // fetch(b, d0, d1, real): issue the loads of block b, whose descriptor
-    // pair (d0, d1) = (desc[b], desc[b + 1]) was read beforehand
+    // pair (d0, d1) = (desc[b], desc[b + 1]) was read beforehand; with
+    // real == false only one chunk is touched (the loop's last pass issues the
+    // same loads on both paths, so the wait counts of the gathers do not
+    // depend on the branch).
     auto fetch = [&](int64_t b, const int4 d0, const int4 d1, bool real) {
         r0 = d0.x;
         nrows = d1.x - d0.x;
@@ -189,18 +203,9 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
             shift = d0.y - (int)a0;
             const int chunks = real ? (shift + nz + 3) / 4 : 1;
             const int t = tid < chunks ? tid : chunks - 1;
-            const uint8_t *seg = sm.cidx + (int64_t)d0.z * 16;
-            const int base = d0.w & 0x7fffffff;
-            const bool wide = d0.w < 0;
-            // the same two 8-byte loads for both kinds (no branch, so no wait
-            // is forced before the join): a wide block's 4 indices, or a
-            // narrow block's 4 offsets twice
-            const v2u q0 = *(const v2u *)(seg + (wide ? 16 * t : 8 * t));
-            const v2u q1 = *(const v2u *)(seg + (wide ? 16 * t + 8 : 8 * t));
-            c[0] = wide ? (int)q0.x : base + (int)(q0.x & 0xffffu);
-            c[1] = wide ? (int)q0.y : base + (int)(q0.x >> 16);
-            c[2] = wide ? (int)q1.x : base + (int)(q0.y & 0xffffu);
-            c[3] = wide ? (int)q1.y : base + (int)(q0.y >> 16);
+            li = *(const uint32_t *)(sm.lidx + (int64_t)d0.z * 16 + 4 * t);
+            const int ncol = d1.w - d0.w;
+            cc = sm.cols[d0.w + (tid < ncol ? tid : ncol - 1)];
             load_quad(vals, a0 + 4 * (int64_t)t, last_even, last, v);
         } else {
             const int32_t *__restrict__ colidx = sm.colidx;
@@ -231,19 +236,36 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
         const int64_t nb = more ? next : blk;
         const int4 n0 = desc[nb], n1 = desc[nb + 1];
         T xv[kPer], vv[kPer];
+        T xc = T(0);
+        const uint32_t cli = li;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            xv[j] = xget(c[j]);
+            if (!VEC) xv[j] = xget(c[j]);
             const int w = pos(j);
             vv[j] = (w >= csh && w < csh + cnz) ? v[j] : T(0);
         }
+        if (VEC) xc = xget(cc);
         const T wrow = wget(cr0 + (row < cn ? row : cn - 1));
         fetch(nb, n0, n1, more);
         // keep every load of the next block ahead of the first wait on the gathers
         __builtin_amdgcn_sched_barrier(0);
+        if (VEC) {
+            // masked values, local indices and the gathered column set to LDS;
+            // the row threads form the products
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j] * xv[j];
+            for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j];
+            lw[tid] = cli;
+            xs[tid] = xc;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j] * xv[j];
+        }
         __syncthreads();
+        // entry q's product: a rounded product, never fused with the sum
+        auto term = [&](int q) {
+            if (VEC) return mul_rn(prod[q], xs[(lw[q >> 2] >> (8 * (q & 3))) & 0xffu]);
+            return prod[q];
+        };
         // two interleaved partial sums per thread: entries sub, sub + 8, ...
         // and sub + 4, sub + 12, ... (a fixed order)
         T s = T(0), s1 = T(0);
@@ -251,10 +273,10 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
             const int q1 = rps[row + 1];
             int q = rps[row] + sub;
             for (; q + kTPR < q1; q += 2 * kTPR) {
-                s += prod[q];
-                s1 += prod[q + kTPR];
+                s += term(q);
+                s1 += term(q + kTPR);
             }
-            if (q < q1) s += prod[q];
+            if (q < q1) s += term(q);
         }
         s += s1;
         s += __shfl_xor(s, 1, kTPR);
