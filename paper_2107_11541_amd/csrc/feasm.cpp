@@ -177,59 +177,63 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
     // row in a 256-thread group), <= kSpmvBlockNnz - 3 nonzeros (a 4-aligned
     // window of kSpmvBlockNnz entries in LDS) and <= kSpmvBlockCols distinct
     // columns.  A single row always fits (rows are <= 255 entries).
-    // stamp[c] = the block that last counted column c; loc[c] its local index
+    // One pass over the pattern builds the blocks, their column sets (distinct
+    // columns in first-touch order) and the local indices: stamp[c] = the
+    // block that last took column c, loc[c] its index in that block's set.
+    // The set order is free (a product is v * x[col] whatever slot x[col]
+    // is staged in); first-touch order keeps it nearly ascending.
     std::vector<int32_t> stamp((size_t)P.N, -1), loc((size_t)P.N, 0);
-    std::vector<int32_t> rb{0};
+    std::vector<int32_t> rb{0}, col_off{0};
+    std::vector<int64_t> seg_off;   // byte offset of each block's local indices
+    I.spmv_cols.clear();
+    I.spmv_lidx.clear();
+    I.spmv_lidx.reserve((size_t)P.nnz + 16 * (size_t)(P.N / 16 + 1));
     for (int64_t r = 0; r < P.N;) {
         const int32_t bid = (int32_t)rb.size() - 1;
-        int ncol = 0;
-        auto add_row = [&](int64_t row, bool commit) {
-            int fresh = 0;
-            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) fresh += stamp[P.colidx[q]] != bid;
-            if (!commit) return fresh;
-            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) stamp[P.colidx[q]] = bid;
-            return fresh;
+        const int32_t c0 = (int32_t)I.spmv_cols.size();
+        const int64_t p0 = P.rowptr[r], a0 = p0 & ~(int64_t)3;
+        const size_t s0 = I.spmv_lidx.size();   // 16-byte aligned
+        I.spmv_lidx.resize(s0 + (size_t)(p0 - a0), 0);   // window entries before the block
+        auto take = [&](int64_t row) {
+            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) {
+                const int32_t c = P.colidx[q];
+                if (stamp[c] != bid) {
+                    stamp[c] = bid;
+                    loc[c] = (int32_t)I.spmv_cols.size() - c0;
+                    I.spmv_cols.push_back(c);
+                }
+                I.spmv_lidx.push_back((uint8_t)loc[c]);
+            }
         };
-        ncol += add_row(r, true);
+        take(r);
         int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3 &&
-               ncol + add_row(r1, false) <= kSpmvBlockCols) {
-            ncol += add_row(r1, true);
+        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) {
+            const size_t nc = I.spmv_cols.size(), nl = I.spmv_lidx.size();
+            take(r1);
+            if ((int64_t)I.spmv_cols.size() - c0 > kSpmvBlockCols) {   // row r1 opens the next block
+                for (size_t k = nc; k < I.spmv_cols.size(); ++k) stamp[I.spmv_cols[k]] = -1;
+                I.spmv_cols.resize(nc);
+                I.spmv_lidx.resize(nl);
+                break;
+            }
             ++r1;
         }
+        // pad the window to a multiple of 4 entries, the segment to 16 bytes
+        const int64_t win = ((p0 & 3) + (P.rowptr[r1] - p0) + 3) & ~(int64_t)3;
+        I.spmv_lidx.resize(s0 + (size_t)((win + 15) & ~(int64_t)15), 0);
+        seg_off.push_back((int64_t)s0);
+        col_off.push_back((int32_t)I.spmv_cols.size());
         rb.push_back((int32_t)r1);
         r = r1;
     }
+    I.spmv_lidx.resize(I.spmv_lidx.size() + 16, 0);
     d.spmv_nrb = (int64_t)rb.size() - 1;
     I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int4{0, 0, 0, 0});
     I.spmv_roff.assign((size_t)(P.N + d.spmv_nrb), 0);
-    // column sets (sorted distinct columns) and one-byte local indices, block
-    // by block; each block's local indices start on a 16-byte boundary
-    {
-        I.spmv_cols.clear();
-        size_t bytes = 0;
-        std::vector<int32_t> set;
-        for (int64_t b = 0; b < d.spmv_nrb; ++b) {
-            const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]];
-            const int64_t win = ((p0 & 3) + (p1 - p0) + 3) & ~(int64_t)3;
-            set.assign(P.colidx.begin() + p0, P.colidx.begin() + p1);
-            std::sort(set.begin(), set.end());
-            set.erase(std::unique(set.begin(), set.end()), set.end());
-            I.spmv_desc[b] = int4{rb[b], (int32_t)p0, (int32_t)(bytes / 16), (int32_t)I.spmv_cols.size()};
-            I.spmv_cols.insert(I.spmv_cols.end(), set.begin(), set.end());
-            bytes += (size_t)(win + 15) & ~(size_t)15;
-        }
-        I.spmv_desc[d.spmv_nrb] =
-            int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)(bytes / 16), (int32_t)I.spmv_cols.size()};
-        I.spmv_lidx.assign(bytes + 16, 0);
-        for (int64_t b = 0; b < d.spmv_nrb; ++b) {
-            const int64_t p0 = P.rowptr[rb[b]], p1 = P.rowptr[rb[b + 1]], a0 = p0 & ~(int64_t)3;
-            const int32_t c0 = I.spmv_desc[b].w, c1 = I.spmv_desc[b + 1].w;
-            for (int32_t k = c0; k < c1; ++k) loc[I.spmv_cols[k]] = k - c0;
-            uint8_t *seg = I.spmv_lidx.data() + (size_t)I.spmv_desc[b].z * 16;
-            for (int64_t q = p0; q < p1; ++q) seg[q - a0] = (uint8_t)loc[P.colidx[q]];
-        }
-    }
+    for (int64_t b = 0; b < d.spmv_nrb; ++b)
+        I.spmv_desc[b] = int4{rb[b], P.rowptr[rb[b]], (int32_t)(seg_off[b] / 16), col_off[b]};
+    I.spmv_desc[d.spmv_nrb] = int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)((I.spmv_lidx.size() - 16) / 16),
+                                   col_off[d.spmv_nrb]};
     for (int64_t b = 0; b < d.spmv_nrb; ++b)
         for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
             I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);

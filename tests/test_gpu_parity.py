@@ -238,53 +238,102 @@ def test_spmv_dot_axpy_parity(fe_ctx):
     assert fe.dot(fe_ctx, dev(np.zeros(0)), dev(np.zeros(0))) == 0.0
 
 
-def _spmv_block_spans(mesh):
-    """Column span of every SpMV row block (<= 64 rows, <= 1021 nonzeros),
-    computed from the pattern the library exposes."""
+def _spmv_blocks(mesh):
+    """The SpMV row blocks of the documented rule (<= 64 rows, <= 1021
+    nonzeros, <= 256 distinct columns, rows taken greedily), simulated on the
+    pattern the library exposes: per block its distinct-column count and
+    whether the column limit is what ended it."""
     rp, ci = mesh.pattern_host()
     rp = rp.astype(np.int64)
     n = len(rp) - 1
-    spans, r = [], 0
+    ncols, capped, r = [], [], 0
     while r < n:
-        r1 = r + 1
+        cols = set(ci[rp[r]:rp[r + 1]].tolist())
+        r1, cap = r + 1, False
         while r1 < n and r1 - r < 64 and rp[r1 + 1] - rp[r] <= 1021:
+            more = cols | set(ci[rp[r1]:rp[r1 + 1]].tolist())
+            if len(more) > 256:
+                cap = True
+                break
+            cols = more
             r1 += 1
-        c = ci[rp[r]:rp[r1]]
-        spans.append(int(c.max()) - int(c.min()))
+        ncols.append(len(cols))
+        capped.append(cap)
         r = r1
-    return np.array(spans)
+    return np.array(ncols), np.array(capped)
+
+
+def _spmv_forms(mesh, vals_host, x):
+    """y from the 16-byte form (aligned values) and from the one-entry form
+    (the same values at an 8-byte offset)."""
+    fe = _fe()
+    import torch
+    nnz = mesh.nnz
+    va = dev(vals_host)
+    buf = torch.empty(nnz + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = va
+    vm = buf[1:]
+    assert va.data_ptr() % 16 == 0 and vm.data_ptr() % 16 == 8
+    return fe.spmv(mesh, va, x), fe.spmv(mesh, vm, x)
 
 
 @pytest.mark.parametrize("etype,n", [(meshgen.HEX08, 8), (meshgen.HEX08, 10), (meshgen.TET04, 3),
                                      (meshgen.HEX08, 9), (meshgen.HEX08, 48)])
 def test_spmv_load_forms_agree(fe_ctx, etype, n):
-    """16-byte loads (aligned values, packed column indices) and one-entry
-    loads (values offset by 8 bytes, plain column indices) give bitwise the
-    same y; nnz % 4 = 1, 3, 2, 0 exercises the end-of-array handling of the
-    16-byte form, and the 48^3 mesh has both 16-bit ("narrow") and 32-bit
-    ("wide") column-index blocks."""
-    fe = _fe()
+    """16-byte loads (aligned values, one-byte local indices into each row
+    block's column set) and one-entry loads (values offset by 8 bytes, plain
+    column indices) give bitwise the same y; nnz % 4 = 1, 3, 2, 0 exercises
+    the end-of-array handling of the 16-byte form."""
     import torch
     case = meshgen.make_case(n, etype, 0.1, case_id=53, shuffle=True)
     mesh, v, b, _ = gpu_assemble(fe_ctx, case, MOM)
-    nnz = mesh.nnz
-    va = dev(v[0])
-    buf = torch.empty(nnz + 1, dtype=torch.float64, device="cuda")
-    buf[1:] = va
-    vm = buf[1:]
-    assert va.data_ptr() % 16 == 0 and vm.data_ptr() % 16 == 8
     x = mesh.to_mesh(dev(np.random.default_rng(3).normal(0, 1, case.n_nodes)))
-    ya = fe.spmv(mesh, va, x)
-    ym = fe.spmv(mesh, vm, x)
+    ya, ym = _spmv_forms(mesh, v[0], x)
     assert torch.equal(ya, ym)
     rp, ci, V, _ = oracle_assemble(case, MOM)
     yr = oracle.spmv(rp, ci, V[0], rhs_user(mesh, host(x)))
-    spans = _spmv_block_spans(mesh)
-    wide = float(np.mean(spans > 65535))
-    print(etype, n, "nnz % 4 =", nnz % 4, "wide blocks", wide, flush=True)
-    if n == 48:
-        assert 0.0 < wide < 1.0
+    ncols, _ = _spmv_blocks(mesh)
+    print(etype, n, "nnz % 4 =", mesh.nnz % 4, "columns per block max", ncols.max(), flush=True)
     assert rel(rhs_user(mesh, host(ya)), yr) <= 1e-13
+
+
+def test_spmv_blocks_end_at_the_column_limit(fe_ctx):
+    """A TET04 mesh with one node in 80 elements (a 241-entry row) next to
+    short rows: row blocks end where a 257th distinct column would enter.
+    Both load forms against the definition y_i = sum_j A_ij x_j, with A_ij a
+    seeded counter-based value of the user ids (i, j) on the element-sharing
+    pattern."""
+    import math
+    import torch
+    fe = _fe()
+    rng = np.random.default_rng(3)
+    nf, tail = 80, 200
+    N = 1 + 3 * nf + tail
+    conn = [[0, 1 + 3 * k, 2 + 3 * k, 3 + 3 * k] for k in range(nf)]
+    extra = list(range(1 + 3 * nf, N))
+    conn += [[extra[k], extra[k + 1], extra[k + 2], extra[k + 3]] for k in range(len(extra) - 3)]
+    conn = np.array(conn, np.int32)
+    coords = rng.random((N, 3))
+    mesh = fe.Mesh(fe_ctx, meshgen.TET04, coords, conn, np.zeros(0, np.int32))
+    ncols, capped = _spmv_blocks(mesh)
+    assert capped.any() and ncols.max() <= 256, (ncols.max(), capped.sum())
+    rp_m, ci_m = mesh.pattern_host()
+    perm = mesh.node_perm.astype(np.int64)
+    vals = _pair_values(np.repeat(perm, np.diff(rp_m)), perm[ci_m], N)
+    xu = rng.uniform(-1.0, 1.0, N)
+    ya, ym = _spmv_forms(mesh, vals, dev(xu[perm]))
+    assert torch.equal(ya, ym)
+    y = host(ya)
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(N)
+    worst = 0.0
+    for i in range(N):
+        cols = np.unique(conn[(conn == i).any(axis=1)])
+        terms = _pair_values(np.full(cols.size, i), cols, N) * xu[cols]
+        worst = max(worst, abs(y[iperm[i]] - math.fsum(terms)) / np.abs(terms).sum())
+    print("blocks", ncols.size, "ended by the column limit", int(capped.sum()), "worst", worst, flush=True)
+    assert worst <= 1e-13
+    mesh.close()
 
 
 def test_pcg_graph_replays_match_eager_launches(fe_ctx):
