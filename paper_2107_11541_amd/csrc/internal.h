@@ -47,7 +47,7 @@ struct DevMesh {
 };
 
 // What the SpMV kernels read besides values and vectors.  Each row block has
-// a column set: its distinct columns, sorted (<= kSpmvBlockCols of them,
+// a column set: its distinct columns in first-touch order (<= kSpmvBlockCols of them,
 // cols[desc[b].w .. desc[b + 1].w)), and one byte per entry that indexes it.
 // The local indices cover the block's 4-aligned window (first nonzero
 // rounded down to a multiple of 4, a multiple of 4 entries); window entries
