@@ -86,26 +86,32 @@ __device__ inline void store_flag(int32_t *p, int v)
 }
 
 // CSR-stream SpMV: a work-group takes a row block whose nonzeros are
-// contiguous (<= kSpmvBlockNnz - 3 of them, <= kStreamRows rows), streams
-// values and column indices with coalesced loads, forms the products in LDS
-// and lets kTPR threads per row add them (thread j takes entries j, j+kTPR,
-// ..., then a fixed shuffle combines the four).  Row blocks are fixed at
-// upload: the summation order, and the result, do not depend on the grid.
+// contiguous (<= kSpmvBlockNnz - 3 of them, <= kStreamRows rows, <=
+// kSpmvBlockCols distinct columns), streams its values with coalesced loads,
+// and lets kTPR threads per row add the products (thread j takes entries j,
+// j+kTPR, ..., then a fixed shuffle combines the four).  Row blocks are fixed
+// at upload: the summation order, and the result, do not depend on the grid.
 //
-// The upload stores, per block b, desc[b] = {first row, first nonzero} and
-// the in-block row offsets roff[first row + b + i] = rowptr[r0 + i] -
-// rowptr[r0] (i = 0..rows, uint16), so every load of a block depends only on
-// its descriptor.
+// The upload stores, per block b, desc[b] = {first row, first nonzero,
+// local-index segment, column-set offset}, the in-block row offsets
+// roff[first row + b + i] = rowptr[r0 + i] - rowptr[r0] (i = 0..rows,
+// uint16), the block's column set (its distinct columns) and one local index
+// per entry into that set, so every load of a block depends only on its
+// descriptor.
 //
 // Loads (VEC): the block is read through a window that starts at its first
 // nonzero rounded down to a multiple of 4; thread t owns window entries
-// 4t..4t+3 and reads them with one 16-byte column-index load and 16-byte
-// value loads (entries outside the block are weighted 0).  Column indices
-// are padded by 4 at upload.  FP64 values belong to the caller and are
-// never read past nnz - 1: a pair that would cross the end is re-based to
-// the last full pair and the final entry comes from one uniform load.  When
-// the caller's value array is not 16-byte aligned, the scalar form (one
-// entry per thread and pass, stride 256) is used instead.
+// 4t..4t+3 and reads their 4 local indices with one 4-byte load and their
+// values with 16-byte loads (entries outside the block are weighted 0), and
+// column t of the set.  Thread t gathers that column's vector entry once;
+// the values, local indices and gathered entries go to LDS, and the row
+// threads form each product there, rounded on its own (as a stored product
+// would be).  FP64 values belong to the caller and are never read past
+// nnz - 1: a pair that would cross the end is re-based to the last full
+// pair and the final entry comes from one uniform load.  When the caller's
+// value array is not 16-byte aligned, the scalar form (one entry per thread
+// and pass, stride 256, plain column indices, products in registers) is
+// used instead; both forms give bitwise the same y.
 // The next block's loads are issued before the current block's products are
 // formed, and both paths of the loop's last pass issue the same loads, so
 // the stream never waits behind the gathers.
@@ -118,8 +124,6 @@ static_assert(kStreamRows * kTPR == 256, "four threads per row in a 256-thread g
 static_assert(kStreamRows < 256, "the row index of a block's rows must fit the thread count");
 constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
