@@ -110,7 +110,7 @@ constexpr int kPartDoubles = 8192;
 // padded by kColPad zeros.
 constexpr int kSpmvBlockRows = 64, kSpmvBlockNnz = 1024, kSpmvBlockCols = 256, kColPad = 4;
 int stream_blocks(int64_t n);
-// Sizes the SpMV grid for the device: four work-groups per CU, at most as many
+// Sizes the SpMV grid for the device: five work-groups per CU, at most as many
 // as are co-resident (context creation).
 hipError_t init_spmv_grid(int device);
 hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s);

@@ -7,9 +7,9 @@
 //     threads, each thread walking a fixed strided subset, so every reduction
 //     has a fixed order and results are bitwise reproducible;
 //   * SpMV streams row blocks whose nonzeros are contiguous (fixed at
-//     upload) on four work-groups per CU: 16-byte loads of values and packed
-//     column indices, the products staged in LDS, four threads per row adding
-//     them in a fixed order;
+//     upload) on five work-groups per CU: 16-byte loads of values and one-byte
+//     indices into each block's column set, the products formed in LDS, four
+//     threads per row adding them in a fixed order;
 //   * one PCG iteration is three launches: SpMV fused with p.Ap; the r, z
 //     update fused with r.z and r.r; the x and p updates with the stop test.
 //     (Forming z + beta p inside the SpMV gather was measured slower: two
@@ -315,13 +315,14 @@ inline bool spmv_vec_ok(const T *vals, int64_t nnz)
     return ((uintptr_t)vals & 15) == 0 && nnz >= 4;
 }
 
-// Work-groups of the stream SpMV: four per CU (fewer than can be
-// co-resident: on the 128^3 HEX08 Poisson matrix, 8 groups per CU took
-// 155.8 us, 4 took 152.4 us and 3, 5, 6 or 7 took 156-158.5 us; eight
+// Work-groups of the stream SpMV: five per CU (fewer than can be
+// co-resident: on the 128^3 HEX08 Poisson matrix the column-set kernel took
+// 130.6 us with 5 groups per CU, 134.8 with 4 or 6, 137.1 with 8, 141.8 with
+// 3, and 137.8 / 140.6 with 4.5 / 5.5 (an uneven count per CU); more
 // concurrent streams per CU contend in the memory system without hiding more
 // latency), at most kMaxParts, at most one per row block.  Fixed per device,
 // so reductions over the per-group partials keep a fixed order.
-constexpr int kSpmvGroupsPerCU = 4;
+constexpr int kSpmvGroupsPerCU = 5;
 int g_spmv_resident = 0;
 
 int spmv_blocks(int64_t nrb)
