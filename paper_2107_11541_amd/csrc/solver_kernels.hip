@@ -164,11 +164,21 @@ __device__ inline T mul_rn(T a, T b)
 // done_flags (may be null): a solve's flag word; a group returns right
 // after issuing its first block's loads when the solve has already stopped
 // (checked there so that the check's latency overlaps those loads).
+// Row blocks reduced per work-group pass.  A pass has a fixed cost (the
+// column-set gathers, two barriers, the LDS round trip) and FP32 blocks carry
+// half the value bytes of FP64 ones, so the FP32 form reduces two blocks per
+// pass (256^3 mixed-precision solve 0.448 -> 0.398 s); two per pass were
+// slower for FP64 (128^3 SpMV 132.3 -> 139.0 us).  A group's blocks enter its
+// partial sum in the same order either way.
+template <class T> struct SpmvPass { static constexpr int BPI = 1; };
+template <> struct SpmvPass<float> { static constexpr int BPI = 2; };
+
 template <class T, bool VEC, class XF, class WF, class YF>
 __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
-                                     int wg, int G, XF xget, WF wget, YF yput, T *prod, int *rps,
+                                     int wg, int G, XF xget, WF wget, YF yput,
                                      const int32_t *done_flags = nullptr)
 {
+    constexpr int BPI = SpmvPass<T>::BPI;
     const uint16_t *__restrict__ roff = sm.roff;
     const int64_t nrb = sm.nrb, nnz = sm.nnz;
     const int tid = threadIdx.x;
@@ -185,107 +195,153 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
     if (blk >= hi) return acc;                    // uniform over the group
     const int64_t last_even = (nnz - 2) & ~(int64_t)1;
     const T last = VEC ? vals[nnz - 1] : T(0);
-    // VEC: the block's column set and local indices, gathered once per column
-    __shared__ T xs[kSpmvBlockCols];
-    __shared__ uint32_t lw[kSpmvBlockNnz / 4];
-    uint32_t li = 0;   // VEC: local indices of this thread's 4 window entries
-    int cc = 0;        // VEC: this thread's column of the set
-    int c[kPer];       // one-entry form: column indices
-    T v[kPer];
-    int r0 = 0, nrows = 0, nz = 0, ro = 0, shift = 0;
-    // fetch(b, d0, d1, real): issue the loads of block b, whose descriptor
-    // pair (d0, d1) = (desc[b], desc[b + 1]) was read beforehand; with
-    // real == false only one chunk is touched (the loop's last pass issues the
-    // same loads on both paths, so the wait counts of the gathers do not
-    // depend on the branch).
-    auto fetch = [&](int64_t b, const int4 d0, const int4 d1, bool real) {
-        r0 = d0.x;
-        nrows = d1.x - d0.x;
-        nz = d1.y - d0.y;
+    // A pass reduces BPI blocks of the group (blk + u * ngrp, u < BPI) with
+    // one pair of barriers; a slot past the group's share holds a copy of
+    // the first block's loads and no rows.
+    __shared__ T prod[BPI][kStreamNnz];          // VEC: masked values; else products
+    __shared__ int rps[BPI][kStreamRows + 1];    // row starts in the window
+    __shared__ T xs[BPI][kSpmvBlockCols];        // VEC: the gathered column set
+    __shared__ uint32_t lw[BPI][kSpmvBlockNnz / 4];   // VEC: local indices
+    uint32_t li[BPI];   // VEC: local indices of this thread's 4 window entries
+    int cc[BPI];        // VEC: this thread's column of the set
+    int c[BPI][kPer];   // one-entry form: column indices
+    T v[BPI][kPer];
+    int r0[BPI], nrows[BPI], nz[BPI], ro[BPI], shift[BPI];
+    bool live[BPI];
+    // fetch(u, b, d0, d1, real): issue the loads of block b into slot u, whose
+    // descriptor pair (d0, d1) = (desc[b], desc[b + 1]) was read beforehand;
+    // with real == false only one chunk is touched (the loop's last pass
+    // issues the same loads on both paths, so the wait counts of the gathers
+    // do not depend on the branch).
+    auto fetch = [&](int u, int64_t b, const int4 d0, const int4 d1, bool real) {
+        r0[u] = d0.x;
+        nrows[u] = d1.x - d0.x;
+        nz[u] = d1.y - d0.y;
+        live[u] = real;
         if (VEC) {
             const int64_t a0 = (int64_t)d0.y & ~(int64_t)3;
-            shift = d0.y - (int)a0;
-            const int chunks = real ? (shift + nz + 3) / 4 : 1;
+            shift[u] = d0.y - (int)a0;
+            const int chunks = real ? (shift[u] + nz[u] + 3) / 4 : 1;
             const int t = tid < chunks ? tid : chunks - 1;
-            li = *(const uint32_t *)(sm.lidx + (int64_t)d0.z * 16 + 4 * t);
+            li[u] = *(const uint32_t *)(sm.lidx + (int64_t)d0.z * 16 + 4 * t);
             const int ncol = d1.w - d0.w;
-            cc = sm.cols[d0.w + (tid < ncol ? tid : ncol - 1)];
-            load_quad(vals, a0 + 4 * (int64_t)t, last_even, last, v);
+            cc[u] = sm.cols[d0.w + (tid < ncol ? tid : ncol - 1)];
+            load_quad(vals, a0 + 4 * (int64_t)t, last_even, last, v[u]);
         } else {
             const int32_t *__restrict__ colidx = sm.colidx;
             const int64_t p0 = d0.y;
-            shift = 0;
-            const int span = real ? nz : 1;
+            shift[u] = 0;
+            const int span = real ? nz[u] : 1;
 #pragma unroll
             for (int j = 0; j < kPer; ++j) {
                 const int kk = tid + 256 * j;
                 const int64_t idx = p0 + (kk < span ? kk : span - 1);
-                c[j] = colidx[idx];
-                v[j] = vals[idx];
+                c[u][j] = colidx[idx];
+                v[u][j] = vals[idx];
             }
         }
-        ro = roff[(int64_t)r0 + b + (tid < nrows ? tid : nrows)];
+        ro[u] = roff[(int64_t)r0[u] + b + (tid < nrows[u] ? tid : nrows[u])];
     };
     auto pos = [&](int j) { return VEC ? 4 * tid + j : tid + 256 * j; };
-    fetch(blk, desc[blk], desc[blk + 1], true);
+    {
+        int4 d0[BPI], d1[BPI];
+        int64_t fb[BPI];
+        bool ok[BPI];
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) {
+            const int64_t b = blk + (int64_t)u * ngrp;
+            ok[u] = b < hi;
+            fb[u] = ok[u] ? b : blk;
+            d0[u] = desc[fb[u]];
+            d1[u] = desc[fb[u] + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) fetch(u, fb[u], d0[u], d1[u], ok[u]);
+    }
     if (done_flags && wg_done(done_flags)) return acc;
     const int row = tid / kTPR, sub = tid % kTPR;
     for (;;) {
-        const int cr0 = r0, cn = nrows, cnz = nz, csh = shift;
-        if (tid <= cn) rps[tid] = ro + csh;
-        // the next block's descriptor is read before the gathers are issued,
-        // so that waiting for it never waits for them
-        const int64_t next = blk + ngrp;
-        const bool more = next < hi;
-        const int64_t nb = more ? next : blk;
-        const int4 n0 = desc[nb], n1 = desc[nb + 1];
-        T xv[kPer], vv[kPer];
-        T xc = T(0);
-        const uint32_t cli = li;
+        int cr0[BPI], cn[BPI], cnz[BPI], csh[BPI];
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            if (!VEC) xv[j] = xget(c[j]);
-            const int w = pos(j);
-            vv[j] = (w >= csh && w < csh + cnz) ? v[j] : T(0);
+        for (int u = 0; u < BPI; ++u) {
+            cr0[u] = r0[u];
+            cn[u] = live[u] ? nrows[u] : 0;
+            cnz[u] = nz[u];
+            csh[u] = shift[u];
+            if (tid <= cn[u]) rps[u][tid] = ro[u] + csh[u];
         }
-        if (VEC) xc = xget(cc);
-        const T wrow = wget(cr0 + (row < cn ? row : cn - 1));
-        fetch(nb, n0, n1, more);
-        // keep every load of the next block ahead of the first wait on the gathers
+        // the next pass's descriptors are read before the gathers are issued,
+        // so that waiting for them never waits for the gathers
+        const int64_t next = blk + (int64_t)BPI * ngrp;
+        const bool more = next < hi;
+        int4 n0[BPI], n1[BPI];
+        int64_t nb[BPI];
+        bool nok[BPI];
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) {
+            const int64_t b = next + (int64_t)u * ngrp;
+            nok[u] = more && b < hi;
+            nb[u] = nok[u] ? b : blk;
+            n0[u] = desc[nb[u]];
+            n1[u] = desc[nb[u] + 1];
+        }
+        T xv[BPI][kPer], vv[BPI][kPer], xc[BPI], wrow[BPI];
+        uint32_t cli[BPI];
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) {
+            cli[u] = li[u];
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                if (!VEC) xv[u][j] = xget(c[u][j]);
+                const int w = pos(j);
+                vv[u][j] = (w >= csh[u] && w < csh[u] + cnz[u]) ? v[u][j] : T(0);
+            }
+            xc[u] = VEC ? xget(cc[u]) : T(0);
+            wrow[u] = wget(cr0[u] + (row < nrows[u] ? row : nrows[u] - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) fetch(u, nb[u], n0[u], n1[u], nok[u]);
+        // keep every load of the next pass ahead of the first wait on the gathers
         __builtin_amdgcn_sched_barrier(0);
-        if (VEC) {
-            // masked values, local indices and the gathered column set to LDS;
-            // the row threads form the products
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j];
-            lw[tid] = cli;
-            xs[tid] = xc;
-        } else {
+        for (int u = 0; u < BPI; ++u) {
+            if (VEC) {
+                // masked values, local indices and the gathered column set to
+                // LDS; the row threads form the products
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) prod[pos(j)] = vv[j] * xv[j];
+                for (int j = 0; j < kPer; ++j) prod[u][pos(j)] = vv[u][j];
+                lw[u][tid] = cli[u];
+                xs[u][tid] = xc[u];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kPer; ++j) prod[u][pos(j)] = vv[u][j] * xv[u][j];
+            }
         }
         __syncthreads();
-        // entry q's product: a rounded product, never fused with the sum
-        auto term = [&](int q) {
-            if (VEC) return mul_rn(prod[q], xs[(lw[q >> 2] >> (8 * (q & 3))) & 0xffu]);
-            return prod[q];
-        };
-        // two interleaved partial sums per thread: entries sub, sub + 8, ...
-        // and sub + 4, sub + 12, ... (a fixed order)
-        T s = T(0), s1 = T(0);
-        if (row < cn) {
-            const int q1 = rps[row + 1];
-            int q = rps[row] + sub;
-            for (; q + kTPR < q1; q += 2 * kTPR) {
-                s += term(q);
-                s1 += term(q + kTPR);
+#pragma unroll
+        for (int u = 0; u < BPI; ++u) {
+            // entry q's product: a rounded product, never fused with the sum
+            auto term = [&](int q) {
+                if (VEC) return mul_rn(prod[u][q], xs[u][(lw[u][q >> 2] >> (8 * (q & 3))) & 0xffu]);
+                return prod[u][q];
+            };
+            // two interleaved partial sums per thread: entries sub, sub + 8,
+            // ... and sub + 4, sub + 12, ... (a fixed order)
+            T s = T(0), s1 = T(0);
+            if (row < cn[u]) {
+                const int q1 = rps[u][row + 1];
+                int q = rps[u][row] + sub;
+                for (; q + kTPR < q1; q += 2 * kTPR) {
+                    s += term(q);
+                    s1 += term(q + kTPR);
+                }
+                if (q < q1) s += term(q);
             }
-            if (q < q1) s += term(q);
+            s += s1;
+            s += __shfl_xor(s, 1, kTPR);
+            s += __shfl_xor(s, 2, kTPR);
+            if (sub == 0 && row < cn[u]) acc += yput(cr0[u] + row, s, wrow[u]);
         }
-        s += s1;
-        s += __shfl_xor(s, 1, kTPR);
-        s += __shfl_xor(s, 2, kTPR);
-        if (sub == 0 && row < cn) acc += yput(cr0 + row, s, wrow);
         if (!more) break;
         __syncthreads();
         blk = next;
@@ -297,15 +353,12 @@ template <class T, bool VEC>
 __global__ void __launch_bounds__(kTB) k_spmv(SpmvMap sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
                                               const T *__restrict__ x, T *__restrict__ y)
 {
-    __shared__ T prod[kStreamNnz];
-    __shared__ int rps[kStreamRows + 1];
     spmv_stream<T, VEC>(
         sm, desc, vals, blockIdx.x, gridDim.x, [&](int col) { return x[col]; }, [&](int) { return T(0); },
         [&](int row, T val, T) {
             y[row] = val;
             return 0.0;
-        },
-        prod, rps);
+        });
 }
 
 // The 16-byte form needs the value array 16-byte aligned and nnz >= 4.
@@ -494,8 +547,6 @@ __device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict
                                        T *__restrict__ q, double *__restrict__ part, const int32_t *flags, int wg,
                                        int G)
 {
-    __shared__ T prod[kStreamNnz];
-    __shared__ int rps[kStreamRows + 1];
     __shared__ double sh[4];
     double acc = spmv_stream<T, VEC>(
         sm, desc, vals, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
@@ -503,7 +554,7 @@ __device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict
             q[row] = val;
             return (double)prow * (double)val;
         },
-        prod, rps, flags);
+        flags);
     acc = wg_sum(acc, sh);
     if (threadIdx.x == 0) part[kPartPQ + wg] = acc;
 }
