@@ -393,8 +393,8 @@ def main():
                     help="only run a plain 512 MiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU domain decomposition is a design, "
-              "not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (the multi-GPU domain decomposition is designed, "
+              "not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
