@@ -111,12 +111,15 @@ namespace {
 
 // ---- planning (host threads) -----------------------------------------------
 
-void plan_job(Job *j)
+// idle: no other request waits to be planned (see planner_main)
+void plan_job(Job *j, bool idle)
 {
     const fe_job &q = j->desc;
     // one thread per mesh keeps every planner busy; large meshes get a few
-    // more so that they do not set the latency tail alone
-    set_thread_budget((int)std::max<int64_t>(1, std::min<int64_t>(4, q.n_elems / 200000)));
+    // more so that they do not set the latency tail alone, and more again
+    // when nothing else waits for the planners
+    const int64_t threads = idle ? std::min<int64_t>(8, q.n_elems / 100000) : std::min<int64_t>(4, q.n_elems / 200000);
+    set_thread_budget((int)std::max<int64_t>(1, threads));
     j->img = std::make_unique<MeshImage>();
     std::string err;
     int st = FE_OK;
@@ -152,6 +155,7 @@ void planner_main(fe_server_s *S)
 {
     for (;;) {
         Job *j;
+        bool idle = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_plan.wait(lk, [&] { return S->stop || !S->submit_q.empty(); });
@@ -159,9 +163,10 @@ void planner_main(fe_server_s *S)
             j = S->submit_q.front();
             S->submit_q.pop_front();
             ++S->planners_busy;
+            idle = S->submit_q.empty() && S->planners_busy == 1;
         }
         try {
-            plan_job(j);
+            plan_job(j, idle);
         } catch (const std::bad_alloc &) {
             j->img.reset();
             j->fields = std::vector<double>();
