@@ -1,9 +1,10 @@
 """Seeded synthetic meshes and nodal fields.
 
 This module is the one place that both the product path and the oracle take
-their inputs from.  It builds meshes (a jittered unit cube of HEX08 cells, or
-the same cube split into TET04 cells), random renumberings, Dirichlet node
-lists and the nodal fields (velocity, density, viscosity, species).  It holds
+their inputs from.  It builds meshes (a jittered unit cube of HEX08 cells, the
+same cube split into TET04, PEN06 or PYR05 cells, or a hybrid of all four),
+random renumberings, Dirichlet node lists and the nodal fields (velocity,
+density, viscosity, species).  It holds
 none of the finite-element arithmetic: no shape function, quadrature rule,
 Jacobian, elemental matrix or solver lives here.
 
@@ -20,6 +21,22 @@ synthetic cubes stand in for it.  Recipes:
 * TET04: each cube split into six tetrahedra around the 0-6 diagonal,
   (0,1,2,6) (0,2,3,6) (0,3,7,6) (0,7,4,6) (0,4,5,6) (0,5,1,6), all positively
   oriented and conforming across cubes.
+* PEN06: each cube split into two prisms along the 0-2 diagonal of its
+  bottom face, (0,1,2|4,5,6) and (0,2,3|4,6,7) (bottom triangle, then the
+  nodes above it); conforming across cubes.
+* PYR05: each cube split into six pyramids, one per face, with a new apex
+  node at the mean of the cube's eight corners; bases ordered
+  counter-clockwise seen from the apex: (0,1,2,3) (4,7,6,5) (0,4,5,1)
+  (3,2,6,7) (0,3,7,4) (1,5,6,2).  Centre nodes are numbered after the grid
+  nodes, in cube order.
+* HYBRID: slabs of cubes along x, i the cube's x index: prisms for
+  i < n/4, hexahedra for n/4 <= i < n/2, one transition slab i = n/2 and
+  Kuhn tetrahedra beyond.  A transition cube holds one pyramid on its x = 0
+  face (the hexahedra's side) and ten tetrahedra that join its centre node
+  to the halves of its five other faces, each face split along the Kuhn
+  diagonal (its first and third base node above), so every interface
+  conforms.  Connectivity is [E, 8] padded with -1 and `types` gives each
+  element's node count (4, 5, 6 or 8).
 * velocity: Taylor-Green u = sin2πx cos2πy cos2πz, v = -cos2πx sin2πy cos2πz,
   w = 0, plus i.i.d. N(0, 0.01^2) per component.
 * density U[0.2, 1.2] i.i.d. per node; viscosity 1.8e-5 (air).
@@ -36,17 +53,25 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 import math
+from typing import Optional
 
 import numpy as np
 
 HEX08 = 8
 TET04 = 4
+PEN06 = 6
+PYR05 = 5
+HYBRID = 0      # mixed element types, padded connectivity plus a type array
 
 # Six positively oriented tetrahedra per hexahedron, local HEX08 node ids.
 KUHN_TETS = np.array(
     [[0, 1, 2, 6], [0, 2, 3, 6], [0, 3, 7, 6], [0, 7, 4, 6], [0, 4, 5, 6], [0, 5, 1, 6]],
     dtype=np.int64,
 )
+
+PRISM_SPLIT = np.array([[0, 1, 2, 4, 5, 6], [0, 2, 3, 4, 6, 7]], dtype=np.int64)
+PYRAMID_BASES = np.array([[0, 1, 2, 3], [4, 7, 6, 5], [0, 4, 5, 1], [3, 2, 6, 7], [0, 3, 7, 4],
+                          [1, 5, 6, 2]], dtype=np.int64)
 
 AIR_P0 = 101325.0        # Pa
 AIR_R = 287.05           # J/(kg K)
@@ -70,7 +95,8 @@ def streams(case_id: int, sub=None) -> dict:
 class Case:
     """A mesh plus its nodal fields, all in the user's numbering.
 
-    coords [N,3] float64; conn [E,nen] int32; dirichlet int32 node ids;
+    coords [N,3] float64; conn [E,nen] int32 ([E,8] padded with -1 for
+    HYBRID, with types [E] the node counts); dirichlet int32 node ids;
     u [3,N]; rho [N]; mu [N]; Y [k,N]; D [k]; dt scalar.
     """
     elem_type: int
@@ -85,6 +111,7 @@ class Case:
     Y: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
     D: np.ndarray = field(default_factory=lambda: np.zeros(0))
     name: str = ""
+    types: Optional[np.ndarray] = None   # HYBRID: [E] uint8 node counts
 
     @property
     def n_nodes(self) -> int:
@@ -140,16 +167,77 @@ def kuhn_split(hconn: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(t.reshape(-1, 4).astype(np.int32))
 
 
+def prism_split(hconn: np.ndarray) -> np.ndarray:
+    """Split every HEX08 into two PEN06 (hex order kept)."""
+    return np.ascontiguousarray(hconn[:, PRISM_SPLIT].reshape(-1, 6).astype(np.int32))
+
+
+def cube_centres(coords: np.ndarray, hconn: np.ndarray) -> np.ndarray:
+    """Mean of each cube's eight corners."""
+    return coords[hconn].mean(axis=1)
+
+
+def pyramid_split(hconn: np.ndarray, centre_ids: np.ndarray) -> np.ndarray:
+    """Split every HEX08 into six PYR05 around its centre node."""
+    E = hconn.shape[0]
+    base = hconn[:, PYRAMID_BASES]                       # [E, 6, 4]
+    apex = np.broadcast_to(centre_ids[:, None, None], (E, 6, 1))
+    return np.ascontiguousarray(np.concatenate([base, apex], axis=2).reshape(-1, 5).astype(np.int32))
+
+
+def hybrid_mesh(n: int, coords: np.ndarray):
+    """Slabs of prisms, hexahedra, pyramid-tet transition cubes and Kuhn
+    tetrahedra along x (see the module docstring).  Returns the coordinates
+    with the transition cubes' centre nodes appended, the [E, 8] connectivity
+    padded with -1 and the per-element node counts."""
+    if n < 4:
+        raise ValueError("a hybrid cube needs n >= 4")
+    hconn = hex_conn(n).astype(np.int64)
+    ci = np.arange(hconn.shape[0]) % n                   # cube x index
+    i0, i1 = n // 4, n // 2
+    trans = np.flatnonzero(ci == i1)
+    cid = coords.shape[0] + np.arange(trans.size)
+    coords = np.concatenate([coords, cube_centres(coords, hconn[trans])])
+    rows = np.full((hconn.shape[0], 11, 8), -1, dtype=np.int64)
+    typ = np.zeros((hconn.shape[0], 11), dtype=np.uint8)
+    m = ci < i0
+    rows[m, :2, :6] = hconn[m][:, PRISM_SPLIT]
+    typ[m, :2] = PEN06
+    m = (ci >= i0) & (ci < i1)
+    rows[m, 0, :8] = hconn[m]
+    typ[m, 0] = HEX08
+    m = ci > i1
+    rows[m, :6, :4] = hconn[m][:, KUHN_TETS]
+    typ[m, :6] = TET04
+    h = hconn[trans]
+    rows[trans, 0, :4] = h[:, PYRAMID_BASES[4]]
+    rows[trans, 0, 4] = cid
+    typ[trans, 0] = PYR05
+    q = 1
+    for f in (0, 1, 2, 3, 5):
+        b = h[:, PYRAMID_BASES[f]]
+        for tri in ((0, 1, 2), (0, 2, 3)):
+            rows[trans, q, :3] = b[:, list(tri)]
+            rows[trans, q, 3] = cid
+            typ[trans, q] = TET04
+            q += 1
+    keep = typ.ravel() > 0
+    conn = rows.reshape(-1, 8)[keep]
+    return (np.ascontiguousarray(coords), np.ascontiguousarray(conn.astype(np.int32)),
+            np.ascontiguousarray(typ.ravel()[keep]))
+
+
 def boundary_nodes(n: int) -> np.ndarray:
     kk, jj, ii = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
     m = (ii == 0) | (ii == n) | (jj == 0) | (jj == n) | (kk == 0) | (kk == n)
     return np.flatnonzero(m.ravel()).astype(np.int32)
 
 
-def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems):
+def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems, types=None):
     """Random renumbering: new id of old node i is pn[i]; elements shuffled.
 
-    node_fields: list of arrays whose LAST axis is the node axis.
+    node_fields: list of arrays whose LAST axis is the node axis.  Padding
+    entries (-1) of the connectivity stay -1; `types` follows the elements.
     """
     N = coords.shape[0]
     E = conn.shape[0]
@@ -158,10 +246,13 @@ def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems):
     inv = np.empty(N, dtype=np.int64)
     inv[pn] = np.arange(N)
     coords2 = np.ascontiguousarray(coords[inv])
-    conn2 = np.ascontiguousarray(pn[conn[pe]].astype(np.int32))
+    c = conn[pe]
+    conn2 = np.ascontiguousarray(np.where(c >= 0, pn[np.maximum(c, 0)], -1).astype(np.int32))
     dir2 = np.sort(pn[dirichlet]).astype(np.int32)
     f2 = [np.ascontiguousarray(f[..., inv]) for f in node_fields]
-    return coords2, conn2, dir2, f2
+    if types is None:
+        return coords2, conn2, dir2, f2
+    return coords2, conn2, dir2, f2, np.ascontiguousarray(types[pe])
 
 
 def taylor_green(coords, rng=None, noise=0.01) -> np.ndarray:
@@ -199,7 +290,21 @@ def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int
     rs = streams(case_id, sub)
     coords = cube_nodes(n, jitter, rs["jitter"])
     hconn = hex_conn(n)
-    conn = hconn if elem_type == HEX08 else kuhn_split(hconn)
+    types = None
+    if elem_type == HEX08:
+        conn = hconn
+    elif elem_type == TET04:
+        conn = kuhn_split(hconn)
+    elif elem_type == PEN06:
+        conn = prism_split(hconn)
+    elif elem_type == PYR05:
+        cid = coords.shape[0] + np.arange(hconn.shape[0])
+        coords = np.ascontiguousarray(np.concatenate([coords, cube_centres(coords, hconn)]))
+        conn = pyramid_split(hconn, cid)
+    elif elem_type == HYBRID:
+        coords, conn, types = hybrid_mesh(n, coords)
+    else:
+        raise ValueError(f"unknown element type {elem_type}")
     dirichlet = boundary_nodes(n)
     N = coords.shape[0]
     u = taylor_green(coords, rs["unoise"], noise)
@@ -213,10 +318,12 @@ def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int
     Y = rs["Y"].uniform(0.0, 1.0, size=(n_scalars, N)) if n_scalars else np.zeros((0, N))
     D = 10.0 ** rs["D"].uniform(-6.0, -4.0, size=n_scalars) if n_scalars else np.zeros(0)
     if shuffle:
-        coords, conn, dirichlet, (u, rho, mu, Y) = permute(
-            coords, conn, dirichlet, [u, rho, mu, Y], rs["nperm"], rs["eperm"])
+        out = permute(coords, conn, dirichlet, [u, rho, mu, Y], rs["nperm"], rs["eperm"], types)
+        coords, conn, dirichlet, (u, rho, mu, Y) = out[:4]
+        if types is not None:
+            types = out[4]
     return Case(elem_type, n, coords, conn.astype(np.int32), dirichlet, u, rho, mu,
-                time_step(n), Y, D, name)
+                time_step(n), Y, D, name, types)
 
 
 # --- the five workloads -----------------------------------------------------

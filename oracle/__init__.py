@@ -43,9 +43,14 @@ def lib():
         i64, i32, dbl = C.c_int64, C.c_int, C.c_double
         L.or_pattern.restype = i64
         L.or_pattern.argtypes = [i32, i64, i64, P, P, P]
+        L.or_pattern_typed.restype = i64
+        L.or_pattern_typed.argtypes = [i32, P, i64, i64, P, P, P]
         L.or_assemble.restype = i32
         L.or_assemble.argtypes = [i32, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
                                   i32, C.POINTER(i64), C.POINTER(dbl)]
+        L.or_assemble_typed.restype = i32
+        L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
+                                        i32, C.POINTER(i64), C.POINTER(dbl)]
         L.or_dirichlet.restype = i32
         L.or_dirichlet.argtypes = [i64, P, P, P, P, i64, P, P]
         L.or_spmv.restype = None
@@ -54,10 +59,10 @@ def lib():
         L.or_dot.argtypes = [i64, P, P]
         L.or_pcg.restype = i32
         L.or_pcg.argtypes = [i64, P, P, P, P, P, dbl, i32, P]
-        for name in ("or_hex08_shape", "or_tet04_shape"):
+        for name in ("or_hex08_shape", "or_tet04_shape", "or_pen06_shape", "or_pyr05_shape"):
             getattr(L, name).restype = None
             getattr(L, name).argtypes = [P, P, P]
-        for name in ("or_hex08_gauss", "or_tet04_gauss"):
+        for name in ("or_hex08_gauss", "or_tet04_gauss", "or_pen06_gauss", "or_pyr05_gauss"):
             getattr(L, name).restype = None
             getattr(L, name).argtypes = [P, P]
         _lib = L
@@ -78,35 +83,43 @@ def _i32(a):
 
 # --- reference element -------------------------------------------------------
 
+_NAMES = {8: "hex08", 6: "pen06", 5: "pyr05", 4: "tet04"}
+_NGAUSS = {8: 8, 6: 6, 5: 8, 4: 4}
+
+
 def shape(nen: int, xi):
     xi = _f64(xi)
     N = np.zeros(nen)
     dN = np.zeros((nen, 3))
-    fn = lib().or_hex08_shape if nen == 8 else lib().or_tet04_shape
-    fn(_p(xi), _p(N), _p(dN))
+    getattr(lib(), "or_%s_shape" % _NAMES[nen])(_p(xi), _p(N), _p(dN))
     return N, dN
 
 
 def gauss(nen: int):
-    ng = 8 if nen == 8 else 4
+    ng = _NGAUSS[nen]
     pts = np.zeros((ng, 3))
     w = np.zeros(ng)
-    fn = lib().or_hex08_gauss if nen == 8 else lib().or_tet04_gauss
-    fn(_p(pts), _p(w))
+    getattr(lib(), "or_%s_gauss" % _NAMES[nen])(_p(pts), _p(w))
     return pts, w
+
+
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
 
 
 # --- assembly ----------------------------------------------------------------
 
-def pattern(conn, n_nodes: int):
+def pattern(conn, n_nodes: int, types=None):
+    """CSR pattern; conn [E, stride], types [E] node counts (None: single type)."""
     conn = _i32(conn)
-    nen = conn.shape[1]
+    types = _u8(types)
+    S = conn.shape[1]
     rowptr = np.zeros(n_nodes + 1, dtype=np.int32)
-    nnz = lib().or_pattern(nen, n_nodes, conn.shape[0], _p(conn), _p(rowptr), None)
+    nnz = lib().or_pattern_typed(S, _p(types), n_nodes, conn.shape[0], _p(conn), _p(rowptr), None)
     if nnz < 0:
         raise ValueError("invalid connectivity")
     colidx = np.zeros(max(nnz, 1), dtype=np.int32)[:nnz]
-    lib().or_pattern(nen, n_nodes, conn.shape[0], _p(conn), _p(rowptr), _p(colidx))
+    lib().or_pattern_typed(S, _p(types), n_nodes, conn.shape[0], _p(conn), _p(rowptr), _p(colidx))
     return rowptr, colidx
 
 
@@ -117,13 +130,17 @@ class AssembleError(RuntimeError):
 
 
 def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None, D=None,
-             pattern_=None, mixed: bool = False):
-    """Return (rowptr, colidx, values[n_mat, nnz], rhs[n_rhs, N])."""
+             pattern_=None, mixed: bool = False, types=None):
+    """Return (rowptr, colidx, values[n_mat, nnz], rhs[n_rhs, N]).
+
+    conn [E, stride]; types [E] per-element node counts for a mixed mesh
+    (None: every element has `stride` nodes)."""
     coords = _f64(coords)
     conn = _i32(conn)
+    types = _u8(types)
     N = coords.shape[0]
-    nen = conn.shape[1]
-    rowptr, colidx = pattern_ if pattern_ is not None else pattern(conn, N)
+    S = conn.shape[1]
+    rowptr, colidx = pattern_ if pattern_ is not None else pattern(conn, N, types)
     nnz = int(rowptr[-1])
     ns = 0 if Y is None else int(np.asarray(Y).shape[0])
     n_mat = ns if op == OP_SCALAR else 1
@@ -137,9 +154,9 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
     rhs = np.zeros((n_rhs, N))
     bad = C.c_int64(-1)
     mdet = C.c_double(0.0)
-    st = lib().or_assemble(nen, N, _p(coords), conn.shape[0], _p(conn), op, dt, _p(u), _p(rho), _p(mu),
-                           ns, _p(Yp), _p(Dp), _p(rowptr), _p(colidx), _p(values), _p(rhs),
-                           1 if mixed else 0, C.byref(bad), C.byref(mdet))
+    st = lib().or_assemble_typed(S, _p(types), N, _p(coords), conn.shape[0], _p(conn), op, dt, _p(u),
+                                 _p(rho), _p(mu), ns, _p(Yp), _p(Dp), _p(rowptr), _p(colidx),
+                                 _p(values), _p(rhs), 1 if mixed else 0, C.byref(bad), C.byref(mdet))
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return rowptr, colidx, values, rhs

@@ -28,10 +28,22 @@
  *    (Algorithm 1, last step; Section 5.2 names its SpMV, AXPY and dot
  *    kernels).
  *
- * Reference elements: HEX08 trilinear with the 2x2x2 Gauss rule at +-1/sqrt3
- * (weights 1, xi fastest); TET04 linear with the 4-point rule at the
- * barycentric permutations of (b,a,a,a), a = (5-sqrt5)/20, b = 1-3a,
- * weights 1/24.  Jacobian J_ij = d x_i / d xi_j; grad N = J^-T grad_ref N.
+ * Reference elements (the paper's meshes mix tetrahedra, pyramids, prisms
+ * and hexahedra, Sections 3 and 4.2; it gives no element formulation, so
+ * these are the standard isoparametric ones):
+ *  - HEX08 trilinear with the 2x2x2 Gauss rule at +-1/sqrt3 (weights 1, xi
+ *    fastest);
+ *  - TET04 linear with the 4-point rule at the barycentric permutations of
+ *    (b,a,a,a), a = (5-sqrt5)/20, b = 1-3a, weights 1/24;
+ *  - PEN06 (prism) linear-triangle x linear-line with the 3-point triangle
+ *    rule x 2-point Gauss-Legendre (6 points);
+ *  - PYR05 (pyramid) with the rational basis that is bilinear on the base
+ *    and linear on the triangular faces, and the 8-point conical product
+ *    rule (2x2 Gauss-Legendre in collapsed coordinates x 2-point
+ *    Gauss-Jacobi for the weight (1-zeta)^2).
+ * Jacobian J_ij = d x_i / d xi_j; grad N = J^-T grad_ref N.  A mesh may mix
+ * types: the typed entry points take a padded connectivity of stride S and
+ * one node count (4, 5, 6 or 8) per element.
  */
 #include <math.h>
 #include <stdint.h>
@@ -116,22 +128,131 @@ void or_tet04_gauss(double *pts, double *w)
     }
 }
 
+/* Prism on the reference triangle (0,0),(1,0),(0,1) extruded over zeta in
+ * [-1,1]: nodes 0-2 on the triangle at zeta = -1, nodes 3-5 above them at
+ * zeta = +1.  N_a = L_i(xi,eta) (1 -+ zeta)/2 with the barycentric
+ * L = (1-xi-eta, xi, eta). */
+void or_pen06_shape(const double *xi, double *N, double *dN)
+{
+    const double L[3] = {1.0 - xi[0] - xi[1], xi[0], xi[1]};
+    static const double dL[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
+    for (int h = 0; h < 2; ++h) {
+        double s = h ? 1.0 : -1.0;
+        double f = 0.5 * (1.0 + s * xi[2]);
+        for (int i = 0; i < 3; ++i) {
+            int a = 3 * h + i;
+            N[a] = L[i] * f;
+            dN[a * 3 + 0] = dL[i][0] * f;
+            dN[a * 3 + 1] = dL[i][1] * f;
+            dN[a * 3 + 2] = 0.5 * s * L[i];
+        }
+    }
+}
+
+/* Triangle points (1/6,1/6), (2/3,1/6), (1/6,2/3) with weight 1/6 each
+ * (degree 2), times Gauss-Legendre +-1/sqrt3 in zeta; triangle point
+ * fastest.  Reference volume 1. */
+void or_pen06_gauss(double *pts, double *w)
+{
+    static const double tp[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+    double g = 1.0 / sqrt(3.0);
+    int q = 0;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 3; ++i) {
+            pts[q * 3 + 0] = tp[i][0];
+            pts[q * 3 + 1] = tp[i][1];
+            pts[q * 3 + 2] = k ? g : -g;
+            w[q] = 1.0 / 6.0;
+            ++q;
+        }
+}
+
+/* Pyramid with the square base [-1,1]^2 at zeta = 0 (nodes 0-3 at
+ * (-1,-1), (1,-1), (1,1), (-1,1): counter-clockwise seen from the apex) and
+ * the apex, node 4, at (0,0,1).  With m = 1 - zeta and (xa, ya) the base
+ * node's corner, N_a = (m + xa xi)(m + ya eta) / (4 m) and N_4 = zeta:
+ * bilinear on the base, linear on every triangular face, so it conforms with
+ * HEX08 across the base and with TET04 across the sides.  Its derivatives
+ * follow from the quotient rule; d/dzeta reduces to
+ * (xa ya xi eta - m^2) / (4 m^2). */
+void or_pyr05_shape(const double *xi, double *N, double *dN)
+{
+    static const double B[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+    double m = 1.0 - xi[2];
+    for (int a = 0; a < 4; ++a) {
+        double P = m + B[a][0] * xi[0], Q = m + B[a][1] * xi[1];
+        N[a] = P * Q / (4.0 * m);
+        dN[a * 3 + 0] = B[a][0] * Q / (4.0 * m);
+        dN[a * 3 + 1] = B[a][1] * P / (4.0 * m);
+        dN[a * 3 + 2] = (B[a][0] * B[a][1] * xi[0] * xi[1] - m * m) / (4.0 * m * m);
+    }
+    N[4] = xi[2];
+    dN[12] = 0.0;
+    dN[13] = 0.0;
+    dN[14] = 1.0;
+}
+
+/* Conical product rule: (xi, eta) = (1 - zeta)(s, t) with s, t = +-1/sqrt3
+ * (Gauss-Legendre, weights 1) and zeta at the 2-point Gauss-Jacobi nodes for
+ * the weight (1-zeta)^2 on [0,1], the roots 1/3 -+ sqrt(10)/15 of
+ * t^2 - 2t/3 + 1/15, with weights 1/6 +- sqrt(10)/48 (sum 1/3).  s fastest,
+ * then t, then zeta.  Reference volume 4/3. */
+void or_pyr05_gauss(double *pts, double *w)
+{
+    double g = 1.0 / sqrt(3.0), r = sqrt(10.0);
+    const double zt[2] = {1.0 / 3.0 - r / 15.0, 1.0 / 3.0 + r / 15.0};
+    const double zw[2] = {1.0 / 6.0 + r / 48.0, 1.0 / 6.0 - r / 48.0};
+    int q = 0;
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) {
+                double m = 1.0 - zt[k];
+                pts[q * 3 + 0] = (i ? g : -g) * m;
+                pts[q * 3 + 1] = (j ? g : -g) * m;
+                pts[q * 3 + 2] = zt[k];
+                w[q] = zw[k];
+                ++q;
+            }
+}
+
 static int ref_element(int nen, double pts[MAXG][3], double w[MAXG],
                        double N[MAXG][MAXN], double dN[MAXG][MAXN][3])
 {
     int ng;
+    void (*shape)(const double *, double *, double *);
     if (nen == 8) {
         or_hex08_gauss(&pts[0][0], w);
         ng = 8;
-        for (int g = 0; g < ng; ++g) or_hex08_shape(pts[g], N[g], &dN[g][0][0]);
+        shape = or_hex08_shape;
+    } else if (nen == 6) {
+        or_pen06_gauss(&pts[0][0], w);
+        ng = 6;
+        shape = or_pen06_shape;
+    } else if (nen == 5) {
+        or_pyr05_gauss(&pts[0][0], w);
+        ng = 8;
+        shape = or_pyr05_shape;
     } else if (nen == 4) {
         or_tet04_gauss(&pts[0][0], w);
         ng = 4;
-        for (int g = 0; g < ng; ++g) or_tet04_shape(pts[g], N[g], &dN[g][0][0]);
+        shape = or_tet04_shape;
     } else {
         return -1;
     }
+    for (int g = 0; g < ng; ++g) shape(pts[g], N[g], &dN[g][0][0]);
     return ng;
+}
+
+/* Node count of element e: the type array (4, 5, 6 or 8 per element) if
+ * given, else the connectivity stride (a single-type mesh). */
+static int elem_nen(int stride, const uint8_t *types, int64_t e)
+{
+    return types ? (int)types[e] : stride;
+}
+
+static int valid_nen(int nen, int stride)
+{
+    return (nen == 4 || nen == 5 || nen == 6 || nen == 8) && nen <= stride;
 }
 
 /* ------------------------------------------------------------------ */
@@ -146,24 +267,29 @@ static int cmp_i32(const void *a, const void *b)
 }
 
 /* Pass colidx == NULL to get nnz and rowptr; call again to fill colidx.
- * Returns nnz, or -1 on an invalid connectivity entry. */
-int64_t or_pattern(int nen, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
-                   int32_t *rowptr, int32_t *colidx)
+ * conn [n_elems][stride]; element e has elem_nen() nodes, the rest of its
+ * slots are ignored.  Returns nnz, or -1 on an invalid connectivity entry or
+ * element type. */
+int64_t or_pattern_typed(int stride, const uint8_t *types, int64_t n_nodes, int64_t n_elems,
+                         const int32_t *conn, int32_t *rowptr, int32_t *colidx)
 {
     int64_t *cnt = calloc((size_t)n_nodes + 1, sizeof(int64_t));
     if (!cnt) return -1;
-    for (int64_t e = 0; e < n_elems; ++e)
+    for (int64_t e = 0; e < n_elems; ++e) {
+        int nen = elem_nen(stride, types, e);
+        if (!valid_nen(nen, stride)) { free(cnt); return -1; }
         for (int a = 0; a < nen; ++a) {
-            int32_t v = conn[e * nen + a];
+            int32_t v = conn[e * stride + a];
             if (v < 0 || v >= n_nodes) { free(cnt); return -1; }
             cnt[v + 1]++;
         }
+    }
     for (int64_t i = 0; i < n_nodes; ++i) cnt[i + 1] += cnt[i];
     int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
     int64_t *inc = malloc(sizeof(int64_t) * (size_t)(cnt[n_nodes] + 1));
     memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n_nodes + 1));
     for (int64_t e = 0; e < n_elems; ++e)
-        for (int a = 0; a < nen; ++a) inc[fill[conn[e * nen + a]]++] = e;
+        for (int a = 0; a < elem_nen(stride, types, e); ++a) inc[fill[conn[e * stride + a]]++] = e;
     int32_t *buf = malloc(sizeof(int32_t) * 4096);
     size_t cap = 4096;
     int64_t nnz = 0;
@@ -172,11 +298,12 @@ int64_t or_pattern(int nen, int64_t n_nodes, int64_t n_elems, const int32_t *con
         size_t m = 0;
         for (int64_t k = cnt[i]; k < cnt[i + 1]; ++k) {
             int64_t e = inc[k];
+            int nen = elem_nen(stride, types, e);
             if (m + (size_t)nen > cap) {
                 cap *= 2;
                 buf = realloc(buf, sizeof(int32_t) * cap);
             }
-            for (int a = 0; a < nen; ++a) buf[m++] = conn[e * nen + a];
+            for (int a = 0; a < nen; ++a) buf[m++] = conn[e * stride + a];
         }
         qsort(buf, m, sizeof(int32_t), cmp_i32);
         size_t u = 0;
@@ -192,6 +319,13 @@ int64_t or_pattern(int nen, int64_t n_nodes, int64_t n_elems, const int32_t *con
     free(fill);
     free(cnt);
     return nnz;
+}
+
+/* Single-type mesh: conn [n_elems][nen]. */
+int64_t or_pattern(int nen, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
+                   int32_t *rowptr, int32_t *colidx)
+{
+    return or_pattern_typed(nen, NULL, n_nodes, n_elems, conn, rowptr, colidx);
 }
 
 static int64_t find_col(const int32_t *rowptr, const int32_t *colidx, int32_t i, int32_t j)
@@ -259,19 +393,24 @@ static double geometry(int nen, double X[MAXN][3], double dNr[MAXN][3], double d
  * mixed != 0 reproduces, for characterisation only, FP32 quadrature: the
  * Gauss-point inputs are rounded to float, the products and the elemental
  * sums are float, the elemental matrix is widened to double and assembled in
- * double.  Inputs: coords [N][3]; conn [E][nen]; u [3][N]; rho, mu [N];
+ * double.  Inputs: coords [N][3]; conn [E][stride], element e using its
+ * first elem_nen() slots; u [3][N]; rho, mu [N];
  * Y [k][N]; D [k].  Outputs are overwritten.  Returns OR_EBADELEM (with the
  * first element index and the smallest det J) for det J <= 0.
  */
-int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
-                const int32_t *conn, int op, double dt, const double *u, const double *rho,
-                const double *mu, int n_scalars, const double *Y, const double *D,
-                const int32_t *rowptr, const int32_t *colidx, double *values, double *rhs,
-                int mixed, int64_t *bad_elem, double *min_det)
+int or_assemble_typed(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
+                      int64_t n_elems, const int32_t *conn, int op, double dt, const double *u,
+                      const double *rho, const double *mu, int n_scalars, const double *Y,
+                      const double *D, const int32_t *rowptr, const int32_t *colidx, double *values,
+                      double *rhs, int mixed, int64_t *bad_elem, double *min_det)
 {
-    double pts[MAXG][3], w[MAXG], Ng[MAXG][MAXN], dNr[MAXG][MAXN][3];
-    int ng = ref_element(nen, pts, w, Ng, dNr);
-    if (ng < 0) return OR_EINVAL;
+    /* reference tables of every element type, indexed by node count */
+    double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], Nt[MAXN + 1][MAXG][MAXN],
+        dNt[MAXN + 1][MAXG][MAXN][3];
+    int ngt[MAXN + 1];
+    for (int t = 0; t <= MAXN; ++t) ngt[t] = ref_element(t, pts[t], w[t], Nt[t], dNt[t]);
+    for (int64_t e = 0; e < n_elems; ++e)
+        if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
     if (op == OP_SCALAR && (n_scalars < 1 || n_scalars > MAXS)) return OR_EINVAL;
     int n_mat = (op == OP_SCALAR) ? n_scalars : 1;
     int n_rhs = (op == OP_MOMENTUM) ? 3 : (op == OP_SCALAR ? n_scalars : 1);
@@ -283,7 +422,11 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
     int status = OR_OK;
 
     for (int64_t e = 0; e < n_elems; ++e) {
-        const int32_t *c = conn + e * nen;
+        const int nen = elem_nen(stride, types, e), ng = ngt[nen];
+        double (*Ng)[MAXN] = Nt[nen];
+        double (*dNr)[MAXN][3] = dNt[nen];
+        const double *wg = w[nen];
+        const int32_t *c = conn + e * stride;
         double X[MAXN][3];
         for (int a = 0; a < nen; ++a)
             for (int i = 0; i < 3; ++i) X[a][i] = coords[(int64_t)c[a] * 3 + i];
@@ -302,7 +445,7 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
                 status = OR_EBADELEM;
                 break;
             }
-            double dV = w[g] * det;
+            double dV = wg[g] * det;
             double rg = 0.0, mg = 0.0, ug[3] = {0.0, 0.0, 0.0}, yg[MAXS] = {0};
             for (int a = 0; a < nen; ++a) {
                 double Na = Ng[g][a];
@@ -400,6 +543,17 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
         }
     }
     return status;
+}
+
+/* Single-type mesh: conn [n_elems][nen]. */
+int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
+                const int32_t *conn, int op, double dt, const double *u, const double *rho,
+                const double *mu, int n_scalars, const double *Y, const double *D,
+                const int32_t *rowptr, const int32_t *colidx, double *values, double *rhs,
+                int mixed, int64_t *bad_elem, double *min_det)
+{
+    return or_assemble_typed(nen, NULL, n_nodes, coords, n_elems, conn, op, dt, u, rho, mu,
+                             n_scalars, Y, D, rowptr, colidx, values, rhs, mixed, bad_elem, min_det);
 }
 
 /* ------------------------------------------------------------------ */
