@@ -99,14 +99,14 @@ def assembly_roofline(workload, E, ms_mom, ms_poi, ms_mix):
             "poisson_hbm_frac": f["poisson_hbm_bytes_per_operator"] / (ms_poi * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def momentum_bytes(nnz, n, e, nen):
-    # coords 24 + u 24 + rho 8 + mu 8 per node, conn 4 nen per element,
-    # values 8 per entry, rhs 24 per node (written once)
-    return n * 64 + e * 4 * nen + nnz * 8 + n * 24
+def momentum_bytes(nnz, n, conn_entries):
+    # coords 24 + u 24 + rho 8 + mu 8 per node, 4 per connectivity entry
+    # (nen per element), values 8 per entry, rhs 24 per node (written once)
+    return n * 64 + 4 * conn_entries + nnz * 8 + n * 24
 
 
-def poisson_bytes(nnz, n, e, nen):
-    return n * 56 + e * 4 * nen + nnz * 8 + n * 8
+def poisson_bytes(nnz, n, conn_entries):
+    return n * 56 + 4 * conn_entries + nnz * 8 + n * 8
 
 
 def measured_traffic(workload):
@@ -148,6 +148,9 @@ def make_workload(name):
         return meshgen.cfg1(64), "hex08-64^3-shuffled-jitter15: momentum+Poisson assembly, Dirichlet, 200 PCG"
     if name == "tet128":
         return meshgen.cfg2(128), "tet04-6x128^3-flame: momentum+Poisson assembly, Dirichlet, 200 PCG"
+    if name == "hybrid128":
+        return meshgen.hybrid(128), ("hybrid-128^3-flame (prism | hex | pyramid-tet transition | tet slabs): "
+                                     "momentum+Poisson assembly, Dirichlet, 200 PCG")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -420,7 +423,14 @@ def main():
     log(f"workload {wl}: N={case.n_nodes} E={case.n_elems}")
     ctx = fe.Context(0)
     t0 = time.perf_counter()
-    mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=True)
+    if case.types is None:
+        mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=True)
+        conn_entries = case.n_elems * case.nen
+        type_counts = {str(case.nen): case.n_elems}
+    else:
+        mesh = fe.Mesh(ctx, fe.HYBRID, case.coords, case.conn, case.dirichlet, renumber=True, types=case.types)
+        conn_entries = int(case.types.astype(np.int64).sum())
+        type_counts = {str(t): int(c) for t, c in enumerate(np.bincount(case.types)) if c}
     upload_s = time.perf_counter() - t0
     info = mesh.info()
     log(f"mesh uploaded in {upload_s:.2f} s: nnz={mesh.nnz} blocks={info['n_blocks']} colours={info['n_colors']}")
@@ -511,7 +521,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl, "elements": E, "nodes": N, "nnz": nnz, "cg_iterations": CG_ITERS,
-                   "blocks": info["n_blocks"], "colours": info["n_colors"]},
+                   "blocks": info["n_blocks"], "colours": info["n_colors"],
+                   "elements_by_nodes_per_element": type_counts},
         "roofline": {"bound": "hbm", "kernel": "k_cg_spmv_pq (CSR SpMV fused with p.Ap)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload), "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_us,
@@ -520,8 +531,8 @@ def main():
             "assembly_ms_per_step": ms_asm / prof_steps,
             "momentum_assembly_ms": ms_mom, "poisson_assembly_ms": ms_poi,
             "momentum_melem_s": E / (ms_mom * 1e-3) / 1e6, "poisson_melem_s": E / (ms_poi * 1e-3) / 1e6,
-            "momentum_effective_gbs": momentum_bytes(nnz, N, E, mesh.nen) / (ms_mom * 1e-3) / 1e9,
-            "poisson_effective_gbs": poisson_bytes(nnz, N, E, mesh.nen) / (ms_poi * 1e-3) / 1e9,
+            "momentum_effective_gbs": momentum_bytes(nnz, N, conn_entries) / (ms_mom * 1e-3) / 1e9,
+            "poisson_effective_gbs": poisson_bytes(nnz, N, conn_entries) / (ms_poi * 1e-3) / 1e9,
             "momentum_mixed_assembly_ms": ms_mix, "momentum_mixed_melem_s": E / (ms_mix * 1e-3) / 1e6,
             "momentum_mixed_vs_fp64": mixed_err,
             "assembly_roofline": assembly_roofline(args.workload, E, ms_mom, ms_poi, ms_mix),

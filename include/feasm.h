@@ -49,7 +49,9 @@ typedef enum {
     FE_EBUSY = 8        /* serving: no slot free */
 } fe_status;
 
-typedef enum { FE_TET04 = 4, FE_HEX08 = 8 } fe_elem_type;   /* value = nodes per element */
+/* Element types, value = nodes per element (the paper's meshes mix
+ * tetrahedra, pyramids, prisms and hexahedra: Sections 3 and 4.2). */
+typedef enum { FE_TET04 = 4, FE_PYR05 = 5, FE_PEN06 = 6, FE_HEX08 = 8 } fe_elem_type;
 typedef enum { FE_FP64 = 0, FE_MIXED = 1 } fe_precision;
 typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_operator;
 
@@ -77,10 +79,15 @@ fe_status fe_ctx_set_stream(fe_ctx ctx, void *hip_stream);
  * Preprocess and upload a single-type mesh (Section 4.2: unstructured mesh;
  * Section 4.3: elements grouped and renumbered for SIMD/SIMT execution).
  *   coords  host [n_nodes][3] float64 (user numbering)
- *   conn    host [n_elems][nen] int32, 0-based.  HEX08 node order
- *           0:(-,-,-) 1:(+,-,-) 2:(+,+,-) 3:(-,+,-) 4:(-,-,+) 5:(+,-,+)
- *           6:(+,+,+) 7:(-,+,+) in the reference cube; TET04 vertices
- *           positively oriented (det J > 0)
+ *   conn    host [n_elems][nen] int32, 0-based, every element positively
+ *           oriented (det J > 0).  Node orders:
+ *           HEX08 0:(-,-,-) 1:(+,-,-) 2:(+,+,-) 3:(-,+,-) 4:(-,-,+) 5:(+,-,+)
+ *                 6:(+,+,+) 7:(-,+,+) in the reference cube [-1,1]^3;
+ *           PEN06 (prism) 0,1,2 a triangle, 3,4,5 the nodes opposite 0,1,2
+ *                 (reference triangle (0,0),(1,0),(0,1) at zeta = -1, +1);
+ *           PYR05 (pyramid) 0-3 the quadrilateral base, counter-clockwise
+ *                 seen from the apex 4 (reference (+-1,+-1,0), apex (0,0,1));
+ *           TET04 vertices 0-3 of (0,0,0),(1,0,0),(0,1,0),(0,0,1).
  *   dirichlet_nodes host [n_dirichlet] user node ids, or NULL if n_dirichlet = 0
  * Builds the canonical CSR pattern (row i = every node sharing an element
  * with node i, columns ascending, explicit zeros kept), the element blocks,
@@ -91,13 +98,29 @@ fe_status fe_mesh_upload(fe_ctx ctx, fe_elem_type type, int64_t n_nodes, const d
                          int64_t n_elems, const int32_t *conn, int64_t n_dirichlet,
                          const int32_t *dirichlet_nodes, uint32_t flags, fe_mesh *out);
 
+/*
+ * Hybrid mesh (the paper's meshes mix element types; Section 4.3 groups the
+ * elements by type for vector execution): as fe_mesh_upload, with
+ *   elem_types host [n_elems] uint8, the node count of each element
+ *              (4 TET04, 5 PYR05, 6 PEN06, 8 HEX08)
+ *   conn       host [n_elems][8] int32: element e's nodes in its first
+ *              elem_types[e] slots, in its type's node order; the other
+ *              slots are ignored.
+ * Elements are grouped by type, every element block holds one type, and an
+ * assembly runs one launch per (colour, type).  Errors: FE_EINVAL for an
+ * unknown type, as fe_mesh_upload otherwise.
+ */
+fe_status fe_mesh_upload_mixed(fe_ctx ctx, int64_t n_nodes, const double *coords, int64_t n_elems,
+                               const uint8_t *elem_types, const int32_t *conn, int64_t n_dirichlet,
+                               const int32_t *dirichlet_nodes, uint32_t flags, fe_mesh *out);
+
 typedef struct {
-    int32_t nen;              /* nodes per element */
+    int32_t nen;              /* nodes per element (the largest type of a hybrid mesh) */
     int64_t n_nodes, n_elems, nnz;
     const int32_t *rowptr;    /* device [n_nodes+1], mesh numbering */
     const int32_t *colidx;    /* device [nnz], ascending per row */
     int64_t n_blocks;         /* element blocks (one wavefront each) */
-    int32_t n_colors;         /* block colours = assembly launches per operator */
+    int32_t n_colors;         /* block colours (assembly launches per operator: one per colour and type) */
     int32_t max_row;          /* longest CSR row */
     int64_t n_dirichlet;
     size_t device_bytes;      /* device memory held by the mesh */
@@ -295,8 +318,20 @@ fe_status fe_plan_info(fe_plan plan, fe_plan_desc *out);
 fe_status fe_plan_export(fe_plan plan, int32_t *node_perm, int32_t *elem_perm, int32_t *rowptr,
                          int32_t *colidx, int32_t *block_elem_ptr, int32_t *block_color,
                          int32_t *block_node_ptr, int32_t *block_nodes);
+/* Same preprocessing as fe_mesh_upload_mixed, kept on the host. */
+fe_status fe_plan_create_mixed(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *elem_types,
+                               const int32_t *conn, uint32_t flags, fe_plan *out);
+/* Types of the plan (any pointer may be NULL): elem_types[n_elems] per
+ * element in mesh order, block_types[n_blocks], and the assembly launches as
+ * launches[3 * n_launches] = {nodes per element, first, count} over the
+ * colour-ordered block list (*n_launches receives their number; size the
+ * array by a first call with launches = NULL). */
+fe_status fe_plan_export_types(fe_plan plan, uint8_t *elem_types, uint8_t *block_types, int32_t *launches,
+                               int64_t *n_launches);
+/* color_blocks[n_blocks]: the blocks in launch order (by colour, then type). */
+fe_status fe_plan_export_color_blocks(fe_plan plan, int32_t *color_blocks);
 void fe_plan_free(fe_plan plan);
-/* Message for the last failure of fe_plan_create on this thread. */
+/* Message for the last failure of fe_plan_create(_mixed) on this thread. */
 const char *fe_plan_last_error(void);
 
 /* Pack layout of Section 4.3: n_elems elements of one type in packs of

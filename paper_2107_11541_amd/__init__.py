@@ -23,14 +23,15 @@ import numpy as np
 
 from . import capi
 from .capi import (FE_FP64, FE_HEX08, FE_MIXED, FE_OP_MOMENTUM, FE_OP_POISSON, FE_OP_SCALAR,
-                   FE_TET04, FE_UPLOAD_RENUMBER)
+                   FE_PEN06, FE_PYR05, FE_TET04, FE_UPLOAD_RENUMBER)
 
-HEX08, TET04 = FE_HEX08, FE_TET04
+HEX08, PEN06, PYR05, TET04 = FE_HEX08, FE_PEN06, FE_PYR05, FE_TET04
+HYBRID = 0   # mixed element types: Mesh(..., types=...) with conn [E, 8]
 MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
-           "FeError", "HEX08", "TET04", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
+           "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
 class FeError(RuntimeError):
@@ -125,19 +126,32 @@ class Context:
 class Mesh:
     """A preprocessed, device-resident mesh (fe_mesh_upload)."""
 
-    def __init__(self, ctx: Context, elem_type: int, coords, conn, dirichlet=None, renumber: bool = True):
+    def __init__(self, ctx: Context, elem_type: int, coords, conn, dirichlet=None, renumber: bool = True,
+                 types=None):
+        """elem_type: HEX08, PEN06, PYR05, TET04 (conn [E, nen]) or HYBRID with
+        types [E] node counts and conn [E, 8] (fe_mesh_upload_mixed)."""
         self.ctx = ctx
         lib = ctx.lib
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
-        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != elem_type:
-            raise ValueError("coords must be [N,3] and conn [E,nen]")
+        width = 8 if elem_type == HYBRID else elem_type
+        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != width:
+            raise ValueError("coords must be [N,3] and conn [E,nen] ([E,8] for a hybrid mesh)")
+        if (elem_type == HYBRID) != (types is not None):
+            raise ValueError("types are given exactly for a HYBRID mesh")
         d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.int32)
+        nd, dp = (0, None) if d is None else (d.shape[0], d.ctypes.data)
+        flags = FE_UPLOAD_RENUMBER if renumber else 0
         h = C.c_void_p()
-        st = lib.fe_mesh_upload(ctx.h, elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
-                                conn.ctypes.data, 0 if d is None else d.shape[0],
-                                None if d is None else d.ctypes.data,
-                                FE_UPLOAD_RENUMBER if renumber else 0, C.byref(h))
+        if types is None:
+            st = lib.fe_mesh_upload(ctx.h, elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                    conn.ctypes.data, nd, dp, flags, C.byref(h))
+        else:
+            types = np.ascontiguousarray(types, dtype=np.uint8)
+            if types.shape != (conn.shape[0],):
+                raise ValueError("types must be [E]")
+            st = lib.fe_mesh_upload_mixed(ctx.h, coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                          types.ctypes.data, conn.ctypes.data, nd, dp, flags, C.byref(h))
         ctx.check(st)
         self.h = h
         ctx._meshes.add(self)
@@ -390,13 +404,19 @@ class Server:
 class Plan:
     """Host-only preprocessing (fe_plan_create): no device needed."""
 
-    def __init__(self, elem_type: int, coords, conn, renumber: bool = True):
+    def __init__(self, elem_type: int, coords, conn, renumber: bool = True, types=None):
         self.lib = capi.load()
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
+        flags = FE_UPLOAD_RENUMBER if renumber else 0
         h = C.c_void_p()
-        st = self.lib.fe_plan_create(elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
-                                     conn.ctypes.data, FE_UPLOAD_RENUMBER if renumber else 0, C.byref(h))
+        if types is None:
+            st = self.lib.fe_plan_create(elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                         conn.ctypes.data, flags, C.byref(h))
+        else:
+            types = np.ascontiguousarray(types, dtype=np.uint8)
+            st = self.lib.fe_plan_create_mixed(coords.shape[0], coords.ctypes.data, conn.shape[0],
+                                               types.ctypes.data, conn.ctypes.data, flags, C.byref(h))
         if st != capi.FE_OK:
             raise FeError(st, self.lib.fe_plan_last_error().decode())
         self.h = h
@@ -418,6 +438,15 @@ class Plan:
         a = [out[k].ctypes.data for k in ("node_perm", "elem_perm", "rowptr", "colidx", "block_elem_ptr",
                                           "block_color", "block_node_ptr", "block_nodes")]
         self.lib.fe_plan_export(self.h, *a)
+        nl = C.c_int64()
+        out["elem_types"] = np.zeros(E, np.uint8)
+        out["block_types"] = np.zeros(nb, np.uint8)
+        self.lib.fe_plan_export_types(self.h, None, None, None, C.byref(nl))
+        out["launches"] = np.zeros((nl.value, 3), np.int32)
+        self.lib.fe_plan_export_types(self.h, out["elem_types"].ctypes.data, out["block_types"].ctypes.data,
+                                      out["launches"].ctypes.data, C.byref(nl))
+        out["color_blocks"] = np.zeros(nb, np.int32)
+        self.lib.fe_plan_export_color_blocks(self.h, out["color_blocks"].ctypes.data)
         return out
 
     def __del__(self):

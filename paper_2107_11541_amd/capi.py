@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libfeasm.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EBADMESH, FE_EBADELEM, FE_ENOCONV, FE_EBREAKDOWN, FE_EDEVICE, FE_EBUSY = range(9)
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EBADMESH", 4: "FE_EBADELEM",
                 5: "FE_ENOCONV", 6: "FE_EBREAKDOWN", 7: "FE_EDEVICE", 8: "FE_EBUSY"}
-FE_TET04, FE_HEX08 = 4, 8
+FE_TET04, FE_PYR05, FE_PEN06, FE_HEX08 = 4, 5, 6, 8
 FE_FP64, FE_MIXED = 0, 1
 FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON = 0, 1, 2
 FE_UPLOAD_RENUMBER = 1
@@ -63,6 +63,7 @@ SIGNATURES = {
     "fe_ctx_last_error": (C.c_char_p, [P]),
     "fe_ctx_set_stream": (C.c_int, [P, P]),
     "fe_mesh_upload": (C.c_int, [P, C.c_int, i64, P, i64, P, i64, P, C.c_uint32, C.POINTER(P)]),
+    "fe_mesh_upload_mixed": (C.c_int, [P, i64, P, i64, P, P, i64, P, C.c_uint32, C.POINTER(P)]),
     "fe_mesh_info": (C.c_int, [P, C.POINTER(MeshDesc)]),
     "fe_mesh_perm": (C.c_int, [P, P, P]),
     "fe_mesh_pattern_host": (C.c_int, [P, P, P]),
@@ -84,6 +85,9 @@ SIGNATURES = {
     "fe_ctx_profile": (C.c_int, [P, C.c_int]),
     "fe_ctx_profile_read": (C.c_int, [P, C.c_int, C.POINTER(i64), C.POINTER(dbl)]),
     "fe_plan_create": (C.c_int, [C.c_int, i64, P, i64, P, C.c_uint32, C.POINTER(P)]),
+    "fe_plan_create_mixed": (C.c_int, [i64, P, i64, P, P, C.c_uint32, C.POINTER(P)]),
+    "fe_plan_export_types": (C.c_int, [P, P, P, P, C.POINTER(i64)]),
+    "fe_plan_export_color_blocks": (C.c_int, [P, P]),
     "fe_plan_info": (C.c_int, [P, C.POINTER(PlanDesc)]),
     "fe_plan_export": (C.c_int, [P, P, P, P, P, P, P, P, P]),
     "fe_plan_free": (None, [P]),

@@ -6,10 +6,11 @@
 // CSR.  Section 4.3 packs elements so that a SIMD unit processes several at
 // once.  gfx950 form:
 //
-//   * one work-group = one block of <= 64 spatially compact elements; a
-//     TET04 element is one lane, a HEX08 element two lanes in two waves
-//     (4 matrix rows each), which keeps a wave under 256 registers so that
-//     two blocks share each SIMD and hide each other's memory latency;
+//   * one work-group = one block of <= 64 spatially compact elements of one
+//     type; a TET04, PYR05 or PEN06 element is one lane, a HEX08 element two
+//     lanes in two waves (4 matrix rows each), which keeps a wave under 256
+//     registers so that two blocks share each SIMD and hide each other's
+//     memory latency;
 //   * the block's nodal fields are staged in LDS (structure of arrays, so that
 //     lanes reading different nodes hit different banks);
 //   * the CSR rows the block touches live in an LDS image, initialised from
@@ -17,9 +18,9 @@
 //     conflict-free ds_add_f64 in a fixed (phase, a, b) order, and written
 //     back once -- one coalesced read-modify-write per touched row instead of
 //     one per element entry;
-//   * blocks of one colour share no node, so a launch per colour needs no
-//     atomics in HBM; the colour order fixes the summation order, so the
-//     result is bitwise reproducible.
+//   * blocks of one colour share no node, so a launch per (colour, element
+//     type) needs no atomics in HBM; the launch order fixes the summation
+//     order, so the result is bitwise reproducible.
 //
 // Precision: FP64, or (mixed) FP32 Gauss-point products and elemental sums
 // with the Jacobian, det J, J^-1 and the CSR accumulation in FP64.
@@ -54,23 +55,25 @@ struct Hex {
     }
 };
 
-struct HexTables {
-    double N[8][8];        // N[g][a]
-    double dN[8][8][3];    // dN[g][a][j]
+// Shape-function values and reference gradients at the Gauss points of an
+// element type, for the rolled Gauss loop (read from constant memory).
+template <class EL> struct RefTables {
+    double N[EL::NG][EL::NEN];        // N[g][a]
+    double dN[EL::NG][EL::NEN][3];    // dN[g][a][j]
 };
 
-constexpr HexTables make_hex_tables()
+template <class EL> constexpr RefTables<EL> make_tables()
 {
-    HexTables t{};
-    for (int g = 0; g < 8; ++g)
-        for (int a = 0; a < 8; ++a) {
-            t.N[g][a] = Hex::N(g, a);
-            for (int j = 0; j < 3; ++j) t.dN[g][a][j] = Hex::dN(g, a, j);
+    RefTables<EL> t{};
+    for (int g = 0; g < EL::NG; ++g)
+        for (int a = 0; a < EL::NEN; ++a) {
+            t.N[g][a] = EL::N(g, a);
+            for (int j = 0; j < 3; ++j) t.dN[g][a][j] = EL::dN(g, a, j);
         }
     return t;
 }
 
-__constant__ HexTables kHexTab = make_hex_tables();
+__constant__ RefTables<Hex> kHexTab = make_tables<Hex>();
 
 // Linear tetrahedron, 4-point degree-2 rule (weights 1/24).
 struct Tet {
@@ -85,12 +88,77 @@ struct Tet {
     __host__ __device__ static constexpr double dN(int, int a, int j) { return a == 0 ? -1.0 : (a == j + 1 ? 1.0 : 0.0); }
 };
 
+// Linear prism: triangle (0,0),(1,0),(0,1) x zeta in [-1,1], nodes 0-2 at
+// zeta = -1 and 3-5 above them; N_a = L_i (1 -+ zeta)/2 with the barycentric
+// L = (1-xi-eta, xi, eta).  Rule: the degree-2 triangle points (1/6,1/6),
+// (2/3,1/6), (1/6,2/3) x Gauss-Legendre +-1/sqrt3 (point g: triangle point
+// g % 3, zeta side g / 3), weights 1/6.
+struct Pen {
+    static constexpr int NEN = 6, NG = 6;
+    static constexpr bool kRolled = true, kSparse = false;
+    static constexpr double kG = 0.57735026918962576451;
+    __host__ __device__ static constexpr double px(int g) { return g % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+    __host__ __device__ static constexpr double py(int g) { return g % 3 == 2 ? 2.0 / 3.0 : 1.0 / 6.0; }
+    __host__ __device__ static constexpr double pz(int g) { return g >= 3 ? kG : -kG; }
+    __host__ __device__ static constexpr double bary(int i, int g)
+    {
+        return i == 0 ? 1.0 - px(g) - py(g) : i == 1 ? px(g) : py(g);
+    }
+    __host__ __device__ static constexpr double side(int a) { return a >= 3 ? 1.0 : -1.0; }
+    __host__ __device__ static constexpr double w(int) { return 1.0 / 6.0; }
+    __host__ __device__ static constexpr double N(int g, int a)
+    {
+        return bary(a % 3, g) * 0.5 * (1.0 + side(a) * pz(g));
+    }
+    __host__ __device__ static constexpr double dN(int g, int a, int j)
+    {
+        // d bary / d xi = (-1, 1, 0), d bary / d eta = (-1, 0, 1)
+        return j == 2 ? 0.5 * side(a) * bary(a % 3, g)
+                      : (a % 3 == 0 ? -1.0 : (a % 3 == j + 1 ? 1.0 : 0.0)) * 0.5 * (1.0 + side(a) * pz(g));
+    }
+};
+
+// Pyramid on the base [-1,1]^2 at zeta = 0 (nodes 0-3 at (-,-), (+,-), (+,+),
+// (-,+)) with the apex, node 4, at (0,0,1).  Rational basis, m = 1 - zeta:
+// N_a = (m + sx xi)(m + sy eta) / (4m), N_4 = zeta.  Rule: conical product,
+// (xi, eta) = m (+-1/sqrt3, +-1/sqrt3) and zeta at the 2-point Gauss-Jacobi
+// nodes for the weight (1-zeta)^2 on [0,1], 1/3 -+ sqrt10/15, with weights
+// 1/6 +- sqrt10/48 (point g: xi side bit 0, eta side bit 1, zeta node bit 2).
+struct Pyr {
+    static constexpr int NEN = 5, NG = 8;
+    static constexpr bool kRolled = true, kSparse = false;
+    static constexpr double kG = 0.57735026918962576451;    // 1/sqrt(3)
+    static constexpr double kR = 3.16227766016837933200;    // sqrt(10)
+    __host__ __device__ static constexpr double pz(int g) { return (g & 4) ? 1.0 / 3.0 + kR / 15.0 : 1.0 / 3.0 - kR / 15.0; }
+    __host__ __device__ static constexpr double pm(int g) { return 1.0 - pz(g); }
+    __host__ __device__ static constexpr double px(int g) { return ((g & 1) ? kG : -kG) * pm(g); }
+    __host__ __device__ static constexpr double py(int g) { return ((g & 2) ? kG : -kG) * pm(g); }
+    __host__ __device__ static constexpr double sx(int a) { return (a == 1 || a == 2) ? 1.0 : -1.0; }
+    __host__ __device__ static constexpr double sy(int a) { return a >= 2 ? 1.0 : -1.0; }
+    __host__ __device__ static constexpr double w(int g) { return (g & 4) ? 1.0 / 6.0 - kR / 48.0 : 1.0 / 6.0 + kR / 48.0; }
+    __host__ __device__ static constexpr double N(int g, int a)
+    {
+        return a == 4 ? pz(g) : (pm(g) + sx(a) * px(g)) * (pm(g) + sy(a) * py(g)) / (4.0 * pm(g));
+    }
+    __host__ __device__ static constexpr double dN(int g, int a, int j)
+    {
+        return a == 4 ? (j == 2 ? 1.0 : 0.0)
+             : j == 0 ? sx(a) * (pm(g) + sy(a) * py(g)) / (4.0 * pm(g))
+             : j == 1 ? sy(a) * (pm(g) + sx(a) * px(g)) / (4.0 * pm(g))
+                      : (sx(a) * sy(a) * px(g) * py(g) - pm(g) * pm(g)) / (4.0 * pm(g) * pm(g));
+    }
+};
+
+__constant__ RefTables<Pen> kPenTab = make_tables<Pen>();
+__constant__ RefTables<Pyr> kPyrTab = make_tables<Pyr>();
+
 struct KArgs {
     const double *X;
     const int32_t *blk_elem_ptr, *blk_node_ptr, *blk_nodes, *blk_rdesc, *blk_rowstart, *color_blk;
     const uint8_t *blk_nphase, *elem_off, *elem_phase;
     const uint16_t *elem_lnode;
     int64_t N, E;
+    int off_stride;           // bytes of elem_off per element
     const double *u, *rho, *mu, *Y;
     double dt, Dk;
     double *values, *rhs;
@@ -120,6 +188,10 @@ template <> __device__ inline double RefN<Hex>(int g, int a) { return kHexTab.N[
 template <> __device__ inline double RefdN<Hex>(int g, int a, int j) { return kHexTab.dN[g][a][j]; }
 template <> __device__ inline double RefN<Tet>(int g, int a) { return Tet::N(g, a); }
 template <> __device__ inline double RefdN<Tet>(int g, int a, int j) { return Tet::dN(g, a, j); }
+template <> __device__ inline double RefN<Pen>(int g, int a) { return kPenTab.N[g][a]; }
+template <> __device__ inline double RefdN<Pen>(int g, int a, int j) { return kPenTab.dN[g][a][j]; }
+template <> __device__ inline double RefN<Pyr>(int g, int a) { return kPyrTab.N[g][a]; }
+template <> __device__ inline double RefdN<Pyr>(int g, int a, int j) { return kPyrTab.dN[g][a][j]; }
 
 // One Gauss point for rows [a0, a0 + RA) of the elemental matrix.
 // Geometry in FP64 (from the LDS-staged nodal data), products in Q.
@@ -129,8 +201,8 @@ template <> __device__ inline double RefdN<Tet>(int g, int a, int j) { return Te
 //   POI    : A_ab += dV grad N_a . grad N_b,
 //            B_a += dV / dt grad N_a . (rho u).
 // Geometry of one element kept in registers for the Gauss loop: HEX08 the
-// trilinear coefficients c1..c7 of x(xi), TET04 the vertex coordinates.
-template <class EL> struct Geo { double v[EL::NEN == 8 ? 7 : 4][3]; };
+// trilinear coefficients c1..c7 of x(xi), the other types the node coordinates.
+template <class EL> struct Geo { double v[EL::NEN == 8 ? 7 : EL::NEN][3]; };
 
 template <class EL>
 __device__ __forceinline__ void load_geo(const double *nd, int T, const int (&ln)[EL::NEN], Geo<EL> &G)
@@ -191,7 +263,7 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
 #pragma unroll
                 for (int a = 0; a < NEN; ++a) {
                     const double d = RefdN<EL>(g, a, j);
-                    if (d != 0.0) s += geo[a][i] * d;
+                    if (!EL::kSparse || d != 0.0) s += geo[a][i] * d;
                 }
                 J[i][j] = s;
             }
@@ -330,11 +402,15 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     int ln[NEN];
 #pragma unroll
     for (int a = 0; a < NEN; ++a) ln[a] = k.elem_lnode[(int64_t)a * k.E + e];
-    uint32_t offw[RA * NEN / 4];
+    // in-row offsets of this lane's rows: a multiple of 4 bytes from a 4-byte
+    // boundary (off_stride is a multiple of 4, a0 * NEN is 0 or 32), padded
+    // to whole words inside the element's slot
+    constexpr int kOffWords = (RA * NEN + 3) / 4;
+    uint32_t offw[kOffWords];
     {
-        const uint32_t *op = (const uint32_t *)(k.elem_off + (int64_t)e * (NEN * NEN) + a0 * NEN);
+        const uint32_t *op = (const uint32_t *)(k.elem_off + (int64_t)e * k.off_stride + a0 * NEN);
 #pragma unroll
-        for (int q = 0; q < RA * NEN / 4; ++q) offw[q] = op[q];
+        for (int q = 0; q < kOffWords; ++q) offw[q] = op[q];
     }
     const int ph = act ? (int)k.elem_phase[e] : -1;
 
@@ -520,19 +596,18 @@ __global__ void __launch_bounds__(kStatusThreads) k_asm_status(const double *min
 }
 
 template <class EL, int OP, class Q>
-hipError_t run(const AsmArgs &a, const KArgs &k0, hipStream_t s)
+void launch_one(const AsmLaunch &L, KArgs k, hipStream_t s)
 {
-    const DevMesh &m = *a.m;
-    constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
-    const size_t lds = m.max_lds[OP];
-    KArgs k = k0;
-    for (int c = 0; c < m.n_colors; ++c) {
-        const int nb = m.color_ptr[c + 1] - m.color_ptr[c];
-        if (nb == 0) continue;
-        k.blk_offset = m.color_ptr[c];
-        hipLaunchKernelGGL((k_assemble<EL, OP, Q>), dim3(nb), dim3(64 * Split<EL>::W), lds, s, k);
-    }
-    return hipGetLastError();
+    k.blk_offset = L.first;
+    hipLaunchKernelGGL((k_assemble<EL, OP, Q>), dim3(L.count), dim3(64 * Split<EL>::W), L.lds[OP], s, k);
+}
+
+template <class EL>
+void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStream_t s)
+{
+    if (op == OP_MOM) mixed ? launch_one<EL, OP_MOM, float>(L, k, s) : launch_one<EL, OP_MOM, double>(L, k, s);
+    else if (op == OP_SCA) mixed ? launch_one<EL, OP_SCA, float>(L, k, s) : launch_one<EL, OP_SCA, double>(L, k, s);
+    else mixed ? launch_one<EL, OP_POI, float>(L, k, s) : launch_one<EL, OP_POI, double>(L, k, s);
 }
 
 }  // namespace
@@ -565,21 +640,20 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     // status scratch lives right after the AsmStatus word
     k.blk_mindet = (double *)(a.status + 1);
     k.blk_bad = (long long *)(k.blk_mindet + m.nblk);
-    hipError_t err;
-    const bool hex = m.nen == 8;
-#define FE_RUN(EL, OPV)                                                                     \
-    err = mixed ? run<EL, OPV, float>(a, k, s) : run<EL, OPV, double>(a, k, s)
-    if (hex) {
-        if (a.op == OP_MOM) FE_RUN(Hex, OP_MOM);
-        else if (a.op == OP_SCA) FE_RUN(Hex, OP_SCA);
-        else FE_RUN(Hex, OP_POI);
-    } else {
-        if (a.op == OP_MOM) FE_RUN(Tet, OP_MOM);
-        else if (a.op == OP_SCA) FE_RUN(Tet, OP_SCA);
-        else FE_RUN(Tet, OP_POI);
+    k.off_stride = m.off_stride;
+    // one launch per (colour, element type), in the planned order
+    for (const AsmLaunch &L : m.launches) {
+        if (L.count == 0) continue;
+        switch (L.nen) {
+        case 8: launch_type<Hex>(L, k, a.op, mixed, s); break;
+        case 6: launch_type<Pen>(L, k, a.op, mixed, s); break;
+        case 5: launch_type<Pyr>(L, k, a.op, mixed, s); break;
+        case 4: launch_type<Tet>(L, k, a.op, mixed, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
     }
-#undef FE_RUN
-    if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.nblk, a.status);
     return hipGetLastError();
 }

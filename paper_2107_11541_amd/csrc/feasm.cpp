@@ -126,20 +126,16 @@ size_t MeshImage::device_bytes() const
     return total;
 }
 
-int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
-                 int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber, MeshImage &I,
-                 std::string &err)
+int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
+                 const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
+                 MeshImage &I, std::string &err)
 {
-    if (type != FE_HEX08 && type != FE_TET04) {
-        err = "unknown element type " + std::to_string((int)type);
-        return FE_EINVAL;
-    }
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet_nodes)) {
         err = "bad Dirichlet list";
         return FE_EINVAL;
     }
     Plan &P = I.P;
-    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, renumber, P, err);
+    int st = build_plan(stride, types, n_nodes, coords, n_elems, conn, renumber, P, err);
     if (st != FE_OK) return st;
     I.is_dir.assign(n_nodes, 0);
     for (int64_t k = 0; k < n_dirichlet; ++k) {
@@ -161,6 +157,7 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
     DevMesh &d = I.d;
     d = DevMesh();
     d.nen = P.nen;
+    d.off_stride = P.off_stride;
     d.N = P.N;
     d.E = P.E;
     d.nnz = P.nnz;
@@ -170,7 +167,6 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
     d.max_L = P.max_L;
     d.max_row = P.max_row;
     d.max_phase = P.max_phase;
-    d.color_ptr = P.color_ptr;
     d.n_dir = ndir;
     d.n_dir_rows = (int64_t)I.dir_rows.size();
     // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
@@ -239,18 +235,25 @@ int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64
             I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
     // the SpMV reads column indices in aligned groups of 4: pad the device copy
     P.colidx.resize((size_t)P.nnz + kColPad, 0);
-    // assembly LDS per operator: [fields NF][rhs NRHS] doubles per row, one int
-    // descriptor per row (+ alignment), then the row image
+    // assembly launches and their LDS per operator: [fields NF][rhs NRHS]
+    // doubles per row, one int descriptor per row (+ alignment), then the row
+    // image, for the launch's largest block
     const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
-    for (int64_t b = 0; b < d.nblk; ++b) {
-        const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
-        int64_t L = 0;
-        for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
-            L += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
-        for (int op = 0; op < 3; ++op) {
-            size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)L * 8;
-            d.max_lds[op] = std::max(d.max_lds[op], by);
+    d.launches.clear();
+    for (const AsmSeg &g : P.segs) {
+        AsmLaunch L{g.nen, g.first, g.count, {0, 0, 0}};
+        for (int q = g.first; q < g.first + g.count; ++q) {
+            const int32_t b = P.color_blk[q];
+            const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
+            int64_t nl = 0;
+            for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
+                nl += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
+            for (int op = 0; op < 3; ++op) {
+                size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)nl * 8;
+                L.lds[op] = std::max(L.lds[op], by);
+            }
         }
+        d.launches.push_back(L);
     }
     return FE_OK;
 }
@@ -559,16 +562,16 @@ fe_status fe_ctx_set_stream(fe_ctx c, void *hip_stream)
     return FE_OK;
 }
 
-fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
-                         const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, uint32_t flags,
-                         fe_mesh *out)
+static fe_status mesh_upload(fe_ctx c, int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
+                             int64_t n_elems, const int32_t *conn, int64_t n_dirichlet,
+                             const int32_t *dirichlet_nodes, uint32_t flags, fe_mesh *out)
 {
     if (!c || !out) return FE_EINVAL;
     *out = nullptr;
     HIPCALL(c, hipSetDevice(c->device));
     auto img = std::make_unique<MeshImage>();
     std::string err;
-    int st = mesh_prepare(type, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes,
+    int st = mesh_prepare(stride, types, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes,
                           (flags & FE_UPLOAD_RENUMBER) != 0, *img, err);
     if (st != FE_OK) return fail(c, (fe_status)st, "%s", err.c_str());
     auto *m = new fe_mesh_s();
@@ -586,6 +589,23 @@ fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const dou
     c->meshes.push_back(m);
     *out = m;
     return FE_OK;
+}
+
+fe_status fe_mesh_upload(fe_ctx c, fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
+                         const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, uint32_t flags,
+                         fe_mesh *out)
+{
+    return mesh_upload(c, (int)type, nullptr, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes, flags,
+                       out);
+}
+
+fe_status fe_mesh_upload_mixed(fe_ctx c, int64_t n_nodes, const double *coords, int64_t n_elems,
+                               const uint8_t *elem_types, const int32_t *conn, int64_t n_dirichlet,
+                               const int32_t *dirichlet_nodes, uint32_t flags, fe_mesh *out)
+{
+    if (!elem_types) return c ? fail(c, FE_EINVAL, "elem_types is NULL") : FE_EINVAL;
+    return mesh_upload(c, 8, elem_types, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes, flags,
+                       out);
 }
 
 fe_status fe_mesh_info(fe_mesh m, fe_mesh_desc *o)
@@ -840,14 +860,15 @@ struct fe_plan_s {
 
 static thread_local std::string g_plan_err;
 
-fe_status fe_plan_create(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
-                         const int32_t *conn, uint32_t flags, fe_plan *out)
+static fe_status plan_create(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
+                             int64_t n_elems, const int32_t *conn, uint32_t flags, fe_plan *out)
 {
     if (!out) return FE_EINVAL;
     *out = nullptr;
     auto *p = new fe_plan_s();
     std::string err;
-    int st = build_plan((int)type, n_nodes, coords, n_elems, conn, (flags & FE_UPLOAD_RENUMBER) != 0, p->P, err);
+    int st = build_plan(stride, types, n_nodes, coords, n_elems, conn, (flags & FE_UPLOAD_RENUMBER) != 0, p->P,
+                        err);
     if (st != FE_OK) {
         g_plan_err = err;
         delete p;
@@ -855,6 +876,19 @@ fe_status fe_plan_create(fe_elem_type type, int64_t n_nodes, const double *coord
     }
     *out = p;
     return FE_OK;
+}
+
+fe_status fe_plan_create(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems,
+                         const int32_t *conn, uint32_t flags, fe_plan *out)
+{
+    return plan_create((int)type, nullptr, n_nodes, coords, n_elems, conn, flags, out);
+}
+
+fe_status fe_plan_create_mixed(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *elem_types,
+                               const int32_t *conn, uint32_t flags, fe_plan *out)
+{
+    if (!elem_types) return FE_EINVAL;
+    return plan_create(8, elem_types, n_nodes, coords, n_elems, conn, flags, out);
 }
 
 fe_status fe_plan_info(fe_plan p, fe_plan_desc *o)
@@ -889,6 +923,32 @@ fe_status fe_plan_export(fe_plan p, int32_t *node_perm, int32_t *elem_perm, int3
     cp(block_color, P.blk_color);
     cp(block_node_ptr, P.blk_node_ptr);
     cp(block_nodes, P.blk_nodes);
+    return FE_OK;
+}
+
+fe_status fe_plan_export_types(fe_plan p, uint8_t *elem_types, uint8_t *block_types, int32_t *launches,
+                               int64_t *n_launches)
+{
+    if (!p) return FE_EINVAL;
+    const Plan &P = p->P;
+    if (elem_types)
+        for (int64_t e = 0; e < P.E; ++e) elem_types[e] = P.etype.empty() ? (uint8_t)P.nen : P.etype[e];
+    if (block_types && !P.blk_nen.empty()) memcpy(block_types, P.blk_nen.data(), P.blk_nen.size());
+    if (launches)
+        for (size_t q = 0; q < P.segs.size(); ++q) {
+            launches[3 * q] = P.segs[q].nen;
+            launches[3 * q + 1] = P.segs[q].first;
+            launches[3 * q + 2] = P.segs[q].count;
+        }
+    if (n_launches) *n_launches = (int64_t)P.segs.size();
+    return FE_OK;
+}
+
+fe_status fe_plan_export_color_blocks(fe_plan p, int32_t *color_blocks)
+{
+    if (!p || !color_blocks) return FE_EINVAL;
+    const Plan &P = p->P;
+    if (!P.color_blk.empty()) memcpy(color_blocks, P.color_blk.data(), P.color_blk.size() * sizeof(int32_t));
     return FE_OK;
 }
 

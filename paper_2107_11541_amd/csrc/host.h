@@ -96,9 +96,10 @@ struct MeshImage {
 
 // Validates and plans a mesh on the host (no device calls).  0 or an
 // fe_status code with a message in err.
-int mesh_prepare(fe_elem_type type, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
-                 int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber, MeshImage &img,
-                 std::string &err);
+// conn [n_elems][stride]; types as for build_plan (NULL: one type, stride nodes).
+int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
+                 const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
+                 MeshImage &img, std::string &err);
 // Allocates (from m->arena or hipMalloc) and queues the copies of img on
 // `stream`.  img must stay alive until the copies have completed.
 fe_status mesh_commit(fe_mesh_s *m, MeshImage &img, hipStream_t stream);

@@ -11,13 +11,21 @@
 
 namespace feasm {
 
+// One assembly launch: the blocks color_blk[first, first + count), all of one
+// colour and one element type (nen nodes); lds[op] = LDS bytes of its
+// largest block for operator op.
+struct AsmLaunch {
+    int nen, first, count;
+    size_t lds[3];
+};
+
 // Device-resident mesh: geometry, CSR pattern and the block scatter plan.
 struct DevMesh {
-    int nen = 0;
+    int nen = 0;                        // connectivity stride: nodes of the largest element type
+    int off_stride = 0;                 // bytes of elem_off per element
     int64_t N = 0, E = 0, nnz = 0, nblk = 0;
     int n_colors = 0, max_T = 0, max_L = 0, max_row = 0, max_phase = 0;
-    size_t max_lds[3] = {0, 0, 0};      // assembly LDS bytes per operator (max over blocks)
-    std::vector<int32_t> color_ptr;     // host copy: blocks of colour c are color_blk[color_ptr[c]..]
+    std::vector<AsmLaunch> launches;    // host: launch order (colour-major, then type)
 
     double *X = nullptr;                // [3][N]
     int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
@@ -25,7 +33,7 @@ struct DevMesh {
     int32_t *blk_rdesc = nullptr, *blk_rowstart = nullptr;   // per touched row
     uint8_t *blk_nphase = nullptr;
     uint16_t *elem_lnode = nullptr;     // [nen][E]
-    uint8_t *elem_off = nullptr;        // [E][nen*nen]
+    uint8_t *elem_off = nullptr;        // [E][off_stride], row a of an n-node element at a * n
     uint8_t *elem_phase = nullptr;      // [E]
     int32_t *color_blk = nullptr;
     int32_t *node_perm = nullptr;       // mesh -> user

@@ -54,9 +54,10 @@ static inline uint64_t spread3(uint64_t v)
     return v;
 }
 
-// Element order along a Morton curve of the centroids (ties: user order).
-static void morton_order(int nen, int64_t N, const double *coords, int64_t E, const int32_t *conn,
-                         std::vector<int32_t> &order)
+// Element order along a Morton curve of the centroids (ties: user order);
+// with several element types, grouped by type first (type_rank).
+static void morton_order(int S, const uint8_t *types, int64_t N, const double *coords, int64_t E,
+                         const int32_t *conn, std::vector<int32_t> &order)
 {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = 0; i < N; ++i)
@@ -67,10 +68,11 @@ static void morton_order(int nen, int64_t N, const double *coords, int64_t E, co
     std::vector<uint64_t> key(E);
     parallel_for(E, [&](int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
+            const int nen = types ? types[e] : S;
             uint64_t k = 0;
             for (int d = 0; d < 3; ++d) {
                 double c = 0.0;
-                for (int j = 0; j < nen; ++j) c += coords[(int64_t)conn[e * nen + j] * 3 + d];
+                for (int j = 0; j < nen; ++j) c += coords[(int64_t)conn[e * S + j] * 3 + d];
                 c /= nen;
                 double span = hi[d] - lo[d];
                 double t = span > 0 ? (c - lo[d]) / span : 0.0;
@@ -82,7 +84,14 @@ static void morton_order(int nen, int64_t N, const double *coords, int64_t E, co
     });
     order.resize(E);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    if (types) {
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            const int ra = type_rank(types[a]), rb = type_rank(types[b]);
+            return ra != rb ? ra < rb : key[a] < key[b];
+        });
+    } else {
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
 }
 
 // CSR pattern in mesh numbering: row i = sorted unique nodes of the elements
@@ -93,24 +102,27 @@ static void morton_order(int nen, int64_t N, const double *coords, int64_t E, co
 // buffers are concatenated behind the row pointers.  The same pass fills the
 // scatter offsets: with the row sorted, the table maps each column to its
 // position, and every incident element e (node i at local position a) gets
-// elem_off[e][a][c] = position of its node c in row i.
+// elem_off[e][a][c] = position of its node c in row i.  Element e has n_e
+// nodes (its type) and its connectivity at stride S.
 static void build_pattern(Plan &P)
 {
-    const int nen = P.nen;
+    const int S = P.nen;
     const int64_t N = P.N, E = P.E;
+    const uint8_t *ty = P.etype.empty() ? nullptr : P.etype.data();
+    auto nen_of = [&](int64_t e) { return ty ? (int)ty[e] : S; };
     std::vector<int64_t> ip(N + 1, 0);
     for (int64_t e = 0; e < E; ++e)
-        for (int a = 0; a < nen; ++a) ip[P.conn[e * nen + a] + 1]++;
+        for (int a = 0; a < nen_of(e); ++a) ip[P.conn[e * S + a] + 1]++;
     for (int64_t i = 0; i < N; ++i) ip[i + 1] += ip[i];
     std::vector<int32_t> inc(ip[N]);
     {
         std::vector<int64_t> fill(ip.begin(), ip.end() - 1);
         for (int64_t e = 0; e < E; ++e)
-            for (int a = 0; a < nen; ++a) inc[fill[P.conn[e * nen + a]]++] = (int32_t)e;
+            for (int a = 0; a < nen_of(e); ++a) inc[fill[P.conn[e * S + a]]++] = (int32_t)e;
     }
     std::vector<int32_t> len(N);
-    const int nn2 = nen * nen;
-    P.elem_off.assign((size_t)E * nn2, 0);
+    const int OS = P.off_stride;
+    P.elem_off.assign((size_t)E * OS, 0);
     const int nt = std::max(1, (int)std::min<int64_t>(host_threads(), (N + 4095) / 4096));
     const int64_t chunk = (N + nt - 1) / nt;
     std::vector<std::vector<int32_t>> cols(nt);
@@ -131,13 +143,15 @@ static void build_pattern(Plan &P)
         for (int64_t i = lo; i < hi; ++i) {
             const size_t start = out.size();
             const int64_t deg = ip[i + 1] - ip[i];
-            if ((int64_t)hs.size() < deg * nen) {
-                hs.resize(deg * nen);
+            if ((int64_t)hs.size() < deg * S) {
+                hs.resize(deg * S);
                 where.resize(deg);
             }
             int nused = 0;
             for (int64_t k = 0; k < deg; ++k) {
-                const int32_t *c = &P.conn[(int64_t)inc[ip[i] + k] * nen];
+                const int64_t ek = inc[ip[i] + k];
+                const int32_t *c = &P.conn[ek * S];
+                const int nen = nen_of(ek);
                 uint32_t mk = 0;
                 for (int a = 0; a < nen; ++a) mk |= (uint32_t)(c[a] == (int32_t)i) << a;
                 where[k] = (uint8_t)mk;
@@ -145,7 +159,7 @@ static void build_pattern(Plan &P)
                     const int32_t v = c[a];
                     uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
                     while (table[h] != -1 && table[h] != v) h = (h + 1) & (kSlots - 1);
-                    hs[k * nen + a] = (uint16_t)h;
+                    hs[k * S + a] = (uint16_t)h;
                     // branch-free insert (whether a column is new is unpredictable)
                     const bool fresh = table[h] == -1;
                     if (fresh & (nused == kSlots / 2)) {   // row longer than any admissible one
@@ -178,6 +192,7 @@ static void build_pattern(Plan &P)
                 int prev_a = -1;
                 for (int64_t k = 0; k < deg; ++k) {
                     const int64_t e = inc[ip[i] + k];
+                    const int nen = nen_of(e);
                     // the k-th occurrence of i in e (an element may repeat a
                     // node; its repeats are consecutive in inc)
                     uint32_t mk = where[k];
@@ -185,8 +200,8 @@ static void build_pattern(Plan &P)
                     const int a = mk ? __builtin_ctz(mk) : nen;
                     prev_a = a;
                     if (a == nen) continue;
-                    uint8_t *off = &P.elem_off[(size_t)e * nn2 + (size_t)a * nen];
-                    const uint16_t *hk = &hs[k * nen];
+                    uint8_t *off = &P.elem_off[(size_t)e * OS + (size_t)a * nen];
+                    const uint16_t *hk = &hs[k * S];
                     for (int q = 0; q < nen; ++q) off[q] = posv[hk[q]];
                 }
             } else {
@@ -232,10 +247,11 @@ static void build_pattern(Plan &P)
     });
 }
 
-int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_t *conn, bool renumber,
-               Plan &P, std::string &err)
+int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int64_t E, const int32_t *conn,
+               bool renumber, Plan &P, std::string &err)
 {
-    if ((nen != 4 && nen != 8) || N <= 0 || E <= 0 || !coords || !conn) {
+    const bool typed_stride = types ? (S >= 4 && S <= 8) : (S == 4 || S == 5 || S == 6 || S == 8);
+    if (!typed_stride || N <= 0 || E <= 0 || !coords || !conn) {
         err = "invalid mesh arguments";
         return FE_EINVAL;
     }
@@ -243,31 +259,50 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         err = "mesh too large for int32 ids";
         return FE_EINVAL;
     }
-    for (int64_t k = 0; k < E * nen; ++k)
-        if (conn[k] < 0 || conn[k] >= N) {
-            err = "connectivity entry " + std::to_string(k) + " out of range";
-            return FE_EBADMESH;
+    auto nen_u = [&](int64_t e) { return types ? (int)types[e] : S; };
+    bool one_type = true;
+    int maxt = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int t = nen_u(e);
+        if ((t != 4 && t != 5 && t != 6 && t != 8) || t > S) {
+            err = "element " + std::to_string(e) + " has an unknown type (" + std::to_string(t) + " nodes)";
+            return FE_EINVAL;
         }
+        one_type &= t == nen_u(0);
+        maxt = std::max(maxt, t);
+        for (int a = 0; a < t; ++a)
+            if (conn[e * S + a] < 0 || conn[e * S + a] >= N) {
+                err = "connectivity entry " + std::to_string(e * S + a) + " out of range";
+                return FE_EBADMESH;
+            }
+    }
     P = Plan();
-    P.nen = nen;
+    P.nen = maxt;   // the plan's connectivity stride
+    P.off_stride = (maxt * maxt + 3) & ~3;
+    const int PS = maxt;
     P.N = N;
     P.E = E;
 
-    // 1. element order
+    // 1. element order (grouped by type when several are present)
     if (renumber) {
-        morton_order(nen, N, coords, E, conn, P.elem_perm);
+        morton_order(S, types, N, coords, E, conn, P.elem_perm);
     } else {
         P.elem_perm.resize(E);
         std::iota(P.elem_perm.begin(), P.elem_perm.end(), 0);
     }
+    if (types && !one_type) {
+        P.etype.resize(E);
+        for (int64_t e = 0; e < E; ++e) P.etype[e] = types[P.elem_perm[e]];
+    }
+    auto nen_of = [&](int64_t e) { return P.etype.empty() ? PS : (int)P.etype[e]; };
     // 2. node order: first touch along the element order (or identity)
     P.node_iperm.assign(N, -1);
     P.node_perm.assign(N, -1);
     if (renumber) {
         int32_t next = 0;
         for (int64_t e = 0; e < E; ++e)
-            for (int a = 0; a < nen; ++a) {
-                int32_t v = conn[(int64_t)P.elem_perm[e] * nen + a];
+            for (int a = 0; a < nen_of(e); ++a) {
+                int32_t v = conn[(int64_t)P.elem_perm[e] * S + a];
                 if (P.node_iperm[v] < 0) {
                     P.node_iperm[v] = next;
                     P.node_perm[next] = v;
@@ -280,7 +315,8 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         }
     } else {
         std::vector<char> used(N, 0);
-        for (int64_t k = 0; k < E * nen; ++k) used[conn[k]] = 1;
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < nen_u(e); ++a) used[conn[e * S + a]] = 1;
         for (int64_t i = 0; i < N; ++i) {
             if (!used[i]) {
                 err = "node " + std::to_string(i) + " belongs to no element";
@@ -290,9 +326,13 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
             P.node_perm[i] = (int32_t)i;
         }
     }
-    P.conn.resize(E * nen);
-    for (int64_t e = 0; e < E; ++e)
-        for (int a = 0; a < nen; ++a) P.conn[e * nen + a] = P.node_iperm[conn[(int64_t)P.elem_perm[e] * nen + a]];
+    // mesh connectivity; the unused slots of a short element repeat its first node
+    P.conn.resize(E * PS);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *c = conn + (int64_t)P.elem_perm[e] * S;
+        const int t = nen_of(e);
+        for (int a = 0; a < PS; ++a) P.conn[e * PS + a] = P.node_iperm[c[a < t ? a : 0]];
+    }
     P.X.resize(3 * N);
     for (int64_t i = 0; i < N; ++i)
         for (int d = 0; d < 3; ++d) P.X[d * N + i] = coords[(int64_t)P.node_perm[i] * 3 + d];
@@ -304,8 +344,7 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         return FE_EBADMESH;
     }
 
-    // 4. blocks: consecutive elements, <= 64, LDS image within budget
-    const int nn2 = nen * nen;
+    // 4. blocks: consecutive elements of one type, <= 64, LDS image within budget
     std::vector<int32_t> stamp(N, -1), local(N, 0);
     P.blk_elem_ptr.push_back(0);
     P.blk_node_ptr.push_back(0);
@@ -329,34 +368,36 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         };
         int64_t start = 0;
         for (int64_t e = 0; e < E; ++e) {
+            const int nen = nen_of(e);
+            const int32_t *ce = &P.conn[e * PS];
             int newT = 0;
             int64_t newL = 0;
             for (int a = 0; a < nen; ++a) {
-                int32_t v = P.conn[e * nen + a];
+                int32_t v = ce[a];
                 if (stamp[v] != bid) {
                     bool dup = false;
-                    for (int b = 0; b < a; ++b) dup |= (P.conn[e * nen + b] == v);
+                    for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
                     if (!dup) {
                         ++newT;
                         newL += P.rowptr[v + 1] - P.rowptr[v];
                     }
                 }
             }
-            if (e > start && (e - start >= kBlockElems ||
+            if (e > start && (e - start >= kBlockElems || nen != nen_of(start) ||
                               lds_bytes((int64_t)cur.size() + newT, L + newL) > kLdsBudget)) {
                 close_block(e);
                 start = e;
                 newT = 0;
                 newL = 0;
                 for (int a = 0; a < nen; ++a) {
-                    int32_t v = P.conn[e * nen + a];
+                    int32_t v = ce[a];
                     bool dup = false;
-                    for (int b = 0; b < a; ++b) dup |= (P.conn[e * nen + b] == v);
+                    for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
                     if (!dup) newL += P.rowptr[v + 1] - P.rowptr[v];
                 }
             }
             for (int a = 0; a < nen; ++a) {
-                int32_t v = P.conn[e * nen + a];
+                int32_t v = ce[a];
                 if (stamp[v] != bid) {
                     stamp[v] = bid;
                     cur.push_back(v);
@@ -373,9 +414,11 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
     const int64_t nblk = P.n_blocks();
 
     // 5. per element: local rows, in-row offsets, phases
-    P.elem_lnode.assign(nen * E, 0);
+    P.elem_lnode.assign((size_t)PS * E, 0);
     P.elem_phase.assign(E, 0);
     P.blk_nphase.assign(nblk, 1);
+    P.blk_nen.assign(nblk, (uint8_t)PS);
+    for (int64_t b = 0; b < nblk; ++b) P.blk_nen[b] = (uint8_t)nen_of(P.blk_elem_ptr[b]);
     std::atomic<int> bad{0};
     std::atomic<int> maxph{1};
     parallel_for(nblk, [&](int64_t b0, int64_t b1) {
@@ -399,12 +442,13 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
                 key[h] = nb[k];
                 val[h] = (uint16_t)k;
             }
+            const int nen = P.blk_nen[b];
             used.assign((size_t)T * nen, 0);
             int nph = 1;
             for (int64_t e = P.blk_elem_ptr[b]; e < P.blk_elem_ptr[b + 1]; ++e) {
                 int ln[8];
                 for (int a = 0; a < nen; ++a) {
-                    int32_t v = P.conn[e * nen + a];
+                    int32_t v = P.conn[e * PS + a];
                     uint32_t h = hslot(v);
                     while (key[h] != v) h = (h + 1) & (kSlots - 1);
                     ln[a] = val[h];
@@ -473,6 +517,20 @@ int build_plan(int nen, int64_t N, const double *coords, int64_t E, const int32_
         P.color_blk.resize(nblk);
         std::vector<int32_t> fill(P.color_ptr.begin(), P.color_ptr.end() - 1);
         for (int64_t b = 0; b < nblk; ++b) P.color_blk[fill[P.blk_color[b]]++] = (int32_t)b;
+        // inside a colour, blocks by type; one launch per (colour, type)
+        P.segs.clear();
+        for (int c = 0; c < ncol; ++c) {
+            int32_t *b0 = P.color_blk.data() + P.color_ptr[c], *b1 = P.color_blk.data() + P.color_ptr[c + 1];
+            std::stable_sort(b0, b1, [&](int32_t x, int32_t y) {
+                return type_rank(P.blk_nen[x]) < type_rank(P.blk_nen[y]);
+            });
+            for (int32_t *q = b0; q < b1;) {
+                int32_t *r = q;
+                while (r < b1 && P.blk_nen[*r] == P.blk_nen[*q]) ++r;
+                P.segs.push_back(AsmSeg{P.blk_nen[*q], (int)(q - P.color_blk.data()), (int)(r - q)});
+                q = r;
+            }
+        }
     }
 
     // 7. row descriptors: image offset, length and first-writer flag (launch

@@ -35,14 +35,26 @@ constexpr int kMaxRow = 255;   // in-row offsets are stored as uint8
 // first-writer flag (bit 31).
 constexpr uint32_t kFirstBit = 0x80000000u;
 
+// One assembly launch: blocks color_blk[first, first + count) of one colour
+// and one element type (nen nodes per element).
+struct AsmSeg {
+    int nen, first, count;
+};
+
+// Position of an element type (by node count) in the order a mixed mesh
+// groups them: HEX08, PEN06, PYR05, TET04.
+inline int type_rank(int nen) { return nen == 8 ? 0 : nen == 6 ? 1 : nen == 5 ? 2 : 3; }
+
 struct Plan {
-    int nen = 0;
+    int nen = 0;          // connectivity stride: nodes of the largest element type
+    int off_stride = 0;   // bytes of elem_off per element (nen * nen rounded up to 4)
     int64_t N = 0, E = 0, nnz = 0;
     std::vector<int32_t> node_perm;   // mesh index -> user node id
     std::vector<int32_t> node_iperm;  // user node id -> mesh index
     std::vector<int32_t> elem_perm;   // mesh element -> user element id
     std::vector<double> X;            // [3][N] coordinates, mesh numbering
-    std::vector<int32_t> conn;        // [E][nen] mesh numbering, mesh order
+    std::vector<int32_t> conn;        // [E][nen] mesh numbering, mesh order (short types padded)
+    std::vector<uint8_t> etype;       // [E] nodes of each element (mesh order); empty: all nen
     std::vector<int32_t> rowptr, colidx, diagpos;
     int max_row = 0;
 
@@ -55,18 +67,23 @@ struct Plan {
     std::vector<int32_t> blk_color;      // [nblk]
     std::vector<uint8_t> blk_nphase;     // [nblk]
     std::vector<uint16_t> elem_lnode;    // [nen][E] local row index of node a
-    std::vector<uint8_t> elem_off;       // [E][nen*nen] offset of col b in row a
+    std::vector<uint8_t> elem_off;       // [E][off_stride]: offset of col b in row a at a * n_e + b
+    std::vector<uint8_t> blk_nen;        // [nblk] element type of each block
     std::vector<uint8_t> elem_phase;     // [E]
     std::vector<int32_t> color_ptr;      // [ncolor+1]
-    std::vector<int32_t> color_blk;      // blocks ordered by colour
+    std::vector<int32_t> color_blk;      // blocks ordered by colour, then type (type_rank)
+    std::vector<AsmSeg> segs;            // launch order: colour-major, one per type present
     int n_colors = 0, max_T = 0, max_L = 0, max_phase = 0;
 
     int64_t n_blocks() const { return (int64_t)blk_elem_ptr.size() - 1; }
 };
 
-// Returns 0 on success, else an fe_status code with a message in err.
-int build_plan(int nen, int64_t n_nodes, const double *coords, int64_t n_elems, const int32_t *conn,
-               bool renumber, Plan &P, std::string &err);
+// conn [n_elems][stride]; types [n_elems] gives each element's node count
+// (4, 5, 6 or 8, at most stride; the remaining slots are ignored) or is NULL
+// for a mesh of one type with stride nodes.  Returns 0 on success, else an
+// fe_status code with a message in err.
+int build_plan(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
+               const int32_t *conn, bool renumber, Plan &P, std::string &err);
 
 // Number of worker threads used by the host preprocessing.
 int host_threads();

@@ -70,3 +70,30 @@ def submesh_rows(case, nodes):
     loc = np.full(case.n_nodes, -1, np.int64)
     loc[glob] = np.arange(glob.size)
     return case.coords[glob], loc[sub].astype(np.int32), loc, glob
+
+
+def make_mesh(ctx, case, renumber=True):
+    """Upload a case: fe_mesh_upload, or fe_mesh_upload_mixed for a hybrid one."""
+    import paper_2107_11541_amd as fe
+    if case.types is None:
+        return fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=renumber)
+    return fe.Mesh(ctx, fe.HYBRID, case.coords, case.conn, case.dirichlet, renumber=renumber, types=case.types)
+
+
+def submesh_rows_typed(case, nodes):
+    """submesh_rows for a mesh with per-element types (padded connectivity).
+
+    Returns (coords, conn, types, local_of_global, global_of_local)."""
+    conn = case.conn
+    types = case.types if case.types is not None else np.full(case.n_elems, case.nen, np.uint8)
+    valid = np.arange(conn.shape[1])[None, :] < types[:, None]
+    safe = np.where(valid, conn, 0)
+    mark = np.zeros(case.n_nodes, bool)
+    mark[nodes] = True
+    emask = (mark[safe] & valid).any(axis=1)
+    sub, sv = safe[emask], valid[emask]
+    glob = np.unique(sub[sv])
+    loc = np.full(case.n_nodes, -1, np.int64)
+    loc[glob] = np.arange(glob.size)
+    sconn = np.where(sv, loc[sub], -1).astype(np.int32)
+    return case.coords[glob], sconn, types[emask], loc, glob

@@ -128,7 +128,7 @@ def test_plan_rejects_bad_meshes():
         fe.Plan(8, X2, conn)
     assert ei.value.status == capi.FE_EBADMESH
     with pytest.raises(fe.FeError) as ei:
-        fe.Plan(5, X, conn[:, :5])
+        fe.Plan(7, X, conn[:, :7])          # no element type has 7 nodes
     assert ei.value.status == capi.FE_EINVAL
 
 
