@@ -51,6 +51,9 @@ def lib():
         L.or_assemble_typed.restype = i32
         L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
                                         i32, C.POINTER(i64), C.POINTER(dbl)]
+        L.or_element_vectors.restype = i32
+        L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, P, P, P, P, P, C.POINTER(i64),
+                                         C.POINTER(dbl)]
         L.or_dirichlet.restype = i32
         L.or_dirichlet.argtypes = [i64, P, P, P, P, i64, P, P]
         L.or_spmv.restype = None
@@ -160,6 +163,80 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return rowptr, colidx, values, rhs
+
+
+def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None):
+    coords, conn, types = _f64(coords), _i32(conn), _u8(types)
+    N = coords.shape[0]
+    out = np.zeros((4 if kind == 0 else 3, N))
+    bad = C.c_int64(-1)
+    mdet = C.c_double(0.0)
+    st = lib().or_element_vectors(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), kind,
+                                  _p(None if u is None else _f64(u)), _p(None if rho is None else _f64(rho)),
+                                  _p(None if mu is None else _f64(mu)), _p(None if p is None else _f64(p)),
+                                  _p(out), C.byref(bad), C.byref(mdet))
+    if st != OK:
+        raise AssembleError(st, bad.value, mdet.value)
+    return out
+
+
+def residual(coords, conn, u, rho, mu, types=None):
+    """Matrix-free momentum residual r[3, N] = -(C(u) + K_mu) u_i and the
+    rho-weighted lumped mass m[N] (or_element_vectors kind 0)."""
+    out = _element_vectors(coords, conn, 0, u=u, rho=rho, mu=mu, types=types)
+    return out[:3], out[3]
+
+
+def gradient(coords, conn, p, types=None):
+    """g[3, N]: g_j[a] = int N_a d p_h / d x_j (or_element_vectors kind 1)."""
+    return _element_vectors(coords, conn, 1, p=p, types=types)
+
+
+# Shu-Osher strong-stability-preserving third-order Runge-Kutta: stage s
+# maps (u^n, u_s) to alpha_s u^n + beta_s (u_s + dt L(u_s)).
+SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
+
+
+def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=SSP_RK3):
+    """Explicit RK stages of M_L du/dt = R(u) (velocity held at Dirichlet
+    nodes).  Returns (u*, lumped mass m)."""
+    free = np.ones(u.shape[1], bool)
+    free[np.asarray(dirichlet_nodes)] = False
+    u0 = np.array(u, dtype=np.float64)
+    us = u0.copy()
+    m = None
+    for a, b in rk:
+        r, m = residual(coords, conn, us, rho, mu, types)
+        nxt = a * u0 + b * (us + dt * r / m)
+        us = np.where(free, nxt, u0)
+    return us, m
+
+
+def fractional_step(coords, conn, dirichlet_nodes, dt, u, rho, mu, L, rtol=1e-12, max_iter=20000, p0=None,
+                    types=None, rk=SSP_RK3):
+    """One step of the fractional-step scheme around the assembly (Algorithm 1):
+      1. momentum predictor, explicit RK (SSP-RK3) on M_L du/dt = R(u), with
+         M_L the rho-weighted lumped mass and R the matrix-free residual; the
+         velocity at Dirichlet nodes is held;
+      2. pressure: (rowptr, colidx, values) = L, the Poisson matrix after the
+         Dirichlet elimination; right-hand side (1/dt) int grad N . (rho u*),
+         zero at Dirichlet rows; Jacobi-PCG from p0 (zero if None);
+      3. correction u = u* - dt M_L^-1 G p at free nodes.
+    Returns (u_new[3, N], p[N], cg_iterations)."""
+    rp, ci, Lv = L
+    dn = np.asarray(dirichlet_nodes)
+    free = np.ones(u.shape[1], bool)
+    free[dn] = False
+    us, m = rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types, rk)
+    _, _, _, f = assemble(coords, conn, OP_POISSON, dt, us, rho, None, pattern_=(rp, ci), types=types)
+    f = f[0]
+    f[dn] = 0.0
+    p, st, it, _, _ = pcg(rp, ci, Lv, f, x0=p0, rtol=rtol, max_iter=max_iter)
+    if st != OK:
+        raise RuntimeError(f"oracle pressure solve failed: {st}")
+    g = gradient(coords, conn, p, types)
+    un = np.where(free, us - dt * g / m, us)
+    return un, p, it
 
 
 def dirichlet(rowptr, colidx, values, rhs, dnodes, g=None):

@@ -557,6 +557,96 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
 }
 
 /* ------------------------------------------------------------------ */
+/* Matrix-free element vectors for the explicit step (Algorithm 1)     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Element loop that integrates nodal vectors instead of matrices (the
+ * Runge-Kutta stages of Algorithm 1 assemble the momentum equations as
+ * residuals; the paper gives no formulation, see the step below):
+ *
+ *   kind 0  residual: r_i[a] = - sum_g dV (rho_g N_a (u_g . grad u_i,g)
+ *                                          + mu_g grad N_a . grad u_i,g)
+ *           for i = 0..2 into out[0..2][N], and the rho-weighted lumped mass
+ *           m[a] = sum_g dV rho_g N_a into out[3][N];
+ *   kind 1  gradient: g_j[a] = sum_g dV N_a (grad p)_j,g into out[0..2][N];
+ *
+ * with u_g, grad u_i,g, rho_g, mu_g, grad p_g interpolated from the nodal
+ * fields.  out is overwritten.  Same element types, connectivity convention
+ * and bad-element report as or_assemble_typed.
+ */
+int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
+                       int64_t n_elems, const int32_t *conn, int kind, const double *u,
+                       const double *rho, const double *mu, const double *p, double *out,
+                       int64_t *bad_elem, double *min_det)
+{
+    double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], Nt[MAXN + 1][MAXG][MAXN],
+        dNt[MAXN + 1][MAXG][MAXN][3];
+    int ngt[MAXN + 1];
+    for (int t = 0; t <= MAXN; ++t) ngt[t] = ref_element(t, pts[t], w[t], Nt[t], dNt[t]);
+    if (kind != 0 && kind != 1) return OR_EINVAL;
+    for (int64_t e = 0; e < n_elems; ++e)
+        if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
+    int nout = kind == 0 ? 4 : 3;
+    memset(out, 0, sizeof(double) * (size_t)(n_nodes * nout));
+    *bad_elem = -1;
+    *min_det = INFINITY;
+    int status = OR_OK;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        const int nen = elem_nen(stride, types, e), ng = ngt[nen];
+        const int32_t *c = conn + e * stride;
+        double X[MAXN][3];
+        for (int a = 0; a < nen; ++a)
+            for (int i = 0; i < 3; ++i) X[a][i] = coords[(int64_t)c[a] * 3 + i];
+        double B[4][MAXN] = {{0}};
+        int bad = 0;
+        for (int g = 0; g < ng; ++g) {
+            double dNx[MAXN][3];
+            double det = geometry(nen, X, dNt[nen][g], dNx);
+            if (det < *min_det) *min_det = det;
+            if (!(det > 0.0)) {
+                if (*bad_elem < 0) *bad_elem = e;
+                status = OR_EBADELEM;
+                bad = 1;
+                break;
+            }
+            double dV = w[nen][g] * det;
+            const double *Ng = Nt[nen][g];
+            if (kind == 0) {
+                double rg = 0.0, mg = 0.0, ug[3] = {0, 0, 0}, gu[3][3] = {{0}};
+                for (int b = 0; b < nen; ++b) {
+                    rg += Ng[b] * rho[c[b]];
+                    mg += Ng[b] * mu[c[b]];
+                    for (int i = 0; i < 3; ++i) {
+                        double ub = u[(int64_t)i * n_nodes + c[b]];
+                        ug[i] += Ng[b] * ub;
+                        for (int j = 0; j < 3; ++j) gu[i][j] += dNx[b][j] * ub;   /* d u_i / d x_j */
+                    }
+                }
+                for (int a = 0; a < nen; ++a) {
+                    for (int i = 0; i < 3; ++i) {
+                        double adv = ug[0] * gu[i][0] + ug[1] * gu[i][1] + ug[2] * gu[i][2];
+                        double vis = dNx[a][0] * gu[i][0] + dNx[a][1] * gu[i][1] + dNx[a][2] * gu[i][2];
+                        B[i][a] -= dV * (rg * Ng[a] * adv + mg * vis);
+                    }
+                    B[3][a] += dV * rg * Ng[a];
+                }
+            } else {
+                double gp[3] = {0, 0, 0};
+                for (int b = 0; b < nen; ++b)
+                    for (int j = 0; j < 3; ++j) gp[j] += dNx[b][j] * p[c[b]];
+                for (int a = 0; a < nen; ++a)
+                    for (int j = 0; j < 3; ++j) B[j][a] += dV * Ng[a] * gp[j];
+            }
+        }
+        if (bad) continue;
+        for (int a = 0; a < nen; ++a)
+            for (int k = 0; k < nout; ++k) out[(int64_t)k * n_nodes + c[a]] += B[k][a];
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
 /* Dirichlet elimination (symmetric)                                   */
 /* ------------------------------------------------------------------ */
 
