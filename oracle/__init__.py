@@ -167,14 +167,14 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
 
 def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None):
     coords, conn, types = _f64(coords), _i32(conn), _u8(types)
+    # contiguous copies held in locals: they must outlive the C call
+    u, rho, mu, p = [None if a is None else _f64(a) for a in (u, rho, mu, p)]
     N = coords.shape[0]
     out = np.zeros((4 if kind == 0 else 3, N))
     bad = C.c_int64(-1)
     mdet = C.c_double(0.0)
     st = lib().or_element_vectors(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), kind,
-                                  _p(None if u is None else _f64(u)), _p(None if rho is None else _f64(rho)),
-                                  _p(None if mu is None else _f64(mu)), _p(None if p is None else _f64(p)),
-                                  _p(out), C.byref(bad), C.byref(mdet))
+                                  _p(u), _p(rho), _p(mu), _p(p), _p(out), C.byref(bad), C.byref(mdet))
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return out
@@ -254,7 +254,8 @@ def spmv(rowptr, colidx, values, x):
     N = rowptr.shape[0] - 1
     x = _f64(x)
     y = np.zeros(N)
-    lib().or_spmv(N, _p(rowptr), _p(colidx), _p(_f64(values)), _p(x), _p(y))
+    values = _f64(values)   # held until the call returns
+    lib().or_spmv(N, _p(rowptr), _p(colidx), _p(values), _p(x), _p(y))
     return y
 
 
