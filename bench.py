@@ -503,6 +503,34 @@ def main():
                  "rhs_rel": float(torch.linalg.norm(Bx - Bm) / torch.linalg.norm(Bm))}
     del Vx, Bx
 
+    # explicit step (Algorithm 1's Runge-Kutta stages, pressure solve and
+    # correction), outside the timed region: one element-vector residual pass
+    # and one whole fractional step to a pressure residual of 1e-8
+    R4 = torch.empty((4, N), dtype=torch.float64, device=dev)
+    ctx.profile(True)
+    for _ in range(5):
+        fe.residual(mesh, u, rho, mu, out=R4)
+    n_res, ms_res = ctx.profile_read(4)
+    ctx.profile(False)
+    del R4
+    fe.assemble(mesh, fe.POISSON, case.dt, u, rho, values=L, rhs=f)
+    fe.apply_dirichlet(mesh, L, f)
+    us = u.clone()
+    ps = torch.zeros(N, dtype=torch.float64, device=dev)
+    fe.fractional_step(mesh, case.dt, rho, mu, L[0], us, ps, rtol=1e-8)   # allocates the step buffers
+    us.copy_(u)
+    ps.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_info = fe.fractional_step(mesh, case.dt, rho, mu, L[0], us, ps, rtol=1e-8)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3
+    del us, ps
+    explicit = {"residual_pass_ms": ms_res / n_res, "residual_melem_s": E / (ms_res / n_res * 1e-3) / 1e6,
+                "fractional_step_ms": step_ms, "pressure_cg_iterations": step_info["cg_iterations"],
+                "pressure_true_rel_residual": step_info["cg_true_rel_residual"]}
+    log(f"explicit step: {json.dumps(explicit)}")
+
     spmv_us = ms_spmv / n_spmv * 1e3
     sb = spmv_bytes(nnz, N)
     achieved = sb / (spmv_us * 1e-6) / 1e9
@@ -541,6 +569,7 @@ def main():
             "cg_iteration_effective_gbs": (sb + 88 * N) / ((spmv_us + ms_upd / max(n_upd, 1) * 1e3) * 1e-6) / 1e9,
             "cg_rel_residual_after_200": cg["rel_residual"], "cg_true_rel_residual": cg["true_rel_residual"],
             "upload_s": upload_s,
+            "explicit_step": explicit,
         },
     }
     if not args.no_cpu_baseline:

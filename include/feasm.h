@@ -212,6 +212,47 @@ typedef struct {
 fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
                       int32_t max_iter, fe_precision prec, fe_cg_info *info);
 
+/* ---- explicit step (Algorithm 1: Runge-Kutta momentum stages, pressure,
+ *      velocity correction) ---------------------------------------------------
+ * The paper's time step assembles the momentum equations inside Runge-Kutta
+ * stages, solves the pressure equation with PCG and corrects the velocity
+ * (Algorithm 1; the scheme itself is in a reference the paper cites).  The
+ * stages use the operator of fe_assemble(MOMENTUM) without its mass term,
+ * applied to the velocity element by element (no matrix is formed).  All
+ * arrays are device, mesh numbering, [k][n_nodes] rows, FP64.  Each call
+ * synchronises the stream and fails with FE_EBADELEM on det J <= 0. */
+
+/* out[4][n]: out_i = -(C(u) + K_mu) u_i for i = 0, 1, 2, i.e. per node a
+ *   -sum_e int rho N_a (u . grad u_i) + mu grad N_a . grad u_i,
+ * and out_3 = the rho-weighted lumped mass int rho N_a (row sums of M_rho). */
+fe_status fe_residual(fe_mesh mesh, const double *u, const double *rho, const double *mu, double *out);
+/* g[3][n]: g_j = int N_a d p / d x_j (the pressure gradient tested with N_a). */
+fe_status fe_gradient(fe_mesh mesh, const double *p, double *g);
+/* f[n] = (1/dt) int grad N_a . (rho u): the right-hand side of
+ * fe_assemble(POISSON) without its matrix. */
+fe_status fe_divergence(fe_mesh mesh, double dt, const double *u, const double *rho, double *f);
+
+typedef struct {
+    int32_t cg_iterations;        /* PCG iterations of the pressure solve */
+    double cg_true_rel_residual;  /* ||f - L p|| / ||f|| in FP64 */
+} fe_step_info;
+
+/*
+ * One fractional step:
+ *   1. predictor: three-stage strong-stability-preserving Runge-Kutta
+ *      (Shu-Osher) on M_L du/dt = fe_residual(u), M_L the lumped rho-mass;
+ *      u at the mesh's Dirichlet nodes is held;
+ *   2. pressure: L p = fe_divergence(u*) with zero at the Dirichlet rows,
+ *      Jacobi-PCG to rtol starting from p (in: initial guess);
+ *   3. correction: u = u* - dt M_L^-1 fe_gradient(p) at the free nodes.
+ * L: device [nnz] values of the Poisson matrix after fe_apply_dirichlet
+ * (assembled once, Algorithm 1, first step).  u [3][n] in/out, p [n] in/out.
+ * Work buffers (11 n doubles) are allocated on the mesh at the first call.
+ * Returns FE_ENOCONV / FE_EBREAKDOWN from the solve (u then holds u*).
+ */
+fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const double *mu, const double *L,
+                             double *u, double *p, double rtol, int32_t max_iter, fe_step_info *info);
+
 /* ---- serving: continuous batching of assemble + solve requests -------------
  * The time-step workload of the paper (Algorithm 1: momentum assembly, the
  * pressure system's assembly and its PCG solve; Section 2) offered as a
@@ -293,7 +334,9 @@ void fe_serve_destroy(fe_server server);
  * With profiling on, the library brackets its launches with HIP events on the
  * context's stream: slot 0 = the SpMV launch of one PCG iteration (fused with
  * p.Ap), slot 1 = one fe_assemble call (all colours), slot 2 = the vector
- * updates of one PCG iteration, slot 3 = fe_apply_dirichlet.
+ * updates of one PCG iteration, slot 3 = fe_apply_dirichlet, slot 4 = one
+ * element-vector pass (fe_residual, fe_gradient, fe_divergence and those of
+ * fe_fractional_step).
  * fe_ctx_profile() clears the records; fe_ctx_profile_read() synchronises
  * and returns the number of bracketed intervals and their summed duration. */
 fe_status fe_ctx_profile(fe_ctx ctx, int enable);

@@ -31,6 +31,7 @@ MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
+           "residual", "gradient", "divergence", "fractional_step",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
@@ -209,6 +210,62 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+def residual(mesh: Mesh, u, rho, mu, out=None):
+    """fe_residual: out[4, N] = -(C(u) + K_mu) u (3 rows) and the lumped rho-mass."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(mu, torch.float64, N, "mu")
+    if out is None:
+        out = torch.empty((4, N), dtype=torch.float64, device=u.device)
+    _check_dev(out, torch.float64, 4 * N, "out")
+    mesh.ctx.check(mesh.ctx.lib.fe_residual(mesh.h, _ptr(u), _ptr(rho), _ptr(mu), _ptr(out)))
+    return out
+
+
+def gradient(mesh: Mesh, p, out=None):
+    """fe_gradient: out[3, N] = int N_a grad p."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(p, torch.float64, N, "p")
+    if out is None:
+        out = torch.empty((3, N), dtype=torch.float64, device=p.device)
+    _check_dev(out, torch.float64, 3 * N, "out")
+    mesh.ctx.check(mesh.ctx.lib.fe_gradient(mesh.h, _ptr(p), _ptr(out)))
+    return out
+
+
+def divergence(mesh: Mesh, dt: float, u, rho, out=None):
+    """fe_divergence: out[N] = (1/dt) int grad N_a . (rho u)."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    if out is None:
+        out = torch.empty(N, dtype=torch.float64, device=u.device)
+    _check_dev(out, torch.float64, N, "out")
+    mesh.ctx.check(mesh.ctx.lib.fe_divergence(mesh.h, float(dt), _ptr(u), _ptr(rho), _ptr(out)))
+    return out
+
+
+def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8, max_iter: int = 20000):
+    """fe_fractional_step: advances u [3, N] and p [N] in place (device,
+    mesh numbering); L is the Poisson matrix after apply_dirichlet.
+    Returns {"cg_iterations", "cg_true_rel_residual"}."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(p, torch.float64, N, "p")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(mu, torch.float64, N, "mu")
+    _check_dev(L, torch.float64, mesh.nnz, "L")
+    info = capi.StepInfo()
+    mesh.ctx.check(mesh.ctx.lib.fe_fractional_step(mesh.h, float(dt), _ptr(rho), _ptr(mu), _ptr(L), _ptr(u),
+                                                   _ptr(p), float(rtol), int(max_iter), C.byref(info)))
+    return {"cg_iterations": info.cg_iterations, "cg_true_rel_residual": info.cg_true_rel_residual}
 
 
 def assemble(mesh: Mesh, op: int, dt: float, u, rho, mu=None, Y=None, D=None, precision: int = FP64,

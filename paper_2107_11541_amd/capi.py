@@ -24,6 +24,10 @@ class Fields(C.Structure):
                 ("n_scalars", i32), ("Y", P), ("D", P)]
 
 
+class StepInfo(C.Structure):
+    _fields_ = [("cg_iterations", i32), ("cg_true_rel_residual", dbl)]
+
+
 class AsmInfo(C.Structure):
     _fields_ = [("min_detJ", dbl), ("first_bad_elem", i64)]
 
@@ -76,6 +80,10 @@ SIGNATURES = {
     "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
     "fe_axpy": (C.c_int, [P, i64, dbl, P, P]),
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
+    "fe_residual": (C.c_int, [P, P, P, P, P]),
+    "fe_gradient": (C.c_int, [P, P, P]),
+    "fe_divergence": (C.c_int, [P, dbl, P, P, P]),
+    "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, P, P, dbl, i32, C.POINTER(StepInfo)]),
     "fe_serve_create": (C.c_int, [P, sz, i32, i32, C.POINTER(P)]),
     "fe_serve_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(i64)]),
     "fe_serve_poll": (C.c_int, [P, i64, C.POINTER(i32), C.POINTER(JobResult)]),

@@ -32,6 +32,9 @@ namespace feasm {
 namespace {
 
 constexpr int OP_MOM = FE_OP_MOMENTUM, OP_SCA = FE_OP_SCALAR, OP_POI = FE_OP_POISSON;
+// element-vector passes of the explicit step (no matrix): residual + lumped
+// mass, pressure gradient, divergence right-hand side
+constexpr int OP_RES = kOpResidual, OP_GRD = kOpGradient, OP_DIV = kOpDivergence;
 
 // Trilinear hexahedron, 2x2x2 Gauss rule (points xi fastest, weights 1).
 struct Hex {
@@ -159,7 +162,7 @@ struct KArgs {
     const uint16_t *elem_lnode;
     int64_t N, E;
     int off_stride;           // bytes of elem_off per element
-    const double *u, *rho, *mu, *Y;
+    const double *u, *rho, *mu, *Y, *p;
     double dt, Dk;
     double *values, *rhs;
     double *blk_mindet;       // [nblk] per-block smallest det J
@@ -171,6 +174,9 @@ template <int OP> struct OpTraits;
 template <> struct OpTraits<FE_OP_MOMENTUM> { static constexpr int NF = 8, NRHS = 3; };
 template <> struct OpTraits<FE_OP_SCALAR> { static constexpr int NF = 8, NRHS = 1; };
 template <> struct OpTraits<FE_OP_POISSON> { static constexpr int NF = 7, NRHS = 1; };
+template <> struct OpTraits<kOpResidual> { static constexpr int NF = 8, NRHS = 4; };    // r_x, r_y, r_z, lumped mass
+template <> struct OpTraits<kOpGradient> { static constexpr int NF = 4, NRHS = 3; };    // x, y, z, p
+template <> struct OpTraits<kOpDivergence> { static constexpr int NF = 7, NRHS = 1; };
 
 // Waves per element block: a HEX08 element's 8 rows are split between two
 // waves (4 rows each) so that a wave needs <= 256 registers and two blocks'
@@ -233,11 +239,9 @@ __device__ __forceinline__ void load_geo(const double *nd, int T, const int (&ln
     }
 }
 
-template <class EL, int OP, class Q, int RA, int A0>
-__device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, int T,
-                                            const int (&ln)[EL::NEN],
-                                            Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
-                                            double inv_dt, double Dk)
+// Jacobian of the map at Gauss point g, its determinant (returned) and inverse.
+template <class EL>
+__device__ __forceinline__ double jacobian_inverse(int g, const Geo<EL> &GE, double (&Ji)[3][3])
 {
     constexpr int NEN = EL::NEN;
     const auto &geo = GE.v;
@@ -272,9 +276,7 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
     const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    mindet = fmin(mindet, det);
     const double id = 1.0 / det;
-    double Ji[3][3];
     Ji[0][0] = c00 * id;
     Ji[1][0] = c01 * id;
     Ji[2][0] = c02 * id;
@@ -284,6 +286,87 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
     Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
     Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    return det;
+}
+
+// One Gauss point of an element-vector pass for rows [A0, A0 + RA), FP64,
+// from the physical gradients dN and dV = w det J:
+//   OP_RES: B_i[a] -= dV (rho N_a (u . grad u_i) + mu grad N_a . grad u_i), i < 3,
+//           B_3[a] += dV rho N_a (lumped mass);
+//   OP_GRD: B_j[a] += dV N_a (grad p)_j;
+//   OP_DIV: B_0[a] += dV / dt grad N_a . (rho u).
+// Fields in LDS: x, y, z, then u_x, u_y, u_z, rho, mu (OP_GRD: p in slot 3).
+template <class EL, int OP, int RA, int A0>
+__device__ __forceinline__ void element_vector_point(int g, const double *nd, int T, const int (&ln)[EL::NEN],
+                                                     const double (&dN)[EL::NEN][3], double dV,
+                                                     double (&B)[OpTraits<OP>::NRHS][RA], double inv_dt)
+{
+    constexpr int NEN = EL::NEN;
+    if constexpr (OP == OP_GRD) {
+        double gp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            const double pb = nd[3 * T + ln[b]];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gp[j] += dN[b][j] * pb;
+        }
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const double wn = dV * RefN<EL>(g, A0 + r);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) B[j][r] += wn * gp[j];
+        }
+    } else {
+        double rg = 0.0, mg = 0.0, ug[3] = {0.0, 0.0, 0.0}, gu[3][3] = {};
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            const double Nb = RefN<EL>(g, b);
+            rg += Nb * nd[6 * T + ln[b]];
+            if (OP == OP_RES) mg += Nb * nd[7 * T + ln[b]];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double ub = nd[(3 + i) * T + ln[b]];
+                ug[i] += Nb * ub;
+                if (OP == OP_RES) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) gu[i][j] += dN[b][j] * ub;   // d u_i / d x_j
+                }
+            }
+        }
+        if constexpr (OP == OP_RES) {
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const int a = A0 + r;
+                const double wr = dV * rg * RefN<EL>(g, a), wm = dV * mg;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double adv = ug[0] * gu[i][0] + ug[1] * gu[i][1] + ug[2] * gu[i][2];
+                    const double vis = dN[a][0] * gu[i][0] + dN[a][1] * gu[i][1] + dN[a][2] * gu[i][2];
+                    B[i][r] -= wr * adv + wm * vis;
+                }
+                B[3][r] += wr;
+            }
+        } else {
+            const double f0 = rg * ug[0], f1 = rg * ug[1], f2 = rg * ug[2], w = dV * inv_dt;
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const int a = A0 + r;
+                B[0][r] += w * (dN[a][0] * f0 + dN[a][1] * f1 + dN[a][2] * f2);
+            }
+        }
+    }
+}
+
+template <class EL, int OP, class Q, int RA, int A0>
+__device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, int T,
+                                            const int (&ln)[EL::NEN],
+                                            Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
+                                            double inv_dt, double Dk)
+{
+    constexpr int NEN = EL::NEN;
+    double Ji[3][3];
+    const double det = jacobian_inverse<EL>(g, GE, Ji);
+    mindet = fmin(mindet, det);
     // physical gradients grad N_a = J^-T grad_ref N_a (all nodes: needed for columns)
     Q dN[NEN][3];
 #pragma unroll
@@ -298,51 +381,55 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
             }
             dN[a][i] = Q(s);
         }
-    double rg = 0.0, fg = 0.0, ug0 = 0.0, ug1 = 0.0, ug2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < NEN; ++a) {
-        const double Na = RefN<EL>(g, a);
-        rg += Na * nd[6 * T + ln[a]];
-        ug0 += Na * nd[3 * T + ln[a]];
-        ug1 += Na * nd[4 * T + ln[a]];
-        ug2 += Na * nd[5 * T + ln[a]];
-        if (OP != OP_POI) fg += Na * nd[7 * T + ln[a]];
-    }
-    const double dV = EL::w(g) * det;
-    if (OP == OP_POI) {
-        const Q qdV = Q(dV), qi = Q(inv_dt);
-        const Q f0 = Q(rg * ug0), f1 = Q(rg * ug1), f2 = Q(rg * ug2);
-#pragma unroll
-        for (int r = 0; r < RA; ++r) {
-            const int a = A0 + r;
-            const Q G0 = qdV * dN[a][0], G1 = qdV * dN[a][1], G2 = qdV * dN[a][2];
-#pragma unroll
-            for (int b = 0; b < NEN; ++b) A[r][b] += G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2];
-            B[0][r] += qi * (G0 * f0 + G1 * f1 + G2 * f2);
-        }
+    if constexpr (OP >= OP_RES) {
+        element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt);
     } else {
-        const Q w1 = Q(dV) * Q(rg);
-        const Q wk = (OP == OP_MOM) ? Q(dV) * Q(fg) : Q(dV) * (Q(rg) * Q(Dk));   // fg = mu (MOM) or Y (SCA)
-        const Q qi = Q(inv_dt);
-        const Q qu0 = Q(ug0), qu1 = Q(ug1), qu2 = Q(ug2);
-        Q s[NEN];
+        double rg = 0.0, fg = 0.0, ug0 = 0.0, ug1 = 0.0, ug2 = 0.0;
 #pragma unroll
-        for (int b = 0; b < NEN; ++b)
-            s[b] = w1 * (Q(RefN<EL>(g, b)) * qi + (qu0 * dN[b][0] + qu1 * dN[b][1] + qu2 * dN[b][2]));
+        for (int a = 0; a < NEN; ++a) {
+            const double Na = RefN<EL>(g, a);
+            rg += Na * nd[6 * T + ln[a]];
+            ug0 += Na * nd[3 * T + ln[a]];
+            ug1 += Na * nd[4 * T + ln[a]];
+            ug2 += Na * nd[5 * T + ln[a]];
+            if (OP != OP_POI) fg += Na * nd[7 * T + ln[a]];
+        }
+        const double dV = EL::w(g) * det;
+        if (OP == OP_POI) {
+            const Q qdV = Q(dV), qi = Q(inv_dt);
+            const Q f0 = Q(rg * ug0), f1 = Q(rg * ug1), f2 = Q(rg * ug2);
 #pragma unroll
-        for (int r = 0; r < RA; ++r) {
-            const int a = A0 + r;
-            const Q Na = Q(RefN<EL>(g, a));
-            const Q G0 = wk * dN[a][0], G1 = wk * dN[a][1], G2 = wk * dN[a][2];
+            for (int r = 0; r < RA; ++r) {
+                const int a = A0 + r;
+                const Q G0 = qdV * dN[a][0], G1 = qdV * dN[a][1], G2 = qdV * dN[a][2];
 #pragma unroll
-            for (int b = 0; b < NEN; ++b) A[r][b] += Na * s[b] + (G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2]);
-            const Q wn = w1 * Na * qi;
-            if (OP == OP_MOM) {
-                B[0][r] += wn * qu0;
-                B[1][r] += wn * qu1;
-                B[2][r] += wn * qu2;
-            } else {
-                B[0][r] += wn * Q(fg);
+                for (int b = 0; b < NEN; ++b) A[r][b] += G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2];
+                B[0][r] += qi * (G0 * f0 + G1 * f1 + G2 * f2);
+            }
+        } else {
+            const Q w1 = Q(dV) * Q(rg);
+            const Q wk = (OP == OP_MOM) ? Q(dV) * Q(fg) : Q(dV) * (Q(rg) * Q(Dk));   // fg = mu (MOM) or Y (SCA)
+            const Q qi = Q(inv_dt);
+            const Q qu0 = Q(ug0), qu1 = Q(ug1), qu2 = Q(ug2);
+            Q s[NEN];
+#pragma unroll
+            for (int b = 0; b < NEN; ++b)
+                s[b] = w1 * (Q(RefN<EL>(g, b)) * qi + (qu0 * dN[b][0] + qu1 * dN[b][1] + qu2 * dN[b][2]));
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const int a = A0 + r;
+                const Q Na = Q(RefN<EL>(g, a));
+                const Q G0 = wk * dN[a][0], G1 = wk * dN[a][1], G2 = wk * dN[a][2];
+#pragma unroll
+                for (int b = 0; b < NEN; ++b) A[r][b] += Na * s[b] + (G0 * dN[b][0] + G1 * dN[b][1] + G2 * dN[b][2]);
+                const Q wn = w1 * Na * qi;
+                if (OP == OP_MOM) {
+                    B[0][r] += wn * qu0;
+                    B[1][r] += wn * qu1;
+                    B[2][r] += wn * qu2;
+                } else {
+                    B[0][r] += wn * Q(fg);
+                }
             }
         }
     }
@@ -382,6 +469,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
 {
     constexpr int NEN = EL::NEN, NG = EL::NG, W = Split<EL>::W, RA = NEN / W, NT = 64 * W;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
+    constexpr bool VEC = OP >= OP_RES;       // element-vector pass: no row image
     extern __shared__ double lds[];
 
     const int blk = k.color_blk[k.blk_offset + blockIdx.x];
@@ -394,7 +482,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     double *nd = lds;                        // [NF][T] nodal fields
     double *rimg = nd + NF * T;              // [NRHS][T] rhs image
     int *rdesc = (int *)(rimg + NRHS * T);   // [T] row descriptors
-    double *img = (double *)(rdesc + T + (T & 1));   // 8-byte aligned row image
+    double *img = (double *)(rdesc + T + (T & 1));   // 8-byte aligned row image (matrix passes)
 
     // Element data that depends only on the block: issue these loads first.
     const bool act = el < ne;
@@ -407,7 +495,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     // to whole words inside the element's slot
     constexpr int kOffWords = (RA * NEN + 3) / 4;
     uint32_t offw[kOffWords];
-    {
+    if constexpr (!VEC) {
         const uint32_t *op = (const uint32_t *)(k.elem_off + (int64_t)e * k.off_stride + a0 * NEN);
 #pragma unroll
         for (int q = 0; q < kOffWords; ++q) offw[q] = op[q];
@@ -421,33 +509,43 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     for (int t = tid; t < T; t += NT) {
         const int g = k.blk_nodes[n0 + t];
         const int rd = k.blk_rdesc[n0 + t];
-        const int r0 = k.blk_rowstart[n0 + t];
-        const int len = (rd >> 16) & 0xff, base = rd & 0xffff;
+        const int r0 = VEC ? 0 : k.blk_rowstart[n0 + t];   // matrix passes: the row in CSR
+        const int len = VEC ? 0 : (rd >> 16) & 0xff, base = rd & 0xffff;
         const bool first = rd < 0;
         double f[NF + NRHS];
         f[0] = k.X[g];
         f[1] = k.X[N + g];
         f[2] = k.X[2 * N + g];
-        f[3] = k.u[g];
-        f[4] = k.u[N + g];
-        f[5] = k.u[2 * N + g];
-        f[6] = k.rho[g];
-        if (OP == OP_MOM) f[7] = k.mu[g];
-        if (OP == OP_SCA) f[7] = k.Y[g];
+        if constexpr (OP == OP_GRD) {
+            f[3] = k.p[g];
+        } else {
+            f[3] = k.u[g];
+            f[4] = k.u[N + g];
+            f[5] = k.u[2 * N + g];
+            f[6] = k.rho[g];
+            if (OP == OP_MOM || OP == OP_RES) f[7] = k.mu[g];
+            if (OP == OP_SCA) f[7] = k.Y[g];
+        }
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) f[NF + r] = first ? 0.0 : k.rhs[r * N + g];
+        // matrix passes: the row's previous values, loaded before the LDS
+        // writes below so that the loads overlap them
         double v[kRowBatch];
+        if constexpr (!VEC) {
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) v[q] = (!first && q < len) ? k.values[r0 + q] : 0.0;
+            for (int q = 0; q < kRowBatch; ++q) v[q] = (!first && q < len) ? k.values[r0 + q] : 0.0;
+        }
 #pragma unroll
         for (int q = 0; q < NF; ++q) nd[q * T + t] = f[q];
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) rimg[r * T + t] = f[NF + r];
         rdesc[t] = rd;
+        if constexpr (!VEC) {
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q)
-            if (q < len) img[base + q] = v[q];
-        for (int q = kRowBatch; q < len; ++q) img[base + q] = first ? 0.0 : k.values[r0 + q];
+            for (int q = 0; q < kRowBatch; ++q)
+                if (q < len) img[base + q] = v[q];
+            for (int q = kRowBatch; q < len; ++q) img[base + q] = first ? 0.0 : k.values[r0 + q];
+        }
     }
     __syncthreads();
 
@@ -487,7 +585,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     //    in (a, b) order -- no two lanes of one instruction hit one address.
     int base[RA];
 #pragma unroll
-    for (int r = 0; r < RA; ++r) base[r] = rdesc[lr[r]] & 0xffff;
+    for (int r = 0; r < RA; ++r) base[r] = VEC ? 0 : rdesc[lr[r]] & 0xffff;
     const int nph = k.blk_nphase[blk];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -496,11 +594,13 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
                 if (ph == p) {
 #pragma unroll
                     for (int r = 0; r < RA; ++r) {
+                        if constexpr (!VEC) {
 #pragma unroll
-                        for (int b = 0; b < NEN; ++b) {
-                            const int idx = r * NEN + b;
-                            const int off = (offw[idx >> 2] >> (8 * (idx & 3))) & 0xff;
-                            lds_add(&img[base[r] + off], (double)A[r][b]);
+                            for (int b = 0; b < NEN; ++b) {
+                                const int idx = r * NEN + b;
+                                const int off = (offw[idx >> 2] >> (8 * (idx & 3))) & 0xff;
+                                lds_add(&img[base[r] + off], (double)A[r][b]);
+                            }
                         }
 #pragma unroll
                         for (int q = 0; q < NRHS; ++q) lds_add(&rimg[q * T + lr[r]], (double)B[q][r]);
@@ -530,7 +630,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
 
     // 5. write back, one touched row per lane (LDS reads batched ahead of the
     //    stores)
-    for (int t = tid; t < T; t += NT) {
+    for (int t = tid; t < T && !VEC; t += NT) {
         const int rd = rdesc[t];
         const int64_t r0 = k.blk_rowstart[n0 + t];
         const int len = (rd >> 16) & 0xff, base = rd & 0xffff;
@@ -605,9 +705,15 @@ void launch_one(const AsmLaunch &L, KArgs k, hipStream_t s)
 template <class EL>
 void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStream_t s)
 {
-    if (op == OP_MOM) mixed ? launch_one<EL, OP_MOM, float>(L, k, s) : launch_one<EL, OP_MOM, double>(L, k, s);
-    else if (op == OP_SCA) mixed ? launch_one<EL, OP_SCA, float>(L, k, s) : launch_one<EL, OP_SCA, double>(L, k, s);
-    else mixed ? launch_one<EL, OP_POI, float>(L, k, s) : launch_one<EL, OP_POI, double>(L, k, s);
+    switch (op) {
+    case OP_MOM: mixed ? launch_one<EL, OP_MOM, float>(L, k, s) : launch_one<EL, OP_MOM, double>(L, k, s); break;
+    case OP_SCA: mixed ? launch_one<EL, OP_SCA, float>(L, k, s) : launch_one<EL, OP_SCA, double>(L, k, s); break;
+    case OP_POI: mixed ? launch_one<EL, OP_POI, float>(L, k, s) : launch_one<EL, OP_POI, double>(L, k, s); break;
+    // element-vector passes are FP64 only
+    case OP_RES: launch_one<EL, OP_RES, double>(L, k, s); break;
+    case OP_GRD: launch_one<EL, OP_GRD, double>(L, k, s); break;
+    default: launch_one<EL, OP_DIV, double>(L, k, s); break;
+    }
 }
 
 }  // namespace
@@ -615,6 +721,7 @@ void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStre
 hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
 {
     const DevMesh &m = *a.m;
+    if (a.op < 0 || a.op >= kNumOps) return hipErrorInvalidValue;
     KArgs k{};
     k.X = m.X;
     k.blk_elem_ptr = m.blk_elem_ptr;
@@ -633,6 +740,7 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     k.rho = a.rho;
     k.mu = a.mu;
     k.Y = a.Y;
+    k.p = a.p;
     k.dt = a.dt;
     k.Dk = a.Dk;
     k.values = a.values;

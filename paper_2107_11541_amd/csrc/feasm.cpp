@@ -238,18 +238,19 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     // assembly launches and their LDS per operator: [fields NF][rhs NRHS]
     // doubles per row, one int descriptor per row (+ alignment), then the row
     // image, for the launch's largest block
-    const int nf[3] = {8, 8, 7}, nr[3] = {3, 1, 1};
+    // (the element-vector passes stage no row image)
+    const int nf[kNumOps] = {8, 8, 7, 8, 4, 7}, nr[kNumOps] = {3, 1, 1, 4, 3, 1};
     d.launches.clear();
     for (const AsmSeg &g : P.segs) {
-        AsmLaunch L{g.nen, g.first, g.count, {0, 0, 0}};
+        AsmLaunch L{g.nen, g.first, g.count, {0, 0, 0, 0, 0, 0}};
         for (int q = g.first; q < g.first + g.count; ++q) {
             const int32_t b = P.color_blk[q];
             const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
             int64_t nl = 0;
             for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
                 nl += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
-            for (int op = 0; op < 3; ++op) {
-                size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (size_t)nl * 8;
+            for (int op = 0; op < kNumOps; ++op) {
+                size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (op < 3 ? (size_t)nl * 8 : 0);
                 L.lds[op] = std::max(L.lds[op], by);
             }
         }
@@ -295,6 +296,7 @@ void mesh_release(fe_mesh_s *m)
     }
     m->allocs.clear();
     m->cg = CGWork();
+    m->step_work = nullptr;
 }
 
 fe_status mesh_commit(fe_mesh_s *m, MeshImage &I, hipStream_t stream)
@@ -425,6 +427,49 @@ fe_status sync(fe_ctx_s *c)
 {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     return FE_OK;
+}
+
+// Reads the status word of the assembly launches queued last (synchronises)
+// and reports the first element with det J <= 0 by its user id.
+fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
+{
+    fe_ctx_s *c = m->ctx;
+    AsmStatus *hs = (AsmStatus *)c->host;
+    HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    double md;
+    memcpy(&md, &hs->min_det_key, 8);
+    long long bad = hs->first_bad;
+    if (info) {
+        info->min_detJ = md;
+        info->first_bad_elem = bad >= 0 ? m->elem_perm[bad] : -1;
+    }
+    if (bad >= 0) return fail(c, FE_EBADELEM, "det J <= 0 in element %d (user id)", m->elem_perm[bad]);
+    return FE_OK;
+}
+
+// Queues one element-vector pass (kOpResidual, kOpGradient, kOpDivergence)
+// writing its rows of N to out, and checks its status word.
+fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, const double *rho, const double *mu,
+                          const double *p, double *out)
+{
+    fe_ctx_s *c = m->ctx;
+    AsmArgs a{};
+    a.m = &m->dm;
+    a.op = op;
+    a.dt = dt;
+    a.u = u;
+    a.rho = rho;
+    a.mu = mu;
+    a.p = p;
+    a.rhs = out;
+    a.status = m->status;
+    {
+        ProfScope ps(c, 4);
+        HIPCALL(c, launch_assemble(a, false, c->stream));
+    }
+    return read_asm_status(m, nullptr);
 }
 
 // Iterations recorded per PCG graph.  A graph replays them with no launch
@@ -691,19 +736,7 @@ fe_status fe_assemble(fe_mesh m, const fe_fields *f, fe_precision prec, double *
         fe_status s = assemble_queue(m, f, prec, values, rhs, c->stream);
         if (s != FE_OK) return s;
     }
-    AsmStatus *hs = (AsmStatus *)c->host;
-    HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
-    fe_status s = sync(c);
-    if (s != FE_OK) return s;
-    double md;
-    memcpy(&md, &hs->min_det_key, 8);
-    long long bad = hs->first_bad;
-    if (info) {
-        info->min_detJ = md;
-        info->first_bad_elem = bad >= 0 ? m->elem_perm[bad] : -1;
-    }
-    if (bad >= 0) return fail(c, FE_EBADELEM, "det J <= 0 in element %d (user id)", m->elem_perm[bad]);
-    return FE_OK;
+    return read_asm_status(m, info);
 }
 
 fe_status fe_apply_dirichlet(fe_mesh m, double *values, double *rhs, const double *g)
@@ -825,6 +858,71 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
     return FE_OK;
 }
 
+// ---- explicit step ----------------------------------------------------------
+
+fe_status fe_residual(fe_mesh m, const double *u, const double *rho, const double *mu, double *out)
+{
+    if (!m) return FE_EINVAL;
+    if (!u || !rho || !mu || !out) return fail(m->ctx, FE_EINVAL, "null u/rho/mu/out");
+    HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
+    return element_vectors(m, kOpResidual, 1.0, u, rho, mu, nullptr, out);
+}
+
+fe_status fe_gradient(fe_mesh m, const double *p, double *g)
+{
+    if (!m) return FE_EINVAL;
+    if (!p || !g) return fail(m->ctx, FE_EINVAL, "null p/g");
+    HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
+    return element_vectors(m, kOpGradient, 1.0, nullptr, nullptr, nullptr, p, g);
+}
+
+fe_status fe_divergence(fe_mesh m, double dt, const double *u, const double *rho, double *f)
+{
+    if (!m) return FE_EINVAL;
+    if (!u || !rho || !f) return fail(m->ctx, FE_EINVAL, "null u/rho/f");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m->ctx, FE_EINVAL, "dt must be > 0");
+    HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
+    return element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f);
+}
+
+fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const double *mu, const double *L, double *u,
+                             double *p, double rtol, int32_t max_iter, fe_step_info *info)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (!rho || !mu || !L || !u || !p) return fail(c, FE_EINVAL, "null rho/mu/L/u/p");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FE_EINVAL, "dt must be > 0");
+    if (!(rtol > 0.0) || max_iter < 1) return fail(c, FE_EINVAL, "need rtol > 0 and max_iter >= 1");
+    HIPCALL(c, hipSetDevice(c->device));
+    const DevMesh &d = m->dm;
+    const int64_t N = d.N;
+    fe_status s;
+    if (!m->step_work && (s = mesh_alloc(m, (void **)&m->step_work, 11 * (size_t)N * sizeof(double))) != FE_OK)
+        return s;
+    double *u0 = m->step_work, *res = u0 + 3 * N, *mass = res + 3 * N, *f = res + 4 * N, *g = f + N;
+    // 1. Runge-Kutta predictor (Shu-Osher SSP-RK3) on M_L du/dt = R(u)
+    static const double kStage[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+    HIPCALL(c, hipMemcpyAsync(u0, u, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    for (const auto &st : kStage) {
+        if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res)) != FE_OK) return s;
+        HIPCALL(c, launch_rk_stage(d, st[0], st[1], dt, u0, res, mass, u, c->stream));
+    }
+    // 2. pressure: L p = (1/dt) int grad N . (rho u*), zero at Dirichlet rows
+    if ((s = element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f)) != FE_OK) return s;
+    HIPCALL(c, launch_zero_fixed(d, f, c->stream));
+    fe_cg_info ci{};
+    s = fe_cg_solve(m, L, f, p, rtol, max_iter, FE_FP64, &ci);
+    if (info) {
+        info->cg_iterations = ci.iterations;
+        info->cg_true_rel_residual = ci.true_rel_residual;
+    }
+    if (s != FE_OK) return s;
+    // 3. correction u = u* - dt M_L^-1 G p
+    if ((s = element_vectors(m, kOpGradient, dt, nullptr, nullptr, nullptr, p, g)) != FE_OK) return s;
+    HIPCALL(c, launch_correct(d, dt, g, mass, u, c->stream));
+    return sync(c);
+}
+
 // ---- profiling hooks (not part of the numerical API) -------------------------
 
 fe_status fe_ctx_profile(fe_ctx c, int enable)
@@ -838,7 +936,7 @@ fe_status fe_ctx_profile(fe_ctx c, int enable)
 
 fe_status fe_ctx_profile_read(fe_ctx c, int slot, int64_t *launches, double *total_ms)
 {
-    if (!c || slot < 0 || slot >= 4 || !launches || !total_ms) return FE_EINVAL;
+    if (!c || slot < 0 || slot >= 5 || !launches || !total_ms) return FE_EINVAL;
     HIPCALL(c, hipStreamSynchronize(c->stream));
     ProfSlot &p = c->prof[slot];
     double tot = 0.0;

@@ -48,7 +48,8 @@ struct fe_ctx_s {
     double *host = nullptr;       // pinned read-back area (64 doubles)
     bool profiling = false;
     std::vector<fe_mesh_s *> meshes;   // live meshes, freed by fe_ctx_destroy
-    feasm::ProfSlot prof[4];      // 0 CG SpMV + p.q, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet
+    feasm::ProfSlot prof[5];      // 0 CG SpMV + p.q, 1 assembly (all colours), 2 CG vector updates, 3 Dirichlet,
+                                  // 4 element-vector pass (explicit step)
 };
 
 struct fe_mesh_s {
@@ -59,6 +60,7 @@ struct fe_mesh_s {
     size_t bytes = 0;
     feasm::AsmStatus *status = nullptr;  // + per-block scratch
     feasm::CGWork cg;
+    double *step_work = nullptr;         // explicit step: u0 [3][N], residual + mass [4][N], f [N], g [3][N]
     feasm::DevArena *arena = nullptr;    // device memory source (nullptr: hipMalloc)
     bool listed = true;                  // in ctx->meshes (freed with the context)
     // recorded PCG iterations (FP64, FP32), valid for the pointers they were

@@ -11,12 +11,18 @@
 
 namespace feasm {
 
+// Element-vector passes of the explicit step, numbered after the fe_operator
+// values: residual -(C(u) + K_mu) u per component plus the rho-weighted
+// lumped mass, pressure gradient int N grad p, divergence right-hand side
+// (1/dt) int grad N . (rho u).
+constexpr int kOpResidual = 3, kOpGradient = 4, kOpDivergence = 5, kNumOps = 6;
+
 // One assembly launch: the blocks color_blk[first, first + count), all of one
 // colour and one element type (nen nodes); lds[op] = LDS bytes of its
-// largest block for operator op.
+// largest block for operator (or element-vector pass) op.
 struct AsmLaunch {
     int nen, first, count;
-    size_t lds[3];
+    size_t lds[kNumOps];
 };
 
 // Device-resident mesh: geometry, CSR pattern and the block scatter plan.
@@ -82,11 +88,12 @@ struct AsmStatus {
 
 struct AsmArgs {
     const DevMesh *m;
-    int op;                  // fe_operator
+    int op;                  // fe_operator, or kOpResidual / kOpGradient / kOpDivergence
     double dt, Dk;
     const double *u, *rho, *mu, *Y;   // Y: the scalar of this pass
+    const double *p;         // kOpGradient: the pressure
     double *values;          // operator's value array [nnz]
-    double *rhs;             // first rhs row [N] (momentum: 3 rows of N)
+    double *rhs;             // first rhs row [N] (momentum: 3 rows of N; element-vector passes: their rows)
     AsmStatus *status;
 };
 
@@ -125,6 +132,12 @@ hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, do
 hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part, double *out, hipStream_t s);
 hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 hipError_t launch_dirichlet(const DevMesh &m, double *vals, double *rhs, const double *g, hipStream_t s);
+// Explicit-step updates on [3][N] velocity rows (k_rk_stage, k_correct) and
+// zeroing a right-hand side at the Dirichlet nodes.
+hipError_t launch_rk_stage(const DevMesh &m, double alpha, double beta, double dt, const double *u0,
+                           const double *r, const double *mass, double *u, hipStream_t s);
+hipError_t launch_correct(const DevMesh &m, double dt, const double *g, const double *mass, double *u, hipStream_t s);
+hipError_t launch_zero_fixed(const DevMesh &m, double *f, hipStream_t s);
 hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const double *in, double *out, bool gather,
                           hipStream_t s);
 

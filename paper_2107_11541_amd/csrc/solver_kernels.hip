@@ -423,6 +423,41 @@ __global__ void __launch_bounds__(kTB) k_axpy(int64_t n, double a, const double 
     for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) y[i] += a * x[i];
 }
 
+// Explicit-step vector updates ([3][n] velocity rows, mass m[n], Dirichlet
+// flags): one Runge-Kutta stage u = alpha u0 + beta (u + dt r / m) at free
+// nodes, u = u0 at Dirichlet nodes (u may alias neither u0 nor r); the
+// velocity correction u -= dt g / m at free nodes; and f = 0 at Dirichlet rows.
+__global__ void __launch_bounds__(kTB) k_rk_stage(int64_t n, double alpha, double beta, double dt, const double *u0,
+                                                  const double *r, const double *m, const uint8_t *is_dir, double *u)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        const bool fixed = is_dir[i] != 0;
+        const double h = dt / m[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t j = c * n + i;
+            u[j] = fixed ? u0[j] : alpha * u0[j] + beta * (u[j] + h * r[j]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kTB) k_correct(int64_t n, double dt, const double *g, const double *m,
+                                                 const uint8_t *is_dir, double *u)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        if (is_dir[i]) continue;
+        const double h = dt / m[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[c * n + i] -= h * g[c * n + i];
+    }
+}
+
+__global__ void __launch_bounds__(kTB) k_zero_fixed(int64_t n, const uint8_t *is_dir, double *f)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        if (is_dir[i]) f[i] = 0.0;
+}
+
 // Symmetric Dirichlet elimination on the affected rows, G lanes per row.
 template <int G>
 __global__ void __launch_bounds__(kTB) k_dirichlet(const int32_t *rowptr, const int32_t *colidx, const int32_t *rows,
@@ -818,6 +853,26 @@ hipError_t launch_dot(int64_t n, const double *x, const double *y, double *part,
 hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 {
     hipLaunchKernelGGL(k_axpy, dim3(stream_blocks(n)), dim3(kTB), 0, s, n, a, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_stage(const DevMesh &m, double alpha, double beta, double dt, const double *u0,
+                           const double *r, const double *mass, double *u, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rk_stage, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, alpha, beta, dt, u0, r, mass,
+                       m.is_dir, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const DevMesh &m, double dt, const double *g, const double *mass, double *u, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_correct, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, dt, g, mass, m.is_dir, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_fixed(const DevMesh &m, double *f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_fixed, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, m.is_dir, f);
     return hipGetLastError();
 }
 
