@@ -52,7 +52,7 @@ def lib():
         L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
                                         i32, C.POINTER(i64), C.POINTER(dbl)]
         L.or_element_vectors.restype = i32
-        L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, P, P, P, P, P, C.POINTER(i64),
+        L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, C.POINTER(i64),
                                          C.POINTER(dbl)]
         L.or_dirichlet.restype = i32
         L.or_dirichlet.argtypes = [i64, P, P, P, P, i64, P, P]
@@ -165,7 +165,10 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
     return rowptr, colidx, values, rhs
 
 
-def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None):
+FULL_STRESS, EMAC = 1, 2    # residual operator variants (bits of `form`)
+
+
+def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None, form=0):
     coords, conn, types = _f64(coords), _i32(conn), _u8(types)
     # contiguous copies held in locals: they must outlive the C call
     u, rho, mu, p = [None if a is None else _f64(a) for a in (u, rho, mu, p)]
@@ -173,17 +176,19 @@ def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, type
     out = np.zeros((4 if kind == 0 else 3, N))
     bad = C.c_int64(-1)
     mdet = C.c_double(0.0)
-    st = lib().or_element_vectors(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), kind,
+    st = lib().or_element_vectors(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), kind, form,
                                   _p(u), _p(rho), _p(mu), _p(p), _p(out), C.byref(bad), C.byref(mdet))
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return out
 
 
-def residual(coords, conn, u, rho, mu, types=None):
+def residual(coords, conn, u, rho, mu, types=None, form=0):
     """Matrix-free momentum residual r[3, N] = -(C(u) + K_mu) u_i and the
-    rho-weighted lumped mass m[N] (or_element_vectors kind 0)."""
-    out = _element_vectors(coords, conn, 0, u=u, rho=rho, mu=mu, types=types)
+    rho-weighted lumped mass m[N] (or_element_vectors kind 0); form: bits
+    FULL_STRESS (viscous term 2 mu eps(u)) and EMAC (convective term of
+    Eq. (1) at the Gauss points)."""
+    out = _element_vectors(coords, conn, 0, u=u, rho=rho, mu=mu, types=types, form=form)
     return out[:3], out[3]
 
 
@@ -197,7 +202,7 @@ def gradient(coords, conn, p, types=None):
 SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
-def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=SSP_RK3):
+def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=SSP_RK3, form=0):
     """Explicit RK stages of M_L du/dt = R(u) (velocity held at Dirichlet
     nodes).  Returns (u*, lumped mass m)."""
     free = np.ones(u.shape[1], bool)
@@ -206,14 +211,14 @@ def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=S
     us = u0.copy()
     m = None
     for a, b in rk:
-        r, m = residual(coords, conn, us, rho, mu, types)
+        r, m = residual(coords, conn, us, rho, mu, types, form)
         nxt = a * u0 + b * (us + dt * r / m)
         us = np.where(free, nxt, u0)
     return us, m
 
 
 def fractional_step(coords, conn, dirichlet_nodes, dt, u, rho, mu, L, rtol=1e-12, max_iter=20000, p0=None,
-                    types=None, rk=SSP_RK3):
+                    types=None, rk=SSP_RK3, form=0):
     """One step of the fractional-step scheme around the assembly (Algorithm 1):
       1. momentum predictor, explicit RK (SSP-RK3) on M_L du/dt = R(u), with
          M_L the rho-weighted lumped mass and R the matrix-free residual; the
@@ -227,7 +232,7 @@ def fractional_step(coords, conn, dirichlet_nodes, dt, u, rho, mu, L, rtol=1e-12
     dn = np.asarray(dirichlet_nodes)
     free = np.ones(u.shape[1], bool)
     free[dn] = False
-    us, m = rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types, rk)
+    us, m = rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types, rk, form)
     _, _, _, f = assemble(coords, conn, OP_POISSON, dt, us, rho, None, pattern_=(rp, ci), types=types)
     f = f[0]
     f[dn] = 0.0

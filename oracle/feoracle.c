@@ -568,7 +568,13 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
  *   kind 0  residual: r_i[a] = - sum_g dV (rho_g N_a (u_g . grad u_i,g)
  *                                          + mu_g grad N_a . grad u_i,g)
  *           for i = 0..2 into out[0..2][N], and the rho-weighted lumped mass
- *           m[a] = sum_g dV rho_g N_a into out[3][N];
+ *           m[a] = sum_g dV rho_g N_a into out[3][N].  form selects the
+ *           operator variants of Eq. (1): bit 0 the full-stress viscous term
+ *           2 mu eps(u) tested with grad N_a, i.e. + mu_g (d u_j / d x_i)
+ *           (d N_a / d x_j) on top of the Laplacian form; bit 1 the EMAC
+ *           convective term 2 eps(u) u + (div u) u - grad(|u|^2)/2 evaluated
+ *           at the Gauss point, which is (u . grad) u + (div u) u there, i.e.
+ *           + rho_g N_a (div u_g) u_i,g on top of the advective form;
  *   kind 1  gradient: g_j[a] = sum_g dV N_a (grad p)_j,g into out[0..2][N];
  *
  * with u_g, grad u_i,g, rho_g, mu_g, grad p_g interpolated from the nodal
@@ -576,7 +582,7 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
  * and bad-element report as or_assemble_typed.
  */
 int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
-                       int64_t n_elems, const int32_t *conn, int kind, const double *u,
+                       int64_t n_elems, const int32_t *conn, int kind, int form, const double *u,
                        const double *rho, const double *mu, const double *p, double *out,
                        int64_t *bad_elem, double *min_det)
 {
@@ -623,10 +629,15 @@ int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const 
                         for (int j = 0; j < 3; ++j) gu[i][j] += dNx[b][j] * ub;   /* d u_i / d x_j */
                     }
                 }
+                double divu = gu[0][0] + gu[1][1] + gu[2][2];
                 for (int a = 0; a < nen; ++a) {
                     for (int i = 0; i < 3; ++i) {
                         double adv = ug[0] * gu[i][0] + ug[1] * gu[i][1] + ug[2] * gu[i][2];
                         double vis = dNx[a][0] * gu[i][0] + dNx[a][1] * gu[i][1] + dNx[a][2] * gu[i][2];
+                        if (form & 1) /* + (grad u)^T part of 2 eps(u) */
+                            vis += dNx[a][0] * gu[0][i] + dNx[a][1] * gu[1][i] + dNx[a][2] * gu[2][i];
+                        if (form & 2) /* EMAC: + (div u) u */
+                            adv += divu * ug[i];
                         B[i][a] -= dV * (rg * Ng[a] * adv + mg * vis);
                     }
                     B[3][a] += dV * rg * Ng[a];

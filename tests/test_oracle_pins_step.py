@@ -108,3 +108,68 @@ def test_fractional_step_keeps_boundary_and_reduces_divergence():
     # an approximate projection (lumped mass): the discrete divergence drops,
     # not to zero
     assert np.linalg.norm(rhs(un)[free]) < 0.95 * np.linalg.norm(f[free])
+
+
+# --- operator variants of Eq. (1): full-stress viscous term, EMAC convection ---
+
+def _lin(c, A, b=None):
+    """Nodal values of the linear field u = A x (+ b), [3, N]."""
+    u = (c.coords @ np.asarray(A).T).T
+    return np.ascontiguousarray(u if b is None else u + np.asarray(b)[:, None])
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "hybrid"])
+def test_full_stress_on_rotations_and_strains(kind):
+    # rho = 0 isolates the viscous term; constant mu
+    c = case_of(kind, seed=5)
+    N = c.n_nodes
+    zero, mu = np.zeros(N), np.full(N, 1.7e-3)
+    W = np.array([[0.0, -0.4, 0.9], [0.4, 0.0, -1.3], [-0.9, 1.3, 0.0]])     # rigid rotation: eps(u) = 0
+    r_fs, _ = oracle.residual(c.coords, c.conn, _lin(c, W), zero, mu, c.types, oracle.FULL_STRESS)
+    r_lap, _ = oracle.residual(c.coords, c.conn, _lin(c, W), zero, mu, c.types)
+    assert np.abs(r_fs).max() <= 1e-14 * np.abs(r_lap).max()
+    assert np.abs(r_lap).max() > 1e-6            # the Laplacian form does not vanish there
+    S = np.array([[0.7, 0.2, -0.3], [0.2, -0.1, 0.5], [-0.3, 0.5, 0.4]])      # symmetric, trace != 0
+    r_fs, _ = oracle.residual(c.coords, c.conn, _lin(c, S), zero, mu, c.types, oracle.FULL_STRESS)
+    r_lap, _ = oracle.residual(c.coords, c.conn, _lin(c, S), zero, mu, c.types)
+    assert np.abs(r_fs - 2.0 * r_lap).max() <= 1e-13 * np.abs(r_lap).max()
+    # symmetric bilinear form: v . V(u) = u . V(v)
+    rng = np.random.default_rng(6)
+    u, v = rng.normal(size=(3, N)), rng.normal(size=(3, N))
+    ru, _ = oracle.residual(c.coords, c.conn, u, zero, mu, c.types, oracle.FULL_STRESS)
+    rv, _ = oracle.residual(c.coords, c.conn, v, zero, mu, c.types, oracle.FULL_STRESS)
+    assert abs(np.sum(v * ru) - np.sum(u * rv)) <= 1e-12 * np.abs(v * ru).sum()
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "hybrid"])
+def test_emac_divergence_term_and_momentum_conservation(kind):
+    c = case_of(kind, seed=6)
+    N = c.n_nodes
+    one, zero = np.ones(N), np.zeros(N)
+    # divergence-free linear field: EMAC = advective form
+    A = np.array([[0.3, -0.7, 0.2], [0.5, 0.1, -0.4], [0.6, 0.9, -0.4]])    # trace 0
+    r_e, _ = oracle.residual(c.coords, c.conn, _lin(c, A, [0.2, -0.1, 0.3]), one, zero, c.types, oracle.EMAC)
+    r_a, _ = oracle.residual(c.coords, c.conn, _lin(c, A, [0.2, -0.1, 0.3]), one, zero, c.types)
+    assert np.abs(r_e - r_a).max() <= 1e-14 * np.abs(r_a).max()
+    # uniform dilatation u = s x: the extra term is -(div u) M u_i = -3 s M u_i
+    s = 0.8
+    u = _lin(c, s * np.eye(3))
+    r_e, _ = oracle.residual(c.coords, c.conn, u, one, zero, c.types, oracle.EMAC)
+    r_a, _ = oracle.residual(c.coords, c.conn, u, one, zero, c.types)
+    rp, ci, M, _ = oracle.assemble(c.coords, c.conn, MOM, 1.0, np.zeros((3, N)), one, zero, types=c.types)
+    for i in range(3):
+        ref = -3.0 * s * oracle.spmv(rp, ci, M[0], u[i])
+        assert np.abs(r_e[i] - r_a[i] - ref).max() <= 1e-13 * np.abs(ref).max()
+    # total momentum is conserved by the divergence (EMAC) form when u . n = 0
+    # on the boundary, not by the advective form
+    rng = np.random.default_rng(7)
+    u = rng.normal(size=(3, N))
+    X = c.coords
+    for j in range(3):
+        on = (np.abs(X[:, j]) < 1e-12) | (np.abs(X[:, j] - 1.0) < 1e-12)
+        u[j, on] = 0.0
+    r_e, _ = oracle.residual(c.coords, c.conn, u, one, zero, c.types, oracle.EMAC)
+    r_a, _ = oracle.residual(c.coords, c.conn, u, one, zero, c.types)
+    scale = np.abs(r_e).sum(axis=1)
+    assert np.all(np.abs(r_e.sum(axis=1)) <= 1e-13 * scale), r_e.sum(axis=1) / scale
+    assert np.any(np.abs(r_a.sum(axis=1)) > 1e-3 * np.abs(r_a).sum(axis=1))
