@@ -222,10 +222,18 @@ fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, dou
  * arrays are device, mesh numbering, [k][n_nodes] rows, FP64.  Each call
  * synchronises the stream and fails with FE_EBADELEM on det J <= 0. */
 
+/* Operator variants of Eq. (1) for the residual (bits of `form`; 0 = the
+ * advective convection and Laplacian viscous forms of fe_assemble). */
+#define FE_FORM_FULL_STRESS 1u   /* viscous term div(2 mu eps(u)): adds mu (d u_j/d x_i)(d N_a/d x_j) */
+#define FE_FORM_EMAC 2u          /* convective term 2 eps(u) u + (div u) u - grad(|u|^2)/2 at the Gauss
+                                  * points, i.e. (u . grad) u + (div u) u: adds rho N_a (div u) u_i */
+
 /* out[4][n]: out_i = -(C(u) + K_mu) u_i for i = 0, 1, 2, i.e. per node a
- *   -sum_e int rho N_a (u . grad u_i) + mu grad N_a . grad u_i,
- * and out_3 = the rho-weighted lumped mass int rho N_a (row sums of M_rho). */
-fe_status fe_residual(fe_mesh mesh, const double *u, const double *rho, const double *mu, double *out);
+ *   -sum_e int rho N_a (u . grad u_i) + mu grad N_a . grad u_i
+ * (with the terms `form` adds), and out_3 = the rho-weighted lumped mass
+ * int rho N_a (row sums of M_rho).  FE_EINVAL for unknown form bits. */
+fe_status fe_residual(fe_mesh mesh, const double *u, const double *rho, const double *mu, uint32_t form,
+                      double *out);
 /* g[3][n]: g_j = int N_a d p / d x_j (the pressure gradient tested with N_a). */
 fe_status fe_gradient(fe_mesh mesh, const double *p, double *g);
 /* f[n] = (1/dt) int grad N_a . (rho u): the right-hand side of
@@ -240,7 +248,7 @@ typedef struct {
 /*
  * One fractional step:
  *   1. predictor: three-stage strong-stability-preserving Runge-Kutta
- *      (Shu-Osher) on M_L du/dt = fe_residual(u), M_L the lumped rho-mass;
+ *      (Shu-Osher) on M_L du/dt = fe_residual(u, form), M_L the lumped rho-mass;
  *      u at the mesh's Dirichlet nodes is held;
  *   2. pressure: L p = fe_divergence(u*) with zero at the Dirichlet rows,
  *      Jacobi-PCG to rtol starting from p (in: initial guess);
@@ -251,7 +259,8 @@ typedef struct {
  * Returns FE_ENOCONV / FE_EBREAKDOWN from the solve (u then holds u*).
  */
 fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const double *mu, const double *L,
-                             double *u, double *p, double rtol, int32_t max_iter, fe_step_info *info);
+                             uint32_t form, double *u, double *p, double rtol, int32_t max_iter,
+                             fe_step_info *info);
 
 /* ---- serving: continuous batching of assemble + solve requests -------------
  * The time-step workload of the paper (Algorithm 1: momentum assembly, the

@@ -31,7 +31,7 @@ MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
-           "residual", "gradient", "divergence", "fractional_step",
+           "residual", "gradient", "divergence", "fractional_step", "FULL_STRESS", "EMAC",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
@@ -212,8 +212,12 @@ class Mesh:
             pass
 
 
-def residual(mesh: Mesh, u, rho, mu, out=None):
-    """fe_residual: out[4, N] = -(C(u) + K_mu) u (3 rows) and the lumped rho-mass."""
+FULL_STRESS, EMAC = capi.FE_FORM_FULL_STRESS, capi.FE_FORM_EMAC
+
+
+def residual(mesh: Mesh, u, rho, mu, out=None, form: int = 0):
+    """fe_residual: out[4, N] = -(C(u) + K_mu) u (3 rows) and the lumped
+    rho-mass; form: FULL_STRESS and/or EMAC operator variants."""
     torch = _torch()
     N = mesh.n_nodes
     _check_dev(u, torch.float64, 3 * N, "u")
@@ -222,7 +226,7 @@ def residual(mesh: Mesh, u, rho, mu, out=None):
     if out is None:
         out = torch.empty((4, N), dtype=torch.float64, device=u.device)
     _check_dev(out, torch.float64, 4 * N, "out")
-    mesh.ctx.check(mesh.ctx.lib.fe_residual(mesh.h, _ptr(u), _ptr(rho), _ptr(mu), _ptr(out)))
+    mesh.ctx.check(mesh.ctx.lib.fe_residual(mesh.h, _ptr(u), _ptr(rho), _ptr(mu), int(form), _ptr(out)))
     return out
 
 
@@ -251,7 +255,8 @@ def divergence(mesh: Mesh, dt: float, u, rho, out=None):
     return out
 
 
-def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8, max_iter: int = 20000):
+def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8, max_iter: int = 20000,
+                    form: int = 0):
     """fe_fractional_step: advances u [3, N] and p [N] in place (device,
     mesh numbering); L is the Poisson matrix after apply_dirichlet.
     Returns {"cg_iterations", "cg_true_rel_residual"}."""
@@ -263,8 +268,8 @@ def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8,
     _check_dev(mu, torch.float64, N, "mu")
     _check_dev(L, torch.float64, mesh.nnz, "L")
     info = capi.StepInfo()
-    mesh.ctx.check(mesh.ctx.lib.fe_fractional_step(mesh.h, float(dt), _ptr(rho), _ptr(mu), _ptr(L), _ptr(u),
-                                                   _ptr(p), float(rtol), int(max_iter), C.byref(info)))
+    mesh.ctx.check(mesh.ctx.lib.fe_fractional_step(mesh.h, float(dt), _ptr(rho), _ptr(mu), _ptr(L), int(form),
+                                                   _ptr(u), _ptr(p), float(rtol), int(max_iter), C.byref(info)))
     return {"cg_iterations": info.cg_iterations, "cg_true_rel_residual": info.cg_true_rel_residual}
 
 

@@ -14,6 +14,7 @@ FE_TET04, FE_PYR05, FE_PEN06, FE_HEX08 = 4, 5, 6, 8
 FE_FP64, FE_MIXED = 0, 1
 FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON = 0, 1, 2
 FE_UPLOAD_RENUMBER = 1
+FE_FORM_FULL_STRESS, FE_FORM_EMAC = 1, 2
 
 P = C.c_void_p
 i32, i64, dbl, sz = C.c_int32, C.c_int64, C.c_double, C.c_size_t
@@ -80,10 +81,10 @@ SIGNATURES = {
     "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
     "fe_axpy": (C.c_int, [P, i64, dbl, P, P]),
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
-    "fe_residual": (C.c_int, [P, P, P, P, P]),
+    "fe_residual": (C.c_int, [P, P, P, P, C.c_uint32, P]),
     "fe_gradient": (C.c_int, [P, P, P]),
     "fe_divergence": (C.c_int, [P, dbl, P, P, P]),
-    "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, P, P, dbl, i32, C.POINTER(StepInfo)]),
+    "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, C.c_uint32, P, P, dbl, i32, C.POINTER(StepInfo)]),
     "fe_serve_create": (C.c_int, [P, sz, i32, i32, C.POINTER(P)]),
     "fe_serve_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(i64)]),
     "fe_serve_poll": (C.c_int, [P, i64, C.POINTER(i32), C.POINTER(JobResult)]),

@@ -162,6 +162,7 @@ struct KArgs {
     const uint16_t *elem_lnode;
     int64_t N, E;
     int off_stride;           // bytes of elem_off per element
+    int form;                 // residual pass: FE_FORM_* operator variants
     const double *u, *rho, *mu, *Y, *p;
     double dt, Dk;
     double *values, *rhs;
@@ -292,14 +293,18 @@ __device__ __forceinline__ double jacobian_inverse(int g, const Geo<EL> &GE, dou
 // One Gauss point of an element-vector pass for rows [A0, A0 + RA), FP64,
 // from the physical gradients dN and dV = w det J:
 //   OP_RES: B_i[a] -= dV (rho N_a (u . grad u_i) + mu grad N_a . grad u_i), i < 3,
-//           B_3[a] += dV rho N_a (lumped mass);
+//           B_3[a] += dV rho N_a (lumped mass); form FE_FORM_FULL_STRESS adds
+//           mu (d u_j / d x_i)(d N_a / d x_j) (the viscous term 2 mu eps(u)),
+//           FE_FORM_EMAC adds rho N_a (div u) u_i (Eq. (1)'s convective form
+//           at the Gauss point);
 //   OP_GRD: B_j[a] += dV N_a (grad p)_j;
 //   OP_DIV: B_0[a] += dV / dt grad N_a . (rho u).
 // Fields in LDS: x, y, z, then u_x, u_y, u_z, rho, mu (OP_GRD: p in slot 3).
 template <class EL, int OP, int RA, int A0>
 __device__ __forceinline__ void element_vector_point(int g, const double *nd, int T, const int (&ln)[EL::NEN],
                                                      const double (&dN)[EL::NEN][3], double dV,
-                                                     double (&B)[OpTraits<OP>::NRHS][RA], double inv_dt)
+                                                     double (&B)[OpTraits<OP>::NRHS][RA], double inv_dt,
+                                                     int form)
 {
     constexpr int NEN = EL::NEN;
     if constexpr (OP == OP_GRD) {
@@ -334,14 +339,18 @@ __device__ __forceinline__ void element_vector_point(int g, const double *nd, in
             }
         }
         if constexpr (OP == OP_RES) {
+            const bool full = (form & FE_FORM_FULL_STRESS) != 0, emac = (form & FE_FORM_EMAC) != 0;
+            const double divu = gu[0][0] + gu[1][1] + gu[2][2];
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
                 const int a = A0 + r;
                 const double wr = dV * rg * RefN<EL>(g, a), wm = dV * mg;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const double adv = ug[0] * gu[i][0] + ug[1] * gu[i][1] + ug[2] * gu[i][2];
-                    const double vis = dN[a][0] * gu[i][0] + dN[a][1] * gu[i][1] + dN[a][2] * gu[i][2];
+                    double adv = ug[0] * gu[i][0] + ug[1] * gu[i][1] + ug[2] * gu[i][2];
+                    double vis = dN[a][0] * gu[i][0] + dN[a][1] * gu[i][1] + dN[a][2] * gu[i][2];
+                    if (full) vis += dN[a][0] * gu[0][i] + dN[a][1] * gu[1][i] + dN[a][2] * gu[2][i];
+                    if (emac) adv += divu * ug[i];
                     B[i][r] -= wr * adv + wm * vis;
                 }
                 B[3][r] += wr;
@@ -361,7 +370,7 @@ template <class EL, int OP, class Q, int RA, int A0>
 __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, int T,
                                             const int (&ln)[EL::NEN],
                                             Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
-                                            double inv_dt, double Dk)
+                                            double inv_dt, double Dk, int form)
 {
     constexpr int NEN = EL::NEN;
     double Ji[3][3];
@@ -382,7 +391,7 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
             dN[a][i] = Q(s);
         }
     if constexpr (OP >= OP_RES) {
-        element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt);
+        element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt, form);
     } else {
         double rg = 0.0, fg = 0.0, ug0 = 0.0, ug1 = 0.0, ug2 = 0.0;
 #pragma unroll
@@ -443,7 +452,7 @@ template <class EL> struct Rows { int v[EL::NEN]; };
 template <class EL, int OP, class Q, int RA, int A0>
 __device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, int T, Rows<EL> rows,
                                            Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
-                                           double inv_dt, double Dk)
+                                           double inv_dt, double Dk, int form)
 {
     constexpr int NEN = EL::NEN, NG = EL::NG;
     int ln[NEN];
@@ -454,11 +463,12 @@ __device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, 
         for (int g = 0; g < NG; ++g) {
 #pragma unroll
             for (int a = 0; a < NEN; ++a) asm volatile("" : "+v"(ln[a]));
-            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk);
+            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk, form);
         }
     } else {
 #pragma unroll
-        for (int g = 0; g < NG; ++g) gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk);
+        for (int g = 0; g < NG; ++g)
+            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk, form);
     }
 }
 
@@ -568,8 +578,8 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
         Rows<EL> rows;
 #pragma unroll
         for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
-        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk);
-        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk);
+        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, k.form);
+        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, k.form);
     }
     // this lane's rows of the element, selected without dynamic indexing
     int lr[RA];
@@ -749,6 +759,7 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     k.blk_mindet = (double *)(a.status + 1);
     k.blk_bad = (long long *)(k.blk_mindet + m.nblk);
     k.off_stride = m.off_stride;
+    k.form = a.form;
     // one launch per (colour, element type), in the planned order
     for (const AsmLaunch &L : m.launches) {
         if (L.count == 0) continue;

@@ -452,7 +452,7 @@ fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
 // Queues one element-vector pass (kOpResidual, kOpGradient, kOpDivergence)
 // writing its rows of N to out, and checks its status word.
 fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, const double *rho, const double *mu,
-                          const double *p, double *out)
+                          const double *p, double *out, int form = 0)
 {
     fe_ctx_s *c = m->ctx;
     AsmArgs a{};
@@ -463,6 +463,7 @@ fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, cons
     a.rho = rho;
     a.mu = mu;
     a.p = p;
+    a.form = form;
     a.rhs = out;
     a.status = m->status;
     {
@@ -860,12 +861,15 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
 
 // ---- explicit step ----------------------------------------------------------
 
-fe_status fe_residual(fe_mesh m, const double *u, const double *rho, const double *mu, double *out)
+static bool valid_form(uint32_t form) { return (form & ~(uint32_t)(FE_FORM_FULL_STRESS | FE_FORM_EMAC)) == 0; }
+
+fe_status fe_residual(fe_mesh m, const double *u, const double *rho, const double *mu, uint32_t form, double *out)
 {
     if (!m) return FE_EINVAL;
     if (!u || !rho || !mu || !out) return fail(m->ctx, FE_EINVAL, "null u/rho/mu/out");
+    if (!valid_form(form)) return fail(m->ctx, FE_EINVAL, "unknown form bits 0x%x", form);
     HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
-    return element_vectors(m, kOpResidual, 1.0, u, rho, mu, nullptr, out);
+    return element_vectors(m, kOpResidual, 1.0, u, rho, mu, nullptr, out, (int)form);
 }
 
 fe_status fe_gradient(fe_mesh m, const double *p, double *g)
@@ -885,12 +889,13 @@ fe_status fe_divergence(fe_mesh m, double dt, const double *u, const double *rho
     return element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f);
 }
 
-fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const double *mu, const double *L, double *u,
-                             double *p, double rtol, int32_t max_iter, fe_step_info *info)
+fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const double *mu, const double *L,
+                             uint32_t form, double *u, double *p, double rtol, int32_t max_iter, fe_step_info *info)
 {
     if (!m) return FE_EINVAL;
     fe_ctx_s *c = m->ctx;
     if (!rho || !mu || !L || !u || !p) return fail(c, FE_EINVAL, "null rho/mu/L/u/p");
+    if (!valid_form(form)) return fail(c, FE_EINVAL, "unknown form bits 0x%x", form);
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FE_EINVAL, "dt must be > 0");
     if (!(rtol > 0.0) || max_iter < 1) return fail(c, FE_EINVAL, "need rtol > 0 and max_iter >= 1");
     HIPCALL(c, hipSetDevice(c->device));
@@ -904,7 +909,7 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     static const double kStage[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
     HIPCALL(c, hipMemcpyAsync(u0, u, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     for (const auto &st : kStage) {
-        if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res)) != FE_OK) return s;
+        if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res, (int)form)) != FE_OK) return s;
         HIPCALL(c, launch_rk_stage(d, st[0], st[1], dt, u0, res, mass, u, c->stream));
     }
     // 2. pressure: L p = (1/dt) int grad N . (rho u*), zero at Dirichlet rows

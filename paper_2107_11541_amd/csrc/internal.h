@@ -92,6 +92,7 @@ struct AsmArgs {
     double dt, Dk;
     const double *u, *rho, *mu, *Y;   // Y: the scalar of this pass
     const double *p;         // kOpGradient: the pressure
+    int form;                // kOpResidual: FE_FORM_* operator variants
     double *values;          // operator's value array [nnz]
     double *rhs;             // first rhs row [N] (momentum: 3 rows of N; element-vector passes: their rows)
     AsmStatus *status;

@@ -168,3 +168,43 @@ def test_full_size_residual_and_gradient_sampled_rows(fe_ctx):
         assert np.abs(g[i][nodes] - gr[i][li]).max() <= 1e-12 * np.abs(gr[i]).max()
     assert np.abs(out[3][nodes] - m[li]).max() <= 1e-13 * m.max()
     mesh.close()
+
+
+@pytest.mark.parametrize("form", [1, 2, 3])
+@pytest.mark.parametrize("kind,n", [("hex", 5), ("tet", 4), ("hybrid", 6)])
+def test_residual_operator_variants_match_oracle(fe_ctx, kind, n, form):
+    """Full-stress viscous term (1), EMAC convection (2), both (3)."""
+    fe = _fe()
+    c = case_of(kind, n, seed=20 + n)
+    mesh = make_mesh(fe_ctx, c)
+    u, rho, mu = to_mesh(mesh, c.u), to_mesh(mesh, c.rho), to_mesh(mesh, c.mu)
+    out = to_user(mesh, fe.residual(mesh, u, rho, mu, form=form))
+    r, m = oracle.residual(c.coords, c.conn, c.u, c.rho, c.mu, c.types, form)
+    r0, _ = oracle.residual(c.coords, c.conn, c.u, c.rho, c.mu, c.types)
+    assert rel(r, r0) > 1e-6                 # the variant changes the residual
+    for i in range(3):
+        assert rel(out[i], r[i]) <= 1e-12, (i, rel(out[i], r[i]))
+    assert rel(out[3], m) <= 1e-13
+    with pytest.raises(fe.FeError) as ei:
+        fe.residual(mesh, u, rho, mu, form=4)
+    assert ei.value.status == 1
+    mesh.close()
+
+
+def test_fractional_step_full_stress_emac_matches_oracle(fe_ctx):
+    fe = _fe()
+    import torch
+    c = case_of("hex", 6, seed=9)
+    dt = 0.4 / 6
+    mesh = make_mesh(fe_ctx, c)
+    L = _poisson(fe, mesh, c, dt)
+    u = to_mesh(mesh, c.u)
+    p = torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda")
+    form = fe.FULL_STRESS | fe.EMAC
+    fe.fractional_step(mesh, dt, to_mesh(mesh, c.rho), to_mesh(mesh, c.mu), L, u, p, rtol=1e-12, max_iter=5000,
+                       form=form)
+    un, pn, _ = oracle.fractional_step(c.coords, c.conn, c.dirichlet, dt, c.u, c.rho, c.mu,
+                                       _oracle_poisson(c, dt), rtol=1e-12, form=form)
+    assert rel(to_user(mesh, p), pn) <= 1e-8
+    assert rel(to_user(mesh, u), un) <= 1e-9
+    mesh.close()
