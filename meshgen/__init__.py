@@ -112,6 +112,8 @@ class Case:
     D: np.ndarray = field(default_factory=lambda: np.zeros(0))
     name: str = ""
     types: Optional[np.ndarray] = None   # HYBRID: [E] uint8 node counts
+    wall_nen: Optional[np.ndarray] = None    # wall faces: [F] uint8, 3 or 4 nodes
+    wall_conn: Optional[np.ndarray] = None   # [F, 4] int32 node ids, -1 padded
 
     @property
     def n_nodes(self) -> int:
@@ -236,17 +238,44 @@ def hybrid_mesh(n: int, coords: np.ndarray):
     return np.ascontiguousarray(coords), np.ascontiguousarray(conn), np.ascontiguousarray(types)
 
 
+def wall_faces_z0(n: int, elem_type: int):
+    """Element faces on the z = 0 plane (the wall of the wall-model tests),
+    node ids of the unshuffled cube: a quadrilateral (0,1,2,3) where the
+    cell's bottom is a HEX08 face or a PYR05 base, else the two triangles
+    (0,1,2) and (0,2,3) along the cell's 0-2 diagonal (prism bottoms, Kuhn and
+    transition tetrahedra).  Returns (nen [F] uint8, conn [F, 4] int32)."""
+    hconn = hex_conn(n)[: n * n]                          # cells with k = 0
+    ci = np.arange(n * n) % n
+    if elem_type in (HEX08, PYR05):
+        quad = np.ones(n * n, bool)
+    elif elem_type == HYBRID:
+        quad = (ci >= n // 4) & (ci < n // 2)
+    else:
+        quad = np.zeros(n * n, bool)
+    nen, conn = [], []
+    for c in range(n * n):
+        h = hconn[c]
+        if quad[c]:
+            nen.append(4)
+            conn.append([h[0], h[1], h[2], h[3]])
+        else:
+            nen += [3, 3]
+            conn += [[h[0], h[1], h[2], -1], [h[0], h[2], h[3], -1]]
+    return np.array(nen, np.uint8), np.array(conn, np.int32)
+
+
 def boundary_nodes(n: int) -> np.ndarray:
     kk, jj, ii = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
     m = (ii == 0) | (ii == n) | (jj == 0) | (jj == n) | (kk == 0) | (kk == n)
     return np.flatnonzero(m.ravel()).astype(np.int32)
 
 
-def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems, types=None):
+def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems, types=None, faces=None):
     """Random renumbering: new id of old node i is pn[i]; elements shuffled.
 
     node_fields: list of arrays whose LAST axis is the node axis.  Padding
-    entries (-1) of the connectivity stay -1; `types` follows the elements.
+    entries (-1) of the connectivity stay -1; `types` follows the elements;
+    `faces` (a face connectivity, -1 padded) is renumbered, not reordered.
     """
     N = coords.shape[0]
     E = conn.shape[0]
@@ -259,9 +288,11 @@ def permute(coords, conn, dirichlet, node_fields, rng_nodes, rng_elems, types=No
     conn2 = np.ascontiguousarray(np.where(c >= 0, pn[np.maximum(c, 0)], -1).astype(np.int32))
     dir2 = np.sort(pn[dirichlet]).astype(np.int32)
     f2 = [np.ascontiguousarray(f[..., inv]) for f in node_fields]
-    if types is None:
+    faces2 = None if faces is None else np.ascontiguousarray(
+        np.where(faces >= 0, pn[np.maximum(faces, 0)], -1).astype(np.int32))
+    if types is None and faces is None:
         return coords2, conn2, dir2, f2
-    return coords2, conn2, dir2, f2, np.ascontiguousarray(types[pe])
+    return coords2, conn2, dir2, f2, None if types is None else np.ascontiguousarray(types[pe]), faces2
 
 
 def taylor_green(coords, rng=None, noise=0.01) -> np.ndarray:
@@ -294,7 +325,7 @@ def time_step(n: int, u0: float = 1.0) -> float:
 
 def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int = 0,
               sub=None, shuffle: bool = False, temperature: bool = False,
-              n_scalars: int = 0, noise: float = 0.01, name: str = "") -> Case:
+              n_scalars: int = 0, noise: float = 0.01, name: str = "", walls: bool = False) -> Case:
     """Build one synthetic case (see the module docstring for the recipe)."""
     rs = streams(case_id, sub)
     coords = cube_nodes(n, jitter, rs["jitter"])
@@ -315,6 +346,7 @@ def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int
     else:
         raise ValueError(f"unknown element type {elem_type}")
     dirichlet = boundary_nodes(n)
+    wnen, wconn = wall_faces_z0(n, elem_type) if walls else (None, None)
     N = coords.shape[0]
     u = taylor_green(coords, rs["unoise"], noise)
     if temperature:
@@ -327,12 +359,14 @@ def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int
     Y = rs["Y"].uniform(0.0, 1.0, size=(n_scalars, N)) if n_scalars else np.zeros((0, N))
     D = 10.0 ** rs["D"].uniform(-6.0, -4.0, size=n_scalars) if n_scalars else np.zeros(0)
     if shuffle:
-        out = permute(coords, conn, dirichlet, [u, rho, mu, Y], rs["nperm"], rs["eperm"], types)
+        out = permute(coords, conn, dirichlet, [u, rho, mu, Y], rs["nperm"], rs["eperm"], types, wconn)
         coords, conn, dirichlet, (u, rho, mu, Y) = out[:4]
         if types is not None:
             types = out[4]
+        if wconn is not None:
+            wconn = out[5]
     return Case(elem_type, n, coords, conn.astype(np.int32), dirichlet, u, rho, mu,
-                time_step(n), Y, D, name, types)
+                time_step(n), Y, D, name, types, wnen, wconn)
 
 
 # --- the five workloads -----------------------------------------------------

@@ -54,6 +54,10 @@ def lib():
         L.or_element_vectors.restype = i32
         L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, C.POINTER(i64),
                                          C.POINTER(dbl)]
+        L.or_wall_utau.restype = dbl
+        L.or_wall_utau.argtypes = [dbl, dbl, dbl]
+        L.or_wall_traction.restype = i32
+        L.or_wall_traction.argtypes = [i64, P, i64, P, P, P, P, P, dbl, P]
         L.or_dirichlet.restype = i32
         L.or_dirichlet.argtypes = [i64, P, P, P, P, i64, P, P]
         L.or_spmv.restype = None
@@ -197,14 +201,34 @@ def gradient(coords, conn, p, types=None):
     return _element_vectors(coords, conn, 1, p=p, types=types)
 
 
+def wall_utau(U, nu, delta):
+    """Friction velocity of the equilibrium wall law (Reichardt) at distance delta."""
+    return lib().or_wall_utau(float(U), float(nu), float(delta))
+
+
+def wall_traction(coords, face_nen, face_conn, u, rho, mu, delta):
+    """Wall-model traction out[3, N] = sum over wall faces of int N_a t dS,
+    t = -rho u_tau^2 u_t / |u_t| (or_wall_traction)."""
+    coords, u, rho, mu = _f64(coords), _f64(u), _f64(rho), _f64(mu)
+    nen, fc = _u8(face_nen), _i32(face_conn)
+    N = coords.shape[0]
+    out = np.zeros((3, N))
+    st = lib().or_wall_traction(N, _p(coords), nen.shape[0], _p(nen), _p(fc), _p(u), _p(rho), _p(mu),
+                                float(delta), _p(out))
+    if st != OK:
+        raise ValueError(f"oracle wall traction failed: {st}")
+    return out
+
+
 # Shu-Osher strong-stability-preserving third-order Runge-Kutta: stage s
 # maps (u^n, u_s) to alpha_s u^n + beta_s (u_s + dt L(u_s)).
 SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
-def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=SSP_RK3, form=0):
+def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=SSP_RK3, form=0, wall=None):
     """Explicit RK stages of M_L du/dt = R(u) (velocity held at Dirichlet
-    nodes).  Returns (u*, lumped mass m)."""
+    nodes); wall = (face_nen, face_conn, delta) adds the wall-model traction
+    to R.  Returns (u*, lumped mass m)."""
     free = np.ones(u.shape[1], bool)
     free[np.asarray(dirichlet_nodes)] = False
     u0 = np.array(u, dtype=np.float64)
@@ -212,13 +236,15 @@ def rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types=None, rk=S
     m = None
     for a, b in rk:
         r, m = residual(coords, conn, us, rho, mu, types, form)
+        if wall is not None:
+            r = r + wall_traction(coords, wall[0], wall[1], us, rho, mu, wall[2])
         nxt = a * u0 + b * (us + dt * r / m)
         us = np.where(free, nxt, u0)
     return us, m
 
 
 def fractional_step(coords, conn, dirichlet_nodes, dt, u, rho, mu, L, rtol=1e-12, max_iter=20000, p0=None,
-                    types=None, rk=SSP_RK3, form=0):
+                    types=None, rk=SSP_RK3, form=0, wall=None):
     """One step of the fractional-step scheme around the assembly (Algorithm 1):
       1. momentum predictor, explicit RK (SSP-RK3) on M_L du/dt = R(u), with
          M_L the rho-weighted lumped mass and R the matrix-free residual; the
@@ -232,7 +258,7 @@ def fractional_step(coords, conn, dirichlet_nodes, dt, u, rho, mu, L, rtol=1e-12
     dn = np.asarray(dirichlet_nodes)
     free = np.ones(u.shape[1], bool)
     free[dn] = False
-    us, m = rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types, rk, form)
+    us, m = rk_predictor(coords, conn, dirichlet_nodes, dt, u, rho, mu, types, rk, form, wall)
     _, _, _, f = assemble(coords, conn, OP_POISSON, dt, us, rho, None, pattern_=(rp, ci), types=types)
     f = f[0]
     f[dn] = 0.0

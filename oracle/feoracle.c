@@ -658,6 +658,112 @@ int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const 
 }
 
 /* ------------------------------------------------------------------ */
+/* Boundary assembly: equilibrium wall model (Algorithm 1)             */
+/* ------------------------------------------------------------------ */
+
+#define WALL_KAPPA 0.41
+#define WALL_NEWTON 16
+
+/* Reichardt's law of the wall u+ (y+) and its derivative. */
+static double reichardt(double yp, double *dudy)
+{
+    double e1 = exp(-yp / 11.0), e3 = exp(-yp / 3.0);
+    *dudy = 1.0 / (1.0 + WALL_KAPPA * yp) + 7.8 * (e1 / 11.0 - e3 / 11.0 + yp * e3 / 33.0);
+    return log(1.0 + WALL_KAPPA * yp) / WALL_KAPPA + 7.8 * (1.0 - e1 - yp / 11.0 * e3);
+}
+
+/* Friction velocity u_tau from U = u_tau u+(delta u_tau / nu): Newton on
+ * g(u_tau) = u_tau u+(delta u_tau / nu) - U from the laminar guess
+ * sqrt(nu U / delta), a fixed number of steps. */
+double or_wall_utau(double U, double nu, double delta)
+{
+    if (!(U > 0.0)) return 0.0;
+    double ut = sqrt(nu * U / delta);
+    for (int k = 0; k < WALL_NEWTON; ++k) {
+        double yp = delta * ut / nu, d;
+        double up = reichardt(yp, &d);
+        double g = ut * up - U;
+        double dg = up + yp * d;
+        ut -= g / dg;
+        if (ut <= 0.0) ut = 1e-300;
+    }
+    return ut;
+}
+
+/*
+ * Wall-model traction on wall faces (the boundary assembly of Algorithm 1;
+ * the paper names it but gives no law, so the equilibrium law above is used):
+ * at each face Gauss point the velocity u_h is interpolated from the face's
+ * nodes, its tangential part u_t = u_h - (u_h . n) n gives U = |u_t|, rho
+ * and mu are interpolated, u_tau solves the law at distance delta, and the
+ * traction t = -rho u_tau^2 u_t / U is integrated:
+ *   out_i[a] = sum_faces sum_g w_g |dx/dxi x dx/deta| N_a t_i.
+ * Faces: face_nen[f] = 3 (triangle, reference (0,0),(1,0),(0,1), the
+ * 3-point rule (1/6,1/6),(2/3,1/6),(1/6,2/3), weights 1/6) or 4
+ * (quadrilateral [-1,1]^2, nodes counter-clockwise, 2x2 Gauss); face_conn
+ * [F][4].  out [3][N] is overwritten.
+ */
+int or_wall_traction(int64_t n_nodes, const double *coords, int64_t n_faces, const uint8_t *face_nen,
+                     const int32_t *face_conn, const double *u, const double *rho, const double *mu,
+                     double delta, double *out)
+{
+    if (!(delta > 0.0)) return OR_EINVAL;
+    memset(out, 0, sizeof(double) * (size_t)(3 * n_nodes));
+    const double g = 1.0 / sqrt(3.0);
+    for (int64_t f = 0; f < n_faces; ++f) {
+        int nn = face_nen[f];
+        if (nn != 3 && nn != 4) return OR_EINVAL;
+        const int32_t *c = face_conn + 4 * f;
+        for (int a = 0; a < nn; ++a)
+            if (c[a] < 0 || c[a] >= n_nodes) return OR_EINVAL;
+        int ng = nn == 3 ? 3 : 4;
+        for (int q = 0; q < ng; ++q) {
+            double N[4], dNs[4], dNt[4], w;
+            if (nn == 3) {
+                static const double tp[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+                double s = tp[q][0], t = tp[q][1];
+                N[0] = 1.0 - s - t; N[1] = s; N[2] = t;
+                dNs[0] = -1.0; dNs[1] = 1.0; dNs[2] = 0.0;
+                dNt[0] = -1.0; dNt[1] = 0.0; dNt[2] = 1.0;
+                w = 1.0 / 6.0;
+            } else {
+                static const double cs[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+                double s = (q & 1) ? g : -g, t = (q & 2) ? g : -g;
+                for (int a = 0; a < 4; ++a) {
+                    N[a] = 0.25 * (1.0 + cs[a][0] * s) * (1.0 + cs[a][1] * t);
+                    dNs[a] = 0.25 * cs[a][0] * (1.0 + cs[a][1] * t);
+                    dNt[a] = 0.25 * cs[a][1] * (1.0 + cs[a][0] * s);
+                }
+                w = 1.0;
+            }
+            double xs[3] = {0, 0, 0}, xt[3] = {0, 0, 0}, ug[3] = {0, 0, 0}, rg = 0.0, mg = 0.0;
+            for (int a = 0; a < nn; ++a) {
+                for (int i = 0; i < 3; ++i) {
+                    xs[i] += dNs[a] * coords[(int64_t)c[a] * 3 + i];
+                    xt[i] += dNt[a] * coords[(int64_t)c[a] * 3 + i];
+                    ug[i] += N[a] * u[(int64_t)i * n_nodes + c[a]];
+                }
+                rg += N[a] * rho[c[a]];
+                mg += N[a] * mu[c[a]];
+            }
+            double nv[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
+                            xs[0] * xt[1] - xs[1] * xt[0]};
+            double area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            if (!(area > 0.0)) return OR_EBADELEM;
+            double un = (ug[0] * nv[0] + ug[1] * nv[1] + ug[2] * nv[2]) / (area * area);
+            double ut[3] = {ug[0] - un * nv[0], ug[1] - un * nv[1], ug[2] - un * nv[2]};
+            double U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+            if (!(U > 0.0)) continue;
+            double tau = or_wall_utau(U, mg / rg, delta);
+            double fac = -w * area * rg * tau * tau / U;
+            for (int a = 0; a < nn; ++a)
+                for (int i = 0; i < 3; ++i) out[(int64_t)i * n_nodes + c[a]] += fac * N[a] * ut[i];
+        }
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Dirichlet elimination (symmetric)                                   */
 /* ------------------------------------------------------------------ */
 
