@@ -240,6 +240,29 @@ fe_status fe_gradient(fe_mesh mesh, const double *p, double *g);
  * fe_assemble(POISSON) without its matrix. */
 fe_status fe_divergence(fe_mesh mesh, double dt, const double *u, const double *rho, double *f);
 
+/*
+ * Boundary assembly of the wall model (Algorithm 1; the paper names the wall
+ * model without its law).  An equilibrium law of the wall, Reichardt's with
+ * kappa = 0.41, at exchange distance delta: at each Gauss point of a wall
+ * face the tangential part u_t of the interpolated velocity gives u_tau from
+ * |u_t| = u_tau u+(delta u_tau / nu), nu = mu / rho (16 Newton steps from
+ * the laminar guess), and the traction t = -rho u_tau^2 u_t / |u_t| is
+ * integrated against the face's shape functions.
+ *
+ * fe_wall_faces registers (or, with n_faces = 0, clears) the mesh's wall
+ * faces: face_nen host [n_faces] 3 (triangle: 3-point rule) or 4
+ * (quadrilateral, nodes in cyclic order: 2x2 Gauss); face_conn host
+ * [n_faces][4] user node ids (a triangle's fourth slot is ignored); delta
+ * > 0.  Faces must have non-zero area.  Errors: FE_EINVAL.
+ * fe_wall_traction: out[3][n] (device, mesh numbering) = the traction's
+ * nodal vector, zero away from the wall; deterministic (fixed summation
+ * order).  fe_fractional_step adds it to every Runge-Kutta stage's residual
+ * when wall faces are registered.
+ */
+fe_status fe_wall_faces(fe_mesh mesh, int64_t n_faces, const uint8_t *face_nen, const int32_t *face_conn,
+                        double delta);
+fe_status fe_wall_traction(fe_mesh mesh, const double *u, const double *rho, const double *mu, double *out);
+
 typedef struct {
     int32_t cg_iterations;        /* PCG iterations of the pressure solve */
     double cg_true_rel_residual;  /* ||f - L p|| / ||f|| in FP64 */
@@ -248,7 +271,8 @@ typedef struct {
 /*
  * One fractional step:
  *   1. predictor: three-stage strong-stability-preserving Runge-Kutta
- *      (Shu-Osher) on M_L du/dt = fe_residual(u, form), M_L the lumped rho-mass;
+ *      (Shu-Osher) on M_L du/dt = fe_residual(u, form) (+ fe_wall_traction(u)
+ *      when wall faces are registered), M_L the lumped rho-mass;
  *      u at the mesh's Dirichlet nodes is held;
  *   2. pressure: L p = fe_divergence(u*) with zero at the Dirichlet rows,
  *      Jacobi-PCG to rtol starting from p (in: initial guess);

@@ -377,8 +377,9 @@ def cfg0() -> Case:
 
 
 def cfg1(n: int = 128) -> Case:
-    """128^3 HEX08, jitter 15 %, node and element ids shuffled."""
-    return make_case(n, HEX08, 0.15, case_id=1, shuffle=True, name=f"hex08-{n}^3-shuffled")
+    """128^3 HEX08, jitter 15 %, node and element ids shuffled; the z = 0
+    faces are the wall of the wall model."""
+    return make_case(n, HEX08, 0.15, case_id=1, shuffle=True, name=f"hex08-{n}^3-shuffled", walls=True)
 
 
 def cfg2(n: int = 128) -> Case:

@@ -31,7 +31,7 @@ MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
-           "residual", "gradient", "divergence", "fractional_step", "FULL_STRESS", "EMAC",
+           "residual", "gradient", "divergence", "fractional_step", "wall_traction", "FULL_STRESS", "EMAC",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
@@ -167,6 +167,16 @@ class Mesh:
         self.elem_perm = np.zeros(self.n_elems, dtype=np.int32)
         ctx.check(lib.fe_mesh_perm(h, self.node_perm.ctypes.data, self.elem_perm.ctypes.data))
 
+    def set_wall(self, face_nen, face_conn, delta: float):
+        """fe_wall_faces: register the wall faces (face_nen [F] 3 or 4, face_conn
+        [F, 4] user node ids) at exchange distance delta; F = 0 clears them."""
+        nen = np.ascontiguousarray(face_nen, dtype=np.uint8)
+        conn = np.ascontiguousarray(face_conn, dtype=np.int32)
+        if conn.ndim != 2 or conn.shape[1] != 4 or nen.shape != (conn.shape[0],):
+            raise ValueError("face_nen must be [F] and face_conn [F, 4]")
+        self.ctx.check(self.ctx.lib.fe_wall_faces(self.h, conn.shape[0], nen.ctypes.data, conn.ctypes.data,
+                                                  float(delta)))
+
     def info(self) -> dict:
         d = capi.MeshDesc()
         self.ctx.check(self.ctx.lib.fe_mesh_info(self.h, C.byref(d)))
@@ -239,6 +249,20 @@ def gradient(mesh: Mesh, p, out=None):
         out = torch.empty((3, N), dtype=torch.float64, device=p.device)
     _check_dev(out, torch.float64, 3 * N, "out")
     mesh.ctx.check(mesh.ctx.lib.fe_gradient(mesh.h, _ptr(p), _ptr(out)))
+    return out
+
+
+def wall_traction(mesh: Mesh, u, rho, mu, out=None):
+    """fe_wall_traction: out[3, N] = the wall model's traction (nodal vector)."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(mu, torch.float64, N, "mu")
+    if out is None:
+        out = torch.empty((3, N), dtype=torch.float64, device=u.device)
+    _check_dev(out, torch.float64, 3 * N, "out")
+    mesh.ctx.check(mesh.ctx.lib.fe_wall_traction(mesh.h, _ptr(u), _ptr(rho), _ptr(mu), _ptr(out)))
     return out
 
 

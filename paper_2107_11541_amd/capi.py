@@ -83,6 +83,8 @@ SIGNATURES = {
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
     "fe_residual": (C.c_int, [P, P, P, P, C.c_uint32, P]),
     "fe_gradient": (C.c_int, [P, P, P]),
+    "fe_wall_faces": (C.c_int, [P, i64, P, P, dbl]),
+    "fe_wall_traction": (C.c_int, [P, P, P, P, P]),
     "fe_divergence": (C.c_int, [P, dbl, P, P, P]),
     "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, C.c_uint32, P, P, dbl, i32, C.POINTER(StepInfo)]),
     "fe_serve_create": (C.c_int, [P, sz, i32, i32, C.POINTER(P)]),

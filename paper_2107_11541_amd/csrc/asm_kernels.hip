@@ -24,6 +24,7 @@
 //
 // Precision: FP64, or (mixed) FP32 Gauss-point products and elemental sums
 // with the Jacobian, det J, J^-1 and the CSR accumulation in FP64.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -726,7 +727,140 @@ void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStre
     }
 }
 
+// ---- boundary assembly: equilibrium wall model ---------------------------
+// The wall law (Reichardt, kappa = 0.41) at exchange distance delta: u_tau
+// from U = u_tau u+(delta u_tau / nu) by a fixed number of Newton steps from
+// the laminar guess sqrt(nu U / delta); traction -rho u_tau^2 u_t / |u_t|
+// with u_t the tangential part of the interpolated velocity.
+constexpr double kWallKappa = 0.41;
+constexpr int kWallNewton = 16;
+
+__device__ double wall_utau(double U, double nu, double delta)
+{
+    if (!(U > 0.0)) return 0.0;
+    double ut = sqrt(nu * U / delta);
+    for (int k = 0; k < kWallNewton; ++k) {
+        const double yp = delta * ut / nu;
+        const double e1 = exp(-yp / 11.0), e3 = exp(-yp / 3.0);
+        const double up = log(1.0 + kWallKappa * yp) / kWallKappa + 7.8 * (1.0 - e1 - yp / 11.0 * e3);
+        const double du = 1.0 / (1.0 + kWallKappa * yp) + 7.8 * (e1 / 11.0 - e3 / 11.0 + yp * e3 / 33.0);
+        ut -= (ut * up - U) / (up + yp * du);
+        if (ut <= 0.0) ut = 1e-300;
+    }
+    return ut;
+}
+
+// One thread per face: its nodal contributions sum_g w |x_s x x_t| N_a t
+// (3-point rule on triangles, 2x2 Gauss on quadrilaterals) into part.
+__global__ void __launch_bounds__(256) k_wall_faces(int64_t F, const uint8_t *fnen, const int32_t *fconn,
+                                                    const double *X, int64_t N, const double *u, const double *rho,
+                                                    const double *mu, double delta, double *part)
+{
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= F) return;
+    const int nn = fnen[f];
+    int c[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) c[a] = fconn[4 * f + a];
+    double P[4][3] = {};
+    const double g = 0.57735026918962576451;
+    for (int q = 0; q < 4; ++q) {
+        if (nn == 3 && q == 3) break;
+        double Nq[4], ds[4], dt[4], w;
+        if (nn == 3) {
+            const double s = q == 1 ? 2.0 / 3.0 : 1.0 / 6.0, t = q == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
+            Nq[0] = 1.0 - s - t; Nq[1] = s; Nq[2] = t; Nq[3] = 0.0;
+            ds[0] = -1.0; ds[1] = 1.0; ds[2] = 0.0; ds[3] = 0.0;
+            dt[0] = -1.0; dt[1] = 0.0; dt[2] = 1.0; dt[3] = 0.0;
+            w = 1.0 / 6.0;
+        } else {
+            const double s = (q & 1) ? g : -g, t = (q & 2) ? g : -g;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double cx = (a == 1 || a == 2) ? 1.0 : -1.0, cy = a >= 2 ? 1.0 : -1.0;
+                Nq[a] = 0.25 * (1.0 + cx * s) * (1.0 + cy * t);
+                ds[a] = 0.25 * cx * (1.0 + cy * t);
+                dt[a] = 0.25 * cy * (1.0 + cx * s);
+            }
+            w = 1.0;
+        }
+        double xs[3] = {}, xt[3] = {}, ug[3] = {}, rg = 0.0, mg = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            if (a >= nn) break;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double xi = X[i * N + c[a]];
+                xs[i] += ds[a] * xi;
+                xt[i] += dt[a] * xi;
+                ug[i] += Nq[a] * u[i * N + c[a]];
+            }
+            rg += Nq[a] * rho[c[a]];
+            mg += Nq[a] * mu[c[a]];
+        }
+        const double nv[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
+                              xs[0] * xt[1] - xs[1] * xt[0]};
+        const double a2 = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
+        if (!(a2 > 0.0)) continue;
+        const double area = sqrt(a2);
+        const double un = (ug[0] * nv[0] + ug[1] * nv[1] + ug[2] * nv[2]) / a2;
+        const double ut[3] = {ug[0] - un * nv[0], ug[1] - un * nv[1], ug[2] - un * nv[2]};
+        const double U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        if (!(U > 0.0)) continue;
+        const double tau = wall_utau(U, mg / rg, delta);
+        const double fac = -w * area * rg * tau * tau / U;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) P[a][i] += fac * Nq[a] * ut[i];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) part[(4 * f + a) * 3 + i] = P[a][i];
+}
+
+// One thread per wall node: its face entries summed in their fixed order.
+__global__ void __launch_bounds__(256) k_wall_gather(int64_t W, const int32_t *nodes, const int32_t *ptr,
+                                                     const int32_t *ent, const double *part, int64_t N, double *out)
+{
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= W) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int32_t k = ptr[w]; k < ptr[w + 1]; ++k) {
+        const double *p = part + (int64_t)ent[k] * 3;
+        s0 += p[0];
+        s1 += p[1];
+        s2 += p[2];
+    }
+    const int64_t i = nodes[w];
+    out[i] += s0;
+    out[N + i] += s1;
+    out[2 * N + i] += s2;
+}
+
+__global__ void __launch_bounds__(256) k_zero(int64_t n, double *x)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_wall_traction(const DevMesh &m, const DevWall &w, const double *u, const double *rho,
+                                const double *mu, double *out, bool zero_first, hipStream_t s)
+{
+    if (zero_first) {
+        const int64_t n = 3 * m.N;
+        const int64_t nb = std::min<int64_t>((n + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, n, out);
+    }
+    if (w.F == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_wall_faces, dim3((unsigned)((w.F + 255) / 256)), dim3(256), 0, s, w.F, w.nen, w.conn, m.X,
+                       m.N, u, rho, mu, w.delta, w.part);
+    hipLaunchKernelGGL(k_wall_gather, dim3((unsigned)((w.W + 255) / 256)), dim3(256), 0, s, w.W, w.nodes, w.ptr,
+                       w.ent, w.part, m.N, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
 {

@@ -297,6 +297,7 @@ void mesh_release(fe_mesh_s *m)
     m->allocs.clear();
     m->cg = CGWork();
     m->step_work = nullptr;
+    m->wall = DevWall();
 }
 
 fe_status mesh_commit(fe_mesh_s *m, MeshImage &I, hipStream_t stream)
@@ -910,6 +911,7 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     HIPCALL(c, hipMemcpyAsync(u0, u, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     for (const auto &st : kStage) {
         if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res, (int)form)) != FE_OK) return s;
+        if (m->wall.F > 0) HIPCALL(c, launch_wall_traction(d, m->wall, u, rho, mu, res, false, c->stream));
         HIPCALL(c, launch_rk_stage(d, st[0], st[1], dt, u0, res, mass, u, c->stream));
     }
     // 2. pressure: L p = (1/dt) int grad N . (rho u*), zero at Dirichlet rows
@@ -926,6 +928,84 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     if ((s = element_vectors(m, kOpGradient, dt, nullptr, nullptr, nullptr, p, g)) != FE_OK) return s;
     HIPCALL(c, launch_correct(d, dt, g, mass, u, c->stream));
     return sync(c);
+}
+
+// ---- boundary assembly: wall model ------------------------------------------
+
+fe_status fe_wall_faces(fe_mesh m, int64_t n_faces, const uint8_t *face_nen, const int32_t *face_conn,
+                        double delta)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (n_faces < 0 || (n_faces > 0 && (!face_nen || !face_conn))) return fail(c, FE_EINVAL, "bad wall faces");
+    if (n_faces > 0 && !(delta > 0.0 && std::isfinite(delta))) return fail(c, FE_EINVAL, "delta must be > 0");
+    const int64_t N = m->dm.N;
+    std::vector<int32_t> iperm(N);
+    for (int64_t i = 0; i < N; ++i) iperm[m->node_perm[i]] = (int32_t)i;
+    std::vector<int32_t> conn(4 * (size_t)n_faces);
+    for (int64_t f = 0; f < n_faces; ++f) {
+        const int nn = face_nen[f];
+        if (nn != 3 && nn != 4) return fail(c, FE_EINVAL, "wall face %lld has %d nodes", (long long)f, nn);
+        for (int a = 0; a < 4; ++a) {
+            const int32_t v = face_conn[4 * f + (a < nn ? a : 0)];
+            if (v < 0 || v >= N) return fail(c, FE_EINVAL, "wall face %lld: node out of range", (long long)f);
+            conn[4 * f + a] = iperm[v];
+        }
+    }
+    // wall nodes ascending; each node's (face, slot) entries by face index
+    std::vector<int32_t> cnt(N + 1, 0);
+    for (int64_t f = 0; f < n_faces; ++f)
+        for (int a = 0; a < face_nen[f]; ++a) cnt[conn[4 * f + a] + 1]++;
+    std::vector<int32_t> nodes, ptr{0};
+    for (int64_t i = 0; i < N; ++i)
+        if (cnt[i + 1]) {
+            nodes.push_back((int32_t)i);
+            ptr.push_back(ptr.back() + cnt[i + 1]);
+        }
+    std::vector<int32_t> first(N, -1);
+    for (size_t w = 0; w < nodes.size(); ++w) first[nodes[w]] = ptr[w];
+    std::vector<int32_t> ent(ptr.back());
+    for (int64_t f = 0; f < n_faces; ++f)
+        for (int a = 0; a < face_nen[f]; ++a) ent[first[conn[4 * f + a]]++] = (int32_t)(4 * f + a);
+    HIPCALL(c, hipSetDevice(c->device));
+    for (void *p : {(void *)m->wall.nen, (void *)m->wall.conn, (void *)m->wall.nodes, (void *)m->wall.ptr,
+                    (void *)m->wall.ent, (void *)m->wall.part})
+        mesh_free_ptr(m, p);
+    m->wall = DevWall();
+    if (n_faces == 0) return FE_OK;
+    DevWall w;
+    w.F = n_faces;
+    w.W = (int64_t)nodes.size();
+    w.delta = delta;
+    fe_status s;
+    auto up = [&](void **dst, const void *src, size_t bytes) -> fe_status {
+        fe_status r = mesh_alloc(m, dst, bytes);
+        if (r != FE_OK) return r;
+        if (src) HIPCALL(c, hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+        return FE_OK;
+    };
+    if ((s = up((void **)&w.nen, face_nen, (size_t)n_faces)) != FE_OK ||
+        (s = up((void **)&w.conn, conn.data(), conn.size() * 4)) != FE_OK ||
+        (s = up((void **)&w.nodes, nodes.data(), nodes.size() * 4)) != FE_OK ||
+        (s = up((void **)&w.ptr, ptr.data(), ptr.size() * 4)) != FE_OK ||
+        (s = up((void **)&w.ent, ent.data(), ent.size() * 4)) != FE_OK ||
+        (s = up((void **)&w.part, nullptr, 12 * (size_t)n_faces * sizeof(double))) != FE_OK)
+        return s;
+    if ((s = sync(c)) != FE_OK) return s;   // the host vectors go out of scope
+    m->wall = w;
+    return FE_OK;
+}
+
+fe_status fe_wall_traction(fe_mesh m, const double *u, const double *rho, const double *mu, double *out)
+{
+    if (!m) return FE_EINVAL;
+    if (!u || !rho || !mu || !out) return fail(m->ctx, FE_EINVAL, "null u/rho/mu/out");
+    HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
+    {
+        ProfScope ps(m->ctx, 4);
+        HIPCALL(m->ctx, launch_wall_traction(m->dm, m->wall, u, rho, mu, out, true, m->ctx->stream));
+    }
+    return FE_OK;
 }
 
 // ---- profiling hooks (not part of the numerical API) -------------------------

@@ -80,6 +80,25 @@ inline SpmvMap spmv_map(const DevMesh &m)
     return SpmvMap{m.spmv_desc, m.spmv_roff, m.spmv_lidx, m.spmv_cols, m.colidx, m.spmv_nrb, m.nnz};
 }
 
+// Wall faces of a mesh (boundary assembly of the wall model): face node
+// counts and connectivity (mesh numbering, unused slots repeat slot 0), the
+// wall nodes with, for each, its (face, slot) entries in ascending order,
+// and the per-face partial sums [F][4][3].
+struct DevWall {
+    int64_t F = 0, W = 0;
+    double delta = 0.0;
+    uint8_t *nen = nullptr;
+    int32_t *conn = nullptr;    // [F][4]
+    int32_t *nodes = nullptr;   // [W]
+    int32_t *ptr = nullptr;     // [W + 1]
+    int32_t *ent = nullptr;     // face * 4 + slot
+    double *part = nullptr;     // [F][4][3]
+};
+// Wall-model traction (asm_kernels.hip): out[3][N] += sum over faces of
+// int N_a t dS at the wall nodes (zero elsewhere when zero_first).
+hipError_t launch_wall_traction(const DevMesh &m, const DevWall &w, const double *u, const double *rho,
+                                const double *mu, double *out, bool zero_first, hipStream_t s);
+
 // Device status word of an assembly launch sequence.
 struct AsmStatus {
     unsigned long long min_det_key;     // order-preserving key of the smallest det J
