@@ -68,8 +68,8 @@ def measured_valu(workload):
         return None
     keys = ("momentum_fp64_flops_per_element", "poisson_fp64_flops_per_element",
             "mixed_momentum_fp64_flops_per_element", "mixed_momentum_fp32_flops_per_element",
-            "momentum_hbm_bytes_per_operator", "poisson_hbm_bytes_per_operator")
-    return {k: float(kv[k]) for k in keys}
+            "momentum_hbm_bytes_per_operator", "poisson_hbm_bytes_per_operator", "residual_fp64_flops_per_element")
+    return {k: float(kv[k]) for k in keys if k in kv}
 
 
 def assembly_roofline(workload, E, ms_mom, ms_poi, ms_mix):
@@ -543,8 +543,21 @@ def main():
     step_info = fe.fractional_step(mesh, case.dt, rho, mu, L[0], us, ps, rtol=1e-8)
     torch.cuda.synchronize()
     step_ms = (time.perf_counter() - t0) * 1e3
+    # the same step with the pressure solved in mixed precision
+    us.copy_(u)
+    ps.zero_()
+    fe.fractional_step(mesh, case.dt, rho, mu, L[0], us, ps, rtol=1e-8, precision=fe.MIXED)   # FP32 buffers
+    us.copy_(u)
+    ps.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_mixed = fe.fractional_step(mesh, case.dt, rho, mu, L[0], us, ps, rtol=1e-8, precision=fe.MIXED)
+    torch.cuda.synchronize()
+    step_mixed_ms = (time.perf_counter() - t0) * 1e3
     del us, ps
     explicit = {"residual_pass_ms": ms_res / n_res, "residual_melem_s": E / (ms_res / n_res * 1e-3) / 1e6,
+                "fractional_step_mixed_pressure_ms": step_mixed_ms,
+                "mixed_pressure_true_rel_residual": step_mixed["cg_true_rel_residual"],
                 "residual_full_stress_emac_ms": ms_rfe / n_rfe,
                 "fractional_step_ms": step_ms, "pressure_cg_iterations": step_info["cg_iterations"],
                 "pressure_true_rel_residual": step_info["cg_true_rel_residual"], **wall}
@@ -591,6 +604,11 @@ def main():
             "explicit_step": explicit,
         },
     }
+    counted = measured_valu(args.workload)
+    if counted and "residual_fp64_flops_per_element" in counted:
+        tf = counted["residual_fp64_flops_per_element"] * E / (explicit["residual_pass_ms"] * 1e-3) / 1e12
+        explicit["residual_fp64_tflops"] = tf
+        explicit["residual_fp64_frac"] = tf / FP64_PEAK_TFLOPS
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the same recipe at {args.cpu_sample_n}^3")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)

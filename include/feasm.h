@@ -275,7 +275,8 @@ typedef struct {
  *      when wall faces are registered), M_L the lumped rho-mass;
  *      u at the mesh's Dirichlet nodes is held;
  *   2. pressure: L p = fe_divergence(u*) with zero at the Dirichlet rows,
- *      Jacobi-PCG to rtol starting from p (in: initial guess);
+ *      fe_cg_solve to rtol in precision prec (FE_MIXED: FP32 PCG inside FP64
+ *      refinement) starting from p (in: initial guess);
  *   3. correction: u = u* - dt M_L^-1 fe_gradient(p) at the free nodes.
  * L: device [nnz] values of the Poisson matrix after fe_apply_dirichlet
  * (assembled once, Algorithm 1, first step).  u [3][n] in/out, p [n] in/out.
@@ -284,7 +285,7 @@ typedef struct {
  */
 fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const double *mu, const double *L,
                              uint32_t form, double *u, double *p, double rtol, int32_t max_iter,
-                             fe_step_info *info);
+                             fe_precision prec, fe_step_info *info);
 
 /* ---- serving: continuous batching of assemble + solve requests -------------
  * The time-step workload of the paper (Algorithm 1: momentum assembly, the

@@ -280,7 +280,7 @@ def divergence(mesh: Mesh, dt: float, u, rho, out=None):
 
 
 def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8, max_iter: int = 20000,
-                    form: int = 0):
+                    form: int = 0, precision: int = FP64):
     """fe_fractional_step: advances u [3, N] and p [N] in place (device,
     mesh numbering); L is the Poisson matrix after apply_dirichlet.
     Returns {"cg_iterations", "cg_true_rel_residual"}."""
@@ -293,7 +293,8 @@ def fractional_step(mesh: Mesh, dt: float, rho, mu, L, u, p, rtol: float = 1e-8,
     _check_dev(L, torch.float64, mesh.nnz, "L")
     info = capi.StepInfo()
     mesh.ctx.check(mesh.ctx.lib.fe_fractional_step(mesh.h, float(dt), _ptr(rho), _ptr(mu), _ptr(L), int(form),
-                                                   _ptr(u), _ptr(p), float(rtol), int(max_iter), C.byref(info)))
+                                                   _ptr(u), _ptr(p), float(rtol), int(max_iter), int(precision),
+                                                   C.byref(info)))
     return {"cg_iterations": info.cg_iterations, "cg_true_rel_residual": info.cg_true_rel_residual}
 
 

@@ -86,7 +86,7 @@ SIGNATURES = {
     "fe_wall_faces": (C.c_int, [P, i64, P, P, dbl]),
     "fe_wall_traction": (C.c_int, [P, P, P, P, P]),
     "fe_divergence": (C.c_int, [P, dbl, P, P, P]),
-    "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, C.c_uint32, P, P, dbl, i32, C.POINTER(StepInfo)]),
+    "fe_fractional_step": (C.c_int, [P, dbl, P, P, P, C.c_uint32, P, P, dbl, i32, C.c_int, C.POINTER(StepInfo)]),
     "fe_serve_create": (C.c_int, [P, sz, i32, i32, C.POINTER(P)]),
     "fe_serve_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(i64)]),
     "fe_serve_poll": (C.c_int, [P, i64, C.POINTER(i32), C.POINTER(JobResult)]),

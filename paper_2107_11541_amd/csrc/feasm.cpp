@@ -891,7 +891,8 @@ fe_status fe_divergence(fe_mesh m, double dt, const double *u, const double *rho
 }
 
 fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const double *mu, const double *L,
-                             uint32_t form, double *u, double *p, double rtol, int32_t max_iter, fe_step_info *info)
+                             uint32_t form, double *u, double *p, double rtol, int32_t max_iter, fe_precision prec,
+                             fe_step_info *info)
 {
     if (!m) return FE_EINVAL;
     fe_ctx_s *c = m->ctx;
@@ -918,7 +919,7 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     if ((s = element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f)) != FE_OK) return s;
     HIPCALL(c, launch_zero_fixed(d, f, c->stream));
     fe_cg_info ci{};
-    s = fe_cg_solve(m, L, f, p, rtol, max_iter, FE_FP64, &ci);
+    s = fe_cg_solve(m, L, f, p, rtol, max_iter, prec, &ci);
     if (info) {
         info->cg_iterations = ci.iterations;
         info->cg_true_rel_residual = ci.true_rel_residual;

@@ -208,3 +208,25 @@ def test_fractional_step_full_stress_emac_matches_oracle(fe_ctx):
     assert rel(to_user(mesh, p), pn) <= 1e-8
     assert rel(to_user(mesh, u), un) <= 1e-9
     mesh.close()
+
+
+def test_fractional_step_mixed_pressure_solve(fe_ctx):
+    """FE_MIXED solves the pressure in FP32 PCG inside FP64 refinement: the
+    step agrees with the FP64 one to the solve's tolerance."""
+    fe = _fe()
+    import torch
+    c = case_of("hybrid", 6, seed=11)
+    dt = 0.05
+    mesh = make_mesh(fe_ctx, c)
+    L = _poisson(fe, mesh, c, dt)
+    rho, mu = to_mesh(mesh, c.rho), to_mesh(mesh, c.mu)
+    outs = []
+    for prec in (fe.FP64, fe.MIXED):
+        u = to_mesh(mesh, c.u)
+        p = torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda")
+        info = fe.fractional_step(mesh, dt, rho, mu, L, u, p, rtol=1e-10, max_iter=5000, precision=prec)
+        assert info["cg_true_rel_residual"] <= 1e-10
+        outs.append((host(u), host(p)))
+    assert rel(outs[1][1], outs[0][1]) <= 1e-7
+    assert rel(outs[1][0], outs[0][0]) <= 1e-9
+    mesh.close()
