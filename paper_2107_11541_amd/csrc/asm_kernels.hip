@@ -750,36 +750,40 @@ __device__ double wall_utau(double U, double nu, double delta)
     return ut;
 }
 
-// One thread per face: its nodal contributions sum_g w |x_s x x_t| N_a t
-// (3-point rule on triangles, 2x2 Gauss on quadrilaterals) into part.
-__global__ void __launch_bounds__(256) k_wall_faces(int64_t F, const uint8_t *fnen, const int32_t *fconn,
-                                                    const double *X, int64_t N, const double *u, const double *rho,
-                                                    const double *mu, double delta, double *part)
+// Four lanes per face, one per Gauss point (3-point rule on triangles: the
+// fourth lane adds nothing; 2x2 Gauss on quadrilaterals): each lane forms
+// its point's w |x_s x x_t| N_a t, the quad of lanes sums them in the fixed
+// order (q0 + q1) + (q2 + q3) and its first lane writes the face's part.
+__global__ void __launch_bounds__(64) k_wall_faces(int64_t F, const uint8_t *fnen, const int32_t *fconn,
+                                                   const double *X, int64_t N, const double *u, const double *rho,
+                                                   const double *mu, double delta, double *part)
 {
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (f >= F) return;
-    const int nn = fnen[f];
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t f = t >> 2;
+    const int q = (int)(t & 3);
+    const bool live = f < F;                  // whole quads are live or not (64 = 16 quads)
+    const int64_t fs = live ? f : 0;
+    const int nn = fnen[fs];
     int c[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) c[a] = fconn[4 * f + a];
+    for (int a = 0; a < 4; ++a) c[a] = fconn[4 * fs + a];
     double P[4][3] = {};
     const double g = 0.57735026918962576451;
-    for (int q = 0; q < 4; ++q) {
-        if (nn == 3 && q == 3) break;
+    if (live && !(nn == 3 && q == 3)) {
         double Nq[4], ds[4], dt[4], w;
         if (nn == 3) {
-            const double s = q == 1 ? 2.0 / 3.0 : 1.0 / 6.0, t = q == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
-            Nq[0] = 1.0 - s - t; Nq[1] = s; Nq[2] = t; Nq[3] = 0.0;
+            const double s = q == 1 ? 2.0 / 3.0 : 1.0 / 6.0, tt = q == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
+            Nq[0] = 1.0 - s - tt; Nq[1] = s; Nq[2] = tt; Nq[3] = 0.0;
             ds[0] = -1.0; ds[1] = 1.0; ds[2] = 0.0; ds[3] = 0.0;
             dt[0] = -1.0; dt[1] = 0.0; dt[2] = 1.0; dt[3] = 0.0;
             w = 1.0 / 6.0;
         } else {
-            const double s = (q & 1) ? g : -g, t = (q & 2) ? g : -g;
+            const double s = (q & 1) ? g : -g, tt = (q & 2) ? g : -g;
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 const double cx = (a == 1 || a == 2) ? 1.0 : -1.0, cy = a >= 2 ? 1.0 : -1.0;
-                Nq[a] = 0.25 * (1.0 + cx * s) * (1.0 + cy * t);
-                ds[a] = 0.25 * cx * (1.0 + cy * t);
+                Nq[a] = 0.25 * (1.0 + cx * s) * (1.0 + cy * tt);
+                ds[a] = 0.25 * cx * (1.0 + cy * tt);
                 dt[a] = 0.25 * cy * (1.0 + cx * s);
             }
             w = 1.0;
@@ -801,23 +805,37 @@ __global__ void __launch_bounds__(256) k_wall_faces(int64_t F, const uint8_t *fn
         const double nv[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
                               xs[0] * xt[1] - xs[1] * xt[0]};
         const double a2 = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
-        if (!(a2 > 0.0)) continue;
-        const double area = sqrt(a2);
-        const double un = (ug[0] * nv[0] + ug[1] * nv[1] + ug[2] * nv[2]) / a2;
-        const double ut[3] = {ug[0] - un * nv[0], ug[1] - un * nv[1], ug[2] - un * nv[2]};
-        const double U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-        if (!(U > 0.0)) continue;
-        const double tau = wall_utau(U, mg / rg, delta);
-        const double fac = -w * area * rg * tau * tau / U;
+        if (a2 > 0.0) {
+            const double area = sqrt(a2);
+            const double un = (ug[0] * nv[0] + ug[1] * nv[1] + ug[2] * nv[2]) / a2;
+            const double ut[3] = {ug[0] - un * nv[0], ug[1] - un * nv[1], ug[2] - un * nv[2]};
+            const double U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+            if (U > 0.0) {
+                const double tau = wall_utau(U, mg / rg, delta);
+                const double fac = -w * area * rg * tau * tau / U;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) P[a][i] += fac * Nq[a] * ut[i];
+                    for (int i = 0; i < 3; ++i) P[a][i] = fac * Nq[a] * ut[i];
+            }
+        }
     }
+    // (q0 + q1) + (q2 + q3): xor 1 pairs q0/q1 and q2/q3, xor 2 then adds the pairs
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) part[(4 * f + a) * 3 + i] = P[a][i];
+        for (int i = 0; i < 3; ++i) {
+            double v = P[a][i];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            P[a][i] = v;
+        }
+    if (live && q == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) part[(4 * f + a) * 3 + i] = P[a][i];
+    }
 }
 
 // One thread per wall node: its face entries summed in their fixed order.
@@ -855,7 +873,7 @@ hipError_t launch_wall_traction(const DevMesh &m, const DevWall &w, const double
         hipLaunchKernelGGL(k_zero, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, n, out);
     }
     if (w.F == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_wall_faces, dim3((unsigned)((w.F + 255) / 256)), dim3(256), 0, s, w.F, w.nen, w.conn, m.X,
+    hipLaunchKernelGGL(k_wall_faces, dim3((unsigned)((4 * w.F + 63) / 64)), dim3(64), 0, s, w.F, w.nen, w.conn, m.X,
                        m.N, u, rho, mu, w.delta, w.part);
     hipLaunchKernelGGL(k_wall_gather, dim3((unsigned)((w.W + 255) / 256)), dim3(256), 0, s, w.W, w.nodes, w.ptr,
                        w.ent, w.part, m.N, out);
