@@ -253,7 +253,9 @@ fe_status fe_divergence(fe_mesh mesh, double dt, const double *u, const double *
  * faces: face_nen host [n_faces] 3 (triangle: 3-point rule) or 4
  * (quadrilateral, nodes in cyclic order: 2x2 Gauss); face_conn host
  * [n_faces][4] user node ids (a triangle's fourth slot is ignored); delta
- * > 0.  Faces must have non-zero area.  Errors: FE_EINVAL.
+ * > 0.  Faces must have non-zero area.  Errors: FE_EINVAL, FE_ENOMEM,
+ * FE_EDEVICE; after a failed call the mesh has no wall faces.  The call
+ * synchronises the stream before it replaces faces already registered.
  * fe_wall_traction: out[3][n] (device, mesh numbering) = the traction's
  * nodal vector, zero away from the wall; deterministic (fixed summation
  * order).  fe_fractional_step adds it to every Runge-Kutta stage's residual

@@ -969,6 +969,8 @@ fe_status fe_wall_faces(fe_mesh m, int64_t n_faces, const uint8_t *face_nen, con
     for (int64_t f = 0; f < n_faces; ++f)
         for (int a = 0; a < face_nen[f]; ++a) ent[first[conn[4 * f + a]]++] = (int32_t)(4 * f + a);
     HIPCALL(c, hipSetDevice(c->device));
+    fe_status s = sync(c);   // work queued on the previous faces has finished
+    if (s != FE_OK) return s;
     for (void *p : {(void *)m->wall.nen, (void *)m->wall.conn, (void *)m->wall.nodes, (void *)m->wall.ptr,
                     (void *)m->wall.ent, (void *)m->wall.part})
         mesh_free_ptr(m, p);
@@ -978,7 +980,6 @@ fe_status fe_wall_faces(fe_mesh m, int64_t n_faces, const uint8_t *face_nen, con
     w.F = n_faces;
     w.W = (int64_t)nodes.size();
     w.delta = delta;
-    fe_status s;
     auto up = [&](void **dst, const void *src, size_t bytes) -> fe_status {
         fe_status r = mesh_alloc(m, dst, bytes);
         if (r != FE_OK) return r;
@@ -990,8 +991,12 @@ fe_status fe_wall_faces(fe_mesh m, int64_t n_faces, const uint8_t *face_nen, con
         (s = up((void **)&w.nodes, nodes.data(), nodes.size() * 4)) != FE_OK ||
         (s = up((void **)&w.ptr, ptr.data(), ptr.size() * 4)) != FE_OK ||
         (s = up((void **)&w.ent, ent.data(), ent.size() * 4)) != FE_OK ||
-        (s = up((void **)&w.part, nullptr, 12 * (size_t)n_faces * sizeof(double))) != FE_OK)
+        (s = up((void **)&w.part, nullptr, 12 * (size_t)n_faces * sizeof(double))) != FE_OK) {
+        (void)hipStreamSynchronize(c->stream);   // queued copies read the host vectors
+        for (void *p : {(void *)w.nen, (void *)w.conn, (void *)w.nodes, (void *)w.ptr, (void *)w.ent, (void *)w.part})
+            mesh_free_ptr(m, p);
         return s;
+    }
     if ((s = sync(c)) != FE_OK) return s;   // the host vectors go out of scope
     m->wall = w;
     return FE_OK;
