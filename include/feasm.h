@@ -332,6 +332,9 @@ typedef struct {
     int32_t max_iter;
     double *x;                      /* host [n_nodes] out: pressure solution, user numbering */
     double *mom_rhs;                /* host [3][n_nodes] out (user numbering) or NULL */
+    const uint8_t *elem_types;      /* NULL: every element is `type`; else a hybrid mesh as in
+                                     * fe_mesh_upload_mixed: host [n_elems] node counts, conn
+                                     * [n_elems][8] (type is then ignored) */
 } fe_job;
 
 typedef struct {

@@ -417,12 +417,18 @@ class Server:
         ctx._servers.add(self)
 
     def submit(self, elem_type: int, coords, conn, dirichlet, dt: float, u, rho, mu, rtol: float = 1e-8,
-               max_iter: int = 10000, want_mom_rhs: bool = False) -> int:
+               max_iter: int = 10000, want_mom_rhs: bool = False, types=None) -> int:
+        """Queue one request; a hybrid mesh passes elem_type HYBRID, conn [E, 8]
+        and types [E] (node counts)."""
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
         n = coords.shape[0]
-        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != elem_type:
-            raise ValueError("coords must be [N,3] and conn [E,nen]")
+        width = 8 if elem_type == HYBRID else elem_type
+        if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != width:
+            raise ValueError("coords must be [N,3] and conn [E,nen] ([E,8] for a hybrid mesh)")
+        if (elem_type == HYBRID) != (types is not None):
+            raise ValueError("types are given exactly for a HYBRID mesh")
+        ty = None if types is None else np.ascontiguousarray(types, dtype=np.uint8)
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, n)
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(n)
         mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(n)
@@ -432,12 +438,13 @@ class Server:
         job = capi.Job(type=elem_type, n_nodes=n, coords=coords.ctypes.data, n_elems=conn.shape[0],
                        conn=conn.ctypes.data, n_dirichlet=d.shape[0], dirichlet_nodes=d.ctypes.data if d.size else None,
                        dt=float(dt), u=u.ctypes.data, rho=rho.ctypes.data, mu=mu.ctypes.data, rtol=float(rtol),
-                       max_iter=int(max_iter), x=x.ctypes.data, mom_rhs=None if mr is None else mr.ctypes.data)
+                       max_iter=int(max_iter), x=x.ctypes.data, mom_rhs=None if mr is None else mr.ctypes.data,
+                       elem_types=None if ty is None else ty.ctypes.data)
         t = C.c_int64()
         st = self.lib.fe_serve_submit(self.h, C.byref(job), C.byref(t))
         if st != capi.FE_OK:
             raise FeError(st, "fe_serve_submit failed")
-        self._pending[t.value] = (job, coords, conn, d, u, rho, mu, x, mr)
+        self._pending[t.value] = (job, coords, conn, d, u, rho, mu, x, mr, ty)
         return t.value
 
     def _result(self, ticket, r):

@@ -52,7 +52,7 @@ class PlanDesc(C.Structure):
 class Job(C.Structure):
     _fields_ = [("type", C.c_int), ("n_nodes", i64), ("coords", P), ("n_elems", i64), ("conn", P),
                 ("n_dirichlet", i64), ("dirichlet_nodes", P), ("dt", dbl), ("u", P), ("rho", P), ("mu", P),
-                ("rtol", dbl), ("max_iter", i32), ("x", P), ("mom_rhs", P)]
+                ("rtol", dbl), ("max_iter", i32), ("x", P), ("mom_rhs", P), ("elem_types", P)]
 
 
 class JobResult(C.Structure):

@@ -127,7 +127,8 @@ void plan_job(Job *j, bool idle)
         st = FE_EINVAL;
         err = "request needs dt > 0, rtol > 0, max_iter >= 0 and u, rho, mu, x";
     } else {
-        st = mesh_prepare((int)q.type, nullptr, q.n_nodes, q.coords, q.n_elems, q.conn, q.n_dirichlet,
+        st = mesh_prepare(q.elem_types ? 8 : (int)q.type, q.elem_types, q.n_nodes, q.coords, q.n_elems, q.conn,
+                          q.n_dirichlet,
                           q.dirichlet_nodes, true, *j->img, err);
     }
     if (st != FE_OK) {

@@ -169,3 +169,44 @@ def test_many_requests_small_arena(fe_ctx):
     assert all(r["status"] == 0 for r in res), [r["message"] for r in res if r["status"]]
     assert all(r["true_rel_residual"] <= 1.5e-8 for r in res)
     assert st["completed"] == 30
+
+
+def test_hybrid_and_prism_requests_in_a_mix(fe_ctx):
+    """Hybrid (all four types) and prism meshes served in one batch with
+    hexahedral ones: each equals the plain API on the same mesh bitwise and
+    the oracle's pressure to the CG bound."""
+    fe = _fe()
+    import torch
+    from tests.gpu_helpers import dev, host, make_mesh
+    hyb = meshgen.make_case(6, meshgen.HYBRID, 0.1, case_id=3, sub=700, shuffle=True)
+    pen = meshgen.make_case(5, meshgen.PEN06, 0.1, case_id=3, sub=701, shuffle=True)
+    hexes = [_case(n, 702 + i) for i, n in enumerate((4, 7))]
+    srv = fe.Server(fe_ctx, hbm_budget=1 << 30, max_slots=4, host_threads=2)
+    t_h = srv.submit(fe.HYBRID, hyb.coords, hyb.conn, hyb.dirichlet, hyb.dt, hyb.u, hyb.rho, hyb.mu,
+                     rtol=1e-10, max_iter=5000, types=hyb.types)
+    t_p = srv.submit(fe.PEN06, pen.coords, pen.conn, pen.dirichlet, pen.dt, pen.u, pen.rho, pen.mu,
+                     rtol=1e-10, max_iter=5000)
+    t_x = [_submit(srv, c) for c in hexes]
+    res = {"hyb": srv.wait(t_h), "pen": srv.wait(t_p)}
+    for t in t_x:
+        assert srv.wait(t)["status"] == 0
+    srv.close()
+    for key, case in (("hyb", hyb), ("pen", pen)):
+        r = res[key]
+        assert r["status"] == 0, (key, r["message"])
+        mesh = make_mesh(fe_ctx, case)
+        u, rho = mesh.to_mesh(dev(case.u)), mesh.to_mesh(dev(case.rho))
+        L, f, _ = fe.assemble(mesh, fe.POISSON, case.dt, u, rho)
+        fe.apply_dirichlet(mesh, L, f)
+        x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+        x, info = fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-10, max_iter=5000)
+        xu = host(mesh.to_user(x))
+        mesh.close()
+        assert r["iterations"] == info["iterations"]
+        assert np.array_equal(r["x"], xu), key
+        rp, ci, Lo, fo = oracle.assemble(case.coords, case.conn, oracle.OP_POISSON, case.dt, case.u, case.rho,
+                                         None, types=case.types)
+        Lo, fo = Lo[0].copy(), fo[0].copy()
+        oracle.dirichlet(rp, ci, Lo, fo, case.dirichlet)
+        xo, st, it, _, _ = oracle.pcg(rp, ci, Lo, fo, rtol=1e-10)
+        assert np.linalg.norm(r["x"] - xo) <= 1e-8 * np.linalg.norm(xo)
