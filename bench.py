@@ -154,18 +154,22 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(sample_n: int):
+def cpu_baseline(sample_n: int, workload: str = "hex128"):
     """The oracle, as is, on the same recipe at sample_n^3 (bounded CPU time)."""
     import meshgen
     import oracle
-    case = meshgen.cfg1(sample_n)
-    pat = oracle.pattern(case.conn, case.n_nodes)
+    recipe = {"hex128": (meshgen.cfg1, "hex08-"), "hex64": (meshgen.cfg1, "hex08-"),
+              "tet128": (meshgen.cfg2, "tet04-6x"), "hybrid128": (meshgen.hybrid, "hybrid-")}
+    make, label = recipe[workload]
+    case = make(sample_n)
+    ty = case.types
+    pat = oracle.pattern(case.conn, case.n_nodes, ty)
     t0 = time.perf_counter()
     rp, ci, V, B = oracle.assemble(case.coords, case.conn, oracle.OP_MOMENTUM, case.dt, case.u, case.rho, case.mu,
-                                   pattern_=pat)
+                                   pattern_=pat, types=ty)
     t1 = time.perf_counter()
     rp, ci, L, f = oracle.assemble(case.coords, case.conn, oracle.OP_POISSON, case.dt, case.u, case.rho, None,
-                                   pattern_=pat)
+                                   pattern_=pat, types=ty)
     L, f = L[0], f[0]
     oracle.dirichlet(rp, ci, L, f, case.dirichlet)
     t2 = time.perf_counter()
@@ -174,7 +178,7 @@ def cpu_baseline(sample_n: int):
     total = t3 - t0
     return {
         "value": case.n_elems / total / 1e6, "unit": "Melem/s", "cores": 1, "kind": "oracle",
-        "sample": (f"hex08-{sample_n}^3 same recipe ({case.n_elems} elements): momentum+Poisson assembly, "
+        "sample": (f"{label}{sample_n}^3 same recipe ({case.n_elems} elements): momentum+Poisson assembly, "
                    f"Dirichlet, {CG_ITERS} PCG; serial C oracle, {total:.1f} s"),
         "assembly_melem_s": case.n_elems / (t1 - t0) / 1e6,
         "seconds": {"momentum": t1 - t0, "poisson_dirichlet": t2 - t1, "pcg": t3 - t2},
@@ -610,8 +614,9 @@ def main():
         explicit["residual_fp64_tflops"] = tf
         explicit["residual_fp64_frac"] = tf / FP64_PEAK_TFLOPS
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on the same recipe at {args.cpu_sample_n}^3")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
+        log(f"cpu baseline: oracle on the same recipe")
+        n_cpu = args.cpu_sample_n if args.workload in ("hex128", "hex64") else min(args.cpu_sample_n, 64)
+        line["cpu_baseline"] = cpu_baseline(n_cpu, args.workload)
     print(json.dumps(line), flush=True)
 
 
