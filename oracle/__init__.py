@@ -52,8 +52,8 @@ def lib():
         L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
                                         i32, C.POINTER(i64), C.POINTER(dbl)]
         L.or_element_vectors.restype = i32
-        L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, C.POINTER(i64),
-                                         C.POINTER(dbl)]
+        L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, dbl, P,
+                                         C.POINTER(i64), C.POINTER(dbl)]
         L.or_wall_utau.restype = dbl
         L.or_wall_utau.argtypes = [dbl, dbl, dbl]
         L.or_wall_traction.restype = i32
@@ -172,16 +172,17 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
 FULL_STRESS, EMAC = 1, 2    # residual operator variants (bits of `form`)
 
 
-def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None, form=0):
+def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None, form=0, Y=None, D=0.0):
     coords, conn, types = _f64(coords), _i32(conn), _u8(types)
     # contiguous copies held in locals: they must outlive the C call
-    u, rho, mu, p = [None if a is None else _f64(a) for a in (u, rho, mu, p)]
+    u, rho, mu, p, Y = [None if a is None else _f64(a) for a in (u, rho, mu, p, Y)]
     N = coords.shape[0]
-    out = np.zeros((4 if kind == 0 else 3, N))
+    out = np.zeros(({0: 4, 1: 3, 2: 2}[kind], N))
     bad = C.c_int64(-1)
     mdet = C.c_double(0.0)
     st = lib().or_element_vectors(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), kind, form,
-                                  _p(u), _p(rho), _p(mu), _p(p), _p(out), C.byref(bad), C.byref(mdet))
+                                  _p(u), _p(rho), _p(mu), _p(p), _p(Y), float(D), _p(out), C.byref(bad),
+                                  C.byref(mdet))
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return out
@@ -194,6 +195,28 @@ def residual(coords, conn, u, rho, mu, types=None, form=0):
     Eq. (1) at the Gauss points)."""
     out = _element_vectors(coords, conn, 0, u=u, rho=rho, mu=mu, types=types, form=form)
     return out[:3], out[3]
+
+
+def scalar_residual(coords, conn, u, rho, Y, D, types=None):
+    """Matrix-free scalar-transport residual r[N] = -(C(u) + K_{rho D}) Y and
+    the rho-weighted lumped mass m[N] (or_element_vectors kind 2)."""
+    out = _element_vectors(coords, conn, 2, u=u, rho=rho, types=types, Y=Y, D=D)
+    return out[0], out[1]
+
+
+def scalar_step(coords, conn, dirichlet_nodes, dt, u, rho, Y, D, types=None, rk=None):
+    """One explicit Runge-Kutta step (SSP-RK3 by default) of M_L dY/dt =
+    scalar_residual(Y), the scalar held at Dirichlet nodes; no solve
+    (the heat and species equations of Section 2).  Returns Y_new[N]."""
+    rk = SSP_RK3 if rk is None else rk
+    free = np.ones(len(Y), bool)
+    free[np.asarray(dirichlet_nodes)] = False
+    y0 = np.array(Y, dtype=np.float64)
+    ys = y0.copy()
+    for a, b in rk:
+        r, m = scalar_residual(coords, conn, u, rho, ys, D, types)
+        ys = np.where(free, a * y0 + b * (ys + dt * r / m), y0)
+    return ys
 
 
 def gradient(coords, conn, p, types=None):

@@ -576,6 +576,11 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
  *           at the Gauss point, which is (u . grad) u + (div u) u there, i.e.
  *           + rho_g N_a (div u_g) u_i,g on top of the advective form;
  *   kind 1  gradient: g_j[a] = sum_g dV N_a (grad p)_j,g into out[0..2][N];
+ *   kind 2  scalar residual (the heat and species equations, advanced by
+ *           the same Runge-Kutta stages without an algebraic solver,
+ *           Section 2): r[a] = - sum_g dV rho_g (N_a (u_g . grad Y_g)
+ *           + D grad N_a . grad Y_g) into out[0][N] and the lumped mass
+ *           into out[1][N], for the scalar Y with diffusivity D;
  *
  * with u_g, grad u_i,g, rho_g, mu_g, grad p_g interpolated from the nodal
  * fields.  out is overwritten.  Same element types, connectivity convention
@@ -583,17 +588,17 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
  */
 int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
                        int64_t n_elems, const int32_t *conn, int kind, int form, const double *u,
-                       const double *rho, const double *mu, const double *p, double *out,
-                       int64_t *bad_elem, double *min_det)
+                       const double *rho, const double *mu, const double *p, const double *Y,
+                       double D, double *out, int64_t *bad_elem, double *min_det)
 {
     double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], Nt[MAXN + 1][MAXG][MAXN],
         dNt[MAXN + 1][MAXG][MAXN][3];
     int ngt[MAXN + 1];
     for (int t = 0; t <= MAXN; ++t) ngt[t] = ref_element(t, pts[t], w[t], Nt[t], dNt[t]);
-    if (kind != 0 && kind != 1) return OR_EINVAL;
+    if (kind < 0 || kind > 2) return OR_EINVAL;
     for (int64_t e = 0; e < n_elems; ++e)
         if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
-    int nout = kind == 0 ? 4 : 3;
+    int nout = kind == 0 ? 4 : (kind == 1 ? 3 : 2);
     memset(out, 0, sizeof(double) * (size_t)(n_nodes * nout));
     *bad_elem = -1;
     *min_det = INFINITY;
@@ -642,12 +647,27 @@ int or_element_vectors(int stride, const uint8_t *types, int64_t n_nodes, const 
                     }
                     B[3][a] += dV * rg * Ng[a];
                 }
-            } else {
+            } else if (kind == 1) {
                 double gp[3] = {0, 0, 0};
                 for (int b = 0; b < nen; ++b)
                     for (int j = 0; j < 3; ++j) gp[j] += dNx[b][j] * p[c[b]];
                 for (int a = 0; a < nen; ++a)
                     for (int j = 0; j < 3; ++j) B[j][a] += dV * Ng[a] * gp[j];
+            } else {
+                double rg = 0.0, ug[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+                for (int b = 0; b < nen; ++b) {
+                    rg += Ng[b] * rho[c[b]];
+                    for (int i = 0; i < 3; ++i) {
+                        ug[i] += Ng[b] * u[(int64_t)i * n_nodes + c[b]];
+                        gy[i] += dNx[b][i] * Y[c[b]];
+                    }
+                }
+                double adv = ug[0] * gy[0] + ug[1] * gy[1] + ug[2] * gy[2];
+                for (int a = 0; a < nen; ++a) {
+                    double dif = dNx[a][0] * gy[0] + dNx[a][1] * gy[1] + dNx[a][2] * gy[2];
+                    B[0][a] -= dV * rg * (Ng[a] * adv + D * dif);
+                    B[1][a] += dV * rg * Ng[a];
+                }
             }
         }
         if (bad) continue;

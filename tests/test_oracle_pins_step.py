@@ -173,3 +173,39 @@ def test_emac_divergence_term_and_momentum_conservation(kind):
     scale = np.abs(r_e).sum(axis=1)
     assert np.all(np.abs(r_e.sum(axis=1)) <= 1e-13 * scale), r_e.sum(axis=1) / scale
     assert np.any(np.abs(r_a.sum(axis=1)) > 1e-3 * np.abs(r_a).sum(axis=1))
+
+
+# --- scalar transport (heat, species): the same stages without a solve ---
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "hybrid"])
+def test_scalar_residual_is_b_minus_AY(kind):
+    c = case_of(kind, seed=8)
+    N = c.n_nodes
+    Y = np.random.default_rng(9).uniform(0, 1, N)
+    D = 3e-3
+    r, m = oracle.scalar_residual(c.coords, c.conn, c.u, c.rho, Y, D, c.types)
+    dt = 0.21
+    rp, ci, A, b = oracle.assemble(c.coords, c.conn, oracle.OP_SCALAR, dt, c.u, c.rho, None, Y=Y[None, :],
+                                   D=np.array([D]), types=c.types)
+    ref = b[0] - oracle.spmv(rp, ci, A[0], Y)
+    assert np.linalg.norm(r - ref) <= 1e-12 * np.linalg.norm(ref)
+    _, m_mom = oracle.residual(c.coords, c.conn, c.u, c.rho, c.mu, c.types)
+    assert np.array_equal(m, m_mom)
+
+
+def test_scalar_step_keeps_constants_and_is_third_order():
+    c = case_of("hex", n=4, seed=10)
+    N = c.n_nodes
+    # a constant scalar is a steady state (C 1 = 0, K 1 = 0)
+    y = oracle.scalar_step(c.coords, c.conn, c.dirichlet, 0.01, c.u, c.rho, np.full(N, 0.7), 2e-3)
+    assert np.abs(y - 0.7).max() <= 1e-14
+    Y = np.random.default_rng(11).uniform(0, 1, N)
+
+    def err(dt):
+        one = oracle.scalar_step(c.coords, c.conn, c.dirichlet, dt, c.u, c.rho, Y, 2e-3)
+        ref = Y
+        for _ in range(32):
+            ref = oracle.scalar_step(c.coords, c.conn, c.dirichlet, dt / 32, c.u, c.rho, ref, 2e-3)
+        return np.linalg.norm(one - ref)
+    e1, e2 = err(0.02), err(0.01)
+    assert 12.0 < e1 / e2 < 20.0, e1 / e2
