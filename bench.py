@@ -522,6 +522,22 @@ def main():
     n_rfe, ms_rfe = ctx.profile_read(4)
     ctx.profile(False)
     del R4
+    # scalar transport (heat, species): residual pass and one explicit step,
+    # the first velocity component standing in for the scalar
+    Ysc = u[0].clone()
+    S2 = torch.empty((2, N), dtype=torch.float64, device=dev)
+    ctx.profile(True)
+    for _ in range(5):
+        fe.scalar_residual(mesh, u, rho, Ysc, 1e-5, out=S2)
+    n_sr, ms_sr = ctx.profile_read(4)
+    ctx.profile(False)
+    fe.scalar_step(mesh, case.dt, u, rho, 1e-5, Ysc)     # allocates its buffer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fe.scalar_step(mesh, case.dt, u, rho, 1e-5, Ysc)
+    torch.cuda.synchronize()
+    scalar = {"scalar_residual_ms": ms_sr / n_sr, "scalar_step_ms": (time.perf_counter() - t0) * 1e3}
+    del Ysc, S2
     wall = {}
     if case.wall_nen is not None:
         # boundary assembly: the wall model on the z = 0 faces, exchange
@@ -564,7 +580,7 @@ def main():
                 "mixed_pressure_true_rel_residual": step_mixed["cg_true_rel_residual"],
                 "residual_full_stress_emac_ms": ms_rfe / n_rfe,
                 "fractional_step_ms": step_ms, "pressure_cg_iterations": step_info["cg_iterations"],
-                "pressure_true_rel_residual": step_info["cg_true_rel_residual"], **wall}
+                "pressure_true_rel_residual": step_info["cg_true_rel_residual"], **wall, **scalar}
     log(f"explicit step: {json.dumps(explicit)}")
 
     spmv_us = ms_spmv / n_spmv * 1e3

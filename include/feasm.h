@@ -222,6 +222,17 @@ fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, dou
  * arrays are device, mesh numbering, [k][n_nodes] rows, FP64.  Each call
  * synchronises the stream and fails with FE_EBADELEM on det J <= 0. */
 
+/* Scalar transport (the heat and species equations, which the paper
+ * advances with the same Runge-Kutta stages and no algebraic solver,
+ * Section 2).  fe_scalar_residual: out[2][n], out_0 = -(C(u) + K_{rho D}) Y,
+ * i.e. -sum_e int rho (N_a (u . grad Y) + D grad N_a . grad Y), and out_1 =
+ * the lumped rho-mass.  fe_scalar_step: one three-stage SSP Runge-Kutta step
+ * of M_L dY/dt = fe_scalar_residual(Y), Y [n] in/out held at the mesh's
+ * Dirichlet nodes (work buffer of 3 n doubles on the mesh).  D >= 0. */
+fe_status fe_scalar_residual(fe_mesh mesh, const double *u, const double *rho, const double *Y, double D,
+                             double *out);
+fe_status fe_scalar_step(fe_mesh mesh, double dt, const double *u, const double *rho, double D, double *Y);
+
 /* Operator variants of Eq. (1) for the residual (bits of `form`; 0 = the
  * advective convection and Laplacian viscous forms of fe_assemble). */
 #define FE_FORM_FULL_STRESS 1u   /* viscous term div(2 mu eps(u)): adds mu (d u_j/d x_i)(d N_a/d x_j) */

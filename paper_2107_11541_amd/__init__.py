@@ -31,7 +31,8 @@ MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
-           "residual", "gradient", "divergence", "fractional_step", "wall_traction", "FULL_STRESS", "EMAC",
+           "residual", "gradient", "divergence", "fractional_step", "wall_traction", "scalar_residual",
+           "scalar_step", "FULL_STRESS", "EMAC",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
 
@@ -238,6 +239,31 @@ def residual(mesh: Mesh, u, rho, mu, out=None, form: int = 0):
     _check_dev(out, torch.float64, 4 * N, "out")
     mesh.ctx.check(mesh.ctx.lib.fe_residual(mesh.h, _ptr(u), _ptr(rho), _ptr(mu), int(form), _ptr(out)))
     return out
+
+
+def scalar_residual(mesh: Mesh, u, rho, Y, D: float, out=None):
+    """fe_scalar_residual: out[2, N] = -(C(u) + K_{rho D}) Y and the lumped rho-mass."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(Y, torch.float64, N, "Y")
+    if out is None:
+        out = torch.empty((2, N), dtype=torch.float64, device=u.device)
+    _check_dev(out, torch.float64, 2 * N, "out")
+    mesh.ctx.check(mesh.ctx.lib.fe_scalar_residual(mesh.h, _ptr(u), _ptr(rho), _ptr(Y), float(D), _ptr(out)))
+    return out
+
+
+def scalar_step(mesh: Mesh, dt: float, u, rho, D: float, Y):
+    """fe_scalar_step: one explicit SSP-RK3 step of the scalar Y [N] (in place)."""
+    torch = _torch()
+    N = mesh.n_nodes
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(Y, torch.float64, N, "Y")
+    mesh.ctx.check(mesh.ctx.lib.fe_scalar_step(mesh.h, float(dt), _ptr(u), _ptr(rho), float(D), _ptr(Y)))
+    return Y
 
 
 def gradient(mesh: Mesh, p, out=None):

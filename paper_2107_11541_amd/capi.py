@@ -83,6 +83,8 @@ SIGNATURES = {
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
     "fe_residual": (C.c_int, [P, P, P, P, C.c_uint32, P]),
     "fe_gradient": (C.c_int, [P, P, P]),
+    "fe_scalar_residual": (C.c_int, [P, P, P, P, dbl, P]),
+    "fe_scalar_step": (C.c_int, [P, dbl, P, P, dbl, P]),
     "fe_wall_faces": (C.c_int, [P, i64, P, P, dbl]),
     "fe_wall_traction": (C.c_int, [P, P, P, P, P]),
     "fe_divergence": (C.c_int, [P, dbl, P, P, P]),

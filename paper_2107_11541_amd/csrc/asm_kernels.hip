@@ -35,7 +35,7 @@ namespace {
 constexpr int OP_MOM = FE_OP_MOMENTUM, OP_SCA = FE_OP_SCALAR, OP_POI = FE_OP_POISSON;
 // element-vector passes of the explicit step (no matrix): residual + lumped
 // mass, pressure gradient, divergence right-hand side
-constexpr int OP_RES = kOpResidual, OP_GRD = kOpGradient, OP_DIV = kOpDivergence;
+constexpr int OP_RES = kOpResidual, OP_GRD = kOpGradient, OP_DIV = kOpDivergence, OP_SRS = kOpScalarResidual;
 
 // Trilinear hexahedron, 2x2x2 Gauss rule (points xi fastest, weights 1).
 struct Hex {
@@ -179,6 +179,7 @@ template <> struct OpTraits<FE_OP_POISSON> { static constexpr int NF = 7, NRHS =
 template <> struct OpTraits<kOpResidual> { static constexpr int NF = 8, NRHS = 4; };    // r_x, r_y, r_z, lumped mass
 template <> struct OpTraits<kOpGradient> { static constexpr int NF = 4, NRHS = 3; };    // x, y, z, p
 template <> struct OpTraits<kOpDivergence> { static constexpr int NF = 7, NRHS = 1; };
+template <> struct OpTraits<kOpScalarResidual> { static constexpr int NF = 8, NRHS = 2; };   // r, lumped mass
 
 // Waves per element block: a HEX08 element's 8 rows are split between two
 // waves (4 rows each) so that a wave needs <= 256 registers and two blocks'
@@ -299,16 +300,39 @@ __device__ __forceinline__ double jacobian_inverse(int g, const Geo<EL> &GE, dou
 //           FE_FORM_EMAC adds rho N_a (div u) u_i (Eq. (1)'s convective form
 //           at the Gauss point);
 //   OP_GRD: B_j[a] += dV N_a (grad p)_j;
-//   OP_DIV: B_0[a] += dV / dt grad N_a . (rho u).
+//   OP_DIV: B_0[a] += dV / dt grad N_a . (rho u);
+//   OP_SRS: B_0[a] -= dV rho (N_a (u . grad Y) + D grad N_a . grad Y),
+//           B_1[a] += dV rho N_a (Y in slot 7, D = Dk).
 // Fields in LDS: x, y, z, then u_x, u_y, u_z, rho, mu (OP_GRD: p in slot 3).
 template <class EL, int OP, int RA, int A0>
 __device__ __forceinline__ void element_vector_point(int g, const double *nd, int T, const int (&ln)[EL::NEN],
                                                      const double (&dN)[EL::NEN][3], double dV,
                                                      double (&B)[OpTraits<OP>::NRHS][RA], double inv_dt,
-                                                     int form)
+                                                     int form, double Dk)
 {
     constexpr int NEN = EL::NEN;
-    if constexpr (OP == OP_GRD) {
+    if constexpr (OP == OP_SRS) {
+        double rg = 0.0, ug[3] = {0.0, 0.0, 0.0}, gy[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            const double Nb = RefN<EL>(g, b), yb = nd[7 * T + ln[b]];
+            rg += Nb * nd[6 * T + ln[b]];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                ug[i] += Nb * nd[(3 + i) * T + ln[b]];
+                gy[i] += dN[b][i] * yb;
+            }
+        }
+        const double adv = ug[0] * gy[0] + ug[1] * gy[1] + ug[2] * gy[2], w = dV * rg;
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int a = A0 + r;
+            const double Na = RefN<EL>(g, a);
+            const double dif = dN[a][0] * gy[0] + dN[a][1] * gy[1] + dN[a][2] * gy[2];
+            B[0][r] -= w * (Na * adv + Dk * dif);
+            B[1][r] += w * Na;
+        }
+    } else if constexpr (OP == OP_GRD) {
         double gp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int b = 0; b < NEN; ++b) {
@@ -392,7 +416,7 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
             dN[a][i] = Q(s);
         }
     if constexpr (OP >= OP_RES) {
-        element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt, form);
+        element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt, form, Dk);
     } else {
         double rg = 0.0, fg = 0.0, ug0 = 0.0, ug1 = 0.0, ug2 = 0.0;
 #pragma unroll
@@ -535,7 +559,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
             f[5] = k.u[2 * N + g];
             f[6] = k.rho[g];
             if (OP == OP_MOM || OP == OP_RES) f[7] = k.mu[g];
-            if (OP == OP_SCA) f[7] = k.Y[g];
+            if (OP == OP_SCA || OP == OP_SRS) f[7] = k.Y[g];
         }
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) f[NF + r] = first ? 0.0 : k.rhs[r * N + g];
@@ -723,6 +747,7 @@ void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStre
     // element-vector passes are FP64 only
     case OP_RES: launch_one<EL, OP_RES, double>(L, k, s); break;
     case OP_GRD: launch_one<EL, OP_GRD, double>(L, k, s); break;
+    case OP_SRS: launch_one<EL, OP_SRS, double>(L, k, s); break;
     default: launch_one<EL, OP_DIV, double>(L, k, s); break;
     }
 }

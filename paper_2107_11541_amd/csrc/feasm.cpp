@@ -239,10 +239,10 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     // doubles per row, one int descriptor per row (+ alignment), then the row
     // image, for the launch's largest block
     // (the element-vector passes stage no row image)
-    const int nf[kNumOps] = {8, 8, 7, 8, 4, 7}, nr[kNumOps] = {3, 1, 1, 4, 3, 1};
+    const int nf[kNumOps] = {8, 8, 7, 8, 4, 7, 8}, nr[kNumOps] = {3, 1, 1, 4, 3, 1, 2};
     d.launches.clear();
     for (const AsmSeg &g : P.segs) {
-        AsmLaunch L{g.nen, g.first, g.count, {0, 0, 0, 0, 0, 0}};
+        AsmLaunch L{g.nen, g.first, g.count, {0, 0, 0, 0, 0, 0, 0}};
         for (int q = g.first; q < g.first + g.count; ++q) {
             const int32_t b = P.color_blk[q];
             const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
@@ -297,6 +297,7 @@ void mesh_release(fe_mesh_s *m)
     m->allocs.clear();
     m->cg = CGWork();
     m->step_work = nullptr;
+    m->scalar_work = nullptr;
     m->wall = DevWall();
 }
 
@@ -453,7 +454,7 @@ fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
 // Queues one element-vector pass (kOpResidual, kOpGradient, kOpDivergence)
 // writing its rows of N to out, and checks its status word.
 fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, const double *rho, const double *mu,
-                          const double *p, double *out, int form = 0)
+                          const double *p, double *out, int form = 0, const double *Y = nullptr, double D = 0.0)
 {
     fe_ctx_s *c = m->ctx;
     AsmArgs a{};
@@ -464,6 +465,8 @@ fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, cons
     a.rho = rho;
     a.mu = mu;
     a.p = p;
+    a.Y = Y;
+    a.Dk = D;
     a.form = form;
     a.rhs = out;
     a.status = m->status;
@@ -928,6 +931,39 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     // 3. correction u = u* - dt M_L^-1 G p
     if ((s = element_vectors(m, kOpGradient, dt, nullptr, nullptr, nullptr, p, g)) != FE_OK) return s;
     HIPCALL(c, launch_correct(d, dt, g, mass, u, c->stream));
+    return sync(c);
+}
+
+fe_status fe_scalar_residual(fe_mesh m, const double *u, const double *rho, const double *Y, double D, double *out)
+{
+    if (!m) return FE_EINVAL;
+    if (!u || !rho || !Y || !out) return fail(m->ctx, FE_EINVAL, "null u/rho/Y/out");
+    if (!(D >= 0.0) || !std::isfinite(D)) return fail(m->ctx, FE_EINVAL, "D must be >= 0");
+    HIPCALL(m->ctx, hipSetDevice(m->ctx->device));
+    return element_vectors(m, kOpScalarResidual, 1.0, u, rho, nullptr, nullptr, out, 0, Y, D);
+}
+
+fe_status fe_scalar_step(fe_mesh m, double dt, const double *u, const double *rho, double D, double *Y)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (!u || !rho || !Y) return fail(c, FE_EINVAL, "null u/rho/Y");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FE_EINVAL, "dt must be > 0");
+    if (!(D >= 0.0) || !std::isfinite(D)) return fail(c, FE_EINVAL, "D must be >= 0");
+    HIPCALL(c, hipSetDevice(c->device));
+    const DevMesh &d = m->dm;
+    const int64_t N = d.N;
+    fe_status s;
+    if (!m->scalar_work && (s = mesh_alloc(m, (void **)&m->scalar_work, 3 * (size_t)N * sizeof(double))) != FE_OK)
+        return s;
+    double *y0 = m->scalar_work, *res = y0 + N, *mass = res + N;
+    static const double kStage[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+    HIPCALL(c, hipMemcpyAsync(y0, Y, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    for (const auto &st : kStage) {
+        if ((s = element_vectors(m, kOpScalarResidual, dt, u, rho, nullptr, nullptr, res, 0, Y, D)) != FE_OK)
+            return s;
+        HIPCALL(c, launch_rk_stage(d, st[0], st[1], dt, y0, res, mass, Y, c->stream, 1));
+    }
     return sync(c);
 }
 

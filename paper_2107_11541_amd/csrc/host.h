@@ -62,6 +62,7 @@ struct fe_mesh_s {
     feasm::CGWork cg;
     double *step_work = nullptr;         // explicit step: u0 [3][N], residual + mass [4][N], f [N], g [3][N]
     feasm::DevWall wall;                 // wall faces of the wall model (F = 0: none)
+    double *scalar_work = nullptr;       // explicit scalar step: Y0 [N], residual + mass [2][N]
     feasm::DevArena *arena = nullptr;    // device memory source (nullptr: hipMalloc)
     bool listed = true;                  // in ctx->meshes (freed with the context)
     // recorded PCG iterations (FP64, FP32), valid for the pointers they were

@@ -14,8 +14,9 @@ namespace feasm {
 // Element-vector passes of the explicit step, numbered after the fe_operator
 // values: residual -(C(u) + K_mu) u per component plus the rho-weighted
 // lumped mass, pressure gradient int N grad p, divergence right-hand side
-// (1/dt) int grad N . (rho u).
-constexpr int kOpResidual = 3, kOpGradient = 4, kOpDivergence = 5, kNumOps = 6;
+// (1/dt) int grad N . (rho u), scalar-transport residual -(C(u) + K_{rho D}) Y
+// plus the lumped mass.
+constexpr int kOpResidual = 3, kOpGradient = 4, kOpDivergence = 5, kOpScalarResidual = 6, kNumOps = 7;
 
 // One assembly launch: the blocks color_blk[first, first + count), all of one
 // colour and one element type (nen nodes); lds[op] = LDS bytes of its
@@ -155,7 +156,7 @@ hipError_t launch_dirichlet(const DevMesh &m, double *vals, double *rhs, const d
 // Explicit-step updates on [3][N] velocity rows (k_rk_stage, k_correct) and
 // zeroing a right-hand side at the Dirichlet nodes.
 hipError_t launch_rk_stage(const DevMesh &m, double alpha, double beta, double dt, const double *u0,
-                           const double *r, const double *mass, double *u, hipStream_t s);
+                           const double *r, const double *mass, double *u, hipStream_t s, int ncomp = 3);
 hipError_t launch_correct(const DevMesh &m, double dt, const double *g, const double *mass, double *u, hipStream_t s);
 hipError_t launch_zero_fixed(const DevMesh &m, double *f, hipStream_t s);
 hipError_t launch_permute(int64_t n, int ncomp, const int32_t *perm, const double *in, double *out, bool gather,

@@ -427,6 +427,7 @@ __global__ void __launch_bounds__(kTB) k_axpy(int64_t n, double a, const double 
 // flags): one Runge-Kutta stage u = alpha u0 + beta (u + dt r / m) at free
 // nodes, u = u0 at Dirichlet nodes (u may alias neither u0 nor r); the
 // velocity correction u -= dt g / m at free nodes; and f = 0 at Dirichlet rows.
+template <int NC>
 __global__ void __launch_bounds__(kTB) k_rk_stage(int64_t n, double alpha, double beta, double dt, const double *u0,
                                                   const double *r, const double *m, const uint8_t *is_dir, double *u)
 {
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(kTB) k_rk_stage(int64_t n, double alpha, doubl
         const bool fixed = is_dir[i] != 0;
         const double h = dt / m[i];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             const int64_t j = c * n + i;
             u[j] = fixed ? u0[j] : alpha * u0[j] + beta * (u[j] + h * r[j]);
         }
@@ -857,10 +858,14 @@ hipError_t launch_axpy(int64_t n, double a, const double *x, double *y, hipStrea
 }
 
 hipError_t launch_rk_stage(const DevMesh &m, double alpha, double beta, double dt, const double *u0,
-                           const double *r, const double *mass, double *u, hipStream_t s)
+                           const double *r, const double *mass, double *u, hipStream_t s, int ncomp)
 {
-    hipLaunchKernelGGL(k_rk_stage, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, alpha, beta, dt, u0, r, mass,
-                       m.is_dir, u);
+    if (ncomp == 3)
+        hipLaunchKernelGGL(k_rk_stage<3>, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, alpha, beta, dt, u0, r,
+                           mass, m.is_dir, u);
+    else
+        hipLaunchKernelGGL(k_rk_stage<1>, dim3(stream_blocks(m.N)), dim3(kTB), 0, s, m.N, alpha, beta, dt, u0, r,
+                           mass, m.is_dir, u);
     return hipGetLastError();
 }
 

@@ -230,3 +230,25 @@ def test_fractional_step_mixed_pressure_solve(fe_ctx):
     assert rel(outs[1][1], outs[0][1]) <= 1e-7
     assert rel(outs[1][0], outs[0][0]) <= 1e-9
     mesh.close()
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 5), ("tet", 4), ("pyr", 4), ("hybrid", 6)])
+def test_scalar_residual_and_step_match_oracle(fe_ctx, kind, n):
+    """The heat/species residual and one explicit scalar step (no solve)."""
+    fe = _fe()
+    c = case_of(kind, n, seed=30 + n)
+    Y = np.random.default_rng(n).uniform(0, 1, c.n_nodes)
+    D = 2e-3
+    mesh = make_mesh(fe_ctx, c)
+    u, rho, Yd = to_mesh(mesh, c.u), to_mesh(mesh, c.rho), to_mesh(mesh, Y)
+    out = to_user(mesh, fe.scalar_residual(mesh, u, rho, Yd, D))
+    r, m = oracle.scalar_residual(c.coords, c.conn, c.u, c.rho, Y, D, c.types)
+    assert rel(out[0], r) <= 1e-12 and rel(out[1], m) <= 1e-13
+    dt = 0.2 / n
+    fe.scalar_step(mesh, dt, u, rho, D, Yd)
+    yo = oracle.scalar_step(c.coords, c.conn, c.dirichlet, dt, c.u, c.rho, Y, D, c.types)
+    assert rel(to_user(mesh, Yd), yo) <= 1e-12
+    with pytest.raises(fe.FeError) as ei:
+        fe.scalar_step(mesh, dt, u, rho, -1.0, Yd)
+    assert ei.value.status == 1
+    mesh.close()
