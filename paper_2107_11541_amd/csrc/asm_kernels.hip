@@ -499,8 +499,11 @@ __device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, 
 
 // One work-group = one block of <= 64 elements = W waves.  Lane l computes
 // rows [a0, a0 + RA) of element l mod 64 with a0 = (l / 64) * RA.
-template <class EL, int OP, class Q>
-__global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
+// The block body of every assembly and element-vector pass.  FORM >= 0
+// fixes the residual pass's operator variants at compile time; -1 reads them
+// from the arguments.
+template <class EL, int OP, class Q, int FORM>
+__device__ __forceinline__ void assemble_block(const KArgs &k)
 {
     constexpr int NEN = EL::NEN, NG = EL::NG, W = Split<EL>::W, RA = NEN / W, NT = 64 * W;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
@@ -603,8 +606,9 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
         Rows<EL> rows;
 #pragma unroll
         for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
-        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, k.form);
-        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, k.form);
+        const int form = FORM >= 0 ? FORM : k.form;
+        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, form);
+        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, form);
     }
     // this lane's rows of the element, selected without dynamic indexing
     int lr[RA];
@@ -685,6 +689,20 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
     }
 }
 
+template <class EL, int OP, class Q>
+__global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
+{
+    assemble_block<EL, OP, Q, -1>(k);
+}
+
+// The momentum residual pass with its operator variants (FE_FORM_* bits)
+// fixed at compile time.
+template <class EL, int FORM>
+__global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_residual(KArgs k)
+{
+    assemble_block<EL, OP_RES, double, FORM>(k);
+}
+
 // Reduce the per-block status into (min det, first bad mesh element): one
 // group of 1024 threads, four independent loads in flight per thread.
 constexpr int kStatusThreads = 1024;
@@ -737,6 +755,13 @@ void launch_one(const AsmLaunch &L, KArgs k, hipStream_t s)
     hipLaunchKernelGGL((k_assemble<EL, OP, Q>), dim3(L.count), dim3(64 * Split<EL>::W), L.lds[OP], s, k);
 }
 
+template <class EL, int FORM>
+void launch_residual(const AsmLaunch &L, KArgs k, hipStream_t s)
+{
+    k.blk_offset = L.first;
+    hipLaunchKernelGGL((k_residual<EL, FORM>), dim3(L.count), dim3(64 * Split<EL>::W), L.lds[OP_RES], s, k);
+}
+
 template <class EL>
 void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStream_t s)
 {
@@ -745,7 +770,14 @@ void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStre
     case OP_SCA: mixed ? launch_one<EL, OP_SCA, float>(L, k, s) : launch_one<EL, OP_SCA, double>(L, k, s); break;
     case OP_POI: mixed ? launch_one<EL, OP_POI, float>(L, k, s) : launch_one<EL, OP_POI, double>(L, k, s); break;
     // element-vector passes are FP64 only
-    case OP_RES: launch_one<EL, OP_RES, double>(L, k, s); break;
+    case OP_RES:
+        switch (k.form) {
+        case 0: launch_residual<EL, 0>(L, k, s); break;
+        case 1: launch_residual<EL, 1>(L, k, s); break;
+        case 2: launch_residual<EL, 2>(L, k, s); break;
+        default: launch_residual<EL, 3>(L, k, s); break;
+        }
+        break;
     case OP_GRD: launch_one<EL, OP_GRD, double>(L, k, s); break;
     case OP_SRS: launch_one<EL, OP_SRS, double>(L, k, s); break;
     default: launch_one<EL, OP_DIV, double>(L, k, s); break;
