@@ -36,10 +36,10 @@ def test_plan_pattern_matches_oracle(kind, renumber):
     assert np.array_equal(ex["elem_types"], want)
 
 
-@pytest.mark.parametrize("kind", ["pen", "pyr", "hybrid"])
-def test_blocks_colours_and_launches(kind):
+@pytest.mark.parametrize("kind,renumber", [("pen", True), ("pyr", True), ("hybrid", True), ("hybrid", False)])
+def test_blocks_colours_and_launches(kind, renumber):
     case = meshgen.make_case(9, KINDS[kind], 0.1, case_id=22, shuffle=True)
-    P = plan_of(case)
+    P = plan_of(case, renumber)
     ex = P.export()
     d = P.desc
     nb = d["n_blocks"]
@@ -47,10 +47,14 @@ def test_blocks_colours_and_launches(kind):
     et, bt = ex["elem_types"], ex["block_types"]
     assert bep[0] == 0 and bep[-1] == case.n_elems
     assert np.diff(bep).min() >= 1 and np.diff(bep).max() <= 64
-    # renumbering groups the types: HEX08, PEN06, PYR05, TET04
+    # renumbering groups the types: HEX08, PEN06, PYR05, TET04 (without it the
+    # user order is kept and blocks close at every type change)
     rank = {8: 0, 6: 1, 5: 2, 4: 3}
     ranks = np.array([rank[t] for t in et])
-    assert np.all(np.diff(ranks) >= 0)
+    if renumber:
+        assert np.all(np.diff(ranks) >= 0)
+    else:
+        assert np.array_equal(ex["elem_perm"], np.arange(case.n_elems))
     iperm = np.empty(case.n_nodes, np.int64)
     iperm[ex["node_perm"]] = np.arange(case.n_nodes)
     mconn = case.conn[ex["elem_perm"]]
