@@ -252,3 +252,33 @@ def test_scalar_residual_and_step_match_oracle(fe_ctx, kind, n):
         fe.scalar_step(mesh, dt, u, rho, -1.0, Yd)
     assert ei.value.status == 1
     mesh.close()
+
+
+@pytest.mark.parametrize("kind,n,renumber", [("hex", 1, True), ("tet", 1, True), ("pen", 1, True),
+                                             ("pyr", 1, True), ("hex", 2, False), ("hybrid", 4, False),
+                                             ("hybrid", 5, False)])
+def test_element_vector_passes_edge_cases(fe_ctx, kind, n, renumber):
+    """One-cell meshes (a single block, far below a wavefront) and user
+    element order (hybrid blocks closed at every type change): residual with
+    both operator variants, gradient, divergence and the scalar residual."""
+    fe = _fe()
+    c = case_of(kind, n, seed=40 + n)
+    print(f"{kind} n={n} E={c.n_elems} renumber={renumber}", flush=True)
+    mesh = make_mesh(fe_ctx, c, renumber)
+    u, rho, mu = to_mesh(mesh, c.u), to_mesh(mesh, c.rho), to_mesh(mesh, c.mu)
+    out = to_user(mesh, fe.residual(mesh, u, rho, mu, form=3))
+    r, m = oracle.residual(c.coords, c.conn, c.u, c.rho, c.mu, c.types, form=3)
+    for i in range(3):
+        assert rel(out[i], r[i]) <= 1e-12, (i, rel(out[i], r[i]))
+    assert rel(out[3], m) <= 1e-13
+    p = np.random.default_rng(n).normal(size=c.n_nodes)
+    g = to_user(mesh, fe.gradient(mesh, to_mesh(mesh, p)))
+    assert rel(g, oracle.gradient(c.coords, c.conn, p, c.types)) <= 1e-12
+    f = to_user(mesh, fe.divergence(mesh, 0.02, u, rho))
+    _, _, _, fr = oracle.assemble(c.coords, c.conn, POI, 0.02, c.u, c.rho, None, types=c.types)
+    assert rel(f, fr[0]) <= 1e-12
+    Y = np.random.default_rng(n + 1).uniform(0, 1, c.n_nodes)
+    s = to_user(mesh, fe.scalar_residual(mesh, u, rho, to_mesh(mesh, Y), 2e-3))
+    sr, sm = oracle.scalar_residual(c.coords, c.conn, c.u, c.rho, Y, 2e-3, c.types)
+    assert rel(s[0], sr) <= 1e-12 and rel(s[1], sm) <= 1e-13
+    mesh.close()
