@@ -91,7 +91,7 @@ def _oracle_poisson(c, dt):
     return rp, ci, L
 
 
-@pytest.mark.parametrize("kind,n", [("hex", 6), ("hybrid", 6)])
+@pytest.mark.parametrize("kind,n", [("hex", 6), ("tet", 5), ("pen", 5), ("pyr", 4), ("hybrid", 6)])
 def test_fractional_step_matches_oracle(fe_ctx, kind, n):
     fe = _fe()
     import torch
@@ -232,7 +232,7 @@ def test_fractional_step_mixed_pressure_solve(fe_ctx):
     mesh.close()
 
 
-@pytest.mark.parametrize("kind,n", [("hex", 5), ("tet", 4), ("pyr", 4), ("hybrid", 6)])
+@pytest.mark.parametrize("kind,n", [("hex", 5), ("tet", 4), ("pen", 5), ("pyr", 4), ("hybrid", 6)])
 def test_scalar_residual_and_step_match_oracle(fe_ctx, kind, n):
     """The heat/species residual and one explicit scalar step (no solve)."""
     fe = _fe()
