@@ -110,14 +110,15 @@ def poisson_bytes(nnz, n, conn_entries):
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed PMC summary.
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary
+    of this workload (profiles/k_cg_spmv_pq_<workload>.md).
 
     The summary records a hash of the solver kernel sources; once they have
     changed the counters describe another kernel and the figure is dropped
     (None), as it is for any workload the counters were not taken on.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cg_spmv_pq_hex128.md")
+    path = os.path.join(ROOT, "profiles", f"k_cg_spmv_pq_{workload}.md")
     try:
         text = open(path).read()
     except OSError:
