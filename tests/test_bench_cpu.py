@@ -60,3 +60,18 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_committed_traffic_summaries_name_their_workload():
+    # each committed SpMV summary records the workload in its file name, a
+    # positive byte count and a full hash
+    import glob
+    import re
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_cg_spmv_pq_*.md")))
+    assert paths
+    for p in paths:
+        wl = re.match(r"k_cg_spmv_pq_(.+)\.md$", os.path.basename(p)).group(1)
+        kv = dict(ln.strip().split(": ", 1) for ln in open(p) if re.match(r"\s+(traffic_\w+|source_sha256): ", ln))
+        assert kv["traffic_workload"] == wl and kv["traffic_kernel"] == "k_cg_spmv_pq"
+        assert float(kv["traffic_bytes_per_launch"]) > 0
+        assert re.fullmatch(r"[0-9a-f]{64}", kv["source_sha256"])
