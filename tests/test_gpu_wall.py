@@ -82,10 +82,13 @@ def test_wall_argument_errors(fe_ctx):
     mesh.close()
 
 
-def test_fractional_step_with_wall_matches_oracle(fe_ctx):
+@pytest.mark.parametrize("kind,form", [(meshgen.HEX08, 0), (meshgen.HYBRID, 3)])
+def test_fractional_step_with_wall_matches_oracle(fe_ctx, kind, form):
+    """One step with the wall model; on the hybrid cube with the full-stress
+    and EMAC operator variants as well."""
     fe = _fe()
     import torch
-    c = wall_case(meshgen.HEX08, 6, 2)
+    c = wall_case(kind, 6, 2)
     c.u *= 0.3
     # the wall nodes are free (the wall model sets their stress), the other
     # boundary nodes stay Dirichlet
@@ -97,14 +100,16 @@ def test_fractional_step_with_wall_matches_oracle(fe_ctx):
     L, f, _ = fe.assemble(mesh, fe.POISSON, dt, u, rho)
     fe.apply_dirichlet(mesh, L, f)
     p = torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda")
-    fe.fractional_step(mesh, dt, rho, to_mesh(mesh, c.mu), L[0].contiguous(), u, p, rtol=1e-12, max_iter=5000)
-    rp, ci, Lo, fo = oracle.assemble(c.coords, c.conn, oracle.OP_POISSON, dt, c.u, c.rho, None)
+    fe.fractional_step(mesh, dt, rho, to_mesh(mesh, c.mu), L[0].contiguous(), u, p, rtol=1e-12, max_iter=5000,
+                      form=form)
+    rp, ci, Lo, fo = oracle.assemble(c.coords, c.conn, oracle.OP_POISSON, dt, c.u, c.rho, None, types=c.types)
     Lo, fo = Lo[0].copy(), fo[0].copy()
     oracle.dirichlet(rp, ci, Lo, fo, c.dirichlet)
     un, pn, _ = oracle.fractional_step(c.coords, c.conn, c.dirichlet, dt, c.u, c.rho, c.mu, (rp, ci, Lo),
-                                       rtol=1e-12, wall=(c.wall_nen, c.wall_conn, delta))
+                                       rtol=1e-12, wall=(c.wall_nen, c.wall_conn, delta), types=c.types,
+                                       form=form)
     un0, _, _ = oracle.fractional_step(c.coords, c.conn, c.dirichlet, dt, c.u, c.rho, c.mu, (rp, ci, Lo),
-                                       rtol=1e-12)
+                                       rtol=1e-12, types=c.types, form=form)
     assert rel(un, un0) > 1e-8            # the wall term matters
     assert rel(to_user(mesh, p), pn) <= 1e-8
     assert rel(to_user(mesh, u), un) <= 1e-9
