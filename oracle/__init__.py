@@ -47,10 +47,10 @@ def lib():
         L.or_pattern_typed.argtypes = [i32, P, i64, i64, P, P, P]
         L.or_assemble.restype = i32
         L.or_assemble.argtypes = [i32, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
-                                  i32, C.POINTER(i64), C.POINTER(dbl)]
+                                  C.POINTER(i64), C.POINTER(dbl)]
         L.or_assemble_typed.restype = i32
         L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
-                                        i32, C.POINTER(i64), C.POINTER(dbl)]
+                                        C.POINTER(i64), C.POINTER(dbl)]
         L.or_element_vectors.restype = i32
         L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, dbl, P,
                                          C.POINTER(i64), C.POINTER(dbl)]
@@ -137,7 +137,7 @@ class AssembleError(RuntimeError):
 
 
 def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None, D=None,
-             pattern_=None, mixed: bool = False, types=None):
+             pattern_=None, types=None):
     """Return (rowptr, colidx, values[n_mat, nnz], rhs[n_rhs, N]).
 
     conn [E, stride]; types [E] per-element node counts for a mixed mesh
@@ -163,7 +163,7 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
     mdet = C.c_double(0.0)
     st = lib().or_assemble_typed(S, _p(types), N, _p(coords), conn.shape[0], _p(conn), op, dt, _p(u),
                                  _p(rho), _p(mu), ns, _p(Yp), _p(Dp), _p(rowptr), _p(colidx),
-                                 _p(values), _p(rhs), 1 if mixed else 0, C.byref(bad), C.byref(mdet))
+                                 _p(values), _p(rhs), C.byref(bad), C.byref(mdet))
     if st != OK:
         raise AssembleError(st, bad.value, mdet.value)
     return rowptr, colidx, values, rhs

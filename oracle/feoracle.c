@@ -390,10 +390,7 @@ static double geometry(int nen, double X[MAXN][3], double dNr[MAXN][3], double d
  *   M_ab = sum dV rho_g N_a N_b
  *   C_ab = sum dV rho_g N_a (u_g . grad N_b)
  *   K_ab = sum dV coef_g grad N_a . grad N_b.
- * mixed != 0 reproduces, for characterisation only, FP32 quadrature: the
- * Gauss-point inputs are rounded to float, the products and the elemental
- * sums are float, the elemental matrix is widened to double and assembled in
- * double.  Inputs: coords [N][3]; conn [E][stride], element e using its
+ * Inputs: coords [N][3]; conn [E][stride], element e using its
  * first elem_nen() slots; u [3][N]; rho, mu [N];
  * Y [k][N]; D [k].  Outputs are overwritten.  Returns OR_EBADELEM (with the
  * first element index and the smallest det J) for det J <= 0.
@@ -402,7 +399,7 @@ int or_assemble_typed(int stride, const uint8_t *types, int64_t n_nodes, const d
                       int64_t n_elems, const int32_t *conn, int op, double dt, const double *u,
                       const double *rho, const double *mu, int n_scalars, const double *Y,
                       const double *D, const int32_t *rowptr, const int32_t *colidx, double *values,
-                      double *rhs, int mixed, int64_t *bad_elem, double *min_det)
+                      double *rhs, int64_t *bad_elem, double *min_det)
 {
     /* reference tables of every element type, indexed by node count */
     double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], Nt[MAXN + 1][MAXG][MAXN],
@@ -433,8 +430,6 @@ int or_assemble_typed(int stride, const uint8_t *types, int64_t n_nodes, const d
 
         double M[MAXN][MAXN] = {{0}}, C[MAXN][MAXN] = {{0}}, K[MAXS][MAXN][MAXN] = {{{0}}};
         double B[MAXS][MAXN] = {{0}};
-        float Mf[MAXN][MAXN] = {{0}}, Cf[MAXN][MAXN] = {{0}}, Kf[MAXS][MAXN][MAXN] = {{{0}}};
-        float Bf[MAXS][MAXN] = {{0}};
 
         for (int g = 0; g < ng; ++g) {
             double dNx[MAXN][3];
@@ -455,80 +450,33 @@ int or_assemble_typed(int stride, const uint8_t *types, int64_t n_nodes, const d
                 if (op == OP_SCALAR)
                     for (int k = 0; k < n_scalars; ++k) yg[k] += Na * Y[(int64_t)k * n_nodes + c[a]];
             }
-            if (!mixed) {
-                for (int a = 0; a < nen; ++a) {
-                    double Na = Ng[g][a];
-                    for (int b = 0; b < nen; ++b) {
-                        double Nb = Ng[g][b];
-                        double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
-                        double ugb = ug[0] * dNx[b][0] + ug[1] * dNx[b][1] + ug[2] * dNx[b][2];
-                        if (op == OP_POISSON) {
-                            K[0][a][b] += dV * gg;
-                        } else {
-                            M[a][b] += dV * rg * Na * Nb;
-                            C[a][b] += dV * rg * Na * ugb;
-                            if (op == OP_MOMENTUM)
-                                K[0][a][b] += dV * mg * gg;
-                            else
-                                for (int k = 0; k < n_scalars; ++k) K[k][a][b] += dV * (rg * D[k]) * gg;
-                        }
+            for (int a = 0; a < nen; ++a) {
+                double Na = Ng[g][a];
+                for (int b = 0; b < nen; ++b) {
+                    double Nb = Ng[g][b];
+                    double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
+                    double ugb = ug[0] * dNx[b][0] + ug[1] * dNx[b][1] + ug[2] * dNx[b][2];
+                    if (op == OP_POISSON) {
+                        K[0][a][b] += dV * gg;
+                    } else {
+                        M[a][b] += dV * rg * Na * Nb;
+                        C[a][b] += dV * rg * Na * ugb;
+                        if (op == OP_MOMENTUM)
+                            K[0][a][b] += dV * mg * gg;
+                        else
+                            for (int k = 0; k < n_scalars; ++k) K[k][a][b] += dV * (rg * D[k]) * gg;
                     }
-                    if (op == OP_MOMENTUM)
-                        for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ug[i] / dt;
-                    else if (op == OP_SCALAR)
-                        for (int k = 0; k < n_scalars; ++k) B[k][a] += dV * rg * Na * yg[k] / dt;
-                    else
-                        B[0][a] += (1.0 / dt) * dV *
-                                   (dNx[a][0] * (rg * ug[0]) + dNx[a][1] * (rg * ug[1]) + dNx[a][2] * (rg * ug[2]));
                 }
-            } else {
-                float fdV = (float)dV, frg = (float)rg, fmg = (float)mg, fdt = (float)dt;
-                float fug[3] = {(float)ug[0], (float)ug[1], (float)ug[2]};
-                float fyg[MAXS];
-                for (int k = 0; k < n_scalars; ++k) fyg[k] = (float)yg[k];
-                float fN[MAXN], fdN[MAXN][3];
-                for (int a = 0; a < nen; ++a) {
-                    fN[a] = (float)Ng[g][a];
-                    for (int i = 0; i < 3; ++i) fdN[a][i] = (float)dNx[a][i];
-                }
-                for (int a = 0; a < nen; ++a) {
-                    for (int b = 0; b < nen; ++b) {
-                        float gg = fdN[a][0] * fdN[b][0] + fdN[a][1] * fdN[b][1] + fdN[a][2] * fdN[b][2];
-                        float ugb = fug[0] * fdN[b][0] + fug[1] * fdN[b][1] + fug[2] * fdN[b][2];
-                        if (op == OP_POISSON) {
-                            Kf[0][a][b] += fdV * gg;
-                        } else {
-                            Mf[a][b] += fdV * frg * fN[a] * fN[b];
-                            Cf[a][b] += fdV * frg * fN[a] * ugb;
-                            if (op == OP_MOMENTUM)
-                                Kf[0][a][b] += fdV * fmg * gg;
-                            else
-                                for (int k = 0; k < n_scalars; ++k)
-                                    Kf[k][a][b] += fdV * (frg * (float)D[k]) * gg;
-                        }
-                    }
-                    if (op == OP_MOMENTUM)
-                        for (int i = 0; i < 3; ++i) Bf[i][a] += fdV * frg * fN[a] * fug[i] / fdt;
-                    else if (op == OP_SCALAR)
-                        for (int k = 0; k < n_scalars; ++k) Bf[k][a] += fdV * frg * fN[a] * fyg[k] / fdt;
-                    else
-                        Bf[0][a] += (1.0f / fdt) * fdV *
-                                    (fdN[a][0] * (frg * fug[0]) + fdN[a][1] * (frg * fug[1]) +
-                                     fdN[a][2] * (frg * fug[2]));
-                }
+                if (op == OP_MOMENTUM)
+                    for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ug[i] / dt;
+                else if (op == OP_SCALAR)
+                    for (int k = 0; k < n_scalars; ++k) B[k][a] += dV * rg * Na * yg[k] / dt;
+                else
+                    B[0][a] += (1.0 / dt) * dV *
+                               (dNx[a][0] * (rg * ug[0]) + dNx[a][1] * (rg * ug[1]) + dNx[a][2] * (rg * ug[2]));
             }
         }
         if (status != OR_OK) continue;
-        if (mixed) {
-            for (int a = 0; a < nen; ++a) {
-                for (int b = 0; b < nen; ++b) {
-                    M[a][b] = Mf[a][b];
-                    C[a][b] = Cf[a][b];
-                    for (int k = 0; k < n_mat; ++k) K[k][a][b] = Kf[k][a][b];
-                }
-                for (int k = 0; k < n_rhs; ++k) B[k][a] = Bf[k][a];
-            }
-        }
         /* A_e = M/dt + C + K (momentum, scalar) or L (Poisson); scatter. */
         for (int a = 0; a < nen; ++a) {
             for (int b = 0; b < nen; ++b) {
@@ -550,10 +498,10 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
                 const int32_t *conn, int op, double dt, const double *u, const double *rho,
                 const double *mu, int n_scalars, const double *Y, const double *D,
                 const int32_t *rowptr, const int32_t *colidx, double *values, double *rhs,
-                int mixed, int64_t *bad_elem, double *min_det)
+                int64_t *bad_elem, double *min_det)
 {
     return or_assemble_typed(nen, NULL, n_nodes, coords, n_elems, conn, op, dt, u, rho, mu,
-                             n_scalars, Y, D, rowptr, colidx, values, rhs, mixed, bad_elem, min_det);
+                             n_scalars, Y, D, rowptr, colidx, values, rhs, bad_elem, min_det);
 }
 
 /* ------------------------------------------------------------------ */

@@ -47,9 +47,9 @@ def gpu_assemble(ctx, case, op, precision=0, renumber=True, mesh=None):
     return mesh, host(v), host(b), info
 
 
-def oracle_assemble(case, op, mixed=False):
+def oracle_assemble(case, op):
     kw = {"Y": case.Y, "D": case.D} if op == SCA else {}
-    return oracle.assemble(case.coords, case.conn, op, case.dt, case.u, case.rho, case.mu, mixed=mixed, **kw)
+    return oracle.assemble(case.coords, case.conn, op, case.dt, case.u, case.rho, case.mu, **kw)
 
 
 def check_parity(mesh, case, op, v, b, tol=TOL):

@@ -461,13 +461,3 @@ def test_poisson_manufactured_solution_second_order(jitter):
         errs.append(np.sqrt(np.mean((x - p) ** 2)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - 2.0) < 0.25), rates
-
-
-def test_mixed_emulation_is_close_to_fp64():
-    # characterisation only (no closed form): FP32 quadrature vs FP64
-    case = meshgen.cfg0()
-    _, _, V, b = oracle.assemble(case.coords, case.conn, MOM, case.dt, case.u, case.rho, case.mu)
-    _, _, Vm, bm = oracle.assemble(case.coords, case.conn, MOM, case.dt, case.u, case.rho, case.mu, mixed=True)
-    ev = np.linalg.norm(Vm - V) / np.linalg.norm(V)
-    eb = np.linalg.norm(bm - b) / np.linalg.norm(b)
-    assert 1e-10 < ev < 1e-5 and 1e-10 < eb < 1e-5
