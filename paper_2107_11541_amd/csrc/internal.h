@@ -128,7 +128,8 @@ struct CGWork {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
     double *part = nullptr;              // partial sums (kPartDoubles)
     double *hist = nullptr;              // [cap][4] per-iteration scalars
-    int32_t *flags = nullptr;            // [4]: done, status, iterations, spare
+    int32_t *flags = nullptr;            // [4]: stop word (0 running, else completed iterations + 1), status,
+                                         // iterations, iteration counter
     int hist_cap = 0;
     // mixed precision buffers
     float *v32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *x32 = nullptr,

@@ -70,14 +70,32 @@ __device__ inline int load_flag(const int32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The done flag, read once per work-group so that every thread of the group
-// takes the same branch (the flag may be set by another group meanwhile).
-__device__ inline bool wg_done(const int32_t *flags)
+// The stop word flags[0]: 0 while the solve runs; once it stops, the number
+// of iterations completed when the stop was decided, plus one (1 = converged
+// at set-up).  It is read once per work-group so that every thread of the
+// group takes the same branch (another group may store it meanwhile).
+__device__ inline int wg_stop_word(const int32_t *flags)
 {
     __shared__ int f;
     if (threadIdx.x == 0) f = load_flag(flags);
     __syncthreads();
-    return f != 0;
+    return f;
+}
+
+// Nothing in the SpMV launch stores the stop word, and a store in the x/r/z
+// update launch is a breakdown that every group of it detects itself, so for
+// those two any stop counts.
+__device__ inline bool wg_done(const int32_t *flags) { return wg_stop_word(flags) != 0; }
+
+// The p update of iteration k: a stop decided before it (word <= k + 1)
+// ends it, but not the convergence found in this same launch (word k + 2,
+// stored by group 0 while the other groups may not have started): every
+// group finds that convergence from the same reduced r.r and must still
+// apply x += alpha_k p_k.
+__device__ inline bool wg_stopped_before(const int32_t *flags, int k)
+{
+    const int f = wg_stop_word(flags);
+    return f != 0 && f <= k + 1;
 }
 
 __device__ inline void store_flag(int32_t *p, int v)
@@ -507,7 +525,8 @@ __global__ void __launch_bounds__(kTB) k_permute(int64_t n, int ncomp, const int
 }
 
 // ---- PCG ---------------------------------------------------------------------
-// hist[k*4 + 0..3] = rz_k, rr_k, pq_k, alpha_k ;  flags = {done, status, iters, -}
+// hist[k*4 + 0..3] = rz_k, rr_k, pq_k, alpha_k ;  flags = {stop word (wg_stop_word), status, iters,
+// iteration counter}
 // part layout: [0] p.q, [1] r.z, [2] r.r, [3] b.b  (each nb doubles)
 
 template <class T>
@@ -563,7 +582,7 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
         scal[0] = bb;
         const double thr2 = rtol > 0.0 ? rtol * rtol * bb : -1.0;
         scal[1] = thr2;
-        flags[0] = (rr <= thr2) ? 1 : 0;
+        flags[0] = (rr <= thr2) ? 1 : 0;   // stop word: converged with 0 iterations
         flags[1] = FE_OK;
         flags[2] = 0;
         flags[3] = -1;   // iteration counter: each SpMV launch advances it
@@ -622,7 +641,7 @@ __device__ inline void cg_update_xr_step(int64_t n, int k, T *r, T *z, const T *
         if (wg == 0 && threadIdx.x == 0) {
             store_flag(flags + 1, FE_EBREAKDOWN);
             store_flag(flags + 2, k);
-            store_flag(flags + 0, 1);
+            store_flag(flags + 0, k + 1);   // k iterations completed
         }
         return;
     }
@@ -685,7 +704,7 @@ __device__ inline void cg_update_p_step(int64_t n, int k, T *x, const T *z, T *p
         pv = ((const T2 *)p)[j0];
         xv = ((const T2 *)x)[j0];
     }
-    if (wg_done(flags)) return;
+    if (wg_stopped_before(flags, k)) return;
     const double rz1 = reduce_parts(part + kPartRZ, nb, sh);
     const double rr = reduce_parts(part + kPartRR, nb, sh);
     const bool conv = rr <= scal[1];
@@ -693,7 +712,7 @@ __device__ inline void cg_update_p_step(int64_t n, int k, T *x, const T *z, T *p
         hist[(int64_t)(k + 1) * 4 + 0] = rz1;
         hist[(int64_t)(k + 1) * 4 + 1] = rr;
         store_flag(flags + 2, k + 1);
-        if (conv) store_flag(flags + 0, 1);
+        if (conv) store_flag(flags + 0, k + 2);   // k + 1 iterations completed
     }
     const T a = T(hist[(int64_t)k * 4 + 3]);
     const T beta = T(rz1 / hist[(int64_t)k * 4 + 0]);
