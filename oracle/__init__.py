@@ -25,11 +25,14 @@ _lib = None
 
 
 def build() -> str:
-    """Compile liboracle.so with gcc (serial, -ffp-contract=off)."""
+    """Compile liboracle.so with gcc (serial, -ffp-contract=off), and the
+    all-core timing build liboracle_omp.so (oracle/omp.py)."""
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
                            "-std=c99", "-o", tmp, SRC, "-lm"])
     os.replace(tmp, LIB)
+    from . import omp
+    omp.build()
     return LIB
 
 
@@ -50,6 +53,9 @@ def lib():
                                   C.POINTER(i64), C.POINTER(dbl)]
         L.or_assemble_typed.restype = i32
         L.or_assemble_typed.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, i32, P, P, P, P, P, P,
+                                        C.POINTER(i64), C.POINTER(dbl)]
+        L.or_assemble_block.restype = i32
+        L.or_assemble_block.argtypes = [i32, P, i64, P, i64, P, i32, dbl, P, P, P, P, P, P, P,
                                         C.POINTER(i64), C.POINTER(dbl)]
         L.or_element_vectors.restype = i32
         L.or_element_vectors.argtypes = [i32, P, i64, P, i64, P, i32, i32, P, P, P, P, P, dbl, P,
@@ -170,6 +176,29 @@ def assemble(coords, conn, op: int, dt: float, u=None, rho=None, mu=None, Y=None
 
 
 FULL_STRESS, EMAC = 1, 2    # residual operator variants (bits of `form`)
+
+
+def assemble_block(coords, conn, form: int, dt: float, u, rho, mu, pattern_=None, types=None):
+    """Momentum operator with 3x3 blocks (full-stress viscous term with form
+    bit FULL_STRESS, EMAC's (div u) term with EMAC; or_assemble_block).
+    Returns (rowptr, colidx, values[nnz, 3, 3], rhs[3, N])."""
+    coords = _f64(coords)
+    conn = _i32(conn)
+    types = _u8(types)
+    N = coords.shape[0]
+    rowptr, colidx = pattern_ if pattern_ is not None else pattern(conn, N, types)
+    nnz = int(rowptr[-1])
+    u, rho, mu = _f64(u), _f64(rho), _f64(mu)
+    values = np.zeros((nnz, 3, 3))
+    rhs = np.zeros((3, N))
+    bad = C.c_int64(-1)
+    mdet = C.c_double(0.0)
+    st = lib().or_assemble_block(conn.shape[1], _p(types), N, _p(coords), conn.shape[0], _p(conn), int(form), dt,
+                                 _p(u), _p(rho), _p(mu), _p(rowptr), _p(colidx), _p(values), _p(rhs),
+                                 C.byref(bad), C.byref(mdet))
+    if st != OK:
+        raise AssembleError(st, bad.value, mdet.value)
+    return rowptr, colidx, values, rhs
 
 
 def _element_vectors(coords, conn, kind, u=None, rho=None, mu=None, p=None, types=None, form=0, Y=None, D=0.0):

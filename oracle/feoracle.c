@@ -395,100 +395,173 @@ static double geometry(int nen, double X[MAXN][3], double dNr[MAXN][3], double d
  * Y [k][N]; D [k].  Outputs are overwritten.  Returns OR_EBADELEM (with the
  * first element index and the smallest det J) for det J <= 0.
  */
+/* Reference tables of every element type, indexed by node count. */
+typedef struct {
+    double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], N[MAXN + 1][MAXG][MAXN], dN[MAXN + 1][MAXG][MAXN][3];
+    int ng[MAXN + 1];
+} RefSet;
+
+static void ref_set(RefSet *R)
+{
+    for (int t = 0; t <= MAXN; ++t) R->ng[t] = ref_element(t, R->pts[t], R->w[t], R->N[t], R->dN[t]);
+}
+
+/* Operator of one assembly call: fields and sizes. */
+typedef struct {
+    int stride;
+    const uint8_t *types;
+    int64_t n_nodes;
+    const double *coords;
+    const int32_t *conn;
+    int op;
+    double dt;
+    const double *u, *rho, *mu, *Y, *D;
+    int n_scalars, n_mat, n_rhs;
+} AsmOp;
+
+/* Elemental matrices and right-hand sides of element e: the Gauss loop
+ * accumulating M, C, K (one per scalar) and B.  *min_det takes the
+ * smallest det J met; returns OR_EBADELEM at the first det J <= 0. */
+static int element_terms(const RefSet *R, const AsmOp *A, int64_t e, double M[MAXN][MAXN], double Cm[MAXN][MAXN],
+                         double K[MAXS][MAXN][MAXN], double B[MAXS][MAXN], double *min_det)
+{
+    const int op = A->op, n_scalars = A->n_scalars;
+    const int64_t n_nodes = A->n_nodes;
+    const double dt = A->dt, *u = A->u, *rho = A->rho, *mu = A->mu, *Y = A->Y, *D = A->D;
+    const int nen = elem_nen(A->stride, A->types, e), ng = R->ng[nen];
+    const double (*Ng)[MAXN] = R->N[nen];
+    const double (*dNr)[MAXN][3] = R->dN[nen];
+    const double *wg = R->w[nen];
+    const int32_t *c = A->conn + e * A->stride;
+    double X[MAXN][3];
+    for (int a = 0; a < nen; ++a)
+        for (int i = 0; i < 3; ++i) X[a][i] = A->coords[(int64_t)c[a] * 3 + i];
+    memset(M, 0, sizeof(double) * MAXN * MAXN);
+    memset(Cm, 0, sizeof(double) * MAXN * MAXN);
+    memset(K, 0, sizeof(double) * MAXS * MAXN * MAXN);
+    memset(B, 0, sizeof(double) * MAXS * MAXN);
+
+    for (int g = 0; g < ng; ++g) {
+        double dNx[MAXN][3];
+        double det = geometry(nen, X, (double (*)[3])dNr[g], dNx);
+        if (det < *min_det) *min_det = det;
+        if (!(det > 0.0)) return OR_EBADELEM;
+        double dV = wg[g] * det;
+        double rg = 0.0, mg = 0.0, ug[3] = {0.0, 0.0, 0.0}, yg[MAXS] = {0};
+        for (int a = 0; a < nen; ++a) {
+            double Na = Ng[g][a];
+            rg += Na * rho[c[a]];
+            if (op == OP_MOMENTUM) mg += Na * mu[c[a]];
+            for (int i = 0; i < 3; ++i) ug[i] += Na * u[(int64_t)i * n_nodes + c[a]];
+            if (op == OP_SCALAR)
+                for (int k = 0; k < n_scalars; ++k) yg[k] += Na * Y[(int64_t)k * n_nodes + c[a]];
+        }
+        for (int a = 0; a < nen; ++a) {
+            double Na = Ng[g][a];
+            for (int b = 0; b < nen; ++b) {
+                double Nb = Ng[g][b];
+                double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
+                double ugb = ug[0] * dNx[b][0] + ug[1] * dNx[b][1] + ug[2] * dNx[b][2];
+                if (op == OP_POISSON) {
+                    K[0][a][b] += dV * gg;
+                } else {
+                    M[a][b] += dV * rg * Na * Nb;
+                    Cm[a][b] += dV * rg * Na * ugb;
+                    if (op == OP_MOMENTUM)
+                        K[0][a][b] += dV * mg * gg;
+                    else
+                        for (int k = 0; k < n_scalars; ++k) K[k][a][b] += dV * (rg * D[k]) * gg;
+                }
+            }
+            if (op == OP_MOMENTUM)
+                for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ug[i] / dt;
+            else if (op == OP_SCALAR)
+                for (int k = 0; k < n_scalars; ++k) B[k][a] += dV * rg * Na * yg[k] / dt;
+            else
+                B[0][a] += (1.0 / dt) * dV *
+                           (dNx[a][0] * (rg * ug[0]) + dNx[a][1] * (rg * ug[1]) + dNx[a][2] * (rg * ug[2]));
+        }
+    }
+    return OR_OK;
+}
+
+/* A_e = M/dt + C + K (momentum, scalar) or L (Poisson), and B, added into
+ * the CSR rows and right-hand sides of element e's nodes. */
+static int element_scatter(const AsmOp *A, int64_t e, const int32_t *rowptr, const int32_t *colidx,
+                           double M[MAXN][MAXN], double Cm[MAXN][MAXN], double K[MAXS][MAXN][MAXN],
+                           double B[MAXS][MAXN], double *values, double *rhs)
+{
+    const int nen = elem_nen(A->stride, A->types, e);
+    const int32_t *c = A->conn + e * A->stride;
+    const int64_t nnz = rowptr[A->n_nodes], n_nodes = A->n_nodes;
+    for (int a = 0; a < nen; ++a) {
+        for (int b = 0; b < nen; ++b) {
+            int64_t pos = find_col(rowptr, colidx, c[a], c[b]);
+            if (pos < 0) return OR_EINVAL;
+            for (int k = 0; k < A->n_mat; ++k) {
+                double v = (A->op == OP_POISSON) ? K[0][a][b] : (M[a][b] / A->dt + Cm[a][b] + K[k][a][b]);
+                values[(int64_t)k * nnz + pos] += v;
+            }
+        }
+        for (int k = 0; k < A->n_rhs; ++k) rhs[(int64_t)k * n_nodes + c[a]] += B[k][a];
+    }
+    return OR_OK;
+}
+
+/* Checks the arguments, fills *A and zeroes the outputs. */
+static int asm_begin(AsmOp *A, int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
+                     int64_t n_elems, const int32_t *conn, int op, double dt, const double *u, const double *rho,
+                     const double *mu, int n_scalars, const double *Y, const double *D, const int32_t *rowptr,
+                     double *values, double *rhs)
+{
+    for (int64_t e = 0; e < n_elems; ++e)
+        if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
+    if (op == OP_SCALAR && (n_scalars < 1 || n_scalars > MAXS)) return OR_EINVAL;
+    A->stride = stride;
+    A->types = types;
+    A->n_nodes = n_nodes;
+    A->coords = coords;
+    A->conn = conn;
+    A->op = op;
+    A->dt = dt;
+    A->u = u;
+    A->rho = rho;
+    A->mu = mu;
+    A->Y = Y;
+    A->D = D;
+    A->n_scalars = n_scalars;
+    A->n_mat = (op == OP_SCALAR) ? n_scalars : 1;
+    A->n_rhs = (op == OP_MOMENTUM) ? 3 : (op == OP_SCALAR ? n_scalars : 1);
+    int64_t nnz = rowptr[n_nodes];
+    memset(values, 0, sizeof(double) * (size_t)(nnz * A->n_mat));
+    memset(rhs, 0, sizeof(double) * (size_t)(n_nodes * A->n_rhs));
+    return OR_OK;
+}
+
 int or_assemble_typed(int stride, const uint8_t *types, int64_t n_nodes, const double *coords,
                       int64_t n_elems, const int32_t *conn, int op, double dt, const double *u,
                       const double *rho, const double *mu, int n_scalars, const double *Y,
                       const double *D, const int32_t *rowptr, const int32_t *colidx, double *values,
                       double *rhs, int64_t *bad_elem, double *min_det)
 {
-    /* reference tables of every element type, indexed by node count */
-    double pts[MAXN + 1][MAXG][3], w[MAXN + 1][MAXG], Nt[MAXN + 1][MAXG][MAXN],
-        dNt[MAXN + 1][MAXG][MAXN][3];
-    int ngt[MAXN + 1];
-    for (int t = 0; t <= MAXN; ++t) ngt[t] = ref_element(t, pts[t], w[t], Nt[t], dNt[t]);
-    for (int64_t e = 0; e < n_elems; ++e)
-        if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
-    if (op == OP_SCALAR && (n_scalars < 1 || n_scalars > MAXS)) return OR_EINVAL;
-    int n_mat = (op == OP_SCALAR) ? n_scalars : 1;
-    int n_rhs = (op == OP_MOMENTUM) ? 3 : (op == OP_SCALAR ? n_scalars : 1);
-    int64_t nnz = rowptr[n_nodes];
-    memset(values, 0, sizeof(double) * (size_t)(nnz * n_mat));
-    memset(rhs, 0, sizeof(double) * (size_t)(n_nodes * n_rhs));
+    static RefSet R;   /* large: kept off the stack */
+    ref_set(&R);
+    AsmOp A;
+    int st = asm_begin(&A, stride, types, n_nodes, coords, n_elems, conn, op, dt, u, rho, mu, n_scalars, Y, D,
+                       rowptr, values, rhs);
+    if (st != OR_OK) return st;
     *bad_elem = -1;
     *min_det = INFINITY;
     int status = OR_OK;
-
+    double M[MAXN][MAXN], Cm[MAXN][MAXN], K[MAXS][MAXN][MAXN], B[MAXS][MAXN];
+    /* element order: the outer loop of Listing 1 */
     for (int64_t e = 0; e < n_elems; ++e) {
-        const int nen = elem_nen(stride, types, e), ng = ngt[nen];
-        double (*Ng)[MAXN] = Nt[nen];
-        double (*dNr)[MAXN][3] = dNt[nen];
-        const double *wg = w[nen];
-        const int32_t *c = conn + e * stride;
-        double X[MAXN][3];
-        for (int a = 0; a < nen; ++a)
-            for (int i = 0; i < 3; ++i) X[a][i] = coords[(int64_t)c[a] * 3 + i];
-
-        double M[MAXN][MAXN] = {{0}}, C[MAXN][MAXN] = {{0}}, K[MAXS][MAXN][MAXN] = {{{0}}};
-        double B[MAXS][MAXN] = {{0}};
-
-        for (int g = 0; g < ng; ++g) {
-            double dNx[MAXN][3];
-            double det = geometry(nen, X, dNr[g], dNx);
-            if (det < *min_det) *min_det = det;
-            if (!(det > 0.0)) {
-                if (*bad_elem < 0) *bad_elem = e;
-                status = OR_EBADELEM;
-                break;
-            }
-            double dV = wg[g] * det;
-            double rg = 0.0, mg = 0.0, ug[3] = {0.0, 0.0, 0.0}, yg[MAXS] = {0};
-            for (int a = 0; a < nen; ++a) {
-                double Na = Ng[g][a];
-                rg += Na * rho[c[a]];
-                if (op == OP_MOMENTUM) mg += Na * mu[c[a]];
-                for (int i = 0; i < 3; ++i) ug[i] += Na * u[(int64_t)i * n_nodes + c[a]];
-                if (op == OP_SCALAR)
-                    for (int k = 0; k < n_scalars; ++k) yg[k] += Na * Y[(int64_t)k * n_nodes + c[a]];
-            }
-            for (int a = 0; a < nen; ++a) {
-                double Na = Ng[g][a];
-                for (int b = 0; b < nen; ++b) {
-                    double Nb = Ng[g][b];
-                    double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
-                    double ugb = ug[0] * dNx[b][0] + ug[1] * dNx[b][1] + ug[2] * dNx[b][2];
-                    if (op == OP_POISSON) {
-                        K[0][a][b] += dV * gg;
-                    } else {
-                        M[a][b] += dV * rg * Na * Nb;
-                        C[a][b] += dV * rg * Na * ugb;
-                        if (op == OP_MOMENTUM)
-                            K[0][a][b] += dV * mg * gg;
-                        else
-                            for (int k = 0; k < n_scalars; ++k) K[k][a][b] += dV * (rg * D[k]) * gg;
-                    }
-                }
-                if (op == OP_MOMENTUM)
-                    for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ug[i] / dt;
-                else if (op == OP_SCALAR)
-                    for (int k = 0; k < n_scalars; ++k) B[k][a] += dV * rg * Na * yg[k] / dt;
-                else
-                    B[0][a] += (1.0 / dt) * dV *
-                               (dNx[a][0] * (rg * ug[0]) + dNx[a][1] * (rg * ug[1]) + dNx[a][2] * (rg * ug[2]));
-            }
+        if (element_terms(&R, &A, e, M, Cm, K, B, min_det) != OR_OK) {
+            if (*bad_elem < 0) *bad_elem = e;
+            status = OR_EBADELEM;
+            continue;
         }
-        if (status != OR_OK) continue;
-        /* A_e = M/dt + C + K (momentum, scalar) or L (Poisson); scatter. */
-        for (int a = 0; a < nen; ++a) {
-            for (int b = 0; b < nen; ++b) {
-                int64_t pos = find_col(rowptr, colidx, c[a], c[b]);
-                if (pos < 0) return OR_EINVAL;
-                for (int k = 0; k < n_mat; ++k) {
-                    double v = (op == OP_POISSON) ? K[0][a][b] : (M[a][b] / dt + C[a][b] + K[k][a][b]);
-                    values[(int64_t)k * nnz + pos] += v;
-                }
-            }
-            for (int k = 0; k < n_rhs; ++k) rhs[(int64_t)k * n_nodes + c[a]] += B[k][a];
-        }
+        if (element_scatter(&A, e, rowptr, colidx, M, Cm, K, B, values, rhs) != OR_OK) return OR_EINVAL;
     }
     return status;
 }
@@ -502,6 +575,110 @@ int or_assemble(int nen, int64_t n_nodes, const double *coords, int64_t n_elems,
 {
     return or_assemble_typed(nen, NULL, n_nodes, coords, n_elems, conn, op, dt, u, rho, mu,
                              n_scalars, Y, D, rowptr, colidx, values, rhs, bad_elem, min_det);
+}
+
+/* ------------------------------------------------------------------ */
+/* Momentum operator with the full-stress viscous term: 3x3 blocks     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The implicit momentum operator of Eq. (1) with its viscous term in the
+ * full-stress form -div(2 mu eps(u)) and, optionally, the EMAC convective
+ * form, linearised about the nodal velocity a = u (Picard).  Testing
+ * 2 mu eps(u) with N_a e_i couples the components: row (a, i), column
+ * (b, k) of the block matrix is
+ *
+ *   delta_ik (M_ab / dt + C_ab + K_ab + E_ab) + T_ab[i][k],
+ *
+ *   M_ab = sum_g dV rho_g N_a N_b,   C_ab = sum_g dV rho_g N_a (a_g . grad N_b),
+ *   K_ab = sum_g dV mu_g grad N_a . grad N_b            (Laplacian part),
+ *   T_ab[i][k] = sum_g dV mu_g (d N_a / d x_k)(d N_b / d x_i)   (form bit 0),
+ *   E_ab = sum_g dV rho_g (div a)_g N_a N_b                     (form bit 1:
+ *          EMAC's (div u) u term at the Gauss point, with u frozen as a);
+ *
+ * T and E are left out when their bit is clear (form 0 is the scalar
+ * momentum operator of or_assemble times the 3x3 identity).  values[nnz][3][3]
+ * on the canonical scalar pattern (block (i, k) of entry p at p * 9 + 3i + k),
+ * rhs[3][N] = M_rho u_i / dt as for or_assemble.  With b the rhs, b - A u is
+ * the matrix-free residual of or_element_vectors (kind 0, same form).
+ */
+int or_assemble_block(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
+                      const int32_t *conn, int form, double dt, const double *u, const double *rho,
+                      const double *mu, const int32_t *rowptr, const int32_t *colidx, double *values, double *rhs,
+                      int64_t *bad_elem, double *min_det)
+{
+    static RefSet R;
+    ref_set(&R);
+    for (int64_t e = 0; e < n_elems; ++e)
+        if (!valid_nen(elem_nen(stride, types, e), stride)) return OR_EINVAL;
+    if (form & ~3) return OR_EINVAL;
+    const int64_t nnz = rowptr[n_nodes];
+    memset(values, 0, sizeof(double) * (size_t)(9 * nnz));
+    memset(rhs, 0, sizeof(double) * (size_t)(3 * n_nodes));
+    *bad_elem = -1;
+    *min_det = INFINITY;
+    int status = OR_OK;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        const int nen = elem_nen(stride, types, e), ng = R.ng[nen];
+        const int32_t *c = conn + e * stride;
+        double X[MAXN][3];
+        for (int a = 0; a < nen; ++a)
+            for (int i = 0; i < 3; ++i) X[a][i] = coords[(int64_t)c[a] * 3 + i];
+        double S[MAXN][MAXN] = {{0}}, T[MAXN][MAXN][3][3] = {{{{0}}}}, B[3][MAXN] = {{0}};
+        int bad = 0;
+        for (int g = 0; g < ng && !bad; ++g) {
+            double dNx[MAXN][3];
+            double det = geometry(nen, X, R.dN[nen][g], dNx);
+            if (det < *min_det) *min_det = det;
+            if (!(det > 0.0)) {
+                bad = 1;
+                break;
+            }
+            const double dV = R.w[nen][g] * det;
+            double rg = 0.0, mg = 0.0, ag[3] = {0.0, 0.0, 0.0}, diva = 0.0;
+            for (int b = 0; b < nen; ++b) {
+                const double Nb = R.N[nen][g][b];
+                rg += Nb * rho[c[b]];
+                mg += Nb * mu[c[b]];
+                for (int i = 0; i < 3; ++i) {
+                    const double ub = u[(int64_t)i * n_nodes + c[b]];
+                    ag[i] += Nb * ub;
+                    diva += dNx[b][i] * ub;
+                }
+            }
+            for (int a = 0; a < nen; ++a) {
+                const double Na = R.N[nen][g][a];
+                for (int b = 0; b < nen; ++b) {
+                    const double Nb = R.N[nen][g][b];
+                    const double gg = dNx[a][0] * dNx[b][0] + dNx[a][1] * dNx[b][1] + dNx[a][2] * dNx[b][2];
+                    const double agb = ag[0] * dNx[b][0] + ag[1] * dNx[b][1] + ag[2] * dNx[b][2];
+                    /* M / dt + C + K (+ E) */
+                    double s = dV * rg * Na * Nb / dt + dV * rg * Na * agb + dV * mg * gg;
+                    if (form & 2) s += dV * rg * diva * Na * Nb;
+                    S[a][b] += s;
+                    if (form & 1)
+                        for (int i = 0; i < 3; ++i)
+                            for (int k = 0; k < 3; ++k) T[a][b][i][k] += dV * mg * dNx[a][k] * dNx[b][i];
+                }
+                for (int i = 0; i < 3; ++i) B[i][a] += dV * rg * Na * ag[i] / dt;
+            }
+        }
+        if (bad) {
+            if (*bad_elem < 0) *bad_elem = e;
+            status = OR_EBADELEM;
+            continue;
+        }
+        for (int a = 0; a < nen; ++a) {
+            for (int b = 0; b < nen; ++b) {
+                const int64_t pos = find_col(rowptr, colidx, c[a], c[b]);
+                if (pos < 0) return OR_EINVAL;
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) values[pos * 9 + 3 * i + k] += (i == k ? S[a][b] : 0.0) + T[a][b][i][k];
+            }
+            for (int i = 0; i < 3; ++i) rhs[(int64_t)i * n_nodes + c[a]] += B[i][a];
+        }
+    }
+    return status;
 }
 
 /* ------------------------------------------------------------------ */
