@@ -12,7 +12,15 @@ fields are resident in HBM before timing starts.
 Prints one JSON line: value = elements per second of the whole step (Melem/s),
 plus the SpMV roofline (HEX08 SpMV is the dominant kernel: 200 launches per
 step) measured with HIP events on the library's stream, and the CPU oracle
-timed on a bounded sample of the same recipe.
+timed on a bounded sample of the same recipe (one thread and every thread).
+After the timed step, the same run measures the metric's second half and the
+large single mesh, each outside the timed region:
+  serving: the first 400 requests of the serving stream (HEX08 cubes of side
+           8..96, log-uniform; momentum + Poisson assembly + PCG to a true
+           relative residual of 1e-8), sequential FP64 against the batching
+           server, saturated and at 0.8x the sequential capacity;
+  cfg4:    256^3 HEX08 with 5 species: 8 equations assembled, and the Poisson
+           solve to 1e-8 by FP64 PCG and by FP32 PCG in FP64 refinement.
 """
 from __future__ import annotations
 
@@ -141,6 +149,20 @@ def measured_traffic(workload):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def roofline_entry(workload, algo_bytes, avg_us, launches):
+    """The dominant kernel against the HBM roofline: achieved = its
+    algorithmic bytes per launch over its average launch time; beside it the
+    real HBM rate, the counted bytes per launch over the same time, while the
+    counters describe the kernel as built (else null)."""
+    achieved = algo_bytes / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(workload)
+    real = traffic / (avg_us * 1e-6) / 1e9 if traffic else None
+    return {"bound": "hbm", "kernel": "k_cg_spmv_pq (CSR SpMV fused with p.Ap)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "real_hbm_gbs": real, "real_frac": real / HBM_PEAK_GBS if real else None,
+            "algorithmic_bytes_per_launch": algo_bytes, "avg_launch_us": avg_us, "launches": launches}
+
+
 def make_workload(name):
     import meshgen
     if name == "hex128":
@@ -155,54 +177,86 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_cpu():
+    """CPU model and logical core count of this host."""
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(sample_n: int, workload: str = "hex128"):
-    """The oracle, as is, on the same recipe at sample_n^3 (bounded CPU time)."""
+    """The oracle, as is, on the same recipe at sample_n^3 (bounded CPU time):
+    the serial parity build on one thread, then the all-core timing build
+    (elements in colour order, PCG kernels over rows) on every thread it gets
+    (OMP_NUM_THREADS, else every core).  value = the all-core rate."""
     import meshgen
     import oracle
+    from oracle import omp
     recipe = {"hex128": (meshgen.cfg1, "hex08-"), "hex64": (meshgen.cfg1, "hex08-"),
               "tet128": (meshgen.cfg2, "tet04-6x"), "hybrid128": (meshgen.hybrid, "hybrid-")}
     make, label = recipe[workload]
     case = make(sample_n)
     ty = case.types
     pat = oracle.pattern(case.conn, case.n_nodes, ty)
-    t0 = time.perf_counter()
-    rp, ci, V, B = oracle.assemble(case.coords, case.conn, oracle.OP_MOMENTUM, case.dt, case.u, case.rho, case.mu,
-                                   pattern_=pat, types=ty)
-    t1 = time.perf_counter()
-    rp, ci, L, f = oracle.assemble(case.coords, case.conn, oracle.OP_POISSON, case.dt, case.u, case.rho, None,
-                                   pattern_=pat, types=ty)
-    L, f = L[0], f[0]
-    oracle.dirichlet(rp, ci, L, f, case.dirichlet)
-    t2 = time.perf_counter()
-    oracle.pcg(rp, ci, L, f, rtol=0.0, max_iter=CG_ITERS)
-    t3 = time.perf_counter()
-    total = t3 - t0
+
+    def run(mod, **kw):
+        t0 = time.perf_counter()
+        rp, ci, V, B = mod.assemble(case.coords, case.conn, oracle.OP_MOMENTUM, case.dt, case.u, case.rho, case.mu,
+                                    pattern_=pat, types=ty, **kw)
+        t1 = time.perf_counter()
+        rp, ci, L, f = mod.assemble(case.coords, case.conn, oracle.OP_POISSON, case.dt, case.u, case.rho, None,
+                                    pattern_=pat, types=ty, **kw)
+        L, f = L[0], f[0]
+        mod.dirichlet(rp, ci, L, f, case.dirichlet)
+        t2 = time.perf_counter()
+        mod.pcg(rp, ci, L, f, rtol=0.0, max_iter=CG_ITERS)
+        t3 = time.perf_counter()
+        return {"melem_s": case.n_elems / (t3 - t0) / 1e6, "assembly_melem_s": case.n_elems / (t1 - t0) / 1e6,
+                "seconds": {"momentum": t1 - t0, "poisson_dirichlet": t2 - t1, "pcg": t3 - t2, "total": t3 - t0}}
+
+    serial = run(oracle)
+    colouring = omp.colour(case.conn, case.n_nodes, ty)     # set-up, like the GPU's upload: not timed
+    threads = omp.threads()
+    allc = run(omp, colouring=colouring)
+    model, nproc = host_cpu()
     return {
-        "value": case.n_elems / total / 1e6, "unit": "Melem/s", "cores": 1, "kind": "oracle",
+        "value": allc["melem_s"], "unit": "Melem/s", "cores": threads, "kind": "oracle",
         "sample": (f"{label}{sample_n}^3 same recipe ({case.n_elems} elements): momentum+Poisson assembly, "
-                   f"Dirichlet, {CG_ITERS} PCG; serial C oracle, {total:.1f} s"),
-        "assembly_melem_s": case.n_elems / (t1 - t0) / 1e6,
-        "seconds": {"momentum": t1 - t0, "poisson_dirichlet": t2 - t1, "pcg": t3 - t2},
+                   f"Dirichlet, {CG_ITERS} PCG; the C oracle on {threads} threads (colour-ordered element loop, "
+                   f"{colouring[0]} colours) {allc['seconds']['total']:.1f} s, serial on 1 thread "
+                   f"{serial['seconds']['total']:.1f} s"),
+        "host_cpu": model, "nproc": nproc, "threads": threads,
+        "all_threads": allc, "one_thread": serial,
+        "assembly_melem_s": allc["assembly_melem_s"],
     }
 
 
-def serve_bench(args):
-    """Serving workload: independent HEX08 cubes (side 8..96, log-uniform),
-    each a momentum + Poisson assembly and a Jacobi-PCG solve to a true
-    relative residual of 1e-8.  Sequential FP64 (FIFO, one request at a time
-    through the plain API) against the batching server, at an arrival rate
-    of 0.8x, 1.5x the sequential capacity and with everything queued at once."""
+def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8", "load1.5")):
+    """Serving workload: the first nreq requests of the serving stream,
+    independent HEX08 cubes (side 8..96, log-uniform), each a momentum +
+    Poisson assembly and a Jacobi-PCG solve to a true relative residual of
+    1e-8.  Sequential FP64 (FIFO, one request at a time through the plain API)
+    against the batching server: everything queued at once ("saturated") and
+    Poisson arrivals at 0.8x / 1.5x the measured sequential capacity."""
+    import concurrent.futures as cf
     import threading
     import torch
     import meshgen
     import paper_2107_11541_amd as fe
 
-    nreq = args.serve_requests
     t_unit, sides = meshgen.serving_stream(nreq, qps=1.0)
-    log(f"serving: generating {nreq} requests (sides {sides.min()}..{sides.max()}, "
-        f"{int(np.sum(sides.astype(np.int64) ** 3))} elements)")
-    cases = [meshgen.serving_case(i, int(n)) for i, n in enumerate(sides)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        cases = list(ex.map(lambda a: meshgen.serving_case(a[0], int(a[1])), enumerate(sides)))
     elems = np.array([c.n_elems for c in cases])
+    log(f"serving: generated {nreq} requests (sides {sides.min()}..{sides.max()}, {int(elems.sum())} elements) "
+        f"in {time.perf_counter() - t0:.1f} s")
     ctx = fe.Context(0)
     RTOL = 1e-8
 
@@ -242,8 +296,8 @@ def serve_bench(args):
             out[i] = done - arr[i]
         return out
 
-    def run_served(qps, slots, threads):
-        srv = fe.Server(ctx, hbm_budget=args.serve_budget_gb << 30, max_slots=slots, host_threads=threads)
+    def run_served(qps):
+        srv = fe.Server(ctx, hbm_budget=budget_gb << 30, max_slots=slots, host_threads=threads)
         arr = t_unit / qps if qps else np.zeros(nreq)
         tickets = [None] * nreq
 
@@ -278,43 +332,53 @@ def serve_bench(args):
                 "run_ms_mean": float(np.mean([r["run_ms"] for r in res]))}
 
     cap = 1.0 / mean_s
+    loads = {"load0.8": 0.8, "load1.5": 1.5}
     runs = {}
-    for name, q in (("saturated", None), ("load0.8", 0.8 * cap), ("load1.5", 1.5 * cap)):
-        runs[name] = run_served(q, args.serve_slots, args.serve_threads)
+    for name in modes:
+        runs[name] = run_served(None if name == "saturated" else loads[name] * cap)
         log(f"served {name}: {json.dumps(runs[name])}")
-    seq_lat = {k: fifo_latency(t_unit / (f * cap)) for k, f in (("load0.8", 0.8), ("load1.5", 1.5))}
+    seq = {"solves_per_s": nreq / seq_total, "mean_service_ms": mean_s * 1e3,
+           "max_true_rel_residual": float(seq_res.max())}
+    for name in modes:
+        if name in loads:
+            lat = fifo_latency(t_unit / (loads[name] * cap))
+            seq[f"p50_ms_at_{name}"] = float(np.percentile(lat, 50)) * 1e3
+            seq[f"p99_ms_at_{name}"] = float(np.percentile(lat, 99)) * 1e3
+    ctx.close()
+    return {"workload": (f"serve-hex08-cubes-8..96-log-uniform, first {nreq} requests of the stream, "
+                         f"momentum+Poisson assembly + PCG to true rel residual 1e-8"),
+            "requests": nreq, "elements_total": int(elems.sum()), "slots": slots, "planner_threads": threads,
+            "arena_gb": budget_gb, "sequential_fp64": seq, "served": runs,
+            "speedup_saturated_vs_sequential": (runs["saturated"]["solves_per_s"] / seq["solves_per_s"]
+                                                if "saturated" in runs else None)}
+
+
+def serve_bench(args):
+    r = serve_measure(args.serve_requests, args.serve_slots, args.serve_threads, args.serve_budget_gb)
     line = {
         "metric": "served solves/s and p99 at 1e-8 rel err",
-        "value": runs["saturated"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "value": r["served"]["saturated"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"serve-hex08-cubes-8..96-log-uniform, {nreq} requests, momentum+Poisson assembly "
-                               f"+ PCG to true rel residual 1e-8", "requests": nreq,
-                   "elements_total": int(elems.sum()), "slots": args.serve_slots,
-                   "planner_threads": args.serve_threads, "arena_gb": args.serve_budget_gb},
-        "sequential_fp64": {"solves_per_s": nreq / seq_total, "mean_service_ms": mean_s * 1e3,
-                            "p50_ms_at_load0.8": float(np.percentile(seq_lat["load0.8"], 50)) * 1e3,
-                            "p99_ms_at_load0.8": float(np.percentile(seq_lat["load0.8"], 99)) * 1e3,
-                            "p50_ms_at_load1.5": float(np.percentile(seq_lat["load1.5"], 50)) * 1e3,
-                            "p99_ms_at_load1.5": float(np.percentile(seq_lat["load1.5"], 99)) * 1e3,
-                            "max_true_rel_residual": float(seq_res.max())},
-        "served": runs,
+        "config": {k: r[k] for k in ("workload", "requests", "elements_total", "slots", "planner_threads",
+                                      "arena_gb")},
+        "sequential_fp64": r["sequential_fp64"], "served": r["served"],
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
-def cfg4_bench(args):
+def cfg4_measure(n, reps):
     """256^3 HEX08 (jitter 15 %, 5 species): the momentum matrix with its 3
     right-hand sides, 5 scalar-transport matrices with theirs and the Poisson
     system, then the Poisson solve to a true relative residual of 1e-8 twice:
-    FP64 Jacobi-PCG, and FP32 Jacobi-PCG inside FP64 iterative refinement."""
+    FP64 Jacobi-PCG, and FP32 Jacobi-PCG inside FP64 iterative refinement;
+    each solution's relative error against the other is reported."""
     import torch
     import meshgen
     import paper_2107_11541_amd as fe
 
-    n = args.cfg4_n
+    t0 = time.perf_counter()
     case = meshgen.cfg4(n)
-    log(f"cfg4 {n}^3: N={case.n_nodes} E={case.n_elems}")
+    log(f"cfg4 {n}^3: N={case.n_nodes} E={case.n_elems} generated in {time.perf_counter() - t0:.1f} s")
     ctx = fe.Context(0)
     t0 = time.perf_counter()
     mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=True)
@@ -332,9 +396,9 @@ def cfg4_bench(args):
     L = torch.empty((1, nnz), dtype=torch.float64, device=dev)
     f = torch.empty((1, N), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-    log(f"uploaded in {upload_s:.1f} s, nnz={nnz}, device memory {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+    log(f"cfg4 uploaded in {upload_s:.1f} s, nnz={nnz}, device memory {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
-    def timed(fn, reps):
+    def timed(fn):
         fn()
         ctx.profile(True)
         for _ in range(reps):
@@ -342,18 +406,17 @@ def cfg4_bench(args):
         k, ms = ctx.profile_read(1)
         ctx.profile(False)
         return ms / k
-    reps = args.steps
     ms = {
-        "momentum": timed(lambda: fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, values=Vm, rhs=Bm), reps),
+        "momentum": timed(lambda: fe.assemble(mesh, fe.MOMENTUM, case.dt, u, rho, mu, values=Vm, rhs=Bm)),
         "scalars5": timed(lambda: fe.assemble(mesh, fe.SCALAR, case.dt, u, rho, Y=Y, D=case.D, values=Vs,
-                                              rhs=Bs), reps) / 5,
-        "poisson": timed(lambda: fe.assemble(mesh, fe.POISSON, case.dt, u, rho, values=L, rhs=f), reps),
+                                              rhs=Bs)) / 5,
+        "poisson": timed(lambda: fe.assemble(mesh, fe.POISSON, case.dt, u, rho, values=L, rhs=f)),
     }
     del Vs, Bs
     total_ms = ms["momentum"] + 5 * ms["scalars5"] + ms["poisson"]
     fe.apply_dirichlet(mesh, L, f)
     torch.cuda.synchronize()
-    solves = {}
+    solves, xs = {}, {}
     for name, prec in (("fp64_pcg", fe.FP64), ("mixed_ir", fe.MIXED)):
         # untimed warm-up: the first solve of a precision allocates its work
         # vectors (and, mixed, the FP32 value copy) and records its iteration
@@ -366,22 +429,37 @@ def cfg4_bench(args):
         x, info = fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-8, max_iter=20000, precision=prec)
         torch.cuda.synchronize()
         solves[name] = dict(info, seconds=time.perf_counter() - t0)
-        log(f"{name}: {solves[name]}")
-    line = {
-        "metric": "Melem/s assembled (8 equations) and Poisson solve time to 1e-8: FP64 PCG vs FP32-in-FP64 IR",
-        "value": E / (total_ms * 1e-3) / 1e6, "unit": "Melem/s", "n_gpus": 1, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"hex08-{n}^3-jitter15-5species: 1 momentum + 5 scalar + 1 Poisson matrix, "
-                               f"Poisson solve to true rel residual 1e-8", "elements": E, "nodes": N, "nnz": nnz},
+        xs[name] = x
+        log(f"cfg4 {name}: {solves[name]}")
+    # the two solutions against each other (both at true rel residual <= 1e-8)
+    solves["mixed_vs_fp64_rel_solution_diff"] = float(torch.linalg.norm(xs["mixed_ir"] - xs["fp64_pcg"]) /
+                                                      torch.linalg.norm(xs["fp64_pcg"]))
+    out = {
+        "workload": (f"hex08-{n}^3-jitter15-5species: 1 momentum + 5 scalar + 1 Poisson matrix, "
+                     f"Poisson solve to true rel residual 1e-8"),
+        "elements": E, "nodes": N, "nnz": nnz,
+        "assembly_melem_s_8_equations": E / (total_ms * 1e-3) / 1e6,
         "assembly_ms": dict(ms, all_8_equations=total_ms),
         "assembly_melem_s": {k: E / (v * 1e-3) / 1e6 for k, v in ms.items()},
         "solve": solves,
         "ir_speedup": solves["fp64_pcg"]["seconds"] / solves["mixed_ir"]["seconds"],
         "upload_s": upload_s,
     }
-    print(json.dumps(line), flush=True)
     mesh.close()
     ctx.close()
+    return out
+
+
+def cfg4_bench(args):
+    r = cfg4_measure(args.cfg4_n, args.steps)
+    line = {
+        "metric": "Melem/s assembled (8 equations) and Poisson solve time to 1e-8: FP64 PCG vs FP32-in-FP64 IR",
+        "value": r["assembly_melem_s_8_equations"], "unit": "Melem/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {k: r[k] for k in ("workload", "elements", "nodes", "nnz")},
+        **{k: r[k] for k in ("assembly_ms", "assembly_melem_s", "solve", "ir_speedup", "upload_s")},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -393,7 +471,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cfg4-n", type=int, default=256)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--no-serving", action="store_true", help="default workload: skip the serving sub-run")
+    ap.add_argument("--no-cfg4", action="store_true", help="default workload: skip the 256^3 sub-run")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-threads", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
@@ -604,10 +684,7 @@ def main():
         "config": {"workload": wl, "elements": E, "nodes": N, "nnz": nnz, "cg_iterations": CG_ITERS,
                    "blocks": info["n_blocks"], "colours": info["n_colors"],
                    "elements_by_nodes_per_element": type_counts},
-        "roofline": {"bound": "hbm", "kernel": "k_cg_spmv_pq (CSR SpMV fused with p.Ap)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload), "algorithmic_bytes_per_launch": sb, "avg_launch_us": spmv_us,
-                     "launches": n_spmv},
+        "roofline": roofline_entry(args.workload, sb, spmv_us, n_spmv),
         "breakdown": {
             "assembly_ms_per_step": ms_asm / prof_steps,
             "momentum_assembly_ms": ms_mom, "poisson_assembly_ms": ms_poi,
@@ -634,6 +711,20 @@ def main():
         log(f"cpu baseline: oracle on the same recipe")
         n_cpu = args.cpu_sample_n if args.workload in ("hex128", "hex64") else min(args.cpu_sample_n, 64)
         line["cpu_baseline"] = cpu_baseline(n_cpu, args.workload)
+        log(f"cpu baseline: {json.dumps(line['cpu_baseline'])}")
+    if args.workload == "hex128":
+        # the metric's second half and the large single mesh, measured in the
+        # same run (outside the timed region of the step above)
+        del Vm, Bm, L, f, x, u, rho, mu
+        mesh.close()
+        ctx.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        if not args.no_serving:
+            line["serving"] = serve_measure(args.serve_requests, args.serve_slots, args.serve_threads,
+                                            args.serve_budget_gb, modes=("saturated", "load0.8"))
+        if not args.no_cfg4:
+            line["cfg4"] = cfg4_measure(args.cfg4_n, 5)
     print(json.dumps(line), flush=True)
 
 
