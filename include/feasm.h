@@ -212,6 +212,29 @@ typedef struct {
 fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
                       int32_t max_iter, fe_precision prec, fe_cg_info *info);
 
+/*
+ * Allocation-free FP64 Jacobi-PCG, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same solve, arguments, errors and results as
+ * fe_cg_solve(..., FE_FP64, ...) (bitwise: same kernels, same launch
+ * shapes), but the work vectors r, z, p, q, D^-1, the residual, the partial
+ * sums, the per-iteration scalars and the stop word live in one fixed device
+ * area of FE_NOALLOC_BYTES per device (a static device array, held from the
+ * first fe_ctx_create on that device until the process ends) instead of
+ * buffers allocated on the mesh; every iteration is launched on its own (no
+ * graph is recorded).  The call allocates nothing.  It needs
+ *   6 * round256(8 n_nodes) + 65792 + round256(8 (4 max(max_iter + 2, 256) + 4))
+ * bytes of the area (about 1.39 M nodes at 64 MiB): FE_ENOMEM otherwise,
+ * with the sizes in fe_ctx_last_error().  Every call on one device shares
+ * that device's area and leaves its contents behind (each call initialises
+ * what it reads): calls that overlap on one device -- two streams, two
+ * contexts, two host threads -- race and give wrong results.  Synchronises
+ * the stream.
+ */
+#define FE_NOALLOC_BYTES ((size_t)64 << 20)
+fe_status fe_cg_solve_noalloc(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
+                              int32_t max_iter, fe_cg_info *info);
+
 /* ---- explicit step (Algorithm 1: Runge-Kutta momentum stages, pressure,
  *      velocity correction) ---------------------------------------------------
  * The paper's time step assembles the momentum equations inside Runge-Kutta

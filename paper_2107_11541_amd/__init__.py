@@ -31,7 +31,7 @@ MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
 __all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
-           "residual", "gradient", "divergence", "fractional_step", "wall_traction", "scalar_residual",
+           "cg_solve_noalloc", "residual", "gradient", "divergence", "fractional_step", "wall_traction", "scalar_residual",
            "scalar_step", "FULL_STRESS", "EMAC",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
 
@@ -417,6 +417,26 @@ def cg_solve(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_iter: int 
     info = capi.CGInfo()
     st = mesh.ctx.lib.fe_cg_solve(mesh.h, _ptr(values), _ptr(rhs), _ptr(x), float(rtol), int(max_iter),
                                   precision, C.byref(info))
+    out = {"status": st, "iterations": info.iterations, "outer_iterations": info.outer_iterations,
+           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual}
+    if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):
+        raise FeError(st, mesh.ctx.error())
+    return x, out
+
+
+def cg_solve_noalloc(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_iter: int = 10000,
+                     raise_on_noconv: bool = True):
+    """fe_cg_solve_noalloc: FP64 PCG with its work buffers in the library's
+    fixed device area (no device allocation).  Returns (x, info dict)."""
+    torch = _torch()
+    _check_dev(values, torch.float64, mesh.nnz, "values")
+    _check_dev(rhs, torch.float64, mesh.n_nodes, "rhs")
+    if x is None:
+        x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=rhs.device)
+    _check_dev(x, torch.float64, mesh.n_nodes, "x")
+    info = capi.CGInfo()
+    st = mesh.ctx.lib.fe_cg_solve_noalloc(mesh.h, _ptr(values), _ptr(rhs), _ptr(x), float(rtol), int(max_iter),
+                                          C.byref(info))
     out = {"status": st, "iterations": info.iterations, "outer_iterations": info.outer_iterations,
            "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual}
     if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):

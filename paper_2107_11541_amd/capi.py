@@ -81,6 +81,7 @@ SIGNATURES = {
     "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
     "fe_axpy": (C.c_int, [P, i64, dbl, P, P]),
     "fe_cg_solve": (C.c_int, [P, P, P, P, dbl, i32, C.c_int, C.POINTER(CGInfo)]),
+    "fe_cg_solve_noalloc": (C.c_int, [P, P, P, P, dbl, i32, C.POINTER(CGInfo)]),
     "fe_residual": (C.c_int, [P, P, P, P, C.c_uint32, P]),
     "fe_gradient": (C.c_int, [P, P, P]),
     "fe_scalar_residual": (C.c_int, [P, P, P, P, dbl, P]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,10 @@
 #include "plan.h"
 
 using namespace feasm;
+
+// Work area of fe_cg_solve_noalloc (one copy per device, held until the
+// process ends; its device address is looked up per device in fe_ctx_create).
+static __device__ __align__(256) char scratch[FE_NOALLOC_BYTES];
 
 namespace feasm {
 
@@ -518,14 +523,15 @@ fe_status pcg_graph_launch(fe_mesh_s *m, const T *vals, T *x)
 // Unless the context is profiling (which brackets single launches with
 // events), runs of kGraphIters iterations go through a recorded graph; the
 // stop flag is polled on a growing schedule as before.
+// w: the mesh's work buffers (m->cg), or another set of the same sizes when
+// recorded graphs are off (allow_graphs = false: every launch is eager).
 template <class T>
-fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, int max_iter, bool x_zero,
-                  int32_t flags_out[4])
+fe_status run_pcg(fe_mesh_s *m, CGWork &w, const T *vals, const T *b, T *x, double rtol, int max_iter, bool x_zero,
+                  int32_t flags_out[4], bool allow_graphs = true)
 {
     fe_ctx_s *c = m->ctx;
-    CGWork &w = m->cg;
     HIPCALL(c, cg_setup<T>(m->dm, vals, b, x, w, rtol, c->stream, x_zero));
-    const bool graphs = !c->profiling && c->cap_stream != nullptr;
+    const bool graphs = allow_graphs && !c->profiling && c->cap_stream != nullptr;
     int k = 0;
     int next_poll = 8;
     int32_t *hf = (int32_t *)c->host;
@@ -561,6 +567,92 @@ fe_status run_pcg(fe_mesh_s *m, const T *vals, const T *b, T *x, double rtol, in
     return FE_OK;
 }
 
+// FP64 Jacobi-PCG on the work buffers w: fills the iteration count and the
+// recursive residual of inf, and the outcome of the solve in result
+// (FE_OK, FE_ENOCONV or FE_EBREAKDOWN).
+fe_status pcg_fp64(fe_mesh_s *m, CGWork &w, const double *values, const double *rhs, double *x, double rtol,
+                   int max_iter, bool allow_graphs, fe_cg_info &inf, fe_status &result)
+{
+    fe_ctx_s *c = m->ctx;
+    int32_t fl[4];
+    fe_status s = run_pcg<double>(m, w, values, rhs, x, rtol, max_iter, false, fl, allow_graphs);
+    if (s != FE_OK) return s;
+    const int it = fl[2];
+    double hv[2];
+    HIPCALL(c, hipMemcpy(hv, w.hist + 4 * (size_t)it, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    double bb;
+    HIPCALL(c, hipMemcpy(&bb, w.hist + 4 * (size_t)w.hist_cap, sizeof(double), hipMemcpyDeviceToHost));
+    inf.iterations = it;
+    inf.outer_iterations = 1;
+    inf.rel_residual = bb > 0 ? std::sqrt(hv[1] / bb) : std::sqrt(hv[1]);
+    if (fl[1] == FE_EBREAKDOWN) result = FE_EBREAKDOWN;
+    else if (rtol > 0.0 && !fl[0]) result = FE_ENOCONV;
+    return FE_OK;
+}
+
+// The true residual ||b - A x|| / ||b|| in FP64 (w.d64 and w.part as work),
+// then the solve's status and info.
+fe_status pcg_finish(fe_mesh_s *m, CGWork &w, const double *values, const double *rhs, const double *x, int max_iter,
+                     fe_cg_info &inf, fe_status result, fe_cg_info *info)
+{
+    fe_ctx_s *c = m->ctx;
+    HIPCALL(c, residual_f64(m->dm, values, rhs, x, w.d64, w.part, c->scratch + 2048, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 2048, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    inf.true_rel_residual = c->host[1] > 0 ? std::sqrt(c->host[0] / c->host[1]) : std::sqrt(c->host[0]);
+    if (info) *info = inf;
+    if (result == FE_EBREAKDOWN) return fail(c, FE_EBREAKDOWN, "CG breakdown (p.Ap <= 0 or non-finite)");
+    if (result == FE_ENOCONV) return fail(c, FE_ENOCONV, "CG did not reach rtol in %d iterations", max_iter);
+    return FE_OK;
+}
+
+// ---- allocation-free PCG: work buffers in a fixed device area -----------------
+// The area is one file-scope device array.  In host code its name stands for
+// the host-side shadow, not a device address: the device address of each
+// device's copy is looked up once per device (fe_ctx_create) and kept in
+// g_scratch_dev; only that pointer is passed to kernels.
+constexpr size_t kNoAllocBytes = FE_NOALLOC_BYTES;
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// Looks up this device's copy of the area (the device must be current).
+hipError_t noalloc_init(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = (char *)p;
+    return hipSuccess;
+}
+
+// Carves the PCG work buffers for n unknowns and max_iter iterations out of
+// the area at base: r, z, p, q, dinv, d64, the partial sums, the stop word
+// and the per-iteration scalars.  Returns the bytes used (base may be null
+// to only count them).
+size_t noalloc_layout(char *base, int64_t n, int max_iter, CGWork &w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += DevArena::round(bytes);
+        return p;
+    };
+    w = CGWork();
+    w.n = n;
+    double **v[] = {&w.r, &w.z, &w.p, &w.q, &w.dinv, &w.d64};
+    for (double **pp : v) *pp = (double *)take((size_t)n * sizeof(double));
+    w.part = (double *)take(kPartDoubles * sizeof(double));
+    w.flags = (int32_t *)take(4 * sizeof(int32_t));
+    w.hist_cap = std::max(max_iter + 2, 256);
+    w.hist = (double *)take((4 * (size_t)w.hist_cap + 4) * sizeof(double));
+    return off;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -575,6 +667,7 @@ fe_status fe_ctx_create(int device, void *hip_stream, fe_ctx *out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FE_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return FE_EDEVICE;
     if (init_spmv_grid(device) != hipSuccess) return FE_EDEVICE;
+    if (noalloc_init(device) != hipSuccess) return FE_EDEVICE;
     auto *c = new fe_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -803,19 +896,7 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
     fe_cg_info inf{};
     fe_status result = FE_OK;
     if (prec == FE_FP64) {
-        int32_t fl[4];
-        s = run_pcg<double>(m, values, rhs, x, rtol, max_iter, false, fl);
-        if (s != FE_OK) return s;
-        const int it = fl[2];
-        double hv[2];
-        HIPCALL(c, hipMemcpy(hv, w.hist + 4 * (size_t)it, 2 * sizeof(double), hipMemcpyDeviceToHost));
-        double bb;
-        HIPCALL(c, hipMemcpy(&bb, w.hist + 4 * (size_t)w.hist_cap, sizeof(double), hipMemcpyDeviceToHost));
-        inf.iterations = it;
-        inf.outer_iterations = 1;
-        inf.rel_residual = bb > 0 ? std::sqrt(hv[1] / bb) : std::sqrt(hv[1]);
-        if (fl[1] == FE_EBREAKDOWN) result = FE_EBREAKDOWN;
-        else if (rtol > 0.0 && !fl[0]) result = FE_ENOCONV;
+        if ((s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, true, inf, result)) != FE_OK) return s;
     } else {
         HIPCALL(c, cast_f64_f32(d.nnz, values, w.v32, c->stream));
         int used = 0, outer = 0;
@@ -842,7 +923,7 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
             const double tol_in = std::max(0.5 * need, 1e-5);
             HIPCALL(c, scale_f64_to_f32(d.N, 1.0 / rn, w.d64, w.r32, c->stream));
             int32_t fl[4];
-            s = run_pcg<float>(m, w.v32, w.r32, w.x32, tol_in, max_iter - used, true, fl);
+            s = run_pcg<float>(m, m->cg, w.v32, w.r32, w.x32, tol_in, max_iter - used, true, fl);
             if (s != FE_OK) return s;
             used += fl[2];
             HIPCALL(c, add_f32_to_f64(d.N, rn, w.x32, x, c->stream));
@@ -852,15 +933,37 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
         inf.outer_iterations = outer + (result == FE_OK ? 0 : 1);
         inf.rel_residual = rel;
     }
-    // true residual in FP64
-    HIPCALL(c, residual_f64(d, values, rhs, x, w.d64, w.part, c->scratch + 2048, c->stream));
-    HIPCALL(c, hipMemcpyAsync(c->host, c->scratch + 2048, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    if ((s = sync(c)) != FE_OK) return s;
-    inf.true_rel_residual = c->host[1] > 0 ? std::sqrt(c->host[0] / c->host[1]) : std::sqrt(c->host[0]);
-    if (info) *info = inf;
-    if (result == FE_EBREAKDOWN) return fail(c, FE_EBREAKDOWN, "CG breakdown (p.Ap <= 0 or non-finite)");
-    if (result == FE_ENOCONV) return fail(c, FE_ENOCONV, "CG did not reach rtol in %d iterations", max_iter);
-    return FE_OK;
+    return pcg_finish(m, w, values, rhs, x, max_iter, inf, result, info);
+}
+
+fe_status fe_cg_solve_noalloc(fe_mesh m, const double *values, const double *rhs, double *x, double rtol,
+                              int32_t max_iter, fe_cg_info *info)
+{
+    if (!m) return FE_EINVAL;
+    fe_ctx_s *c = m->ctx;
+    if (!values || !rhs || !x) return fail(c, FE_EINVAL, "null values/rhs/x");
+    if (max_iter < 0) return fail(c, FE_EINVAL, "max_iter < 0");
+    if (!std::isfinite(rtol)) return fail(c, FE_EINVAL, "rtol not finite");
+    HIPCALL(c, hipSetDevice(c->device));
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c->device >= 0 && c->device < kNoAllocMaxDevices) base = g_scratch_dev[c->device];
+    }
+    if (!base) return fail(c, FE_EDEVICE, "the fixed PCG work area of device %d was not set up", c->device);
+    CGWork w;
+    const size_t need = noalloc_layout(nullptr, m->dm.N, max_iter, w);
+    if (need > kNoAllocBytes)
+        return fail(c, FE_ENOMEM,
+                    "fe_cg_solve_noalloc: %lld nodes and %d iterations need %zu bytes of work area, the fixed area "
+                    "holds %zu (FE_NOALLOC_BYTES)",
+                    (long long)m->dm.N, max_iter, need, kNoAllocBytes);
+    noalloc_layout(base, m->dm.N, max_iter, w);
+    fe_cg_info inf{};
+    fe_status result = FE_OK;
+    fe_status s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, false, inf, result);
+    if (s != FE_OK) return s;
+    return pcg_finish(m, w, values, rhs, x, max_iter, inf, result, info);
 }
 
 // ---- explicit step ----------------------------------------------------------
