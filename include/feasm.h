@@ -177,6 +177,34 @@ fe_status fe_assemble(fe_mesh mesh, const fe_fields *fields, fe_precision prec, 
                       double *rhs, fe_asm_info *info);
 
 /*
+ * The implicit momentum operator of Eq. (1) with the viscous term in its
+ * full-stress form -div(2 mu eps(u)) (Section 2), which couples the three
+ * velocity components: 3x3 blocks on the mesh's scalar CSR pattern.  Testing
+ * with N_a e_i, row (a, i) and column (b, k) of the element matrix are
+ *   delta_ik (M_ab/dt + C_ab + K_ab + E_ab) + T_ab[i][k],
+ *   T_ab[i][k] = int mu (dN_a/dx_k)(dN_b/dx_i)       (form FE_FORM_FULL_STRESS),
+ *   E_ab       = int rho (div u) N_a N_b              (form FE_FORM_EMAC: the
+ *                (div u) u term of the EMAC convection, u frozen at the nodal
+ *                velocity),
+ * with M_rho, C(u), K_mu those of fe_assemble(MOMENTUM); a term whose bit is
+ * clear is left out (form 0 = fe_assemble(MOMENTUM)'s matrix times the
+ * identity).  FP64.
+ *   u [3][n_nodes], rho, mu [n_nodes]: device, mesh numbering
+ *   values: device [nnz][3][3], overwritten: block (i, k) of CSR entry p at
+ *           values[9 p + 3 i + k] (pattern of fe_mesh_info, mesh numbering)
+ *   rhs:    device [3][n_nodes], overwritten: M_rho u_i / dt
+ * With b = rhs, b - A u equals rows 0-2 of fe_residual(u, form) (the mass
+ * terms cancel).  Every CSR block row is written once (no
+ * read-back); the sums run in a fixed order, so the result is bitwise
+ * reproducible.  The first call on a mesh plans the row-owner assembly on the
+ * host and keeps the plan on the device (about 14 bytes per element node).
+ * Errors: FE_EINVAL, FE_EBADELEM (element in *info), FE_EBADMESH if a node
+ * lies in more than 64 elements, FE_ENOMEM, FE_EDEVICE.
+ */
+fe_status fe_assemble_block(fe_mesh mesh, uint32_t form, double dt, const double *u, const double *rho,
+                            const double *mu, double *values, double *rhs, fe_asm_info *info);
+
+/*
  * Symmetric Dirichlet elimination on the mesh's Dirichlet nodes, in place:
  * free rows i: rhs_i -= sum_{j in D} A_ij g_j, A_ij = 0 (j in D);
  * Dirichlet rows: off-diagonals 0, diagonal kept, rhs_i = A_ii g_i.
@@ -446,6 +474,33 @@ fe_status fe_plan_export_types(fe_plan plan, uint8_t *elem_types, uint8_t *block
                                int64_t *n_launches);
 /* color_blocks[n_blocks]: the blocks in launch order (by colour, then type). */
 fe_status fe_plan_export_color_blocks(fe_plan plan, int32_t *color_blocks);
+/*
+ * Owner plan of the matrix assembly of a single-type mesh (Section 4.2's
+ * element loop regrouped by the CSR rows it writes; fe_assemble runs it for
+ * MOMENTUM, SCALAR and POISSON on HEX08 meshes, and the coloured element
+ * blocks for the other types and for hybrid meshes).  Rows, in mesh numbering, are
+ * cut into groups of consecutive rows; a work-group owns one group and
+ * computes every element contribution to its rows.  A task is one lane's
+ * share: an element's rows that the group owns -- for HEX08 at most 4, with
+ * the element presented in a rotated node order that puts them on its first
+ * face (two tasks when they lie on no single face), for the other types all
+ * of the element's rows, the rows the group does not own being dropped.
+ * fe_plan_owner_info: counts; FE_EINVAL for a hybrid plan.
+ * fe_plan_export_owner (any pointer may be NULL):
+ *   groups[4 n_groups] = {first task, tasks, first row, rows},
+ *   node_ptr[n_groups + 1], nodes[node_ptr[n_groups]]: each group's touched
+ *     nodes, its own rows first (in order), then the others ascending,
+ *   nphase[n_groups]: phases of the group's LDS accumulation,
+ *   task_elem[n_tasks]: mesh element; task_ln[n_tasks * ln_stride] (16-bit):
+ *     the group-local node of each (rotated) element node; task_off[n_tasks *
+ *     off_stride]: for row r < rows_per_task and column b, the position of
+ *     node b in row r's CSR columns at r * nodes_per_element + b (0 for rows
+ *     the group does not own); task_phase[n_tasks].
+ */
+fe_status fe_plan_owner_info(fe_plan plan, int64_t *n_groups, int64_t *n_tasks, int32_t *rows_per_task,
+                             int32_t *ln_stride, int32_t *off_stride);
+fe_status fe_plan_export_owner(fe_plan plan, int32_t *groups, int32_t *node_ptr, int32_t *nodes, uint8_t *nphase,
+                               int32_t *task_elem, uint16_t *task_ln, uint8_t *task_off, uint8_t *task_phase);
 void fe_plan_free(fe_plan plan);
 /* Message for the last failure of fe_plan_create(_mixed) on this thread. */
 const char *fe_plan_last_error(void);

@@ -30,7 +30,7 @@ HYBRID = 0   # mixed element types: Mesh(..., types=...) with conn [E, 8]
 MOMENTUM, SCALAR, POISSON = FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON
 FP64, MIXED = FE_FP64, FE_MIXED
 
-__all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
+__all__ = ["Context", "Mesh", "Plan", "Server", "assemble", "assemble_block", "apply_dirichlet", "spmv", "dot", "axpy", "cg_solve",
            "cg_solve_noalloc", "residual", "gradient", "divergence", "fractional_step", "wall_traction", "scalar_residual",
            "scalar_step", "FULL_STRESS", "EMAC",
            "FeError", "HEX08", "PEN06", "PYR05", "TET04", "HYBRID", "MOMENTUM", "SCALAR", "POISSON", "FP64", "MIXED", "pack_layout"]
@@ -367,6 +367,30 @@ def assemble(mesh: Mesh, op: int, dt: float, u, rho, mu=None, Y=None, D=None, pr
     return values, rhs, out
 
 
+def assemble_block(mesh: Mesh, form: int, dt: float, u, rho, mu, values=None, rhs=None):
+    """fe_assemble_block: the momentum operator with the full-stress viscous
+    term (form FULL_STRESS) and EMAC's (div u) term (form EMAC) as 3x3 blocks.
+    Returns (values[nnz, 3, 3], rhs[3, N], info dict)."""
+    torch = _torch()
+    N, nnz = mesh.n_nodes, mesh.nnz
+    _check_dev(u, torch.float64, 3 * N, "u")
+    _check_dev(rho, torch.float64, N, "rho")
+    _check_dev(mu, torch.float64, N, "mu")
+    if values is None:
+        values = torch.empty((nnz, 3, 3), dtype=torch.float64, device=u.device)
+    if rhs is None:
+        rhs = torch.empty((3, N), dtype=torch.float64, device=u.device)
+    _check_dev(values, torch.float64, 9 * nnz, "values")
+    _check_dev(rhs, torch.float64, 3 * N, "rhs")
+    info = capi.AsmInfo()
+    st = mesh.ctx.lib.fe_assemble_block(mesh.h, int(form), float(dt), _ptr(u), _ptr(rho), _ptr(mu), _ptr(values),
+                                        _ptr(rhs), C.byref(info))
+    out = {"min_detJ": info.min_detJ, "first_bad_elem": info.first_bad_elem, "status": st}
+    if st != capi.FE_OK:
+        raise FeError(st, mesh.ctx.error())
+    return values, rhs, out
+
+
 def apply_dirichlet(mesh: Mesh, values, rhs, g=None):
     torch = _torch()
     _check_dev(values, torch.float64, mesh.nnz, "values")
@@ -587,6 +611,26 @@ class Plan:
                                       out["launches"].ctypes.data, C.byref(nl))
         out["color_blocks"] = np.zeros(nb, np.int32)
         self.lib.fe_plan_export_color_blocks(self.h, out["color_blocks"].ctypes.data)
+        return out
+
+    def export_owner(self) -> dict:
+        """The owner plan of the matrix assembly (single-type meshes)."""
+        G, T = C.c_int64(), C.c_int64()
+        ra, lns, offs = C.c_int32(), C.c_int32(), C.c_int32()
+        st = self.lib.fe_plan_owner_info(self.h, C.byref(G), C.byref(T), C.byref(ra), C.byref(lns), C.byref(offs))
+        if st != capi.FE_OK:
+            raise FeError(st, "no owner plan (hybrid mesh)")
+        G, T = G.value, T.value
+        out = {"rows_per_task": ra.value, "ln_stride": lns.value, "off_stride": offs.value,
+               "groups": np.zeros((G, 4), np.int32), "node_ptr": np.zeros(G + 1, np.int32),
+               "nphase": np.zeros(G, np.uint8), "task_elem": np.zeros(T, np.int32),
+               "task_ln": np.zeros((T, lns.value), np.uint16), "task_off": np.zeros((T, offs.value), np.uint8),
+               "task_phase": np.zeros(T, np.uint8)}
+        self.lib.fe_plan_export_owner(self.h, None, out["node_ptr"].ctypes.data, None, None, None, None, None, None)
+        out["nodes"] = np.zeros(int(out["node_ptr"][-1]), np.int32)
+        a = [out[k].ctypes.data for k in ("groups", "node_ptr", "nodes", "nphase", "task_elem", "task_ln",
+                                          "task_off", "task_phase")]
+        self.lib.fe_plan_export_owner(self.h, *a)
         return out
 
     def __del__(self):

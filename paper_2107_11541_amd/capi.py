@@ -76,6 +76,7 @@ SIGNATURES = {
     "fe_mesh_to_user_order": (C.c_int, [P, P, P, i32]),
     "fe_mesh_free": (None, [P]),
     "fe_assemble": (C.c_int, [P, C.POINTER(Fields), C.c_int, P, P, C.POINTER(AsmInfo)]),
+    "fe_assemble_block": (C.c_int, [P, C.c_uint32, dbl, P, P, P, P, P, C.POINTER(AsmInfo)]),
     "fe_apply_dirichlet": (C.c_int, [P, P, P, P]),
     "fe_spmv": (C.c_int, [P, P, P, P]),
     "fe_dot": (C.c_int, [P, i64, P, P, C.POINTER(dbl)]),
@@ -104,6 +105,9 @@ SIGNATURES = {
     "fe_plan_export_color_blocks": (C.c_int, [P, P]),
     "fe_plan_info": (C.c_int, [P, C.POINTER(PlanDesc)]),
     "fe_plan_export": (C.c_int, [P, P, P, P, P, P, P, P, P]),
+    "fe_plan_owner_info": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(i32)]),
+    "fe_plan_export_owner": (C.c_int, [P, P, P, P, P, P, P, P, P]),
     "fe_plan_free": (None, [P]),
     "fe_plan_last_error": (C.c_char_p, []),
     "fe_pack_layout": (C.c_int, [i64, i32, C.POINTER(i64), C.POINTER(i64)]),

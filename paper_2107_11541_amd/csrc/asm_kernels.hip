@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "plan.h"
 
 namespace feasm {
 namespace {
@@ -703,6 +704,186 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_residual(KArgs k)
     assemble_block<EL, OP_RES, double, FORM>(k);
 }
 
+// ---- owner assembly of the matrix operators ---------------------------------
+// One work-group owns a group of consecutive CSR rows and computes every
+// element contribution to them, so each row is written once and never read
+// back, in a single launch (no colours).  Steps:
+//   1. stage the group's touched nodes' fields in LDS (owned rows first);
+//      zero the owned rows' image and right-hand sides;
+//   2. one task per lane: the Gauss loop of rows [0, RA) of its element,
+//      presented in the task's node order (a HEX08 element rotated so that
+//      the rows the group owns lie on its first face);
+//   3. phase by phase (a barrier between phases), add the owned rows of the
+//      tasks of that phase into LDS: the tasks of one phase hold distinct
+//      owned rows, so no two lanes add to one address and the order of the
+//      sums is fixed by the plan;
+//   4. write the rows (contiguous in CSR) and right-hand sides once.
+struct OArgs {
+    const double *X;
+    const int32_t *rowptr;
+    const int4 *groups;
+    const int32_t *node_ptr, *nodes, *elem;
+    const uint8_t *nphase, *off, *phase;
+    const uint16_t *ln;
+    int ln_stride, off_stride;
+    int64_t N;
+    const double *u, *rho, *mu, *Y;
+    double dt, Dk;
+    double *values, *rhs;
+    double *g_mindet;
+    long long *g_bad;
+};
+
+template <class EL> struct OwnRows { static constexpr int RA = EL::NEN == 8 ? 4 : EL::NEN; };
+
+template <class EL, int OP, class Q>
+__global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
+{
+    constexpr int NEN = EL::NEN, RA = OwnRows<EL>::RA;
+    constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
+    extern __shared__ double lds[];
+    const int4 gd = k.groups[blockIdx.x];   // first task, tasks, first row, rows
+    const int tid = threadIdx.x;
+    const int r0 = gd.z, nr = gd.w;
+    const int n0 = k.node_ptr[blockIdx.x], T = k.node_ptr[blockIdx.x + 1] - n0;
+    const int64_t v0 = k.rowptr[r0];
+    const int L = (int)(k.rowptr[r0 + nr] - v0);
+    const int64_t N = k.N;
+    double *nd = lds;               // [NF][T] fields of the touched nodes
+    double *img = nd + NF * T;      // [L] the owned rows
+    double *rimg = img + L;         // [NRHS][nr] their right-hand sides
+
+    // task data first: its loads overlap the staging below
+    const bool live = tid < gd.y;
+    const int64_t t = gd.x + (live ? tid : 0);
+    int ln[NEN];
+    {
+        const uint16_t *lp = k.ln + t * k.ln_stride;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) ln[a] = lp[a];
+    }
+    constexpr int kOffWords = (RA * NEN + 3) / 4;
+    uint32_t offw[kOffWords];
+    {
+        const uint32_t *op = (const uint32_t *)(k.off + t * k.off_stride);
+#pragma unroll
+        for (int q = 0; q < kOffWords; ++q) offw[q] = op[q];
+    }
+    const int ph = live ? (int)k.phase[t] : -1;
+    const int64_t elem = k.elem[t];
+
+    // 1. stage
+    for (int q = tid; q < T; q += kOwnTasks) {
+        const int g = k.nodes[n0 + q];
+        double f[NF];
+        f[0] = k.X[g];
+        f[1] = k.X[N + g];
+        f[2] = k.X[2 * N + g];
+        f[3] = k.u[g];
+        f[4] = k.u[N + g];
+        f[5] = k.u[2 * N + g];
+        f[6] = k.rho[g];
+        if constexpr (NF > 7) f[7] = OP == OP_MOM ? k.mu[g] : k.Y[g];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) nd[c * T + q] = f[c];
+    }
+    for (int q = tid; q < L; q += kOwnTasks) img[q] = 0.0;
+    for (int q = tid; q < NRHS * nr; q += kOwnTasks) rimg[q] = 0.0;
+    __syncthreads();
+
+    // 2. this lane's rows
+    Q A[RA][NEN];
+    Q B[NRHS][RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) A[r][b] = Q(0);
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) B[q][r] = Q(0);
+    }
+    double mindet = __builtin_huge_val();
+    if (live) {
+        Geo<EL> GE;
+        load_geo<EL>(nd, T, ln, GE);
+        Rows<EL> rows;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
+        gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, 1.0 / k.dt, k.Dk, 0);
+    }
+    int base[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) base[r] = ln[r] < nr ? (int)(k.rowptr[r0 + ln[r]] - v0) : -1;
+
+    // 3. phases
+    const int nph = k.nphase[blockIdx.x];
+    for (int p = 0; p < nph; ++p) {
+        if (ph == p) {
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                if (base[r] < 0) continue;   // a row another group owns
+#pragma unroll
+                for (int b = 0; b < NEN; ++b) {
+                    const int idx = r * NEN + b;
+                    const int o = (offw[idx >> 2] >> (8 * (idx & 3))) & 0xff;
+                    lds_add(&img[base[r] + o], (double)A[r][b]);
+                }
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) lds_add(&rimg[q * nr + ln[r]], (double)B[q][r]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // 4. write the owned rows and right-hand sides once
+    for (int q = tid; q < L; q += kOwnTasks) k.values[v0 + q] = img[q];
+    for (int q = tid; q < NRHS * nr; q += kOwnTasks) {
+        const int c = q / nr, i = q - c * nr;
+        k.rhs[c * N + r0 + i] = rimg[q];
+    }
+    // status: the group's smallest det J and first element with det J <= 0
+    __shared__ double smd[kOwnTasks / 64];
+    __shared__ long long sbad[kOwnTasks / 64];
+    double md = live ? mindet : __builtin_huge_val();
+    long long bad = (live && !(mindet > 0.0)) ? (long long)elem : (long long)0x7fffffffffffffffLL;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        md = fmin(md, __shfl_xor(md, o));
+        const long long ob = __shfl_xor(bad, o);
+        bad = ob < bad ? ob : bad;
+    }
+    if ((tid & 63) == 0) {
+        smd[tid >> 6] = md;
+        sbad[tid >> 6] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int w = 1; w < kOwnTasks / 64; ++w) {
+            md = fmin(md, smd[w]);
+            bad = sbad[w] < bad ? sbad[w] : bad;
+        }
+        k.g_mindet[blockIdx.x] = md;
+        k.g_bad[blockIdx.x] = bad == 0x7fffffffffffffffLL ? -1 : bad;
+    }
+}
+
+template <class EL, int OP>
+void launch_own_op(const OArgs &k, int64_t G, size_t lds, bool mixed, hipStream_t s)
+{
+    if (mixed) hipLaunchKernelGGL((k_own<EL, OP, float>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
+    else hipLaunchKernelGGL((k_own<EL, OP, double>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
+}
+
+template <class EL>
+void launch_own(const OArgs &k, int op, int64_t G, size_t lds, bool mixed, hipStream_t s)
+{
+    switch (op) {
+    case OP_MOM: launch_own_op<EL, OP_MOM>(k, G, lds, mixed, s); break;
+    case OP_SCA: launch_own_op<EL, OP_SCA>(k, G, lds, mixed, s); break;
+    default: launch_own_op<EL, OP_POI>(k, G, lds, mixed, s); break;
+    }
+}
+
 // Reduce the per-block status into (min det, first bad mesh element): one
 // group of 1024 threads, four independent loads in flight per thread.
 constexpr int kStatusThreads = 1024;
@@ -781,6 +962,208 @@ void launch_type(const AsmLaunch &L, const KArgs &k, int op, bool mixed, hipStre
     case OP_GRD: launch_one<EL, OP_GRD, double>(L, k, s); break;
     case OP_SRS: launch_one<EL, OP_SRS, double>(L, k, s); break;
     default: launch_one<EL, OP_DIV, double>(L, k, s); break;
+    }
+}
+
+// ---- momentum operator with the full-stress viscous term: 3x3 blocks ------
+// Eq. (1)'s viscous term -div(2 mu eps(u)) tested with N_a e_i couples the
+// velocity components.  Row (a, i), column (b, k) of the element matrix:
+//   delta_ik (M_ab / dt + C_ab + K_ab [+ E_ab]) [+ T_ab[i][k]],
+//   T_ab[i][k] = sum_g dV mu_g (dN_a / dx_k)(dN_b / dx_i)   (FE_FORM_FULL_STRESS),
+//   E_ab = sum_g dV rho_g (div u)_g N_a N_b                  (FE_FORM_EMAC),
+// with M, C, K those of the scalar momentum operator.  Row-owner form: one
+// lane per (element, row) task, one wavefront per group of whole rows, the
+// rows' block values accumulated in LDS in phase order (a row's tasks in
+// element order) and written to HBM once, contiguously.
+struct BArgs {
+    const double *X;
+    const int32_t *conn;
+    const uint8_t *etype;
+    int stride;
+    const int32_t *rowptr;
+    const int32_t *task_elem;
+    const uint16_t *task_meta;
+    const uint8_t *task_cols;
+    const int4 *wdesc;
+    int64_t N;
+    const double *u, *rho, *mu;
+    double inv_dt;
+    double *values, *rhs;
+    double *w_mindet;
+    long long *w_bad;
+};
+
+// Element e's block row a: S[b] (the scalar part, times the identity) and
+// T[b][3i + k] (the full-stress coupling), and the right-hand side B[i].
+template <class EL, int FORM>
+__device__ __forceinline__ void block_row(const BArgs &k, int64_t e, int a, double (&S)[8], double (&T)[8][9],
+                                          double (&B)[3], double &mindet)
+{
+    constexpr int NEN = EL::NEN, NG = EL::NG;
+    constexpr bool FULL = (FORM & FE_FORM_FULL_STRESS) != 0, EMAC = (FORM & FE_FORM_EMAC) != 0;
+    const int64_t N = k.N;
+    int c[NEN];
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) c[b] = k.conn[e * k.stride + b];
+    double xl[3 * NEN], ul[3][NEN], rl[NEN], ml[NEN];
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            xl[i * NEN + b] = k.X[i * N + c[b]];
+            ul[i][b] = k.u[i * N + c[b]];
+        }
+        rl[b] = k.rho[c[b]];
+        ml[b] = k.mu[c[b]];
+    }
+    int ln[NEN];
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) ln[b] = b;
+    Geo<EL> GE;
+    load_geo<EL>(xl, NEN, ln, GE);
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        double Ji[3][3];
+        const double det = jacobian_inverse<EL>(g, GE, Ji);
+        mindet = fmin(mindet, det);
+        double dN[NEN][3];
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) s += Ji[j][i] * RefdN<EL>(g, b, j);
+                dN[b][i] = s;
+            }
+        // the task's own row a (a runtime index: read from the tables, not
+        // from the register array)
+        double dNa[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s += Ji[j][i] * RefdN<EL>(g, a, j);
+            dNa[i] = s;
+        }
+        const double Na = RefN<EL>(g, a);
+        const double dV = EL::w(g) * det;
+        double rg = 0.0, mg = 0.0, ag[3] = {0.0, 0.0, 0.0}, diva = 0.0;
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            const double Nb = RefN<EL>(g, b);
+            rg += Nb * rl[b];
+            mg += Nb * ml[b];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                ag[i] += Nb * ul[i][b];
+                if (EMAC) diva += dN[b][i] * ul[i][b];
+            }
+        }
+        const double w1 = dV * rg, wm = dV * mg, wa = w1 * Na;
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            const double Nb = RefN<EL>(g, b);
+            const double gg = dNa[0] * dN[b][0] + dNa[1] * dN[b][1] + dNa[2] * dN[b][2];
+            const double agb = ag[0] * dN[b][0] + ag[1] * dN[b][1] + ag[2] * dN[b][2];
+            double sv = wa * (Nb * k.inv_dt + agb) + wm * gg;
+            if (EMAC) sv += wa * diva * Nb;
+            S[b] += sv;
+            if (FULL) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) T[b][3 * i + kk] += wm * dNa[kk] * dN[b][i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) B[i] += wa * ag[i] * k.inv_dt;
+    }
+}
+
+template <int FORM>
+__global__ void __launch_bounds__(64) k_block(BArgs k)
+{
+    extern __shared__ double lds[];
+    const int4 wd = k.wdesc[blockIdx.x];   // first task, tasks, first row, rows
+    const int lane = threadIdx.x;
+    const int r0 = wd.z, nr = wd.w;
+    const int64_t v0 = k.rowptr[r0];
+    const int nimg = 9 * (int)(k.rowptr[r0 + nr] - v0);
+    double *img = lds;            // [nimg] block values of the wave's rows
+    double *rimg = lds + nimg;    // [3][64] their right-hand sides
+    for (int j = lane; j < nimg; j += 64) img[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rimg[i * 64 + lane] = 0.0;
+
+    const bool live = lane < wd.y;
+    const int64_t t = wd.x + (live ? lane : 0);
+    const int64_t e = k.task_elem[t];
+    const int meta = k.task_meta[t];
+    const int a = meta & 15, ph = live ? (meta >> 4) : -1;
+    const int nen = k.etype ? (int)k.etype[e] : k.stride;
+    const uint64_t cols = *(const uint64_t *)(k.task_cols + 8 * t);
+    const int row = k.conn[e * k.stride + a];
+    const int ro = (int)(k.rowptr[row] - v0), rl = row - r0;
+    double S[8], T[8][9], B[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        S[b] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) T[b][q] = 0.0;
+    }
+    double mindet = __builtin_huge_val();
+    if (live) {
+        switch (nen) {
+        case 8: block_row<Hex, FORM>(k, e, a, S, T, B, mindet); break;
+        case 6: block_row<Pen, FORM>(k, e, a, S, T, B, mindet); break;
+        case 5: block_row<Pyr, FORM>(k, e, a, S, T, B, mindet); break;
+        default: block_row<Tet, FORM>(k, e, a, S, T, B, mindet); break;
+        }
+    }
+    __syncthreads();
+    // phases: a row's tasks one after the other in element order; the tasks
+    // of one phase hold distinct rows, so no two lanes add to one address
+    int nph = ph + 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nph = max(nph, __shfl_xor(nph, o));
+    for (int p = 0; p < nph; ++p) {
+        if (ph == p) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < nen) {
+                    double *dst = img + 9 * (ro + (int)((cols >> (8 * b)) & 0xff));
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk)
+                            lds_add(dst + 3 * i + kk, (i == kk ? S[b] : 0.0) + T[b][3 * i + kk]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) lds_add(&rimg[i * 64 + rl], B[i]);
+        }
+    }
+    __syncthreads();
+    // each value and right-hand side entry written once, contiguously
+    double *vout = k.values + 9 * v0;
+    for (int j = lane; j < nimg; j += 64) vout[j] = img[j];
+    if (lane < nr) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) k.rhs[i * k.N + r0 + lane] = rimg[i * 64 + lane];
+    }
+    // status: the wave's smallest det J and first element with det J <= 0
+    double md = live ? mindet : __builtin_huge_val();
+    long long bad = (live && !(mindet > 0.0)) ? (long long)e : (long long)0x7fffffffffffffffLL;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        md = fmin(md, __shfl_xor(md, o));
+        const long long ob = __shfl_xor(bad, o);
+        bad = ob < bad ? ob : bad;
+    }
+    if (lane == 0) {
+        k.w_mindet[blockIdx.x] = md;
+        k.w_bad[blockIdx.x] = bad == 0x7fffffffffffffffLL ? -1 : bad;
     }
 }
 
@@ -964,11 +1347,55 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     k.Dk = a.Dk;
     k.values = a.values;
     k.rhs = a.rhs;
-    // status scratch lives right after the AsmStatus word
+    // status scratch lives right after the AsmStatus word: per-block (or,
+    // owner assembly, per-group) smallest det J, then first bad element, each
+    // sized for the larger of the two counts
+    const int64_t nstat = std::max<int64_t>(m.nblk, m.own_G);
     k.blk_mindet = (double *)(a.status + 1);
-    k.blk_bad = (long long *)(k.blk_mindet + m.nblk);
+    k.blk_bad = (long long *)(k.blk_mindet + nstat);
     k.off_stride = m.off_stride;
     k.form = a.form;
+    if (a.op < OP_RES && m.own_G > 0) {
+        // matrix operators of a single-type mesh: the owner assembly, one launch
+        OArgs o{};
+        o.X = m.X;
+        o.rowptr = m.rowptr;
+        o.groups = m.own_groups;
+        o.node_ptr = m.own_node_ptr;
+        o.nodes = m.own_nodes;
+        o.elem = m.own_elem;
+        o.nphase = m.own_nphase;
+        o.ln = m.own_ln;
+        o.off = m.own_off;
+        o.phase = m.own_phase;
+        o.ln_stride = m.own_ln_stride;
+        o.off_stride = m.own_off_stride;
+        o.N = m.N;
+        o.u = a.u;
+        o.rho = a.rho;
+        o.mu = a.mu;
+        o.Y = a.Y;
+        o.dt = a.dt;
+        o.Dk = a.Dk;
+        o.values = a.values;
+        o.rhs = a.rhs;
+        o.g_mindet = k.blk_mindet;
+        o.g_bad = k.blk_bad;
+        const int nf = a.op == OP_POI ? 7 : 8, nrhs = a.op == OP_MOM ? 3 : 1;
+        const size_t lds = (size_t)(nf * m.own_max_nodes + m.own_max_img + nrhs * m.own_max_rows) * sizeof(double);
+        switch (m.nen) {
+        case 8: launch_own<Hex>(o, a.op, m.own_G, lds, mixed, s); break;
+        case 6: launch_own<Pen>(o, a.op, m.own_G, lds, mixed, s); break;
+        case 5: launch_own<Pyr>(o, a.op, m.own_G, lds, mixed, s); break;
+        case 4: launch_own<Tet>(o, a.op, m.own_G, lds, mixed, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.own_G,
+                           a.status);
+        return hipGetLastError();
+    }
     // one launch per (colour, element type), in the planned order
     for (const AsmLaunch &L : m.launches) {
         if (L.count == 0) continue;
@@ -983,6 +1410,44 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.nblk, a.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_block(const DevMesh &m, const DevRowPlan &r, int form, double dt, const double *u,
+                                 const double *rho, const double *mu, double *values, double *rhs,
+                                 AsmStatus *status, hipStream_t s)
+{
+    if (r.n_waves <= 0) return hipErrorInvalidValue;
+    BArgs k{};
+    k.X = m.X;
+    k.conn = r.conn;
+    k.etype = r.etype;
+    k.stride = r.stride;
+    k.rowptr = m.rowptr;
+    k.task_elem = r.task_elem;
+    k.task_meta = r.task_meta;
+    k.task_cols = r.task_cols;
+    k.wdesc = r.wdesc;
+    k.N = m.N;
+    k.u = u;
+    k.rho = rho;
+    k.mu = mu;
+    k.inv_dt = 1.0 / dt;
+    k.values = values;
+    k.rhs = rhs;
+    k.w_mindet = r.w_mindet;
+    k.w_bad = r.w_bad;
+    const size_t lds = (size_t)(r.max_img + 3 * 64) * sizeof(double);
+    const dim3 grid((unsigned)r.n_waves), blk(64);
+    switch (form) {
+    case 0: hipLaunchKernelGGL(k_block<0>, grid, blk, lds, s, k); break;
+    case 1: hipLaunchKernelGGL(k_block<1>, grid, blk, lds, s, k); break;
+    case 2: hipLaunchKernelGGL(k_block<2>, grid, blk, lds, s, k); break;
+    default: hipLaunchKernelGGL(k_block<3>, grid, blk, lds, s, k); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, r.w_mindet, r.w_bad, r.n_waves, status);
     return hipGetLastError();
 }
 

@@ -63,6 +63,10 @@ struct fe_mesh_s {
     double *step_work = nullptr;         // explicit step: u0 [3][N], residual + mass [4][N], f [N], g [3][N]
     feasm::DevWall wall;                 // wall faces of the wall model (F = 0: none)
     double *scalar_work = nullptr;       // explicit scalar step: Y0 [N], residual + mass [2][N]
+    feasm::DevRowPlan rowplan;           // 3x3-block momentum operator (built on its first use)
+    std::vector<int32_t> conn_m;         // [E][stride_m] connectivity, mesh numbering (block operator plan)
+    std::vector<uint8_t> etype_m;        // [E] node counts (hybrid meshes), else empty
+    int stride_m = 0;
     feasm::DevArena *arena = nullptr;    // device memory source (nullptr: hipMalloc)
     bool listed = true;                  // in ctx->meshes (freed with the context)
     // recorded PCG iterations (FP64, FP32), valid for the pointers they were
@@ -87,6 +91,7 @@ fe_status fail(fe_ctx_s *c, fe_status s, const char *fmt, ...);
 // holds, built without touching the GPU (so planner threads can run it).
 struct MeshImage {
     Plan P;
+    OwnerPlan O;               // matrix assembly of a single-type mesh (no groups otherwise)
     std::vector<uint8_t> is_dir;
     std::vector<int32_t> dir_rows;
     std::vector<int4> spmv_desc;

@@ -54,6 +54,17 @@ struct DevMesh {
     // sentinel); roff holds each block's row offsets relative to its first
     // nonzero, rows + 1 entries at roff[first row + b]; lidx and cols the
     // block-local column indices and column sets (see SpmvMap).
+    // Owner plan of the matrix assembly (single-type meshes; own_G = 0
+    // otherwise): groups {first task, tasks, first row, rows}, their touched
+    // nodes (owned rows first), phases, and per task the element, the local
+    // node of each (rotated) element node and the in-row column positions.
+    int64_t own_G = 0, own_T = 0;
+    int own_ra = 0, own_ln_stride = 0, own_off_stride = 0;
+    int own_max_nodes = 0, own_max_img = 0, own_max_rows = 0;
+    int4 *own_groups = nullptr;
+    int32_t *own_node_ptr = nullptr, *own_nodes = nullptr, *own_elem = nullptr;
+    uint8_t *own_nphase = nullptr, *own_off = nullptr, *own_phase = nullptr;
+    uint16_t *own_ln = nullptr;
     int4 *spmv_desc = nullptr;
     uint16_t *spmv_roff = nullptr;
     uint8_t *spmv_lidx = nullptr;
@@ -120,6 +131,27 @@ struct AsmArgs {
 
 // Launchers (asm_kernels.hip).
 hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s);
+
+// Device copy of the row-owner plan of the 3x3-block momentum operator
+// (plan.h RowPlan), built on the first block assembly of a mesh.
+struct DevRowPlan {
+    int64_t n_tasks = 0, n_waves = 0, max_img = 0;
+    int stride = 0;
+    int32_t *conn = nullptr;       // [E][stride] mesh numbering
+    uint8_t *etype = nullptr;      // [E] node counts, or null (every element has stride nodes)
+    int32_t *task_elem = nullptr;
+    uint16_t *task_meta = nullptr;
+    uint8_t *task_cols = nullptr;  // [T][8]
+    int4 *wdesc = nullptr;         // {first task, tasks, first row, rows}
+    double *w_mindet = nullptr;    // [waves]
+    long long *w_bad = nullptr;    // [waves]
+};
+// values[nnz][3][3], rhs[3][N]: the momentum operator with the form bits'
+// terms (FE_FORM_FULL_STRESS, FE_FORM_EMAC) as 3x3 blocks; status word as
+// for launch_assemble.
+hipError_t launch_assemble_block(const DevMesh &m, const DevRowPlan &r, int form, double dt, const double *u,
+                                 const double *rho, const double *mu, double *values, double *rhs,
+                                 AsmStatus *status, hipStream_t s);
 
 // Solver launchers (solver_kernels.hip).
 struct CGWork {

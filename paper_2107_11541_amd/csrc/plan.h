@@ -85,6 +85,64 @@ struct Plan {
 int build_plan(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                const int32_t *conn, bool renumber, Plan &P, std::string &err);
 
+// Row-owner plan of the 3x3-block momentum operator (rowplan.cpp): tasks =
+// (element, row) pairs ordered by row, then element; whole rows packed into
+// waves of at most kRowTasksMax tasks and kRowImageDoubles block values.
+constexpr int kRowTasksMax = 64;
+constexpr int kRowImageDoubles = 3072;
+struct RowWave {
+    int32_t first_task, n_tasks, first_row, n_rows;
+};
+struct RowPlan {
+    int64_t n_tasks = 0, max_img = 0;
+    std::vector<int32_t> task_elem;    // [T] element (mesh order)
+    std::vector<uint16_t> task_meta;   // [T] local row a (bits 0-3) | phase in the row (bits 4-15)
+    std::vector<uint8_t> task_cols;    // [T][8] position of the element's node b in the row
+    std::vector<RowWave> wdesc;        // [waves]
+};
+// conn [E][stride] and rowptr/colidx in mesh numbering; etype [E] node
+// counts or NULL (every element has stride nodes).  0 or an fe_status code
+// with a message in err (FE_EBADMESH: a node in more than kRowTasksMax
+// elements).
+int build_row_plan(int stride, const uint8_t *etype, int64_t N, int64_t E, const int32_t *conn,
+                   const int32_t *rowptr, const int32_t *colidx, RowPlan &R, std::string &err);
+
+// Owner plan of the matrix assembly (rowplan.cpp): the CSR rows are cut
+// into groups of consecutive rows (mesh numbering, so spatially compact);
+// one work-group owns a group, computes every element contribution to its
+// rows and writes each row once.  A task is one lane's share: an element's
+// rows that the group owns, at most 4 of them for HEX08 (the element is
+// presented in a rotated node order that puts them on its first face; an
+// element with owned nodes on no single face gives two tasks), every row of
+// the element for the other types (rows the group does not own are
+// dropped).  Tasks of one phase hold distinct owned rows.
+constexpr int kOwnTasks = 256;            // lanes of an owner work-group
+constexpr int kOwnNodes = 1024;           // touched nodes of a group (uint16 local ids)
+using OwnLn = uint16_t;                   // a task's group-local node index
+constexpr int kOwnLdsBytes = 64 * 1024;   // LDS of a group for the momentum operator
+struct OwnGroup {
+    int32_t first_task, n_tasks, first_row, n_rows;
+};
+struct OwnerPlan {
+    int ra = 0;                          // rows per task (4 for HEX08, else nodes per element)
+    int ln_stride = 0, off_stride = 0;   // entries per task of tk_ln, bytes per task of tk_off
+    int max_nodes = 0, max_img = 0, max_rows = 0, max_phase = 0;
+    std::vector<OwnGroup> groups;
+    std::vector<int32_t> node_ptr, nodes;   // per group: owned rows first, then the halo ascending
+    std::vector<uint8_t> nphase;            // [groups]
+    std::vector<int32_t> tk_elem;           // [T] mesh element
+    std::vector<OwnLn> tk_ln;               // [T][ln_stride] local node of each (rotated) element node
+    std::vector<uint8_t> tk_off;            // [T][off_stride] position of column b in row r (owned rows)
+    std::vector<uint8_t> tk_phase;          // [T]
+};
+// Single-type meshes only (P.etype empty).  0 or an fe_status code with a
+// message in err.
+int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err);
+// The node order of a HEX08 element seen from face f (0..5: -z, +z, -y, +y,
+// -x, +x): kHexFaceRot[f][b] is the element's local node at the rotated
+// element's node b; nodes 0-3 of the rotated element are face f.
+extern const int kHexFaceRot[6][8];
+
 // Number of worker threads used by the host preprocessing.
 int host_threads();
 // Caps host_threads() for the calling thread (0: no cap); planner threads

@@ -329,7 +329,12 @@ void finish_host(fe_server_s *S, Job *j)
     double md;
     memcpy(&md, &as.min_det_key, 8);
     r.min_detJ = md;
-    r.first_bad_elem = as.first_bad >= 0 ? j->img->P.elem_perm[as.first_bad] : -1;
+    const bool bad_ok = as.first_bad < (long long)j->img->P.elem_perm.size();
+    r.first_bad_elem = as.first_bad >= 0 && bad_ok ? j->img->P.elem_perm[as.first_bad] : -1;
+    if (!bad_ok) {
+        r.status = FE_EDEVICE;
+        set_message(r, "assembly status names an element out of range");
+    }
     if (r.first_bad_elem >= 0) {
         r.status = FE_EBADELEM;
         set_message(r, "det J <= 0 in element " + std::to_string(r.first_bad_elem) + " (user id)");
