@@ -261,7 +261,8 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
     RTOL = 1e-8
 
     def run_plain(c):
-        mesh = fe.Mesh(ctx, c.elem_type, c.coords, c.conn, c.dirichlet, renumber=True)
+        # a mesh assembled once: the coloured blocks (no owner plan to build)
+        mesh = fe.Mesh(ctx, c.elem_type, c.coords, c.conn, c.dirichlet, renumber=True, coloured=True)
         u = mesh.to_mesh(torch.as_tensor(c.u, device="cuda"))
         rho = mesh.to_mesh(torch.as_tensor(c.rho, device="cuda"))
         mu = mesh.to_mesh(torch.as_tensor(c.mu, device="cuda"))

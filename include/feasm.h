@@ -57,6 +57,9 @@ typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_oper
 
 /* fe_mesh_upload flags */
 #define FE_UPLOAD_RENUMBER 1u   /* reorder elements along a Morton curve, nodes by first touch */
+#define FE_UPLOAD_COLOURED 2u   /* HEX08: assemble the matrix operators with the coloured element blocks
+                                 * (the serving runtime's form) instead of the owner groups; the two
+                                 * agree to rounding order */
 
 typedef struct fe_ctx_s *fe_ctx;
 typedef struct fe_mesh_s *fe_mesh;
@@ -371,7 +374,10 @@ fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const d
  *      request's arena space is returned for the next admission.
  * A request's numbers do not depend on the other requests in flight: its
  * work-group counts and summation orders are the ones of a request served
- * alone (and of fe_cg_solve on the same system).
+ * alone (and of fe_cg_solve on the same system, the mesh uploaded with
+ * FE_UPLOAD_COLOURED: served meshes are assembled by coloured element
+ * blocks, since the owner plan's host time exceeds the assembly time it saves
+ * for a mesh assembled once).
  *
  * Host arrays of a request are borrowed from fe_serve_submit until the
  * request is reported done; they must stay valid and unchanged until then.

@@ -143,7 +143,7 @@ size_t MeshImage::device_bytes() const
 
 int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                  const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
-                 MeshImage &I, std::string &err)
+                 MeshImage &I, std::string &err, bool owner_plan)
 {
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet_nodes)) {
         err = "bad Dirichlet list";
@@ -275,7 +275,7 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     // than the coloured element blocks for HEX08; for the other types the
     // coloured blocks are kept)
     I.O = OwnerPlan();
-    if (P.etype.empty() && P.nen == 8) {
+    if (owner_plan && P.etype.empty() && P.nen == 8) {
         st = build_owner_plan(P, I.O, err);
         if (st != FE_OK) return st;
         const OwnerPlan &O = I.O;
@@ -745,7 +745,7 @@ static fe_status mesh_upload(fe_ctx c, int stride, const uint8_t *types, int64_t
     auto img = std::make_unique<MeshImage>();
     std::string err;
     int st = mesh_prepare(stride, types, n_nodes, coords, n_elems, conn, n_dirichlet, dirichlet_nodes,
-                          (flags & FE_UPLOAD_RENUMBER) != 0, *img, err);
+                          (flags & FE_UPLOAD_RENUMBER) != 0, *img, err, (flags & FE_UPLOAD_COLOURED) == 0);
     if (st != FE_OK) return fail(c, (fe_status)st, "%s", err.c_str());
     auto *m = new fe_mesh_s();
     m->ctx = c;

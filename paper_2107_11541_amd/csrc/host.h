@@ -106,9 +106,12 @@ struct MeshImage {
 // Validates and plans a mesh on the host (no device calls).  0 or an
 // fe_status code with a message in err.
 // conn [n_elems][stride]; types as for build_plan (NULL: one type, stride nodes).
+// owner_plan: build the owner plan of the HEX08 matrix assembly (the
+// serving runtime, which assembles each mesh once, skips it: its host time
+// exceeds the assembly time it saves there).
 int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                  const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
-                 MeshImage &img, std::string &err);
+                 MeshImage &img, std::string &err, bool owner_plan = true);
 // Allocates (from m->arena or hipMalloc) and queues the copies of img on
 // `stream`.  img must stay alive until the copies have completed.
 fe_status mesh_commit(fe_mesh_s *m, MeshImage &img, hipStream_t stream);

@@ -129,7 +129,7 @@ void plan_job(Job *j, bool idle)
     } else {
         st = mesh_prepare(q.elem_types ? 8 : (int)q.type, q.elem_types, q.n_nodes, q.coords, q.n_elems, q.conn,
                           q.n_dirichlet,
-                          q.dirichlet_nodes, true, *j->img, err);
+                          q.dirichlet_nodes, true, *j->img, err, false);
     }
     if (st != FE_OK) {
         j->res.status = (fe_status)st;

@@ -101,7 +101,7 @@ def test_served_batch_beyond_residency_equals_plain_api(fe_ctx):
     assert st["mean_batch"] > 1.0
     for c, r in zip(cases, served):
         assert r["status"] == 0, r["message"]
-        mesh = fe.Mesh(fe_ctx, HEX, c.coords, c.conn, c.dirichlet)
+        mesh = fe.Mesh(fe_ctx, HEX, c.coords, c.conn, c.dirichlet, coloured=True)   # the served form
         L, f = _poisson(fe, mesh, c)
         x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
         x, info = fe.cg_solve(mesh, L, f, x=x, rtol=1e-8, max_iter=20000)

@@ -35,10 +35,10 @@ def _fe():
     return fe
 
 
-def gpu_assemble(ctx, case, op, precision=0, renumber=True, mesh=None):
+def gpu_assemble(ctx, case, op, precision=0, renumber=True, mesh=None, coloured=False):
     fe = _fe()
     if mesh is None:
-        mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=renumber)
+        mesh = fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=renumber, coloured=coloured)
     f = mesh_fields(mesh, case)
     kw = {}
     if op == SCA:
@@ -68,12 +68,30 @@ def check_parity(mesh, case, op, v, b, tol=TOL):
 
 # --- assembly ------------------------------------------------------------------
 
+@pytest.mark.parametrize("coloured", [False, True])
 @pytest.mark.parametrize("op", [MOM, POI])
-def test_hex_cfg0_assembly_parity(fe_ctx, op):
+def test_hex_cfg0_assembly_parity(fe_ctx, op, coloured):
+    """Owner groups (the HEX08 default) and coloured element blocks (the
+    served form) against the oracle."""
     case = meshgen.cfg0()
-    mesh, v, b, info = gpu_assemble(fe_ctx, case, op)
+    mesh, v, b, info = gpu_assemble(fe_ctx, case, op, coloured=coloured)
     check_parity(mesh, case, op, v, b)
     assert info["first_bad_elem"] == -1 and info["min_detJ"] > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hex_owner_and_coloured_forms_agree(fe_ctx, precision):
+    """The two HEX08 assembly forms on a jittered, shuffled 12^3 mesh: the
+    same sums in another order (FP64 1e-13, mixed 1e-6 of the row scale)."""
+    case = meshgen.make_case(12, meshgen.HEX08, 0.15, case_id=45, shuffle=True)
+    for op in (MOM, POI):
+        m1, v1, b1, _ = gpu_assemble(fe_ctx, case, op, precision=precision)
+        m2, v2, b2, _ = gpu_assemble(fe_ctx, case, op, precision=precision, coloured=True)
+        assert np.array_equal(m1.node_perm, m2.node_perm)
+        tol = 1e-13 if precision == 0 else 1e-6
+        assert rel(v1, v2) <= tol and rel(b1, b2) <= tol
+        m1.close()
+        m2.close()
 
 
 @pytest.mark.parametrize("n,shuffle,renumber", [(1, False, True), (3, True, True), (7, True, True),

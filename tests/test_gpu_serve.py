@@ -109,7 +109,7 @@ def test_served_equals_plain_api(fe_ctx):
     srv = fe.Server(fe_ctx, hbm_budget=1 << 30, max_slots=2, host_threads=1)
     served = srv.wait(_submit(srv, case, rtol=1e-9))
     srv.close()
-    mesh = fe.Mesh(fe_ctx, HEX, case.coords, case.conn, case.dirichlet)
+    mesh = fe.Mesh(fe_ctx, HEX, case.coords, case.conn, case.dirichlet, coloured=True)
     u, rho = mesh.to_mesh(dev(case.u)), mesh.to_mesh(dev(case.rho))
     L, f, _ = fe.assemble(mesh, fe.POISSON, case.dt, u, rho)
     fe.apply_dirichlet(mesh, L, f)
