@@ -57,9 +57,9 @@ typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_oper
 
 /* fe_mesh_upload flags */
 #define FE_UPLOAD_RENUMBER 1u   /* reorder elements along a Morton curve, nodes by first touch */
-#define FE_UPLOAD_COLOURED 2u   /* HEX08: assemble the matrix operators with the coloured element blocks
-                                 * (the serving runtime's form) instead of the owner groups; the two
-                                 * agree to rounding order */
+#define FE_UPLOAD_COLOURED 2u   /* single-type meshes: assemble the matrix operators with the coloured
+                                 * element blocks (the serving runtime's form, and always that of hybrid
+                                 * meshes) instead of the owner groups; the two agree to rounding order */
 
 typedef struct fe_ctx_s *fe_ctx;
 typedef struct fe_mesh_s *fe_mesh;
@@ -483,15 +483,20 @@ fe_status fe_plan_export_color_blocks(fe_plan plan, int32_t *color_blocks);
 /*
  * Owner plan of the matrix assembly of a single-type mesh (Section 4.2's
  * element loop regrouped by the CSR rows it writes; fe_assemble runs it for
- * MOMENTUM, SCALAR and POISSON on HEX08 meshes, and the coloured element
- * blocks for the other types and for hybrid meshes).  Rows, in mesh numbering, are
+ * MOMENTUM, SCALAR and POISSON on single-type meshes uploaded without
+ * FE_UPLOAD_COLOURED, and the coloured element blocks otherwise and for
+ * hybrid meshes).  Rows, in mesh numbering, are
  * cut into groups of consecutive rows; a work-group owns one group and
  * computes every element contribution to its rows.  A task is one lane's
  * share: an element's rows that the group owns -- for HEX08 at most 4, with
  * the element presented in a rotated node order that puts them on its first
  * face (two tasks when they lie on no single face), for the other types all
  * of the element's rows, the rows the group does not own being dropped.
- * fe_plan_owner_info: counts; FE_EINVAL for a hybrid plan.
+ * fe_plan_owner_info: counts, and *wave_private = 1 when each wavefront (64
+ * consecutive tasks of a group) accumulates into its own copy of the
+ * group's rows (the copies then summed in wave order; phases are then per
+ * wave), 0 for one shared copy with phases over the group (HEX08);
+ * FE_EINVAL for a hybrid plan.
  * fe_plan_export_owner (any pointer may be NULL):
  *   groups[4 n_groups] = {first task, tasks, first row, rows},
  *   node_ptr[n_groups + 1], nodes[node_ptr[n_groups]]: each group's touched
@@ -504,7 +509,7 @@ fe_status fe_plan_export_color_blocks(fe_plan plan, int32_t *color_blocks);
  *     the group does not own); task_phase[n_tasks].
  */
 fe_status fe_plan_owner_info(fe_plan plan, int64_t *n_groups, int64_t *n_tasks, int32_t *rows_per_task,
-                             int32_t *ln_stride, int32_t *off_stride);
+                             int32_t *ln_stride, int32_t *off_stride, int32_t *wave_private);
 fe_status fe_plan_export_owner(fe_plan plan, int32_t *groups, int32_t *node_ptr, int32_t *nodes, uint8_t *nphase,
                                int32_t *task_elem, uint16_t *task_ln, uint8_t *task_off, uint8_t *task_phase);
 void fe_plan_free(fe_plan plan);

@@ -618,12 +618,14 @@ class Plan:
     def export_owner(self) -> dict:
         """The owner plan of the matrix assembly (single-type meshes)."""
         G, T = C.c_int64(), C.c_int64()
-        ra, lns, offs = C.c_int32(), C.c_int32(), C.c_int32()
-        st = self.lib.fe_plan_owner_info(self.h, C.byref(G), C.byref(T), C.byref(ra), C.byref(lns), C.byref(offs))
+        ra, lns, offs, priv = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        st = self.lib.fe_plan_owner_info(self.h, C.byref(G), C.byref(T), C.byref(ra), C.byref(lns), C.byref(offs),
+                                         C.byref(priv))
         if st != capi.FE_OK:
             raise FeError(st, "no owner plan (hybrid mesh)")
         G, T = G.value, T.value
         out = {"rows_per_task": ra.value, "ln_stride": lns.value, "off_stride": offs.value,
+               "wave_private": bool(priv.value),
                "groups": np.zeros((G, 4), np.int32), "node_ptr": np.zeros(G + 1, np.int32),
                "nphase": np.zeros(G, np.uint8), "task_elem": np.zeros(T, np.int32),
                "task_ln": np.zeros((T, lns.value), np.uint16), "task_off": np.zeros((T, offs.value), np.uint8),

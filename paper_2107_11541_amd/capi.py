@@ -107,7 +107,7 @@ SIGNATURES = {
     "fe_plan_info": (C.c_int, [P, C.POINTER(PlanDesc)]),
     "fe_plan_export": (C.c_int, [P, P, P, P, P, P, P, P, P]),
     "fe_plan_owner_info": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
-                                     C.POINTER(i32)]),
+                                     C.POINTER(i32), C.POINTER(i32)]),
     "fe_plan_export_owner": (C.c_int, [P, P, P, P, P, P, P, P, P]),
     "fe_plan_free": (None, [P]),
     "fe_plan_last_error": (C.c_char_p, []),

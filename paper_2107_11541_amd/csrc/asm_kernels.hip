@@ -716,7 +716,10 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_residual(KArgs k)
 //   3. phase by phase (a barrier between phases), add the owned rows of the
 //      tasks of that phase into LDS: the tasks of one phase hold distinct
 //      owned rows, so no two lanes add to one address and the order of the
-//      sums is fixed by the plan;
+//      sums is fixed by the plan.  Wave-private form (PRIV, element types
+//      whose nodes lie in many elements): each wave adds into its own copy
+//      of the rows, phases within the wave, no barriers; the copies are
+//      then summed in wave order;
 //   4. write the rows (contiguous in CSR) and right-hand sides once.
 struct OArgs {
     const double *X;
@@ -736,7 +739,7 @@ struct OArgs {
 
 template <class EL> struct OwnRows { static constexpr int RA = EL::NEN == 8 ? 4 : EL::NEN; };
 
-template <class EL, int OP, class Q>
+template <class EL, int OP, class Q, bool PRIV>
 __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
 {
     constexpr int NEN = EL::NEN, RA = OwnRows<EL>::RA;
@@ -749,9 +752,12 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
     const int64_t v0 = k.rowptr[r0];
     const int L = (int)(k.rowptr[r0 + nr] - v0);
     const int64_t N = k.N;
+    constexpr int NC = PRIV ? kOwnTasks / 64 : 1;   // copies of the rows
     double *nd = lds;               // [NF][T] fields of the touched nodes
-    double *img = nd + NF * T;      // [L] the owned rows
-    double *rimg = img + L;         // [NRHS][nr] their right-hand sides
+    double *img0 = nd + NF * T;     // [NC][L] the owned rows
+    double *rimg0 = img0 + NC * L;  // [NC][NRHS][nr] their right-hand sides
+    double *img = img0 + (PRIV ? (tid >> 6) * L : 0);                 // this wave's copy
+    double *rimg = rimg0 + (PRIV ? (tid >> 6) * NRHS * nr : 0);
 
     // task data first: its loads overlap the staging below
     const bool live = tid < gd.y;
@@ -787,8 +793,8 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
 #pragma unroll
         for (int c = 0; c < NF; ++c) nd[c * T + q] = f[c];
     }
-    for (int q = tid; q < L; q += kOwnTasks) img[q] = 0.0;
-    for (int q = tid; q < NRHS * nr; q += kOwnTasks) rimg[q] = 0.0;
+    for (int q = tid; q < NC * L; q += kOwnTasks) img0[q] = 0.0;
+    for (int q = tid; q < NC * NRHS * nr; q += kOwnTasks) rimg0[q] = 0.0;
     __syncthreads();
 
     // 2. this lane's rows
@@ -831,14 +837,24 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
                 for (int q = 0; q < NRHS; ++q) lds_add(&rimg[q * nr + ln[r]], (double)B[q][r]);
             }
         }
-        __syncthreads();
+        if (!PRIV) __syncthreads();
     }
+    if (PRIV) __syncthreads();
 
-    // 4. write the owned rows and right-hand sides once
-    for (int q = tid; q < L; q += kOwnTasks) k.values[v0 + q] = img[q];
+    // 4. write the owned rows and right-hand sides once (the wave copies
+    //    summed in wave order)
+    for (int q = tid; q < L; q += kOwnTasks) {
+        double v = img0[q];
+#pragma unroll
+        for (int c = 1; c < NC; ++c) v += img0[c * L + q];
+        k.values[v0 + q] = v;
+    }
     for (int q = tid; q < NRHS * nr; q += kOwnTasks) {
         const int c = q / nr, i = q - c * nr;
-        k.rhs[c * N + r0 + i] = rimg[q];
+        double v = rimg0[q];
+#pragma unroll
+        for (int w = 1; w < NC; ++w) v += rimg0[w * NRHS * nr + q];
+        k.rhs[c * N + r0 + i] = v;
     }
     // status: the group's smallest det J and first element with det J <= 0
     __shared__ double smd[kOwnTasks / 64];
@@ -867,11 +883,14 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
     }
 }
 
+// HEX08 accumulates into one copy of the group's rows, the other types
+// wave-privately (the planner's choice, OwnerPlan::wave_private).
 template <class EL, int OP>
 void launch_own_op(const OArgs &k, int64_t G, size_t lds, bool mixed, hipStream_t s)
 {
-    if (mixed) hipLaunchKernelGGL((k_own<EL, OP, float>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
-    else hipLaunchKernelGGL((k_own<EL, OP, double>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
+    constexpr bool PRIV = EL::NEN != 8;
+    if (mixed) hipLaunchKernelGGL((k_own<EL, OP, float, PRIV>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
+    else hipLaunchKernelGGL((k_own<EL, OP, double, PRIV>), dim3((unsigned)G), dim3(kOwnTasks), lds, s, k);
 }
 
 template <class EL>
@@ -1382,7 +1401,10 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
         o.g_mindet = k.blk_mindet;
         o.g_bad = k.blk_bad;
         const int nf = a.op == OP_POI ? 7 : 8, nrhs = a.op == OP_MOM ? 3 : 1;
-        const size_t lds = (size_t)(nf * m.own_max_nodes + m.own_max_img + nrhs * m.own_max_rows) * sizeof(double);
+        const int copies = m.own_priv ? kOwnTasks / 64 : 1;
+        if ((m.own_priv != 0) != (m.nen != 8)) return hipErrorInvalidValue;   // plan and kernel disagree
+        const size_t lds =
+            (size_t)(nf * m.own_max_nodes + copies * (m.own_max_img + nrhs * m.own_max_rows)) * sizeof(double);
         switch (m.nen) {
         case 8: launch_own<Hex>(o, a.op, m.own_G, lds, mixed, s); break;
         case 6: launch_own<Pen>(o, a.op, m.own_G, lds, mixed, s); break;

@@ -271,17 +271,16 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         }
         d.launches.push_back(L);
     }
-    // the owner plan of the matrix assembly: HEX08 meshes (measured faster
-    // than the coloured element blocks for HEX08; for the other types the
-    // coloured blocks are kept)
+    // the owner plan of the matrix assembly (meshes of one element type)
     I.O = OwnerPlan();
-    if (owner_plan && P.etype.empty() && P.nen == 8) {
+    if (owner_plan && P.etype.empty()) {
         st = build_owner_plan(P, I.O, err);
         if (st != FE_OK) return st;
         const OwnerPlan &O = I.O;
         d.own_G = (int64_t)O.groups.size();
         d.own_T = (int64_t)O.tk_elem.size();
         d.own_ra = O.ra;
+        d.own_priv = O.wave_private ? 1 : 0;
         d.own_ln_stride = O.ln_stride;
         d.own_off_stride = O.off_stride;
         d.own_max_nodes = O.max_nodes;
@@ -1383,7 +1382,7 @@ fe_status fe_plan_export_color_blocks(fe_plan p, int32_t *color_blocks)
 }
 
 fe_status fe_plan_owner_info(fe_plan p, int64_t *n_groups, int64_t *n_tasks, int32_t *rows_per_task,
-                             int32_t *ln_stride, int32_t *off_stride)
+                             int32_t *ln_stride, int32_t *off_stride, int32_t *wave_private)
 {
     if (!p) return FE_EINVAL;
     const OwnerPlan &O = p->O;
@@ -1393,6 +1392,7 @@ fe_status fe_plan_owner_info(fe_plan p, int64_t *n_groups, int64_t *n_tasks, int
     if (rows_per_task) *rows_per_task = O.ra;
     if (ln_stride) *ln_stride = O.ln_stride;
     if (off_stride) *off_stride = O.off_stride;
+    if (wave_private) *wave_private = O.wave_private ? 1 : 0;
     return FE_OK;
 }
 

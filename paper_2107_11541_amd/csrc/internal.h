@@ -59,7 +59,7 @@ struct DevMesh {
     // nodes (owned rows first), phases, and per task the element, the local
     // node of each (rotated) element node and the in-row column positions.
     int64_t own_G = 0, own_T = 0;
-    int own_ra = 0, own_ln_stride = 0, own_off_stride = 0;
+    int own_ra = 0, own_ln_stride = 0, own_off_stride = 0, own_priv = 0;
     int own_max_nodes = 0, own_max_img = 0, own_max_rows = 0;
     int4 *own_groups = nullptr;
     int32_t *own_node_ptr = nullptr, *own_nodes = nullptr, *own_elem = nullptr;

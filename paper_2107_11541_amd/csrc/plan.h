@@ -115,7 +115,8 @@ int build_row_plan(int stride, const uint8_t *etype, int64_t N, int64_t E, const
 // presented in a rotated node order that puts them on its first face; an
 // element with owned nodes on no single face gives two tasks), every row of
 // the element for the other types (rows the group does not own are
-// dropped).  Tasks of one phase hold distinct owned rows.
+// dropped).  Tasks of one phase hold distinct owned rows (of the group, or,
+// for wave-private accumulation, of the wave).
 constexpr int kOwnTasks = 256;            // lanes of an owner work-group
 constexpr int kOwnNodes = 1024;           // touched nodes of a group (uint16 local ids)
 using OwnLn = uint16_t;                   // a task's group-local node index
@@ -125,6 +126,9 @@ struct OwnGroup {
 };
 struct OwnerPlan {
     int ra = 0;                          // rows per task (4 for HEX08, else nodes per element)
+    bool wave_private = false;           // each wave accumulates into its own copy of the group's rows
+                                         // (phases per wave, no barriers; the copies are summed in wave
+                                         // order); else one copy, phases over the group with barriers
     int ln_stride = 0, off_stride = 0;   // entries per task of tk_ln, bytes per task of tk_off
     int max_nodes = 0, max_img = 0, max_rows = 0, max_phase = 0;
     std::vector<OwnGroup> groups;

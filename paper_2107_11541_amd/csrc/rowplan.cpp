@@ -154,6 +154,11 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
     const int64_t N = P.N, E = P.E;
     const bool hex = nen == 8;
     O.ra = hex ? 4 : nen;
+    // the other types' nodes lie in many elements (24 for a Kuhn
+    // tetrahedron's), which would make as many barrier-separated phases:
+    // their waves accumulate privately instead
+    O.wave_private = !hex;
+    const int copies = O.wave_private ? kOwnTasks / 64 : 1;
     O.ln_stride = nen;
     O.off_stride = (O.ra * nen + 3) & ~3;
     const int32_t *conn = P.conn.data();
@@ -184,7 +189,7 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
             for (int a = 0; a < nen; ++a) inc[fill[conn[e * nen + a]]++] = (int32_t)(e * 8 + a);
     }
     auto lds_bytes = [&](int64_t tn, int64_t img, int64_t nr) {
-        return (kNodeFields * tn + img + kMaxRhs * nr) * 8;
+        return (kNodeFields * tn + copies * (img + kMaxRhs * nr)) * 8;
     };
 
     // 1. groups of consecutive rows: row r joins the open group unless the
@@ -328,7 +333,7 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
             OwnLn ln[8];
         };
         std::vector<Tk> tk;
-        std::vector<int32_t> cnt;
+        std::vector<int32_t> cnt, wcnt, wfill, wof;
         for (int64_t g = t; g < G; g += nt) {
             const int32_t a0 = gstart[g], a1 = gstart[g + 1], nr = a1 - a0;
             int32_t *gn = O.nodes.data() + O.node_ptr[g];
@@ -366,10 +371,8 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
                 Tk x{};
                 x.e = e;
                 for (int b = 0; b < nen; ++b) x.ln[b] = (OwnLn)lidx[conn[(int64_t)e * nen + (rot ? rot[b] : b)]];
-                uint64_t m[4] = {0, 0, 0, 0};   // phases taken by the task's owned rows
                 for (int r = 0; r < O.ra; ++r) {
                     if (x.ln[r] >= nr) continue;   // a row another group owns
-                    for (int w = 0; w < 4; ++w) m[w] |= used[4 * (size_t)x.ln[r] + w];
                     const uint8_t *pr = pos.data() + (size_t)x.ln[r] * T_g;
                     for (int b = 0; b < nen; ++b) {
                         const uint8_t o = pr[x.ln[b]];
@@ -377,6 +380,15 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
                         x.off[r * nen + b] = o;
                     }
                 }
+                tk.push_back(x);
+            };
+            // greedy phase: the smallest one none of the task's owned rows has
+            // taken (among the tasks sharing its accumulation copy)
+            auto take_phase = [&](Tk &x) {
+                uint64_t m[4] = {0, 0, 0, 0};
+                for (int r = 0; r < O.ra; ++r)
+                    if (x.ln[r] < nr)
+                        for (int w = 0; w < 4; ++w) m[w] |= used[4 * (size_t)x.ln[r] + w];
                 int ph = 0;
                 while (ph < 256 && ((m[ph >> 6] >> (ph & 63)) & 1)) ++ph;
                 if (ph >= 256) {   // cannot happen: a group holds at most 256 tasks
@@ -387,7 +399,6 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
                     if (x.ln[r] < nr) used[4 * (size_t)x.ln[r] + (ph >> 6)] |= 1ull << (ph & 63);
                 x.ph = (uint8_t)ph;
                 nph = std::max(nph, ph + 1);
-                tk.push_back(x);
             };
             for (int32_t e : elems) {
                 const uint8_t m = owned_mask(e, a0, a1);
@@ -403,22 +414,69 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err)
                 }
             }
             if ((int32_t)tk.size() != gtasks[g] || (int)tk.size() > kOwnTasks) gbad[g] = 1;
-            // tasks by phase, stably (a counting sort): a wave then spans
-            // few phases and skips the others' LDS additions
-            cnt.assign(nph + 1, 0);
-            for (const Tk &x : tk) ++cnt[x.ph + 1];
-            for (int p = 0; p < nph; ++p) cnt[p + 1] += cnt[p];
-            const int64_t t0 = O.groups[g].first_task;
-            for (const Tk &x : tk) {
-                const int64_t d = t0 + cnt[x.ph]++;
-                if (d >= t0 + gtasks[g]) {
-                    gbad[g] = 1;
-                    continue;
+            if (O.wave_private) {
+                // spread each row's tasks over the waves: a task goes to the
+                // wave (with room) where its owned rows have the fewest tasks
+                // yet, which bounds the phases each wave steps through
+                const int nw = (int)((tk.size() + 63) / 64);
+                wcnt.assign((size_t)nw * nr, 0);
+                wfill.assign(nw, 0);
+                wof.resize(tk.size());
+                // every wave but the last holds exactly 64 tasks (a task's
+                // wave is its lane / 64 in the kernel)
+                auto cap = [&](int w) { return w < nw - 1 ? 64 : (int)tk.size() - 64 * (nw - 1); };
+                for (size_t q = 0; q < tk.size(); ++q) {
+                    int best = -1, bcost = 1 << 30;
+                    for (int w = 0; w < nw; ++w) {
+                        if (wfill[w] >= cap(w)) continue;
+                        int c = 0;
+                        for (int r = 0; r < O.ra; ++r)
+                            if (tk[q].ln[r] < nr) c = std::max(c, wcnt[(size_t)w * nr + tk[q].ln[r]]);
+                        if (c < bcost) {
+                            bcost = c;
+                            best = w;
+                        }
+                    }
+                    wof[q] = best;
+                    ++wfill[best];
+                    for (int r = 0; r < O.ra; ++r)
+                        if (tk[q].ln[r] < nr) ++wcnt[(size_t)best * nr + tk[q].ln[r]];
                 }
-                O.tk_elem[d] = x.e;
-                O.tk_phase[d] = x.ph;
-                memcpy(&O.tk_ln[(size_t)d * O.ln_stride], x.ln, O.ln_stride * sizeof(OwnLn));
-                memcpy(&O.tk_off[(size_t)d * O.off_stride], x.off, O.off_stride);
+                std::vector<Tk> by;   // tasks wave by wave, each wave in generation order
+                for (int w = 0; w < nw; ++w) {
+                    used.assign(4 * (size_t)nr, 0);
+                    for (size_t q = 0; q < tk.size(); ++q)
+                        if (wof[q] == w) {
+                            take_phase(tk[q]);
+                            by.push_back(tk[q]);
+                        }
+                }
+                tk.swap(by);
+            } else {
+                for (Tk &x : tk) take_phase(x);
+            }
+            // tasks by phase, stably (a counting sort), over the group or,
+            // wave-private, within each wave's 64: a wave then spans few
+            // phases and skips the others' LDS additions
+            const int64_t t0 = O.groups[g].first_task;
+            const size_t span = O.wave_private ? 64 : tk.size() + 1;
+            for (size_t w0 = 0; w0 < tk.size(); w0 += span) {
+                const size_t w1 = std::min(tk.size(), w0 + span);
+                cnt.assign(nph + 1, 0);
+                for (size_t q = w0; q < w1; ++q) ++cnt[tk[q].ph + 1];
+                for (int p = 0; p < nph; ++p) cnt[p + 1] += cnt[p];
+                for (size_t q = w0; q < w1; ++q) {
+                    const Tk &x = tk[q];
+                    const int64_t d = t0 + (int64_t)w0 + cnt[x.ph]++;
+                    if (d >= t0 + gtasks[g]) {
+                        gbad[g] = 1;
+                        continue;
+                    }
+                    O.tk_elem[d] = x.e;
+                    O.tk_phase[d] = x.ph;
+                    memcpy(&O.tk_ln[(size_t)d * O.ln_stride], x.ln, O.ln_stride * sizeof(OwnLn));
+                    memcpy(&O.tk_off[(size_t)d * O.off_stride], x.off, O.off_stride);
+                }
             }
             if (nph > 255) gbad[g] = 1;   // phase counts are stored in a byte
             O.nphase[g] = (uint8_t)nph;

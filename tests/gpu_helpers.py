@@ -72,11 +72,12 @@ def submesh_rows(case, nodes):
     return case.coords[glob], loc[sub].astype(np.int32), loc, glob
 
 
-def make_mesh(ctx, case, renumber=True):
-    """Upload a case: fe_mesh_upload, or fe_mesh_upload_mixed for a hybrid one."""
+def make_mesh(ctx, case, renumber=True, coloured=False):
+    """Upload a case: fe_mesh_upload, or fe_mesh_upload_mixed for a hybrid one
+    (always coloured element blocks)."""
     import paper_2107_11541_amd as fe
     if case.types is None:
-        return fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=renumber)
+        return fe.Mesh(ctx, case.nen, case.coords, case.conn, case.dirichlet, renumber=renumber, coloured=coloured)
     return fe.Mesh(ctx, fe.HYBRID, case.coords, case.conn, case.dirichlet, renumber=renumber, types=case.types)
 
 

@@ -194,7 +194,7 @@ def test_hybrid_and_prism_requests_in_a_mix(fe_ctx):
     for key, case in (("hyb", hyb), ("pen", pen)):
         r = res[key]
         assert r["status"] == 0, (key, r["message"])
-        mesh = make_mesh(fe_ctx, case)
+        mesh = make_mesh(fe_ctx, case, coloured=True)   # the served form
         u, rho = mesh.to_mesh(dev(case.u)), mesh.to_mesh(dev(case.rho))
         L, f, _ = fe.assemble(mesh, fe.POISSON, case.dt, u, rho)
         fe.apply_dirichlet(mesh, L, f)

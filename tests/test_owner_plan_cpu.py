@@ -12,7 +12,8 @@ element type.
   computed by exactly one task;
 * in-row offsets point at the right CSR columns;
 * the tasks of one phase hold distinct owned rows (conflict-free, fixed-order
-  LDS accumulation).
+  LDS accumulation): over the group for HEX08, within each wavefront of 64
+  tasks for the types that accumulate wave-privately.
 """
 import numpy as np
 import pytest
@@ -41,6 +42,8 @@ def test_owner_plan_invariants(kind, n, renumber):
     nen = case.nen
     ra = ow["rows_per_task"]
     assert ra == (4 if nen == 8 else nen)
+    priv = ow["wave_private"]
+    assert priv == (nen != 8)
     cm = mesh_conn(case, ex)
     rp, ci = ex["rowptr"], ex["colidx"]
     N = rp.size - 1
@@ -78,7 +81,7 @@ def test_owner_plan_invariants(kind, n, renumber):
                 assert np.isclose(np.linalg.det(R), 1.0)
             else:
                 assert np.array_equal(tn, cm[e])
-            ph = int(ow["task_phase"][t])
+            ph = (int(ow["task_phase"][t]), (t - t0) // 64 if priv else 0)
             for r in range(ra):
                 if ln[r] >= nr:
                     continue
@@ -91,39 +94,47 @@ def test_owner_plan_invariants(kind, n, renumber):
                 cols = ci[rp[row]:rp[row + 1]]
                 for b in range(nen):
                     assert cols[ow["task_off"][t, r * nen + b]] == tn[b]
-        assert ow["nphase"][g] == max(rows_in_phase) + 1
+        assert ow["nphase"][g] == max(p for p, _ in rows_in_phase) + 1
         # every (element, owned row) contribution of the group is computed once
         want = {(e, row) for row in range(r0, r0 + nr) for e in elems_of[row]}
         assert set(covered) == want
 
 
-def test_owner_plan_high_valence_node():
-    """A TET04 node in 80 elements: its row's 80 tasks need 80 phases (more
-    than one 64-bit mask of them), and the invariants still hold."""
+@pytest.mark.parametrize("nen", [4, 8])
+def test_owner_plan_high_valence_node(nen):
+    """A node in many elements (the planner does not look at the geometry):
+    80 TET04 (a 241-entry row), whose tasks the wave-private accumulation
+    spreads over waves, or 36 HEX08 (a 253-entry row, near the 255 limit),
+    whose shared accumulation needs 36 phases for the row.  The phase
+    invariants hold either way."""
     rng = np.random.default_rng(3)
-    nf, tail = 80, 200
-    N = 1 + 3 * nf + tail
-    conn = [[0, 1 + 3 * k, 2 + 3 * k, 3 + 3 * k] for k in range(nf)]
-    extra = list(range(1 + 3 * nf, N))
-    conn += [[extra[k], extra[k + 1], extra[k + 2], extra[k + 3]] for k in range(len(extra) - 3)]
+    nf, tail = (80 if nen == 4 else 36), 200
+    k = nen - 1
+    N = 1 + k * nf + tail
+    conn = [[0] + [1 + k * q + j for j in range(k)] for q in range(nf)]
+    extra = list(range(1 + k * nf, N))
+    conn += [extra[q:q + nen] for q in range(len(extra) - nen + 1)]
     conn = np.array(conn, np.int32)
-    P = fe.Plan(meshgen.TET04, rng.random((N, 3)), conn)
+    P = fe.Plan(nen, rng.random((N, 3)), conn)
     ow = P.export_owner()
-    assert ow["nphase"].max() >= 80
+    priv = ow["wave_private"]
+    assert priv == (nen != 8)
+    assert ow["nphase"].max() >= (36 if not priv else 4)
     ex = P.export()
     iperm = np.empty_like(ex["node_perm"])
     iperm[ex["node_perm"]] = np.arange(N)
     cm = iperm[conn[ex["elem_perm"]]]
+    ra = ow["rows_per_task"]
     for g, (t0, nt, r0, nr) in enumerate(ow["groups"]):
         nodes = ow["nodes"][ow["node_ptr"][g]:ow["node_ptr"][g + 1]]
         seen = {}
         for t in range(t0, t0 + nt):
-            tn = nodes[ow["task_ln"][t, :4].astype(np.int64)]
-            assert np.array_equal(tn, cm[ow["task_elem"][t]])
-            for r in range(4):
+            tn = nodes[ow["task_ln"][t, :nen].astype(np.int64)]
+            assert sorted(tn) == sorted(cm[ow["task_elem"][t]])
+            for r in range(ra):
                 if tn[r] < r0 or tn[r] >= r0 + nr:
                     continue
-                key = (int(ow["task_phase"][t]), int(tn[r]))
+                key = (int(ow["task_phase"][t]), (t - t0) // 64 if priv else 0, int(tn[r]))
                 assert key not in seen
                 seen[key] = t
 
