@@ -94,8 +94,12 @@ fe_status fe_ctx_set_stream(fe_ctx ctx, void *hip_stream);
  *   dirichlet_nodes host [n_dirichlet] user node ids, or NULL if n_dirichlet = 0
  * Builds the canonical CSR pattern (row i = every node sharing an element
  * with node i, columns ascending, explicit zeros kept), the element blocks,
- * their colouring and the scatter plan.  Errors: FE_EINVAL, FE_EBADMESH,
- * FE_ENOMEM, FE_EDEVICE.  The mesh owns all its device memory.
+ * their colouring and the scatter plan.  Errors: FE_EINVAL, FE_EBADMESH
+ * (a connectivity entry out of range, a node in no element, or a node whose
+ * CSR row would hold more than 255 entries: the scatter plans store in-row
+ * positions as bytes; a hexahedral node may lie in up to 36 elements, a
+ * tetrahedral one in up to ~80), FE_ENOMEM, FE_EDEVICE.  The mesh owns all
+ * its device memory.
  */
 fe_status fe_mesh_upload(fe_ctx ctx, fe_elem_type type, int64_t n_nodes, const double *coords,
                          int64_t n_elems, const int32_t *conn, int64_t n_dirichlet,

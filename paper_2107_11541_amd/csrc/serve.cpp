@@ -369,6 +369,7 @@ void fail_job(fe_server_s *S, Job *j, fe_status s, const std::string &msg)
 // ---- dispatcher ----------------------------------------------------------------
 
 constexpr int kPollEvery = 4;      // batched iterations between flag copies
+constexpr int kMaxBypass = 8;      // admissions that may pass a request that does not fit
 constexpr int kMaxRunAhead = 24;   // iterations launched past an unread poll
 
 void dispatcher_main(fe_server_s *S)
@@ -401,11 +402,14 @@ void dispatcher_main(fe_server_s *S)
             }
         }
         // 2. admissions, in ticket order; a request that does not fit may be
-        // passed by later ones, at most 8 times
+        // passed by later ones: each admission past it counts, and after
+        // kMaxBypass of them nothing behind it is admitted until it fits
+        std::vector<Job *> passed;   // requests of this pass that did not fit
         for (size_t i = 0; i < S->ready.size() && !S->free_slots.empty();) {
             Job *j = S->ready[i];
             if (j->bytes > S->arena->free_bytes()) {
-                if (++j->skipped > 8) break;
+                if (j->skipped >= kMaxBypass) break;
+                passed.push_back(j);
                 ++i;
                 continue;
             }
@@ -432,6 +436,7 @@ void dispatcher_main(fe_server_s *S)
             j->t_admitted = Clock::now();
             j->k = 0;
             S->active.push_back(j);
+            for (Job *p : passed) ++p->skipped;   // j was admitted ahead of them
         }
         // 3. idle?
         if (S->active.empty()) {

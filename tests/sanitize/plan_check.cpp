@@ -1,0 +1,66 @@
+// plan_check.cpp -- runs the host planner (csrc/plan.cpp, csrc/rowplan.cpp)
+// under AddressSanitizer / UndefinedBehaviorSanitizer on small meshes of every
+// kind, renumbered and not, and checks a few of its invariants.  Test
+// infrastructure: built and run by tests/test_sanitizers_cpu.py.
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../paper_2107_11541_amd/csrc/plan.h"
+#include "meshes.h"
+
+using namespace feasm;
+
+static int fails = 0;
+#define CHECK(c)                                                    \
+    do {                                                            \
+        if (!(c)) {                                                 \
+            fprintf(stderr, "check failed: %s (line %d)\n", #c, __LINE__); \
+            ++fails;                                                \
+        }                                                           \
+    } while (0)
+
+int main()
+{
+    for (int kind = 0; kind < 3; ++kind)
+        for (int renumber = 0; renumber < 2; ++renumber)
+            for (int n : {1, 3, 6}) {
+                SanMesh m = san_cube(n, kind);
+                Plan P;
+                std::string err;
+                const int st = build_plan(m.stride, m.types, m.n_nodes, m.coords, m.n_elems, m.conn, renumber != 0,
+                                          P, err);
+                CHECK(st == 0);
+                if (st != 0) {
+                    fprintf(stderr, "build_plan: %s\n", err.c_str());
+                    san_free(&m);
+                    continue;
+                }
+                CHECK(P.rowptr.size() == (size_t)m.n_nodes + 1);
+                for (int64_t i = 0; i < m.n_nodes; ++i)
+                    for (int32_t q = P.rowptr[i] + 1; q < P.rowptr[i + 1]; ++q) CHECK(P.colidx[q - 1] < P.colidx[q]);
+                // the 3x3-block operator's row plan
+                RowPlan R;
+                CHECK(build_row_plan(P.nen, P.etype.empty() ? nullptr : P.etype.data(), P.N, P.E, P.conn.data(),
+                                     P.rowptr.data(), P.colidx.data(), R, err) == 0);
+                int64_t rows = 0;
+                for (const RowWave &w : R.wdesc) rows += w.n_rows;
+                CHECK(rows == m.n_nodes);
+                // the owner plan (single-type meshes)
+                if (P.etype.empty()) {
+                    OwnerPlan O;
+                    CHECK(build_owner_plan(P, O, err) == 0);
+                    int64_t r = 0, t = 0;
+                    for (const OwnGroup &g : O.groups) {
+                        CHECK(g.first_row == r && g.first_task == t);
+                        CHECK(g.n_tasks >= 1 && g.n_tasks <= kOwnTasks);
+                        r += g.n_rows;
+                        t += g.n_tasks;
+                    }
+                    CHECK(r == m.n_nodes && t == (int64_t)O.tk_elem.size());
+                }
+                san_free(&m);
+            }
+    printf("plan_check: %d failed checks\n", fails);
+    return fails ? 1 : 0;
+}
