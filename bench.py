@@ -237,7 +237,7 @@ def cpu_baseline(sample_n: int, workload: str = "hex128"):
     }
 
 
-def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8", "load1.5")):
+def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8", "load1.5"), records=None):
     """Serving workload: the first nreq requests of the serving stream,
     independent HEX08 cubes (side 8..96, log-uniform), each a momentum +
     Poisson assembly and a Jacobi-PCG solve to a true relative residual of
@@ -285,6 +285,10 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
         _, info = run_plain(c)
         seq_s[i] = time.perf_counter() - t0
         seq_res[i] = info["true_rel_residual"]
+        if records is not None:
+            records.append({"record": "request", "mode": "sequential_fp64", "request": i, "side": int(sides[i]),
+                            "elements": int(elems[i]), "service_ms": seq_s[i] * 1e3,
+                            "iterations": info["iterations"], "true_rel_residual": info["true_rel_residual"]})
     seq_total = time.perf_counter() - t_all
     mean_s = float(seq_s.mean())
     log(f"sequential FP64: {nreq / seq_total:.2f} solves/s, mean service {mean_s * 1e3:.1f} ms, "
@@ -297,7 +301,7 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
             out[i] = done - arr[i]
         return out
 
-    def run_served(qps):
+    def run_served(qps, mode):
         srv = fe.Server(ctx, hbm_budget=budget_gb << 30, max_slots=slots, host_threads=threads)
         arr = t_unit / qps if qps else np.zeros(nreq)
         tickets = [None] * nreq
@@ -325,6 +329,12 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
         srv.close()
         lat = np.array([r["total_ms"] for r in res])
         bad = [r for r in res if r["status"] != 0 or not r["true_rel_residual"] <= RTOL * 1.0001]
+        if records is not None:
+            for i, r in enumerate(res):
+                records.append({"record": "request", "mode": mode, "request": i, "side": int(sides[i]),
+                                "elements": int(elems[i]), "arrival_s": float(arr[i]), "status": r["status"],
+                                **{k: r[k] for k in ("plan_ms", "wait_ms", "run_ms", "total_ms", "iterations",
+                                                     "true_rel_residual")}})
         return {"qps_offered": qps, "solves_per_s": nreq / wall, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_batch": st["mean_batch"],
                 "max_true_rel_residual": float(max(r["true_rel_residual"] for r in res)), "failed": len(bad),
@@ -336,7 +346,7 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
     loads = {"load0.8": 0.8, "load1.5": 1.5}
     runs = {}
     for name in modes:
-        runs[name] = run_served(None if name == "saturated" else loads[name] * cap)
+        runs[name] = run_served(None if name == "saturated" else loads[name] * cap, name)
         log(f"served {name}: {json.dumps(runs[name])}")
     seq = {"solves_per_s": nreq / seq_total, "mean_service_ms": mean_s * 1e3,
            "max_true_rel_residual": float(seq_res.max())}
@@ -354,8 +364,20 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
                                                 if "saturated" in runs else None)}
 
 
+def write_records(path, line, records):
+    """JSONL: one record per request of the serving runs, then the run's line."""
+    if not path:
+        return
+    with open(path, "a") as fh:
+        for r in records:
+            fh.write(json.dumps(r) + "\n")
+        fh.write(json.dumps(dict(line, record="run", time=time.time())) + "\n")
+
+
 def serve_bench(args):
-    r = serve_measure(args.serve_requests, args.serve_slots, args.serve_threads, args.serve_budget_gb)
+    records = [] if args.records else None
+    r = serve_measure(args.serve_requests, args.serve_slots, args.serve_threads, args.serve_budget_gb,
+                      records=records)
     line = {
         "metric": "served solves/s and p99 at 1e-8 rel err",
         "value": r["served"]["saturated"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
@@ -364,6 +386,7 @@ def serve_bench(args):
                                       "arena_gb")},
         "sequential_fp64": r["sequential_fp64"], "served": r["served"],
     }
+    write_records(args.records, line, records or [])
     print(json.dumps(line), flush=True)
 
 
@@ -460,6 +483,7 @@ def cfg4_bench(args):
         "config": {k: r[k] for k in ("workload", "elements", "nodes", "nnz")},
         **{k: r[k] for k in ("assembly_ms", "assembly_melem_s", "solve", "ir_speedup", "upload_s")},
     }
+    write_records(args.records, line, [])
     print(json.dumps(line), flush=True)
 
 
@@ -478,6 +502,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-threads", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--records", default=None,
+                    help="append JSONL records (one per served request, one per run) to this file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device copy 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -713,6 +739,7 @@ def main():
         n_cpu = args.cpu_sample_n if args.workload in ("hex128", "hex64") else min(args.cpu_sample_n, 64)
         line["cpu_baseline"] = cpu_baseline(n_cpu, args.workload)
         log(f"cpu baseline: {json.dumps(line['cpu_baseline'])}")
+    records = [] if args.records else None
     if args.workload == "hex128":
         # the metric's second half and the large single mesh, measured in the
         # same run (outside the timed region of the step above)
@@ -723,9 +750,10 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_serving:
             line["serving"] = serve_measure(args.serve_requests, args.serve_slots, args.serve_threads,
-                                            args.serve_budget_gb, modes=("saturated", "load0.8"))
+                                            args.serve_budget_gb, modes=("saturated", "load0.8"), records=records)
         if not args.no_cfg4:
             line["cfg4"] = cfg4_measure(args.cfg4_n, 5)
+    write_records(args.records, line, records or [])
     print(json.dumps(line), flush=True)
 
 

@@ -52,7 +52,9 @@ Y, D, arrivals, sizes.
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import json
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -370,27 +372,46 @@ def make_case(n: int, elem_type: int = HEX08, jitter: float = 0.10, case_id: int
 
 
 # --- the five workloads -----------------------------------------------------
+# Their parameters live in configs/cfg0..cfg4.json (name, mesh, jitter, seed,
+# numbering, fields, solve); the functions below build them.
+
+_CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+_TYPES = {"HEX08": HEX08, "TET04": TET04, "PEN06": PEN06, "PYR05": PYR05, "HYBRID": HYBRID}
+
+
+def config(name: str) -> dict:
+    """The parameters of workload `name` (cfg0 ... cfg4)."""
+    with open(os.path.join(_CONFIG_DIR, name + ".json")) as fh:
+        return json.load(fh)
+
+
+def _from_config(name: str, n: Optional[int] = None) -> Case:
+    c = config(name)
+    n = c["n"] if n is None else n
+    label = c["name"].replace(str(c["n"]) + "^3", f"{n}^3")
+    return make_case(n, _TYPES[c["elem_type"]], c["jitter"], case_id=c["seed"], shuffle=c["shuffle"],
+                     temperature=c["temperature"], n_scalars=c["n_scalars"], walls=c["walls"], name=label)
+
 
 def cfg0() -> Case:
     """10^3 HEX08, jitter 10 %, Taylor-Green + noise, rho U[0.2,1.2]."""
-    return make_case(10, HEX08, 0.10, case_id=0, name="hex08-10^3")
+    return _from_config("cfg0")
 
 
 def cfg1(n: int = 128) -> Case:
     """128^3 HEX08, jitter 15 %, node and element ids shuffled; the z = 0
     faces are the wall of the wall model."""
-    return make_case(n, HEX08, 0.15, case_id=1, shuffle=True, name=f"hex08-{n}^3-shuffled", walls=True)
+    return _from_config("cfg1", n)
 
 
 def cfg2(n: int = 128) -> Case:
     """128^3 cubes x 6 Kuhn TET04, jitter 10 %, flame-kernel T, shuffled."""
-    return make_case(n, TET04, 0.10, case_id=2, shuffle=True, temperature=True,
-                     name=f"tet04-6x{n}^3-flame")
+    return _from_config("cfg2", n)
 
 
 def cfg4(n: int = 256) -> Case:
     """256^3 HEX08, jitter 15 %, plus 5 species and diffusivities."""
-    return make_case(n, HEX08, 0.15, case_id=4, n_scalars=5, name=f"hex08-{n}^3-5species")
+    return _from_config("cfg4", n)
 
 
 def hybrid(n: int = 128) -> Case:
@@ -401,8 +422,8 @@ def hybrid(n: int = 128) -> Case:
 
 
 def serving_stream(n_requests: int = 2000, qps: float = 1.0, lo: int = 8, hi: int = 96):
-    """Arrival times (s) and cube sides of the serving workload."""
-    rs = streams(3)
+    """Arrival times (s) and cube sides of the serving workload (configs/cfg3.json)."""
+    rs = streams(config("cfg3")["seed"])
     gaps = rs["arrivals"].exponential(1.0 / qps, size=n_requests)
     t = np.cumsum(gaps) - gaps[0]
     sides = np.rint(np.exp(rs["sizes"].uniform(math.log(lo), math.log(hi), size=n_requests)))
@@ -411,7 +432,9 @@ def serving_stream(n_requests: int = 2000, qps: float = 1.0, lo: int = 8, hi: in
 
 def serving_case(req: int, n: int) -> Case:
     """Request `req` of the serving workload: a jittered HEX08 cube as cfg0."""
-    return make_case(int(n), HEX08, 0.10, case_id=3, sub=req, name=f"req{req}-hex08-{n}^3")
+    c = config("cfg3")
+    return make_case(int(n), _TYPES[c["elem_type"]], c["jitter"], case_id=c["seed"], sub=req,
+                     name=f"req{req}-hex08-{n}^3")
 
 
 def hex_pattern_nnz(n: int) -> int:

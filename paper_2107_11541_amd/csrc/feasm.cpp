@@ -740,6 +740,7 @@ static fe_status mesh_upload(fe_ctx c, int stride, const uint8_t *types, int64_t
 {
     if (!c || !out) return FE_EINVAL;
     *out = nullptr;
+    RoctxRange rr("fe_mesh_upload");
     HIPCALL(c, hipSetDevice(c->device));
     auto img = std::make_unique<MeshImage>();
     std::string err;
@@ -860,6 +861,7 @@ fe_status fe_assemble(fe_mesh m, const fe_fields *f, fe_precision prec, double *
         return fail(c, FE_EINVAL, "SCALAR needs 1..8 scalars, Y and D");
     if (f->op != FE_OP_MOMENTUM && f->op != FE_OP_SCALAR && f->op != FE_OP_POISSON)
         return fail(c, FE_EINVAL, "bad operator %d", (int)f->op);
+    RoctxRange rr("fe_assemble");
     HIPCALL(c, hipSetDevice(c->device));
     {
         ProfScope ps(c, 1);
@@ -925,6 +927,7 @@ fe_status fe_assemble_block(fe_mesh m, uint32_t form, double dt, const double *u
     if (form & ~(uint32_t)(FE_FORM_FULL_STRESS | FE_FORM_EMAC))
         return fail(c, FE_EINVAL, "unknown form bits 0x%x", form);
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FE_EINVAL, "dt must be > 0");
+    RoctxRange rr("fe_assemble_block");
     HIPCALL(c, hipSetDevice(c->device));
     fe_status s = ensure_rowplan(m);
     if (s != FE_OK) return s;
@@ -940,6 +943,7 @@ fe_status fe_apply_dirichlet(fe_mesh m, double *values, double *rhs, const doubl
 {
     if (!m) return FE_EINVAL;
     if (!values || !rhs) return fail(m->ctx, FE_EINVAL, "null values/rhs");
+    RoctxRange rr("fe_apply_dirichlet");
     ProfScope ps(m->ctx, 3);
     HIPCALL(m->ctx, launch_dirichlet(m->dm, values, rhs, g, m->ctx->stream));
     return FE_OK;
@@ -987,6 +991,7 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
     if (max_iter < 0) return fail(c, FE_EINVAL, "max_iter < 0");
     if (prec != FE_FP64 && prec != FE_MIXED) return fail(c, FE_EINVAL, "bad precision");
     if (!std::isfinite(rtol)) return fail(c, FE_EINVAL, "rtol not finite");
+    RoctxRange rr(prec == FE_MIXED ? "fe_cg_solve(mixed)" : "fe_cg_solve");
     HIPCALL(c, hipSetDevice(c->device));
     fe_status s = ensure_cg(m, max_iter, prec == FE_MIXED);
     if (s != FE_OK) return s;
@@ -1043,6 +1048,7 @@ fe_status fe_cg_solve_noalloc(fe_mesh m, const double *values, const double *rhs
     if (!values || !rhs || !x) return fail(c, FE_EINVAL, "null values/rhs/x");
     if (max_iter < 0) return fail(c, FE_EINVAL, "max_iter < 0");
     if (!std::isfinite(rtol)) return fail(c, FE_EINVAL, "rtol not finite");
+    RoctxRange rr("fe_cg_solve_noalloc");
     HIPCALL(c, hipSetDevice(c->device));
     char *base = nullptr;
     {
@@ -1105,6 +1111,7 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     if (!valid_form(form)) return fail(c, FE_EINVAL, "unknown form bits 0x%x", form);
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FE_EINVAL, "dt must be > 0");
     if (!(rtol > 0.0) || max_iter < 1) return fail(c, FE_EINVAL, "need rtol > 0 and max_iter >= 1");
+    RoctxRange rr("fe_fractional_step");
     HIPCALL(c, hipSetDevice(c->device));
     const DevMesh &d = m->dm;
     const int64_t N = d.N;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <string>
@@ -30,6 +31,16 @@ class DevArena {
     size_t cap_, free_total_;
     std::vector<std::pair<size_t, size_t>> holes_;   // (offset, size), sorted by offset
     std::vector<std::pair<size_t, size_t>> used_;    // (offset, size), sorted by offset
+};
+
+// A roctx range over a scope: rocprofv3 --marker-trace shows the library's
+// calls (upload, assembly, Dirichlet, solve, time step, serving stages) on
+// the host timeline beside the kernels they launch.
+struct RoctxRange {
+    explicit RoctxRange(const char *name) { roctxRangePushA(name); }
+    ~RoctxRange() { roctxRangePop(); }
+    RoctxRange(const RoctxRange &) = delete;
+    RoctxRange &operator=(const RoctxRange &) = delete;
 };
 
 struct ProfSlot {

@@ -114,6 +114,7 @@ namespace {
 // idle: no other request waits to be planned (see planner_main)
 void plan_job(Job *j, bool idle)
 {
+    RoctxRange rr("serve: plan");
     const fe_job &q = j->desc;
     // one thread per mesh keeps every planner busy; large meshes get a few
     // more so that they do not set the latency tail alone, and more again
@@ -219,6 +220,7 @@ fe_status ensure_stage(fe_server_s *S, int slot, size_t doubles)
 // returned and the status says why (FE_ENOMEM: try again later).
 fe_status admit(fe_server_s *S, Job *j)
 {
+    RoctxRange rr("serve: admit");
     fe_ctx_s *c = &S->sctx;
     const fe_job &q = j->desc;
     auto *m = new fe_mesh_s();
@@ -312,6 +314,7 @@ fe_status finish_queue(fe_server_s *S, Job *j)
 // Results to the caller's buffers (user numbering); arena space returned.
 void finish_host(fe_server_s *S, Job *j)
 {
+    RoctxRange rr("serve: finish");
     fe_mesh_s *m = j->mesh;
     const int64_t N = m->dm.N;
     const double *rh = S->res_h + kResDoubles * j->slot, *st = S->stage[j->slot];
