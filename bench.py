@@ -55,7 +55,7 @@ def measured_valu(workload):
     VALU-counter summary, or None once the assembly sources have changed since
     the counters were taken (or for another workload)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_assemble_hex128_valu.md")
+    path = os.path.join(ROOT, "profiles", "assembly_hex128.md")
     try:
         text = open(path).read()
     except OSError:
@@ -69,7 +69,7 @@ def measured_valu(workload):
     if kv.get("valu_workload") != workload:
         return None
     h = hashlib.sha256()
-    for rel in ("asm_kernels.hip", "internal.h", "plan.cpp"):
+    for rel in ("asm_kernels.hip", "internal.h", "plan.cpp", "rowplan.cpp"):
         with open(os.path.join(ROOT, "paper_2107_11541_amd", "csrc", rel), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != kv.get("valu_source_sha256"):
