@@ -739,16 +739,30 @@ struct OArgs {
 
 template <class EL> struct OwnRows { static constexpr int RA = EL::NEN == 8 ? 4 : EL::NEN; };
 
+// Work-groups are dispatched round-robin over MI355X's 8 XCDs (work-group b
+// on XCD b % 8), each with its own L2.  xcd_item maps work-group b of a
+// G-group launch to item i so that every XCD takes one contiguous range of
+// items (a bijection of [0, G)).  Consecutive owner groups cover neighbouring
+// rows and share halo nodes, so their cache lines of the nodal fields are then
+// fetched once into that XCD's L2 instead of once into each of several.
+constexpr int kAsmXcds = 8;
+__device__ inline int xcd_item(int b, int G)
+{
+    const int q = G / kAsmXcds, rem = G % kAsmXcds, x = b % kAsmXcds, slot = b / kAsmXcds;
+    return x * q + (x < rem ? x : rem) + slot;
+}
+
 template <class EL, int OP, class Q, bool PRIV>
 __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
 {
     constexpr int NEN = EL::NEN, RA = OwnRows<EL>::RA;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
     extern __shared__ double lds[];
-    const int4 gd = k.groups[blockIdx.x];   // first task, tasks, first row, rows
+    const int gi = xcd_item(blockIdx.x, gridDim.x);   // this work-group's group
+    const int4 gd = k.groups[gi];   // first task, tasks, first row, rows
     const int tid = threadIdx.x;
     const int r0 = gd.z, nr = gd.w;
-    const int n0 = k.node_ptr[blockIdx.x], T = k.node_ptr[blockIdx.x + 1] - n0;
+    const int n0 = k.node_ptr[gi], T = k.node_ptr[gi + 1] - n0;
     const int64_t v0 = k.rowptr[r0];
     const int L = (int)(k.rowptr[r0 + nr] - v0);
     const int64_t N = k.N;
@@ -821,7 +835,7 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
     for (int r = 0; r < RA; ++r) base[r] = ln[r] < nr ? (int)(k.rowptr[r0 + ln[r]] - v0) : -1;
 
     // 3. phases
-    const int nph = k.nphase[blockIdx.x];
+    const int nph = k.nphase[gi];
     for (int p = 0; p < nph; ++p) {
         if (ph == p) {
 #pragma unroll
@@ -878,8 +892,8 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
             md = fmin(md, smd[w]);
             bad = sbad[w] < bad ? sbad[w] : bad;
         }
-        k.g_mindet[blockIdx.x] = md;
-        k.g_bad[blockIdx.x] = bad == 0x7fffffffffffffffLL ? -1 : bad;
+        k.g_mindet[gi] = md;
+        k.g_bad[gi] = bad == 0x7fffffffffffffffLL ? -1 : bad;
     }
 }
 
@@ -1104,7 +1118,8 @@ template <int FORM>
 __global__ void __launch_bounds__(64) k_block(BArgs k)
 {
     extern __shared__ double lds[];
-    const int4 wd = k.wdesc[blockIdx.x];   // first task, tasks, first row, rows
+    const int wi = xcd_item(blockIdx.x, gridDim.x);   // this wave's row range
+    const int4 wd = k.wdesc[wi];   // first task, tasks, first row, rows
     const int lane = threadIdx.x;
     const int r0 = wd.z, nr = wd.w;
     const int64_t v0 = k.rowptr[r0];
@@ -1181,8 +1196,8 @@ __global__ void __launch_bounds__(64) k_block(BArgs k)
         bad = ob < bad ? ob : bad;
     }
     if (lane == 0) {
-        k.w_mindet[blockIdx.x] = md;
-        k.w_bad[blockIdx.x] = bad == 0x7fffffffffffffffLL ? -1 : bad;
+        k.w_mindet[wi] = md;
+        k.w_bad[wi] = bad == 0x7fffffffffffffffLL ? -1 : bad;
     }
 }
 
