@@ -1430,7 +1430,7 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.own_G,
-                           a.status);
+                           a.status_out ? a.status_out : a.status);
         return hipGetLastError();
     }
     // one launch per (colour, element type), in the planned order
@@ -1446,7 +1446,8 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.nblk, a.status);
+    hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, m.nblk,
+                       a.status_out ? a.status_out : a.status);
     return hipGetLastError();
 }
 

@@ -465,13 +465,10 @@ fe_status sync(fe_ctx_s *c)
 
 // Reads the status word of the assembly launches queued last (synchronises)
 // and reports the first element with det J <= 0 by its user id.
-fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
+// Interprets a status word read back to the host.
+static fe_status check_asm_status(fe_mesh_s *m, const AsmStatus *hs, fe_asm_info *info)
 {
     fe_ctx_s *c = m->ctx;
-    AsmStatus *hs = (AsmStatus *)c->host;
-    HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
-    fe_status s = sync(c);
-    if (s != FE_OK) return s;
     double md;
     memcpy(&md, &hs->min_det_key, 8);
     long long bad = hs->first_bad;
@@ -485,10 +482,23 @@ fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
     return FE_OK;
 }
 
+fe_status read_asm_status(fe_mesh_s *m, fe_asm_info *info)
+{
+    fe_ctx_s *c = m->ctx;
+    AsmStatus *hs = (AsmStatus *)c->host;
+    HIPCALL(c, hipMemcpyAsync(hs, m->status, sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
+    fe_status s = sync(c);
+    if (s != FE_OK) return s;
+    return check_asm_status(m, hs, info);
+}
+
 // Queues one element-vector pass (kOpResidual, kOpGradient, kOpDivergence)
-// writing its rows of N to out, and checks its status word.
+// writing its rows of N to out, and checks its status word; with defer set,
+// the status word goes to *defer (device memory) unread, for the caller to
+// read back with the others of a sequence (one synchronisation).
 fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, const double *rho, const double *mu,
-                          const double *p, double *out, int form = 0, const double *Y = nullptr, double D = 0.0)
+                          const double *p, double *out, int form = 0, const double *Y = nullptr, double D = 0.0,
+                          AsmStatus *defer = nullptr)
 {
     fe_ctx_s *c = m->ctx;
     AsmArgs a{};
@@ -504,11 +514,12 @@ fe_status element_vectors(fe_mesh_s *m, int op, double dt, const double *u, cons
     a.form = form;
     a.rhs = out;
     a.status = m->status;
+    a.status_out = defer;
     {
         ProfScope ps(c, 4);
         HIPCALL(c, launch_assemble(a, false, c->stream));
     }
-    return read_asm_status(m, nullptr);
+    return defer ? FE_OK : read_asm_status(m, nullptr);
 }
 
 // Iterations recorded per PCG graph.  A graph replays them with no launch
@@ -1116,31 +1127,54 @@ fe_status fe_fractional_step(fe_mesh m, double dt, const double *rho, const doub
     const DevMesh &d = m->dm;
     const int64_t N = d.N;
     fe_status s;
-    if (!m->step_work && (s = mesh_alloc(m, (void **)&m->step_work, 11 * (size_t)N * sizeof(double))) != FE_OK)
+    // step_work: u0 [3][N], residual + mass [4][N], f [N], g [3][N], then the
+    // status words of the step's 5 element-vector passes
+    constexpr int kPasses = 5;
+    const size_t work_doubles = 11 * (size_t)N + kPasses * sizeof(AsmStatus) / sizeof(double);
+    if (!m->step_work && (s = mesh_alloc(m, (void **)&m->step_work, work_doubles * sizeof(double))) != FE_OK)
         return s;
     double *u0 = m->step_work, *res = u0 + 3 * N, *mass = res + 3 * N, *f = res + 4 * N, *g = f + N;
+    AsmStatus *pass_status = (AsmStatus *)(g + 3 * N);
+    // The passes' status words are read back once, at the end of the step (a
+    // failed pass leaves undefined values behind it; the first failure in
+    // program order is reported).  The pressure solve synchronises on its own.
     // 1. Runge-Kutta predictor (Shu-Osher SSP-RK3) on M_L du/dt = R(u)
     static const double kStage[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
     HIPCALL(c, hipMemcpyAsync(u0, u, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    int pass = 0;
     for (const auto &st : kStage) {
-        if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res, (int)form)) != FE_OK) return s;
+        if ((s = element_vectors(m, kOpResidual, dt, u, rho, mu, nullptr, res, (int)form, nullptr, 0.0,
+                                 pass_status + pass++)) != FE_OK)
+            return s;
         if (m->wall.F > 0) HIPCALL(c, launch_wall_traction(d, m->wall, u, rho, mu, res, false, c->stream));
         HIPCALL(c, launch_rk_stage(d, st[0], st[1], dt, u0, res, mass, u, c->stream));
     }
     // 2. pressure: L p = (1/dt) int grad N . (rho u*), zero at Dirichlet rows
-    if ((s = element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f)) != FE_OK) return s;
+    if ((s = element_vectors(m, kOpDivergence, dt, u, rho, nullptr, nullptr, f, 0, nullptr, 0.0,
+                             pass_status + pass++)) != FE_OK)
+        return s;
     HIPCALL(c, launch_zero_fixed(d, f, c->stream));
     fe_cg_info ci{};
-    s = fe_cg_solve(m, L, f, p, rtol, max_iter, prec, &ci);
+    const fe_status cs = fe_cg_solve(m, L, f, p, rtol, max_iter, prec, &ci);
     if (info) {
         info->cg_iterations = ci.iterations;
         info->cg_true_rel_residual = ci.true_rel_residual;
     }
-    if (s != FE_OK) return s;
     // 3. correction u = u* - dt M_L^-1 G p
-    if ((s = element_vectors(m, kOpGradient, dt, nullptr, nullptr, nullptr, p, g)) != FE_OK) return s;
-    HIPCALL(c, launch_correct(d, dt, g, mass, u, c->stream));
-    return sync(c);
+    if (cs == FE_OK) {
+        if ((s = element_vectors(m, kOpGradient, dt, nullptr, nullptr, nullptr, p, g, 0, nullptr, 0.0,
+                                 pass_status + pass++)) != FE_OK)
+            return s;
+        HIPCALL(c, launch_correct(d, dt, g, mass, u, c->stream));
+    }
+    AsmStatus *hs = (AsmStatus *)c->host;
+    HIPCALL(c, hipMemcpyAsync(hs, pass_status, pass * sizeof(AsmStatus), hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c)) != FE_OK) return s;
+    // program order: 3 predictor passes, the divergence, the solve, the gradient
+    for (int q = 0; q < 4; ++q)
+        if ((s = check_asm_status(m, hs + q, nullptr)) != FE_OK) return s;
+    if (cs != FE_OK) return cs;
+    return check_asm_status(m, hs + 4, nullptr);
 }
 
 fe_status fe_scalar_residual(fe_mesh m, const double *u, const double *rho, const double *Y, double D, double *out)

@@ -126,7 +126,8 @@ struct AsmArgs {
     int form;                // kOpResidual: FE_FORM_* operator variants
     double *values;          // operator's value array [nnz]
     double *rhs;             // first rhs row [N] (momentum: 3 rows of N; element-vector passes: their rows)
-    AsmStatus *status;
+    AsmStatus *status;       // status word, followed by the per-block / per-group scratch
+    AsmStatus *status_out = nullptr;   // where the reduced word goes instead of *status (null: *status)
 };
 
 // Launchers (asm_kernels.hip).

@@ -142,6 +142,16 @@ def test_step_argument_errors_and_bad_element(fe_ctx):
     with pytest.raises(fe.FeError) as ei:
         fe.residual(mesh, to_mesh(mesh, c.u), to_mesh(mesh, c.rho), to_mesh(mesh, c.mu))
     assert ei.value.status == 4
+    # the fractional step reads its passes' status words back once, at its
+    # end, and still reports the folded element by its user id (L: the
+    # identity on this mesh's pattern, so the solve itself succeeds)
+    rp, ci = mesh.pattern_host()
+    Lh = (ci == np.repeat(np.arange(mesh.n_nodes), np.diff(rp))).astype(np.float64)
+    ub = to_mesh(mesh, c.u)
+    pb = torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda")
+    with pytest.raises(fe.FeError) as ei:
+        fe.fractional_step(mesh, 0.01, to_mesh(mesh, c.rho), to_mesh(mesh, c.mu), dev(Lh), ub, pb)
+    assert ei.value.status == 4 and "element 5 " in str(ei.value)
     mesh.close()
 
 
