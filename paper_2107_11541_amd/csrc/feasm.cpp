@@ -162,12 +162,21 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         I.is_dir[P.node_iperm[v]] = 1;
     }
     int64_t ndir = 0;
-    I.dir_rows.clear();
-    for (int64_t i = 0; i < n_nodes; ++i) {
-        bool hit = I.is_dir[i] != 0;
-        ndir += hit;
-        for (int32_t p = P.rowptr[i]; !hit && p < P.rowptr[i + 1]; ++p) hit = I.is_dir[P.colidx[p]] != 0;
-        if (hit) I.dir_rows.push_back((int32_t)i);
+    for (int64_t i = 0; i < n_nodes; ++i) ndir += I.is_dir[i] != 0;
+    // rows that hold a Dirichlet node (its own row or a column), ascending
+    {
+        const int64_t nch = (n_nodes + kPlanRowChunk - 1) / kPlanRowChunk;
+        std::vector<std::vector<int32_t>> part(nch);
+        parallel_chunks(nch, [&](int64_t c) {
+            const int64_t r0 = c * kPlanRowChunk, r1 = std::min<int64_t>(n_nodes, r0 + kPlanRowChunk);
+            for (int64_t i = r0; i < r1; ++i) {
+                bool hit = I.is_dir[i] != 0;
+                for (int32_t p = P.rowptr[i]; !hit && p < P.rowptr[i + 1]; ++p) hit = I.is_dir[P.colidx[p]] != 0;
+                if (hit) part[c].push_back((int32_t)i);
+            }
+        });
+        I.dir_rows.clear();
+        for (const auto &v : part) I.dir_rows.insert(I.dir_rows.end(), v.begin(), v.end());
     }
     DevMesh &d = I.d;
     d = DevMesh();
@@ -187,67 +196,113 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     // SpMV row blocks: consecutive rows, <= kSpmvBlockRows rows (4 threads per
     // row in a 256-thread group), <= kSpmvBlockNnz - 3 nonzeros (a 4-aligned
     // window of kSpmvBlockNnz entries in LDS) and <= kSpmvBlockCols distinct
-    // columns.  A single row always fits (rows are <= 255 entries).
-    // One pass over the pattern builds the blocks, their column sets (distinct
-    // columns in first-touch order) and the local indices: stamp[c] = the
-    // block that last took column c, loc[c] its index in that block's set.
-    // The set order is free (a product is v * x[col] whatever slot x[col]
-    // is staged in); first-touch order keeps it nearly ascending.
-    std::vector<int32_t> stamp((size_t)P.N, -1), loc((size_t)P.N, 0);
+    // columns, none across a kPlanRowChunk boundary.  A single row always
+    // fits (rows are <= 255 entries).
+    // Each row chunk (in parallel) builds its blocks greedily, their column
+    // sets (distinct columns in first-touch order, found through a small
+    // open-addressing table) and the local indices; the chunks are then
+    // concatenated.  The set order is free (a product is v * x[col] whatever
+    // slot x[col] is staged in); first-touch order keeps it nearly ascending.
+    struct RowChunk {
+        std::vector<int32_t> rb, cols, coff;   // per block: end row, end of its column set
+        std::vector<int64_t> seg;              // per block: byte offset of its local indices
+        std::vector<uint8_t> lidx;             // a multiple of 16 bytes
+    };
+    const int64_t nrch = (P.N + kPlanRowChunk - 1) / kPlanRowChunk;
+    std::vector<RowChunk> rch(nrch);
+    parallel_chunks(nrch, [&](int64_t c) {
+        RowChunk &C = rch[c];
+        const int64_t R0 = c * kPlanRowChunk, R1 = std::min<int64_t>(P.N, R0 + kPlanRowChunk);
+        C.lidx.reserve((size_t)(P.rowptr[R1] - P.rowptr[R0]) + 16 * (size_t)((R1 - R0) / 16 + 1));
+        constexpr int kSlots = 1024;   // > 2 x (kSpmvBlockCols + the longest row)
+        std::vector<int32_t> key(kSlots, -1);
+        std::vector<int32_t> val(kSlots, 0);
+        std::vector<uint16_t> used;   // slots filled, in insertion order
+        for (int64_t r = R0; r < R1;) {
+            const int32_t c0 = (int32_t)C.cols.size();
+            const int64_t p0 = P.rowptr[r], a0 = p0 & ~(int64_t)3;
+            const size_t s0 = C.lidx.size();   // 16-byte aligned
+            C.lidx.resize(s0 + (size_t)(p0 - a0), 0);   // window entries before the block
+            auto take = [&](int64_t row) {
+                for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) {
+                    const int32_t v = P.colidx[q];
+                    uint32_t h = ((uint32_t)v * 2654435761u) >> 22;
+                    while (key[h] != -1 && key[h] != v) h = (h + 1) & (kSlots - 1);
+                    if (key[h] != v) {
+                        key[h] = v;
+                        val[h] = (int32_t)C.cols.size() - c0;
+                        used.push_back((uint16_t)h);
+                        C.cols.push_back(v);
+                    }
+                    C.lidx.push_back((uint8_t)val[h]);
+                }
+            };
+            take(r);
+            int64_t r1 = r + 1;
+            while (r1 < R1 && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) {
+                const size_t nc = C.cols.size(), nl = C.lidx.size(), nu = used.size();
+                take(r1);
+                if ((int64_t)C.cols.size() - c0 > kSpmvBlockCols) {   // row r1 opens the next block
+                    for (size_t k = used.size(); k > nu; --k) key[used[k - 1]] = -1;   // last in, first out
+                    used.resize(nu);
+                    C.cols.resize(nc);
+                    C.lidx.resize(nl);
+                    break;
+                }
+                ++r1;
+            }
+            // pad the window to a multiple of 4 entries, the segment to 16 bytes
+            const int64_t win = ((p0 & 3) + (P.rowptr[r1] - p0) + 3) & ~(int64_t)3;
+            C.lidx.resize(s0 + (size_t)((win + 15) & ~(int64_t)15), 0);
+            C.seg.push_back((int64_t)s0);
+            C.coff.push_back((int32_t)C.cols.size());
+            C.rb.push_back((int32_t)r1);
+            for (uint16_t h : used) key[h] = -1;
+            used.clear();
+            r = r1;
+        }
+    });
     std::vector<int32_t> rb{0}, col_off{0};
     std::vector<int64_t> seg_off;   // byte offset of each block's local indices
-    I.spmv_cols.clear();
-    I.spmv_lidx.clear();
-    I.spmv_lidx.reserve((size_t)P.nnz + 16 * (size_t)(P.N / 16 + 1));
-    for (int64_t r = 0; r < P.N;) {
-        const int32_t bid = (int32_t)rb.size() - 1;
-        const int32_t c0 = (int32_t)I.spmv_cols.size();
-        const int64_t p0 = P.rowptr[r], a0 = p0 & ~(int64_t)3;
-        const size_t s0 = I.spmv_lidx.size();   // 16-byte aligned
-        I.spmv_lidx.resize(s0 + (size_t)(p0 - a0), 0);   // window entries before the block
-        auto take = [&](int64_t row) {
-            for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) {
-                const int32_t c = P.colidx[q];
-                if (stamp[c] != bid) {
-                    stamp[c] = bid;
-                    loc[c] = (int32_t)I.spmv_cols.size() - c0;
-                    I.spmv_cols.push_back(c);
-                }
-                I.spmv_lidx.push_back((uint8_t)loc[c]);
-            }
-        };
-        take(r);
-        int64_t r1 = r + 1;
-        while (r1 < P.N && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) {
-            const size_t nc = I.spmv_cols.size(), nl = I.spmv_lidx.size();
-            take(r1);
-            if ((int64_t)I.spmv_cols.size() - c0 > kSpmvBlockCols) {   // row r1 opens the next block
-                for (size_t k = nc; k < I.spmv_cols.size(); ++k) stamp[I.spmv_cols[k]] = -1;
-                I.spmv_cols.resize(nc);
-                I.spmv_lidx.resize(nl);
-                break;
-            }
-            ++r1;
+    {
+        size_t nl = 16, nc = 0, nb = 0;
+        for (const RowChunk &C : rch) {
+            nl += C.lidx.size();
+            nc += C.cols.size();
+            nb += C.rb.size();
         }
-        // pad the window to a multiple of 4 entries, the segment to 16 bytes
-        const int64_t win = ((p0 & 3) + (P.rowptr[r1] - p0) + 3) & ~(int64_t)3;
-        I.spmv_lidx.resize(s0 + (size_t)((win + 15) & ~(int64_t)15), 0);
-        seg_off.push_back((int64_t)s0);
-        col_off.push_back((int32_t)I.spmv_cols.size());
-        rb.push_back((int32_t)r1);
-        r = r1;
+        I.spmv_cols.clear();
+        I.spmv_lidx.clear();
+        I.spmv_cols.reserve(nc);
+        I.spmv_lidx.reserve(nl);
+        rb.reserve(nb + 1);
+        col_off.reserve(nb + 1);
+        seg_off.reserve(nb);
+        for (const RowChunk &C : rch) {
+            const int64_t lb = (int64_t)I.spmv_lidx.size();
+            const int32_t cb = (int32_t)I.spmv_cols.size();
+            I.spmv_lidx.insert(I.spmv_lidx.end(), C.lidx.begin(), C.lidx.end());
+            I.spmv_cols.insert(I.spmv_cols.end(), C.cols.begin(), C.cols.end());
+            for (size_t k = 0; k < C.rb.size(); ++k) {
+                rb.push_back(C.rb[k]);
+                col_off.push_back(cb + C.coff[k]);
+                seg_off.push_back(lb + C.seg[k]);
+            }
+        }
     }
     I.spmv_lidx.resize(I.spmv_lidx.size() + 16, 0);
     d.spmv_nrb = (int64_t)rb.size() - 1;
     I.spmv_desc.assign((size_t)d.spmv_nrb + 1, int4{0, 0, 0, 0});
     I.spmv_roff.assign((size_t)(P.N + d.spmv_nrb), 0);
-    for (int64_t b = 0; b < d.spmv_nrb; ++b)
-        I.spmv_desc[b] = int4{rb[b], P.rowptr[rb[b]], (int32_t)(seg_off[b] / 16), col_off[b]};
+    parallel_chunks((d.spmv_nrb + 4095) / 4096, [&](int64_t c) {
+        for (int64_t b = c * 4096; b < std::min<int64_t>(d.spmv_nrb, (c + 1) * 4096); ++b) {
+            I.spmv_desc[b] = int4{rb[b], P.rowptr[rb[b]], (int32_t)(seg_off[b] / 16), col_off[b]};
+            for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
+                I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
+        }
+    });
     I.spmv_desc[d.spmv_nrb] = int4{(int32_t)P.N, (int32_t)P.nnz, (int32_t)((I.spmv_lidx.size() - 16) / 16),
                                    col_off[d.spmv_nrb]};
-    for (int64_t b = 0; b < d.spmv_nrb; ++b)
-        for (int32_t i = rb[b]; i <= rb[b + 1]; ++i)
-            I.spmv_roff[(size_t)(rb[b] + b + (i - rb[b]))] = (uint16_t)(P.rowptr[i] - P.rowptr[rb[b]]);
     // the SpMV reads column indices in aligned groups of 4: pad the device copy
     P.colidx.resize((size_t)P.nnz + kColPad, 0);
     // assembly launches and their LDS per operator: [fields NF][rhs NRHS]
@@ -261,9 +316,7 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         for (int q = g.first; q < g.first + g.count; ++q) {
             const int32_t b = P.color_blk[q];
             const int64_t T = P.blk_node_ptr[b + 1] - P.blk_node_ptr[b];
-            int64_t nl = 0;
-            for (int32_t k = P.blk_node_ptr[b]; k < P.blk_node_ptr[b + 1]; ++k)
-                nl += P.rowptr[P.blk_nodes[k] + 1] - P.rowptr[P.blk_nodes[k]];
+            const int64_t nl = P.blk_img[b];
             for (int op = 0; op < kNumOps; ++op) {
                 size_t by = (size_t)(nf[op] + nr[op]) * T * 8 + (size_t)T * 4 + 8 + (op < 3 ? (size_t)nl * 8 : 0);
                 L.lds[op] = std::max(L.lds[op], by);

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <thread>
 
@@ -41,6 +42,49 @@ static void parallel_for(int64_t n, F f)
         th.emplace_back([=, &f] { f(lo, hi); });
     }
     for (auto &x : th) x.join();
+}
+
+void parallel_chunks(int64_t n, const std::function<void(int64_t)> &f)
+{
+    const int nt = (int)std::min<int64_t>(host_threads(), n);
+    if (nt <= 1) {
+        for (int64_t c = 0; c < n; ++c) f(c);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto run = [&] {
+        for (int64_t c = next.fetch_add(1); c < n; c = next.fetch_add(1)) f(c);
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(run);
+    run();
+    for (auto &x : th) x.join();
+}
+
+// Sorts idx by less, a strict total order (so the result does not depend on
+// how the work is split): runs sorted in parallel, then merged pairwise.
+template <class Less>
+static void parallel_sort(std::vector<int32_t> &idx, Less less)
+{
+    const int64_t n = (int64_t)idx.size();
+    int parts = 1;
+    while (parts < host_threads() && n / (2 * parts) >= 32768) parts *= 2;
+    if (parts == 1) {
+        std::sort(idx.begin(), idx.end(), less);
+        return;
+    }
+    std::vector<int64_t> b(parts + 1);
+    for (int k = 0; k <= parts; ++k) b[k] = n * k / parts;
+    parallel_chunks(parts, [&](int64_t k) { std::sort(idx.begin() + b[k], idx.begin() + b[k + 1], less); });
+    std::vector<int32_t> buf(n);
+    for (int w = 1; w < parts; w *= 2) {
+        parallel_chunks(parts / (2 * w), [&](int64_t q) {
+            const int64_t lo = b[2 * w * q], mid = b[2 * w * q + w], hi = b[2 * w * q + 2 * w];
+            std::merge(idx.begin() + lo, idx.begin() + mid, idx.begin() + mid, idx.begin() + hi, buf.begin() + lo,
+                       less);
+        });
+        idx.swap(buf);
+    }
 }
 
 static inline uint64_t spread3(uint64_t v)
@@ -84,13 +128,15 @@ static void morton_order(int S, const uint8_t *types, int64_t N, const double *c
     });
     order.resize(E);
     std::iota(order.begin(), order.end(), 0);
+    // ties keep the user order
     if (types) {
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        parallel_sort(order, [&](int32_t a, int32_t b) {
             const int ra = type_rank(types[a]), rb = type_rank(types[b]);
-            return ra != rb ? ra < rb : key[a] < key[b];
+            if (ra != rb) return ra < rb;
+            return key[a] != key[b] ? key[a] < key[b] : a < b;
         });
     } else {
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        parallel_sort(order, [&](int32_t a, int32_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
     }
 }
 
@@ -110,15 +156,57 @@ static void build_pattern(Plan &P)
     const int64_t N = P.N, E = P.E;
     const uint8_t *ty = P.etype.empty() ? nullptr : P.etype.data();
     auto nen_of = [&](int64_t e) { return ty ? (int)ty[e] : S; };
+    // node -> incident elements, ascending (an element repeating a node
+    // appears once per repeat): counted and filled in parallel, then each
+    // list sorted
     std::vector<int64_t> ip(N + 1, 0);
-    for (int64_t e = 0; e < E; ++e)
-        for (int a = 0; a < nen_of(e); ++a) ip[P.conn[e * S + a] + 1]++;
-    for (int64_t i = 0; i < N; ++i) ip[i + 1] += ip[i];
-    std::vector<int32_t> inc(ip[N]);
-    {
+    std::vector<int32_t> inc;
+    if (host_threads() <= 1 || E < 65536) {
+        // one thread: counted and filled in element order (ascending as is)
+        for (int64_t e = 0; e < E; ++e)
+            for (int q = 0; q < nen_of(e); ++q) ip[P.conn[e * S + q] + 1]++;
+        for (int64_t i = 0; i < N; ++i) ip[i + 1] += ip[i];
+        inc.resize(ip[N]);
         std::vector<int64_t> fill(ip.begin(), ip.end() - 1);
         for (int64_t e = 0; e < E; ++e)
-            for (int a = 0; a < nen_of(e); ++a) inc[fill[P.conn[e * S + a]]++] = (int32_t)e;
+            for (int q = 0; q < nen_of(e); ++q) inc[fill[P.conn[e * S + q]]++] = (int32_t)e;
+    } else {
+        std::unique_ptr<std::atomic<int32_t>[]> cnt(new std::atomic<int32_t>[N]);
+        parallel_for(N, [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i) cnt[i].store(0, std::memory_order_relaxed);
+        });
+        parallel_for(E, [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; ++e)
+                for (int q = 0; q < nen_of(e); ++q) cnt[P.conn[e * S + q]].fetch_add(1, std::memory_order_relaxed);
+        });
+        for (int64_t i = 0; i < N; ++i) {
+            ip[i + 1] = ip[i] + cnt[i].load(std::memory_order_relaxed);
+            cnt[i].store(0, std::memory_order_relaxed);
+        }
+        inc.resize(ip[N]);
+        parallel_for(E, [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; ++e)
+                for (int q = 0; q < nen_of(e); ++q) {
+                    const int32_t v = P.conn[e * S + q];
+                    inc[ip[v] + cnt[v].fetch_add(1, std::memory_order_relaxed)] = (int32_t)e;
+                }
+        });
+        cnt.reset();
+        parallel_for(N, [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i) {
+                int32_t *l = inc.data() + ip[i];
+                const int64_t d = ip[i + 1] - ip[i];
+                for (int64_t x = 1; x < d; ++x) {   // insertion sort: lists are short, mostly ascending
+                    const int32_t v = l[x];
+                    int64_t y = x;
+                    while (y > 0 && l[y - 1] > v) {
+                        l[y] = l[y - 1];
+                        --y;
+                    }
+                    l[y] = v;
+                }
+            }
+        });
     }
     std::vector<int32_t> len(N);
     const int OS = P.off_stride;
@@ -230,6 +318,7 @@ static void build_pattern(Plan &P)
     P.nnz = s;
     // a row reaching kSlots / 2 = 256 distinct nodes is over kMaxRow anyway
     P.max_row = overflow ? (1 << 30) : mx;
+    P.colidx.reserve(s + 16);   // the device copy is padded later: no reallocation then
     P.colidx.resize(s);
     P.diagpos.assign(N, 0);
     parallel_for(nt, [&](int64_t t0, int64_t t1) {
@@ -328,14 +417,18 @@ int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int
     }
     // mesh connectivity; the unused slots of a short element repeat its first node
     P.conn.resize(E * PS);
-    for (int64_t e = 0; e < E; ++e) {
-        const int32_t *c = conn + (int64_t)P.elem_perm[e] * S;
-        const int t = nen_of(e);
-        for (int a = 0; a < PS; ++a) P.conn[e * PS + a] = P.node_iperm[c[a < t ? a : 0]];
-    }
+    parallel_for(E, [&](int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e) {
+            const int32_t *c = conn + (int64_t)P.elem_perm[e] * S;
+            const int t = nen_of(e);
+            for (int a = 0; a < PS; ++a) P.conn[e * PS + a] = P.node_iperm[c[a < t ? a : 0]];
+        }
+    });
     P.X.resize(3 * N);
-    for (int64_t i = 0; i < N; ++i)
-        for (int d = 0; d < 3; ++d) P.X[d * N + i] = coords[(int64_t)P.node_perm[i] * 3 + d];
+    parallel_for(N, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int d = 0; d < 3; ++d) P.X[d * N + i] = coords[(int64_t)P.node_perm[i] * 3 + d];
+    });
 
     // 3. CSR pattern
     build_pattern(P);
@@ -344,72 +437,102 @@ int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int
         return FE_EBADMESH;
     }
 
-    // 4. blocks: consecutive elements of one type, <= 64, LDS image within budget
-    std::vector<int32_t> stamp(N, -1), local(N, 0);
-    P.blk_elem_ptr.push_back(0);
-    P.blk_node_ptr.push_back(0);
+    // 4. blocks: consecutive elements of one type, <= 64, LDS image within
+    //    budget, none across a kPlanElemChunk boundary (chunks in parallel)
     {
-        std::vector<int32_t> cur;  // touched nodes of the open block
-        int64_t L = 0;
-        int32_t bid = 0;
         auto lds_bytes = [&](int64_t T, int64_t Limg) {
             return (T * (kNodeFields + kMaxRhs)) * 8 + T * 4 + 8 + Limg * 8;
         };
-        auto close_block = [&](int64_t e_end) {
-            std::sort(cur.begin(), cur.end());
-            P.blk_nodes.insert(P.blk_nodes.end(), cur.begin(), cur.end());
-            P.blk_elem_ptr.push_back((int32_t)e_end);
-            P.blk_node_ptr.push_back((int32_t)P.blk_nodes.size());
-            P.max_T = std::max<int>(P.max_T, (int)cur.size());
-            P.max_L = std::max<int>(P.max_L, (int)L);
-            cur.clear();
-            L = 0;
-            ++bid;
+        struct Chunk {
+            std::vector<int32_t> eptr, nptr, nodes, img;   // per block: end element, end of its nodes, image
+            int max_T = 0, max_L = 0;
+            bool too_big = false;
         };
-        int64_t start = 0;
-        for (int64_t e = 0; e < E; ++e) {
-            const int nen = nen_of(e);
-            const int32_t *ce = &P.conn[e * PS];
-            int newT = 0;
-            int64_t newL = 0;
-            for (int a = 0; a < nen; ++a) {
-                int32_t v = ce[a];
-                if (stamp[v] != bid) {
-                    bool dup = false;
-                    for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
-                    if (!dup) {
-                        ++newT;
-                        newL += P.rowptr[v + 1] - P.rowptr[v];
+        const int64_t nchunk = (E + kPlanElemChunk - 1) / kPlanElemChunk;
+        std::vector<Chunk> ch(nchunk);
+        parallel_chunks(nchunk, [&](int64_t c) {
+            Chunk &C = ch[c];
+            const int64_t e0 = c * kPlanElemChunk, e1 = std::min(E, e0 + kPlanElemChunk);
+            // the open block's touched nodes: open addressing over 1024 slots
+            // (the LDS budget keeps a block below 450 nodes)
+            constexpr int kSlots = 1024;
+            std::vector<int32_t> key(kSlots, -1);
+            std::vector<int32_t> cur, slots;
+            auto slot_of = [&](int32_t v) {
+                uint32_t h = ((uint32_t)v * 2654435761u) >> 22;
+                while (key[h] != -1 && key[h] != v) h = (h + 1) & (kSlots - 1);
+                return h;
+            };
+            int64_t L = 0;
+            auto close_block = [&](int64_t e_end) {
+                std::sort(cur.begin(), cur.end());
+                C.nodes.insert(C.nodes.end(), cur.begin(), cur.end());
+                C.eptr.push_back((int32_t)e_end);
+                C.nptr.push_back((int32_t)C.nodes.size());
+                C.img.push_back((int32_t)L);
+                C.max_T = std::max<int>(C.max_T, (int)cur.size());
+                C.max_L = std::max<int>(C.max_L, (int)L);
+                for (uint32_t h : slots) key[h] = -1;
+                cur.clear();
+                slots.clear();
+                L = 0;
+            };
+            int64_t start = e0;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int nen = nen_of(e);
+                const int32_t *ce = &P.conn[e * PS];
+                int newT = 0;
+                int64_t newL = 0;
+                for (int a = 0; a < nen; ++a) {
+                    const int32_t v = ce[a];
+                    if (key[slot_of(v)] != v) {
+                        bool dup = false;
+                        for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
+                        if (!dup) {
+                            ++newT;
+                            newL += P.rowptr[v + 1] - P.rowptr[v];
+                        }
                     }
                 }
-            }
-            if (e > start && (e - start >= kBlockElems || nen != nen_of(start) ||
-                              lds_bytes((int64_t)cur.size() + newT, L + newL) > kLdsBudget)) {
-                close_block(e);
-                start = e;
-                newT = 0;
-                newL = 0;
+                if (e > start && (e - start >= kBlockElems || nen != nen_of(start) ||
+                                  lds_bytes((int64_t)cur.size() + newT, L + newL) > kLdsBudget)) {
+                    close_block(e);
+                    start = e;
+                }
                 for (int a = 0; a < nen; ++a) {
-                    int32_t v = ce[a];
-                    bool dup = false;
-                    for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
-                    if (!dup) newL += P.rowptr[v + 1] - P.rowptr[v];
+                    const int32_t v = ce[a];
+                    const uint32_t h = slot_of(v);
+                    if (key[h] != v) {
+                        key[h] = v;
+                        slots.push_back(h);
+                        cur.push_back(v);
+                        L += P.rowptr[v + 1] - P.rowptr[v];
+                    }
+                }
+                if (lds_bytes((int64_t)cur.size(), L) > kLdsBudget || (int)cur.size() >= kSlots / 2) {
+                    C.too_big = true;
+                    return;
                 }
             }
-            for (int a = 0; a < nen; ++a) {
-                int32_t v = ce[a];
-                if (stamp[v] != bid) {
-                    stamp[v] = bid;
-                    cur.push_back(v);
-                    L += P.rowptr[v + 1] - P.rowptr[v];
-                }
-            }
-            if (lds_bytes((int64_t)cur.size(), L) > kLdsBudget) {
+            close_block(e1);
+        });
+        P.blk_elem_ptr.assign(1, 0);
+        P.blk_node_ptr.assign(1, 0);
+        for (const Chunk &C : ch) {
+            if (C.too_big) {
                 err = "one element's rows exceed the LDS budget";
                 return FE_EBADMESH;
             }
+            const int32_t base = (int32_t)P.blk_nodes.size();
+            P.blk_nodes.insert(P.blk_nodes.end(), C.nodes.begin(), C.nodes.end());
+            for (size_t k = 0; k < C.eptr.size(); ++k) {
+                P.blk_elem_ptr.push_back(C.eptr[k]);
+                P.blk_node_ptr.push_back(base + C.nptr[k]);
+            }
+            P.blk_img.insert(P.blk_img.end(), C.img.begin(), C.img.end());
+            P.max_T = std::max(P.max_T, C.max_T);
+            P.max_L = std::max(P.max_L, C.max_L);
         }
-        close_block(E);
     }
     const int64_t nblk = P.n_blocks();
 

@@ -7,7 +7,8 @@
 //     renumbered by first touch, so that a block of consecutive elements is
 //     spatially compact and touches few CSR rows;
 //   * a block is at most one wavefront (64) of elements, cut early when the
-//     LDS image of the rows it touches would exceed the budget;
+//     LDS image of the rows it touches would exceed the budget, and at the
+//     fixed element chunks the planner builds blocks in (kPlanElemChunk);
 //   * blocks are coloured so that no two blocks of one colour share a node:
 //     one launch per colour runs without write conflicts (no atomics);
 //   * inside a block, elements are split into phases so that no two lanes of
@@ -19,6 +20,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -31,6 +33,11 @@ constexpr int kLdsBudget = 40 * 1024;
 constexpr int kNodeFields = 8;
 constexpr int kMaxRhs = 3;
 constexpr int kMaxRow = 255;   // in-row offsets are stored as uint8
+// The planner's parallel stages work on fixed chunks (elements for the
+// assembly blocks, rows for the SpMV row blocks), so a plan does not depend
+// on the number of host threads that built it.
+constexpr int64_t kPlanElemChunk = 1 << 16;   // a multiple of kBlockElems
+constexpr int64_t kPlanRowChunk = 1 << 15;
 // Touched-row descriptor: image offset (bits 0-15) | row length (16-23) |
 // first-writer flag (bit 31).
 constexpr uint32_t kFirstBit = 0x80000000u;
@@ -62,6 +69,7 @@ struct Plan {
     std::vector<int32_t> blk_elem_ptr;   // [nblk+1]
     std::vector<int32_t> blk_node_ptr;   // [nblk+1]
     std::vector<int32_t> blk_nodes;      // touched rows, ascending mesh ids
+    std::vector<int32_t> blk_img;        // [nblk] entries of the touched rows (the block's row image)
     std::vector<int32_t> blk_rdesc;      // packed descriptor of each touched row (see kFirstBit)
     std::vector<int32_t> blk_rowstart;   // CSR start of each touched row
     std::vector<int32_t> blk_color;      // [nblk]
@@ -84,6 +92,10 @@ struct Plan {
 // fe_status code with a message in err.
 int build_plan(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                const int32_t *conn, bool renumber, Plan &P, std::string &err);
+
+// Runs f(c) for every c in [0, n) on up to host_threads() threads (chunks
+// handed out in increasing order; f must only write chunk c's results).
+void parallel_chunks(int64_t n, const std::function<void(int64_t)> &f);
 
 // Row-owner plan of the 3x3-block momentum operator (rowplan.cpp): tasks =
 // (element, row) pairs ordered by row, then element; whole rows packed into

@@ -61,6 +61,31 @@ int main()
                 }
                 san_free(&m);
             }
+    // a plan does not depend on the number of host threads that built it:
+    // TET04 (kind 1) and mixed (kind 2) meshes of more than one element
+    // chunk, built with 1 and with 4 threads
+    for (int kind : {1, 2}) {
+        SanMesh m = san_cube(kind == 1 ? 24 : 28, kind);
+        CHECK(m.n_elems > kPlanElemChunk);
+        Plan A, B;
+        std::string err;
+        set_thread_budget(1);
+        const int sa = build_plan(m.stride, m.types, m.n_nodes, m.coords, m.n_elems, m.conn, true, A, err);
+        set_thread_budget(4);
+        const int sb = build_plan(m.stride, m.types, m.n_nodes, m.coords, m.n_elems, m.conn, true, B, err);
+        set_thread_budget(0);
+        CHECK(sa == 0 && sb == 0);
+        CHECK(A.elem_perm == B.elem_perm && A.node_perm == B.node_perm);
+        CHECK(A.rowptr == B.rowptr && A.colidx == B.colidx && A.diagpos == B.diagpos);
+        CHECK(A.elem_off == B.elem_off && A.elem_lnode == B.elem_lnode && A.elem_phase == B.elem_phase);
+        CHECK(A.blk_elem_ptr == B.blk_elem_ptr && A.blk_node_ptr == B.blk_node_ptr && A.blk_nodes == B.blk_nodes);
+        CHECK(A.blk_img == B.blk_img && A.blk_color == B.blk_color && A.color_blk == B.color_blk);
+        CHECK(A.blk_rdesc == B.blk_rdesc && A.blk_rowstart == B.blk_rowstart);
+        // no block crosses an element chunk boundary
+        for (size_t b = 0; b + 1 < A.blk_elem_ptr.size(); ++b)
+            CHECK(A.blk_elem_ptr[b] / kPlanElemChunk == (A.blk_elem_ptr[b + 1] - 1) / kPlanElemChunk);
+        san_free(&m);
+    }
     printf("plan_check: %d failed checks\n", fails);
     return fails ? 1 : 0;
 }
