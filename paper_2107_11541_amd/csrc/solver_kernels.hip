@@ -145,27 +145,35 @@ constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Entries e..e+3 (e a multiple of 4) of a value array of n entries.
-// The matrix values are streamed once per product with nontemporal loads, so
-// that they do not displace the solver's vectors from the memory-side cache
-// between the launches of an iteration (128^3 HEX08: SpMV 131.8 -> 128.4 us,
-// vector updates 39.6 -> 34.9 us per iteration).
+// Entries e..e+3 (e a multiple of 4) of a value array of n entries; NT:
+// nontemporal loads (a template argument: a run-time choice between two
+// loads of one address lets the compiler merge them and drop the hint).
+template <bool NT>
 __device__ inline void load_quad(const double *__restrict__ v, int64_t e, int64_t last_even, double last,
                                  double out[4])
 {
     const int64_t a = e < last_even ? e : last_even;
     const int64_t b = e + 2 < last_even ? e + 2 : last_even;
-    const v2d pa = __builtin_nontemporal_load((const v2d *)(v + a)),
-              pb = __builtin_nontemporal_load((const v2d *)(v + b));
+    v2d pa, pb;
+    if constexpr (NT) {
+        pa = __builtin_nontemporal_load((const v2d *)(v + a));
+        pb = __builtin_nontemporal_load((const v2d *)(v + b));
+    } else {
+        pa = *(const v2d *)(v + a);
+        pb = *(const v2d *)(v + b);
+    }
     out[0] = a == e ? pa.x : last;
     out[1] = pa.y;   // a != e only when entry e+1 is past the end (weighted 0)
     out[2] = b == e + 2 ? pb.x : last;
     out[3] = pb.y;
 }
 // The FP32 copy is the library's own, padded by 4: no re-basing needed.
+template <bool NT>
 __device__ inline void load_quad(const float *__restrict__ v, int64_t e, int64_t, float, float out[4])
 {
-    const v4f q = __builtin_nontemporal_load((const v4f *)(v + e));
+    v4f q;
+    if constexpr (NT) q = __builtin_nontemporal_load((const v4f *)(v + e));
+    else q = *(const v4f *)(v + e);
     out[0] = q.x;
     out[1] = q.y;
     out[2] = q.z;
@@ -196,7 +204,7 @@ __device__ inline T mul_rn(T a, T b)
 template <class T> struct SpmvPass { static constexpr int BPI = 1; };
 template <> struct SpmvPass<float> { static constexpr int BPI = 2; };
 
-template <class T, bool VEC, class XF, class WF, class YF>
+template <class T, bool VEC, bool NT, class XF, class WF, class YF>
 __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
                                      int wg, int G, XF xget, WF wget, YF yput,
                                      const int32_t *done_flags = nullptr)
@@ -249,7 +257,7 @@ __device__ inline double spmv_stream(const SpmvMap &sm, const int4 *__restrict__
             li[u] = *(const uint32_t *)(sm.lidx + (int64_t)d0.z * 16 + 4 * t);
             const int ncol = d1.w - d0.w;
             cc[u] = sm.cols[d0.w + (tid < ncol ? tid : ncol - 1)];
-            load_quad(vals, a0 + 4 * (int64_t)t, last_even, last, v[u]);
+            load_quad<NT>(vals, a0 + 4 * (int64_t)t, last_even, last, v[u]);
         } else {
             const int32_t *__restrict__ colidx = sm.colidx;
             const int64_t p0 = d0.y;
@@ -376,7 +384,7 @@ template <class T, bool VEC>
 __global__ void __launch_bounds__(kTB) k_spmv(SpmvMap sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
                                               const T *__restrict__ x, T *__restrict__ y)
 {
-    spmv_stream<T, VEC>(
+    spmv_stream<T, VEC, false>(
         sm, desc, vals, blockIdx.x, gridDim.x, [&](int col) { return x[col]; }, [&](int) { return T(0); },
         [&](int row, T val, T) {
             y[row] = val;
@@ -413,11 +421,12 @@ int spmv_blocks(int64_t nrb)
 template <class T>
 hipError_t spmv_dispatch(const DevMesh &m, hipStream_t s, const T *v, const T *x, T *y)
 {
+    const SpmvMap sm = spmv_map(m, sizeof(T));
     if (spmv_vec_ok(v, m.nnz))
-        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, sm,
                            (const int4 *)m.spmv_desc, v, x, y);
     else
-        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
+        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, sm,
                            (const int4 *)m.spmv_desc, v, x, y);
     return hipGetLastError();
 }
@@ -601,14 +610,14 @@ __global__ void __launch_bounds__(kTB) k_cg_init_fin(const double *part, int nb,
 // G, never on what else shares the launch.
 
 // Iteration k, first step: q = A p and the partial p . q.
-template <class T, bool VEC>
+template <class T, bool VEC, bool NT>
 __device__ inline void cg_spmv_pq_step(const SpmvMap &sm, const int4 *__restrict__ desc, const T *__restrict__ vals,
                                        const T *__restrict__ p,
                                        T *__restrict__ q, double *__restrict__ part, const int32_t *flags, int wg,
                                        int G)
 {
     __shared__ double sh[4];
-    double acc = spmv_stream<T, VEC>(
+    double acc = spmv_stream<T, VEC, NT>(
         sm, desc, vals, wg, G, [&](int c) { return p[c]; }, [&](int row) { return p[row]; },
         [&](int row, T val, T prow) {
             q[row] = val;
@@ -747,13 +756,13 @@ __device__ inline void cg_update_p_step(int64_t n, int k, T *x, const T *z, T *p
 // and the two updates, which run after it, read it.  No launch argument
 // changes from one iteration to the next, so a run of iterations can be
 // recorded once as a HIP graph and replayed.
-template <class T, bool VEC>
+template <class T, bool VEC, bool NT>
 __global__ void __launch_bounds__(kTB) k_cg_spmv_pq(SpmvMap sm, const int4 *__restrict__ desc,
                                                     const T *__restrict__ vals, const T *__restrict__ p,
                                                     T *__restrict__ q, double *__restrict__ part, int32_t *flags)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) store_flag(flags + 3, load_flag(flags + 3) + 1);
-    cg_spmv_pq_step<T, VEC>(sm, desc, vals, p, q, part, flags, blockIdx.x, gridDim.x);
+    cg_spmv_pq_step<T, VEC, NT>(sm, desc, vals, p, q, part, flags, blockIdx.x, gridDim.x);
 }
 
 template <class T>
@@ -789,7 +798,7 @@ __global__ void __launch_bounds__(kTB) k_bat_spmv_pq(const BatchJob *__restrict_
     const int wg = blockIdx.x - L.wgs[j], G = L.wgs[j + 1] - L.wgs[j];
     // the serving arena keeps every value array 256-byte aligned (and every
     // mesh has nnz >= 4): the 16-byte form only
-    cg_spmv_pq_step<double, true>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
+    cg_spmv_pq_step<double, true, false>(b.sm, b.sm.desc, b.vals, b.p, b.q, b.part, b.flags, wg, G);
 }
 
 __global__ void __launch_bounds__(kTB) k_bat_update_xr(const BatchJob *__restrict__ jobs, BatchList L)
@@ -853,8 +862,8 @@ hipError_t init_spmv_grid(int device)
     hipError_t e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_spmv_pq<double, true>),
-                                                     kTB, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_cg_spmv_pq<double, true, true>), kTB, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     if (per_cu > kSpmvGroupsPerCU) per_cu = kSpmvGroupsPerCU;
@@ -964,12 +973,15 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream
 {
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
-    if (spmv_vec_ok(vals, m.nnz))
-        hipLaunchKernelGGL((k_cg_spmv_pq<T, true>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
-                           (const int4 *)m.spmv_desc, vals, p, q, w.part, w.flags);
+    const SpmvMap sm = spmv_map(m, sizeof(T));
+    const dim3 grid(spmv_blocks(m.spmv_nrb)), block(kTB);
+    const int4 *desc = (const int4 *)m.spmv_desc;
+    if (!spmv_vec_ok(vals, m.nnz))
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, false, false>), grid, block, 0, s, sm, desc, vals, p, q, w.part, w.flags);
+    else if (sm.nt)
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, true, true>), grid, block, 0, s, sm, desc, vals, p, q, w.part, w.flags);
     else
-        hipLaunchKernelGGL((k_cg_spmv_pq<T, false>), dim3(spmv_blocks(m.spmv_nrb)), dim3(kTB), 0, s, spmv_map(m),
-                           (const int4 *)m.spmv_desc, vals, p, q, w.part, w.flags);
+        hipLaunchKernelGGL((k_cg_spmv_pq<T, true, false>), grid, block, 0, s, sm, desc, vals, p, q, w.part, w.flags);
     return hipGetLastError();
 }
 
