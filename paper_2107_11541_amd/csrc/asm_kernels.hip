@@ -392,8 +392,8 @@ __device__ __forceinline__ void element_vector_point(int g, const double *nd, in
     }
 }
 
-template <class EL, int OP, class Q, int RA, int A0>
-__device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, int T,
+template <class EL, int OP, class Q, int RA, int A0, class FT>
+__device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const double *nd, const FT *nf, int T,
                                             const int (&ln)[EL::NEN],
                                             Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
                                             double inv_dt, double Dk, int form)
@@ -419,15 +419,17 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
     if constexpr (OP >= OP_RES) {
         element_vector_point<EL, OP, RA, A0>(g, nd, T, ln, dN, EL::w(g) * det, B, inv_dt, form, Dk);
     } else {
-        double rg = 0.0, fg = 0.0, ug0 = 0.0, ug1 = 0.0, ug2 = 0.0;
+        // nf: the fields after x, y, z (u_x, u_y, u_z, rho, mu / Y), interpolated
+        // in their staged precision FT
+        FT rg = 0, fg = 0, ug0 = 0, ug1 = 0, ug2 = 0;
 #pragma unroll
         for (int a = 0; a < NEN; ++a) {
-            const double Na = RefN<EL>(g, a);
-            rg += Na * nd[6 * T + ln[a]];
-            ug0 += Na * nd[3 * T + ln[a]];
-            ug1 += Na * nd[4 * T + ln[a]];
-            ug2 += Na * nd[5 * T + ln[a]];
-            if (OP != OP_POI) fg += Na * nd[7 * T + ln[a]];
+            const FT Na = FT(RefN<EL>(g, a));
+            rg += Na * nf[3 * T + ln[a]];
+            ug0 += Na * nf[0 * T + ln[a]];
+            ug1 += Na * nf[1 * T + ln[a]];
+            ug2 += Na * nf[2 * T + ln[a]];
+            if (OP != OP_POI) fg += Na * nf[4 * T + ln[a]];
         }
         const double dV = EL::w(g) * det;
         if (OP == OP_POI) {
@@ -475,8 +477,8 @@ __device__ __forceinline__ void gauss_point(int g, const Geo<EL> &GE, const doub
 // field reads are re-issued from LDS instead of being hoisted into registers.
 template <class EL> struct Rows { int v[EL::NEN]; };
 
-template <class EL, int OP, class Q, int RA, int A0>
-__device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, int T, Rows<EL> rows,
+template <class EL, int OP, class Q, int RA, int A0, class FT = double>
+__device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, const FT *nf, int T, Rows<EL> rows,
                                            Q (&A)[RA][EL::NEN], Q (&B)[OpTraits<OP>::NRHS][RA], double &mindet,
                                            double inv_dt, double Dk, int form)
 {
@@ -489,12 +491,12 @@ __device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, 
         for (int g = 0; g < NG; ++g) {
 #pragma unroll
             for (int a = 0; a < NEN; ++a) asm volatile("" : "+v"(ln[a]));
-            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk, form);
+            gauss_point<EL, OP, Q, RA, A0, FT>(g, GE, nd, nf, T, ln, A, B, mindet, inv_dt, Dk, form);
         }
     } else {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            gauss_point<EL, OP, Q, RA, A0>(g, GE, nd, T, ln, A, B, mindet, inv_dt, Dk, form);
+            gauss_point<EL, OP, Q, RA, A0, FT>(g, GE, nd, nf, T, ln, A, B, mindet, inv_dt, Dk, form);
     }
 }
 
@@ -608,8 +610,10 @@ __device__ __forceinline__ void assemble_block(const KArgs &k)
 #pragma unroll
         for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
         const int form = FORM >= 0 ? FORM : k.form;
-        if (W == 1 || wv == 0) gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, form);
-        else gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, T, rows, A, B, mindet, inv_dt, k.Dk, form);
+        if (W == 1 || wv == 0)
+            gauss_loop<EL, OP, Q, RA, 0>(GE, nd, nd + 3 * T, T, rows, A, B, mindet, inv_dt, k.Dk, form);
+        else
+            gauss_loop<EL, OP, Q, RA, (RA % NEN)>(GE, nd, nd + 3 * T, T, rows, A, B, mindet, inv_dt, k.Dk, form);
     }
     // this lane's rows of the element, selected without dynamic indexing
     int lr[RA];
@@ -767,8 +771,13 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
     const int L = (int)(k.rowptr[r0 + nr] - v0);
     const int64_t N = k.N;
     constexpr int NC = PRIV ? kOwnTasks / 64 : 1;   // copies of the rows
-    double *nd = lds;               // [NF][T] fields of the touched nodes
-    double *img0 = nd + NF * T;     // [NC][L] the owned rows
+    // Fields of the touched nodes: x, y, z in FP64 (the geometry is FP64 in
+    // both modes), the others in the quadrature's precision (the mixed mode
+    // interpolates them in FP32, which halves their LDS traffic).
+    using FT = Q;
+    double *nd = lds;                   // [3][T] coordinates
+    FT *nf = (FT *)(nd + 3 * T);        // [NF - 3][T] u_x, u_y, u_z, rho, mu / Y
+    double *img0 = nd + 3 * T + ((NF - 3) * T * (int)sizeof(FT) + 7) / 8;   // [NC][L] the owned rows
     double *rimg0 = img0 + NC * L;  // [NC][NRHS][nr] their right-hand sides
     double *img = img0 + (PRIV ? (tid >> 6) * L : 0);                 // this wave's copy
     double *rimg = rimg0 + (PRIV ? (tid >> 6) * NRHS * nr : 0);
@@ -805,7 +814,9 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
         f[6] = k.rho[g];
         if constexpr (NF > 7) f[7] = OP == OP_MOM ? k.mu[g] : k.Y[g];
 #pragma unroll
-        for (int c = 0; c < NF; ++c) nd[c * T + q] = f[c];
+        for (int c = 0; c < 3; ++c) nd[c * T + q] = f[c];
+#pragma unroll
+        for (int c = 3; c < NF; ++c) nf[(c - 3) * T + q] = FT(f[c]);
     }
     for (int q = tid; q < NC * L; q += kOwnTasks) img0[q] = 0.0;
     for (int q = tid; q < NC * NRHS * nr; q += kOwnTasks) rimg0[q] = 0.0;
@@ -828,7 +839,7 @@ __global__ void __launch_bounds__(kOwnTasks, 2) k_own(OArgs k)
         Rows<EL> rows;
 #pragma unroll
         for (int a = 0; a < NEN; ++a) rows.v[a] = ln[a];
-        gauss_loop<EL, OP, Q, RA, 0>(GE, nd, T, rows, A, B, mindet, 1.0 / k.dt, k.Dk, 0);
+        gauss_loop<EL, OP, Q, RA, 0, FT>(GE, nd, nf, T, rows, A, B, mindet, 1.0 / k.dt, k.Dk, 0);
     }
     int base[RA];
 #pragma unroll
@@ -1418,8 +1429,10 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
         const int nf = a.op == OP_POI ? 7 : 8, nrhs = a.op == OP_MOM ? 3 : 1;
         const int copies = m.own_priv ? kOwnTasks / 64 : 1;
         if ((m.own_priv != 0) != (m.nen != 8)) return hipErrorInvalidValue;   // plan and kernel disagree
-        const size_t lds =
-            (size_t)(nf * m.own_max_nodes + copies * (m.own_max_img + nrhs * m.own_max_rows)) * sizeof(double);
+        // x, y, z in FP64, the other fields in the quadrature's precision
+        const size_t fb = mixed ? sizeof(float) : sizeof(double);
+        const size_t fields = 3 * (size_t)m.own_max_nodes + ((nf - 3) * (size_t)m.own_max_nodes * fb + 7) / 8;
+        const size_t lds = (fields + (size_t)copies * (m.own_max_img + nrhs * m.own_max_rows)) * sizeof(double);
         switch (m.nen) {
         case 8: launch_own<Hex>(o, a.op, m.own_G, lds, mixed, s); break;
         case 6: launch_own<Pen>(o, a.op, m.own_G, lds, mixed, s); break;
