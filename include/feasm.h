@@ -385,6 +385,10 @@ fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const d
  *
  * Host arrays of a request are borrowed from fe_serve_submit until the
  * request is reported done; they must stay valid and unchanged until then.
+ * The server keeps up to host_threads planned images of finished requests
+ * (their host arrays' capacity, as large as the largest mesh planned) and
+ * each planner thread its planning temporaries (up to 512 MiB), reused by
+ * the next plans; fe_serve_destroy releases them.
  * The server functions may be called from any host thread. */
 typedef struct fe_server_s *fe_server;
 

@@ -141,6 +141,28 @@ size_t MeshImage::device_bytes() const
     return total;
 }
 
+void MeshImage::clear()
+{
+    P.clear();
+    O = OwnerPlan();
+    is_dir.clear();
+    dir_rows.clear();
+    spmv_desc.clear();
+    spmv_roff.clear();
+    spmv_lidx.clear();
+    spmv_cols.clear();
+    d = DevMesh();
+}
+
+// Per-chunk outputs of the SpMV row blocks (see mesh_prepare), kept per
+// calling thread like the planner's other temporaries.
+struct RowChunk {
+    std::vector<int32_t> rb, cols, coff;   // per block: end row, end of its column set
+    std::vector<int64_t> seg;              // per block: byte offset of its local indices
+    std::vector<uint8_t> lidx;             // a multiple of 16 bytes
+};
+static thread_local std::vector<RowChunk> t_rowchunks;
+
 int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                  const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
                  MeshImage &I, std::string &err, bool owner_plan)
@@ -203,15 +225,16 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     // open-addressing table) and the local indices; the chunks are then
     // concatenated.  The set order is free (a product is v * x[col] whatever
     // slot x[col] is staged in); first-touch order keeps it nearly ascending.
-    struct RowChunk {
-        std::vector<int32_t> rb, cols, coff;   // per block: end row, end of its column set
-        std::vector<int64_t> seg;              // per block: byte offset of its local indices
-        std::vector<uint8_t> lidx;             // a multiple of 16 bytes
-    };
     const int64_t nrch = (P.N + kPlanRowChunk - 1) / kPlanRowChunk;
-    std::vector<RowChunk> rch(nrch);
+    std::vector<RowChunk> &rch = t_rowchunks;
+    if ((int64_t)rch.size() < nrch) rch.resize(nrch);
     parallel_chunks(nrch, [&](int64_t c) {
         RowChunk &C = rch[c];
+        C.rb.clear();
+        C.cols.clear();
+        C.coff.clear();
+        C.seg.clear();
+        C.lidx.clear();
         const int64_t R0 = c * kPlanRowChunk, R1 = std::min<int64_t>(P.N, R0 + kPlanRowChunk);
         C.lidx.reserve((size_t)(P.rowptr[R1] - P.rowptr[R0]) + 16 * (size_t)((R1 - R0) / 16 + 1));
         constexpr int kSlots = 1024;   // > 2 x (kSpmvBlockCols + the longest row)
@@ -266,7 +289,8 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     std::vector<int64_t> seg_off;   // byte offset of each block's local indices
     {
         size_t nl = 16, nc = 0, nb = 0;
-        for (const RowChunk &C : rch) {
+        for (int64_t c = 0; c < nrch; ++c) {
+            const RowChunk &C = rch[c];
             nl += C.lidx.size();
             nc += C.cols.size();
             nb += C.rb.size();
@@ -278,7 +302,8 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         rb.reserve(nb + 1);
         col_off.reserve(nb + 1);
         seg_off.reserve(nb);
-        for (const RowChunk &C : rch) {
+        for (int64_t c = 0; c < nrch; ++c) {
+            const RowChunk &C = rch[c];
             const int64_t lb = (int64_t)I.spmv_lidx.size();
             const int32_t cb = (int32_t)I.spmv_cols.size();
             I.spmv_lidx.insert(I.spmv_lidx.end(), C.lidx.begin(), C.lidx.end());
@@ -289,6 +314,13 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
                 seg_off.push_back(lb + C.seg[k]);
             }
         }
+    }
+    {
+        size_t kept = 0;
+        for (const RowChunk &C : rch)
+            kept += C.lidx.capacity() + 4 * (C.rb.capacity() + C.cols.capacity() + C.coff.capacity()) +
+                    8 * C.seg.capacity();
+        if (kept > kPlanScratchKeep) rch = std::vector<RowChunk>();
     }
     I.spmv_lidx.resize(I.spmv_lidx.size() + 16, 0);
     d.spmv_nrb = (int64_t)rb.size() - 1;

@@ -112,6 +112,8 @@ struct MeshImage {
     DevMesh d;                 // sizes filled, device pointers null
     // Device bytes of the mesh arrays (256-byte granules), without CG work.
     size_t device_bytes() const;
+    // Empties the image for the next mesh, keeping its host arrays' capacity.
+    void clear();
 };
 
 // Validates and plans a mesh on the host (no device calls).  0 or an

@@ -87,6 +87,43 @@ static void parallel_sort(std::vector<int32_t> &idx, Less less)
     }
 }
 
+void Plan::clear()
+{
+    nen = off_stride = 0;
+    N = E = nnz = 0;
+    max_row = n_colors = max_T = max_L = max_phase = 0;
+    for (auto *v : {&node_perm, &node_iperm, &elem_perm, &conn, &rowptr, &colidx, &diagpos, &blk_elem_ptr,
+                    &blk_node_ptr, &blk_nodes, &blk_img, &blk_rdesc, &blk_rowstart, &blk_color, &color_ptr,
+                    &color_blk})
+        v->clear();
+    for (auto *v : {&etype, &blk_nphase, &elem_off, &blk_nen, &elem_phase}) v->clear();
+    X.clear();
+    elem_lnode.clear();
+    segs.clear();
+}
+
+// Temporaries of one planning call, kept per calling thread (see
+// kPlanScratchKeep).
+struct PlanScratch {
+    std::vector<uint64_t> key;             // Morton keys
+    std::vector<int64_t> ip, np;           // node -> incident elements / blocks (offsets)
+    std::vector<int32_t> inc, len, nblks;  // the lists, row lengths
+    std::vector<std::vector<int32_t>> cols;   // pattern rows of each thread's range
+    size_t bytes() const
+    {
+        size_t b = key.capacity() * 8 + ip.capacity() * 8 + np.capacity() * 8 +
+                   (inc.capacity() + len.capacity() + nblks.capacity()) * 4;
+        for (const auto &c : cols) b += c.capacity() * 4;
+        return b;
+    }
+};
+static thread_local PlanScratch t_scratch;
+
+static void release_scratch_if_large()
+{
+    if (t_scratch.bytes() > kPlanScratchKeep) t_scratch = PlanScratch();
+}
+
 static inline uint64_t spread3(uint64_t v)
 {
     v &= 0x1fffff;
@@ -109,7 +146,8 @@ static void morton_order(int S, const uint8_t *types, int64_t N, const double *c
             lo[d] = std::min(lo[d], coords[i * 3 + d]);
             hi[d] = std::max(hi[d], coords[i * 3 + d]);
         }
-    std::vector<uint64_t> key(E);
+    std::vector<uint64_t> &key = t_scratch.key;
+    key.resize(E);
     parallel_for(E, [&](int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
             const int nen = types ? types[e] : S;
@@ -159,8 +197,9 @@ static void build_pattern(Plan &P)
     // node -> incident elements, ascending (an element repeating a node
     // appears once per repeat): counted and filled in parallel, then each
     // list sorted
-    std::vector<int64_t> ip(N + 1, 0);
-    std::vector<int32_t> inc;
+    std::vector<int64_t> &ip = t_scratch.ip;
+    std::vector<int32_t> &inc = t_scratch.inc;
+    ip.assign(N + 1, 0);
     if (host_threads() <= 1 || E < 65536) {
         // one thread: counted and filled in element order (ascending as is)
         for (int64_t e = 0; e < E; ++e)
@@ -208,12 +247,15 @@ static void build_pattern(Plan &P)
             }
         });
     }
-    std::vector<int32_t> len(N);
+    std::vector<int32_t> &len = t_scratch.len;
+    len.resize(N);
     const int OS = P.off_stride;
     P.elem_off.assign((size_t)E * OS, 0);
     const int nt = std::max(1, (int)std::min<int64_t>(host_threads(), (N + 4095) / 4096));
     const int64_t chunk = (N + nt - 1) / nt;
-    std::vector<std::vector<int32_t>> cols(nt);
+    std::vector<std::vector<int32_t>> &cols = t_scratch.cols;
+    if ((int)cols.size() < nt) cols.resize(nt);
+    for (auto &c : cols) c.clear();
     std::atomic<bool> overflow{false};
     auto work = [&](int t) {
         const int64_t lo = t * chunk, hi = std::min(N, lo + chunk);
@@ -336,8 +378,8 @@ static void build_pattern(Plan &P)
     });
 }
 
-int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int64_t E, const int32_t *conn,
-               bool renumber, Plan &P, std::string &err)
+static int build_plan_impl(int S, const uint8_t *types, int64_t N, const double *coords, int64_t E,
+                           const int32_t *conn, bool renumber, Plan &P, std::string &err)
 {
     const bool typed_stride = types ? (S >= 4 && S <= 8) : (S == 4 || S == 5 || S == 6 || S == 8);
     if (!typed_stride || N <= 0 || E <= 0 || !coords || !conn) {
@@ -365,7 +407,7 @@ int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int
                 return FE_EBADMESH;
             }
     }
-    P = Plan();
+    P.clear();
     P.nen = maxt;   // the plan's connectivity stride
     P.off_stride = (maxt * maxt + 3) & ~3;
     const int PS = maxt;
@@ -604,10 +646,12 @@ int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int
 
     // 6. block colouring: blocks sharing a node get different colours
     {
-        std::vector<int64_t> np(N + 1, 0);
+        std::vector<int64_t> &np = t_scratch.np;
+        np.assign(N + 1, 0);
         for (int32_t v : P.blk_nodes) np[v + 1]++;
         for (int64_t i = 0; i < N; ++i) np[i + 1] += np[i];
-        std::vector<int32_t> nblks(np[N]);
+        std::vector<int32_t> &nblks = t_scratch.nblks;
+        nblks.resize(np[N]);
         {
             std::vector<int64_t> fill(np.begin(), np.end() - 1);
             for (int64_t b = 0; b < nblk; ++b)
@@ -684,6 +728,14 @@ int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int
         }
     }
     return FE_OK;
+}
+
+int build_plan(int S, const uint8_t *types, int64_t N, const double *coords, int64_t E, const int32_t *conn,
+               bool renumber, Plan &P, std::string &err)
+{
+    const int st = build_plan_impl(S, types, N, coords, E, conn, renumber, P, err);
+    release_scratch_if_large();
+    return st;
 }
 
 }  // namespace feasm

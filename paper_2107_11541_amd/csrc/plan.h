@@ -84,6 +84,10 @@ struct Plan {
     int n_colors = 0, max_T = 0, max_L = 0, max_phase = 0;
 
     int64_t n_blocks() const { return (int64_t)blk_elem_ptr.size() - 1; }
+    // Empties the plan but keeps its arrays' capacity, so that a plan object
+    // reused for the next mesh (the serving runtime's planners) does not
+    // fault its pages in again.
+    void clear();
 };
 
 // conn [n_elems][stride]; types [n_elems] gives each element's node count
@@ -92,6 +96,11 @@ struct Plan {
 // fe_status code with a message in err.
 int build_plan(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                const int32_t *conn, bool renumber, Plan &P, std::string &err);
+
+// Host memory of the planner's temporaries (per calling thread, kept between
+// calls up to kPlanScratchKeep bytes so that a thread planning mesh after
+// mesh reuses it; larger ones are released after the call).
+constexpr size_t kPlanScratchKeep = (size_t)512 << 20;
 
 // Runs f(c) for every c in [0, n) on up to host_threads() threads (chunks
 // handed out in increasing order; f must only write chunk c's results).

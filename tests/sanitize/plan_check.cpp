@@ -86,6 +86,31 @@ int main()
             CHECK(A.blk_elem_ptr[b] / kPlanElemChunk == (A.blk_elem_ptr[b + 1] - 1) / kPlanElemChunk);
         san_free(&m);
     }
+    // a plan object reused for another mesh (the serving runtime's images)
+    // equals a fresh one: larger hybrid mesh first, then a smaller TET04 one
+    {
+        SanMesh big = san_cube(6, 2), small = san_cube(3, 1);
+        Plan reused, fresh;
+        std::string err;
+        CHECK(build_plan(big.stride, big.types, big.n_nodes, big.coords, big.n_elems, big.conn, true, reused, err) == 0);
+        CHECK(build_plan(small.stride, small.types, small.n_nodes, small.coords, small.n_elems, small.conn, true, reused,
+                         err) == 0);
+        CHECK(build_plan(small.stride, small.types, small.n_nodes, small.coords, small.n_elems, small.conn, true, fresh,
+                         err) == 0);
+        CHECK(reused.nen == fresh.nen && reused.N == fresh.N && reused.E == fresh.E && reused.nnz == fresh.nnz);
+        CHECK(reused.max_row == fresh.max_row && reused.n_colors == fresh.n_colors && reused.max_T == fresh.max_T &&
+              reused.max_L == fresh.max_L && reused.max_phase == fresh.max_phase);
+        CHECK(reused.elem_perm == fresh.elem_perm && reused.node_perm == fresh.node_perm &&
+              reused.node_iperm == fresh.node_iperm && reused.conn == fresh.conn && reused.X == fresh.X);
+        CHECK(reused.etype == fresh.etype && reused.rowptr == fresh.rowptr && reused.colidx == fresh.colidx);
+        CHECK(reused.elem_off == fresh.elem_off && reused.elem_lnode == fresh.elem_lnode &&
+              reused.elem_phase == fresh.elem_phase && reused.blk_nphase == fresh.blk_nphase);
+        CHECK(reused.blk_elem_ptr == fresh.blk_elem_ptr && reused.blk_nodes == fresh.blk_nodes &&
+              reused.blk_img == fresh.blk_img && reused.blk_rdesc == fresh.blk_rdesc &&
+              reused.color_blk == fresh.color_blk && reused.segs.size() == fresh.segs.size());
+        san_free(&big);
+        san_free(&small);
+    }
     printf("plan_check: %d failed checks\n", fails);
     return fails ? 1 : 0;
 }
