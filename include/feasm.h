@@ -99,7 +99,9 @@ fe_status fe_ctx_set_stream(fe_ctx ctx, void *hip_stream);
  * CSR row would hold more than 255 entries: the scatter plans store in-row
  * positions as bytes; a hexahedral node may lie in up to 36 elements, a
  * tetrahedral one in up to ~80), FE_ENOMEM, FE_EDEVICE.  The mesh owns all
- * its device memory.
+ * its device memory.  The planner keeps its host temporaries on the calling
+ * thread for the next upload while they total at most 256 MiB (meshes up to
+ * about 100^3 hexahedra); larger ones are released before the call returns.
  */
 fe_status fe_mesh_upload(fe_ctx ctx, fe_elem_type type, int64_t n_nodes, const double *coords,
                          int64_t n_elems, const int32_t *conn, int64_t n_dirichlet,
@@ -387,7 +389,7 @@ fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const d
  * request is reported done; they must stay valid and unchanged until then.
  * The server keeps up to host_threads planned images of finished requests
  * (their host arrays' capacity, as large as the largest mesh planned) and
- * each planner thread its planning temporaries (up to 512 MiB), reused by
+ * each planner thread its planning temporaries (up to 256 MiB), reused by
  * the next plans; fe_serve_destroy releases them.
  * The server functions may be called from any host thread. */
 typedef struct fe_server_s *fe_server;

@@ -100,7 +100,7 @@ int build_plan(int stride, const uint8_t *types, int64_t n_nodes, const double *
 // Host memory of the planner's temporaries (per calling thread, kept between
 // calls up to kPlanScratchKeep bytes so that a thread planning mesh after
 // mesh reuses it; larger ones are released after the call).
-constexpr size_t kPlanScratchKeep = (size_t)512 << 20;
+constexpr size_t kPlanScratchKeep = (size_t)256 << 20;
 
 // Runs f(c) for every c in [0, n) on up to host_threads() threads (chunks
 // handed out in increasing order; f must only write chunk c's results).
