@@ -162,6 +162,7 @@ struct RowChunk {
     std::vector<uint8_t> lidx;             // a multiple of 16 bytes
 };
 static thread_local std::vector<RowChunk> t_rowchunks;
+static thread_local std::vector<std::vector<int32_t>> t_spmv_stamp, t_spmv_loc;   // per worker, [N]
 
 int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double *coords, int64_t n_elems,
                  const int32_t *conn, int64_t n_dirichlet, const int32_t *dirichlet_nodes, bool renumber,
@@ -228,7 +229,15 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
     const int64_t nrch = (P.N + kPlanRowChunk - 1) / kPlanRowChunk;
     std::vector<RowChunk> &rch = t_rowchunks;
     if ((int64_t)rch.size() < nrch) rch.resize(nrch);
-    parallel_chunks(nrch, [&](int64_t c) {
+    // a column is in the open block's set while stamp[v] == the block's id
+    // (ids unique per worker), at slot loc[v]
+    const int nw = parallel_workers(nrch);
+    std::vector<std::vector<int32_t>> &stamps = t_spmv_stamp, &locs = t_spmv_loc;
+    if ((int)stamps.size() < nw) stamps.resize(nw);
+    if ((int)locs.size() < nw) locs.resize(nw);
+    std::vector<char> ready(nw, 0);
+    std::vector<int32_t> next_id(nw, 0);
+    parallel_chunks_w(nrch, [&](int64_t c, int w) {
         RowChunk &C = rch[c];
         C.rb.clear();
         C.cols.clear();
@@ -237,11 +246,14 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         C.lidx.clear();
         const int64_t R0 = c * kPlanRowChunk, R1 = std::min<int64_t>(P.N, R0 + kPlanRowChunk);
         C.lidx.reserve((size_t)(P.rowptr[R1] - P.rowptr[R0]) + 16 * (size_t)((R1 - R0) / 16 + 1));
-        constexpr int kSlots = 1024;   // > 2 x (kSpmvBlockCols + the longest row)
-        std::vector<int32_t> key(kSlots, -1);
-        std::vector<int32_t> val(kSlots, 0);
-        std::vector<uint16_t> used;   // slots filled, in insertion order
+        std::vector<int32_t> &stamp = stamps[w], &loc = locs[w];
+        if (!ready[w]) {
+            stamp.assign((size_t)P.N, -1);
+            loc.resize((size_t)P.N);
+            ready[w] = 1;
+        }
         for (int64_t r = R0; r < R1;) {
+            const int32_t bid = next_id[w]++;
             const int32_t c0 = (int32_t)C.cols.size();
             const int64_t p0 = P.rowptr[r], a0 = p0 & ~(int64_t)3;
             const size_t s0 = C.lidx.size();   // 16-byte aligned
@@ -249,25 +261,21 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
             auto take = [&](int64_t row) {
                 for (int32_t q = P.rowptr[row]; q < P.rowptr[row + 1]; ++q) {
                     const int32_t v = P.colidx[q];
-                    uint32_t h = ((uint32_t)v * 2654435761u) >> 22;
-                    while (key[h] != -1 && key[h] != v) h = (h + 1) & (kSlots - 1);
-                    if (key[h] != v) {
-                        key[h] = v;
-                        val[h] = (int32_t)C.cols.size() - c0;
-                        used.push_back((uint16_t)h);
+                    if (stamp[v] != bid) {
+                        stamp[v] = bid;
+                        loc[v] = (int32_t)C.cols.size() - c0;
                         C.cols.push_back(v);
                     }
-                    C.lidx.push_back((uint8_t)val[h]);
+                    C.lidx.push_back((uint8_t)loc[v]);
                 }
             };
             take(r);
             int64_t r1 = r + 1;
             while (r1 < R1 && r1 - r < kSpmvBlockRows && P.rowptr[r1 + 1] - P.rowptr[r] <= kSpmvBlockNnz - 3) {
-                const size_t nc = C.cols.size(), nl = C.lidx.size(), nu = used.size();
+                const size_t nc = C.cols.size(), nl = C.lidx.size();
                 take(r1);
                 if ((int64_t)C.cols.size() - c0 > kSpmvBlockCols) {   // row r1 opens the next block
-                    for (size_t k = used.size(); k > nu; --k) key[used[k - 1]] = -1;   // last in, first out
-                    used.resize(nu);
+                    for (size_t k = nc; k < C.cols.size(); ++k) stamp[C.cols[k]] = -1;
                     C.cols.resize(nc);
                     C.lidx.resize(nl);
                     break;
@@ -280,8 +288,6 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
             C.seg.push_back((int64_t)s0);
             C.coff.push_back((int32_t)C.cols.size());
             C.rb.push_back((int32_t)r1);
-            for (uint16_t h : used) key[h] = -1;
-            used.clear();
             r = r1;
         }
     });
@@ -320,7 +326,13 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
         for (const RowChunk &C : rch)
             kept += C.lidx.capacity() + 4 * (C.rb.capacity() + C.cols.capacity() + C.coff.capacity()) +
                     8 * C.seg.capacity();
-        if (kept > kPlanScratchKeep) rch = std::vector<RowChunk>();
+        for (const auto &v : stamps) kept += 4 * v.capacity();
+        for (const auto &v : locs) kept += 4 * v.capacity();
+        if (kept > kPlanScratchKeep) {
+            rch = std::vector<RowChunk>();
+            stamps = std::vector<std::vector<int32_t>>();
+            locs = std::vector<std::vector<int32_t>>();
+        }
     }
     I.spmv_lidx.resize(I.spmv_lidx.size() + 16, 0);
     d.spmv_nrb = (int64_t)rb.size() - 1;

@@ -44,21 +44,31 @@ static void parallel_for(int64_t n, F f)
     for (auto &x : th) x.join();
 }
 
-void parallel_chunks(int64_t n, const std::function<void(int64_t)> &f)
+int parallel_workers(int64_t n)
 {
-    const int nt = (int)std::min<int64_t>(host_threads(), n);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n));
+}
+
+void parallel_chunks_w(int64_t n, const std::function<void(int64_t, int)> &f)
+{
+    const int nt = parallel_workers(n);
     if (nt <= 1) {
-        for (int64_t c = 0; c < n; ++c) f(c);
+        for (int64_t c = 0; c < n; ++c) f(c, 0);
         return;
     }
     std::atomic<int64_t> next{0};
-    auto run = [&] {
-        for (int64_t c = next.fetch_add(1); c < n; c = next.fetch_add(1)) f(c);
+    auto run = [&](int w) {
+        for (int64_t c = next.fetch_add(1); c < n; c = next.fetch_add(1)) f(c, w);
     };
     std::vector<std::thread> th;
-    for (int t = 1; t < nt; ++t) th.emplace_back(run);
-    run();
+    for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
+    run(0);
     for (auto &x : th) x.join();
+}
+
+void parallel_chunks(int64_t n, const std::function<void(int64_t)> &f)
+{
+    parallel_chunks_w(n, [&](int64_t c, int) { f(c); });
 }
 
 // Sorts idx by less, a strict total order (so the result does not depend on
@@ -109,11 +119,15 @@ struct PlanScratch {
     std::vector<int64_t> ip, np;           // node -> incident elements / blocks (offsets)
     std::vector<int32_t> inc, len, nblks;  // the lists, row lengths
     std::vector<std::vector<int32_t>> cols;   // pattern rows of each thread's range
+    std::vector<std::vector<int32_t>> mark;   // per worker: node -> the last row / block that took it
+    std::vector<std::vector<uint8_t>> pos;    // per worker: node -> its position in that row
     size_t bytes() const
     {
         size_t b = key.capacity() * 8 + ip.capacity() * 8 + np.capacity() * 8 +
                    (inc.capacity() + len.capacity() + nblks.capacity()) * 4;
         for (const auto &c : cols) b += c.capacity() * 4;
+        for (const auto &c : mark) b += c.capacity() * 4;
+        for (const auto &c : pos) b += c.capacity();
         return b;
     }
 };
@@ -257,50 +271,50 @@ static void build_pattern(Plan &P)
     if ((int)cols.size() < nt) cols.resize(nt);
     for (auto &c : cols) c.clear();
     std::atomic<bool> overflow{false};
+    // (the workers run on threads of their own: they reach the caller's
+    // scratch only through these references)
+    std::vector<std::vector<int32_t>> &marks = t_scratch.mark;
+    std::vector<std::vector<uint8_t>> &poss = t_scratch.pos;
+    if ((int)marks.size() < nt) marks.resize(nt);
+    if ((int)poss.size() < nt) poss.resize(nt);
     auto work = [&](int t) {
         const int64_t lo = t * chunk, hi = std::min(N, lo + chunk);
         std::vector<int32_t> &out = cols[t];
         out.reserve((size_t)std::max<int64_t>(0, hi - lo) * 27);
-        constexpr int kSlots = 512;   // > 2 x the longest admissible row
-        int32_t table[kSlots];
-        uint16_t used[kSlots];
-        uint8_t posv[kSlots];
-        int32_t tmp[kSlots / 2 + 1];   // columns in first-touch order (+1: a non-fresh store at the end)
-        int32_t rank[kSlots / 2];
-        std::vector<uint16_t> hs;     // table slot of every (incident element, node)
-        std::vector<uint8_t> where;   // per incident element: bit a set where node a is the row's node
-        for (int q = 0; q < kSlots; ++q) table[q] = -1;
+        // a column is new to row i while mark[v] != i; pos[v] is its place
+        // in the sorted row (so the scatter offsets are one lookup each)
+        std::vector<int32_t> &mark = marks[t];
+        std::vector<uint8_t> &pos = poss[t];
+        mark.assign(N, -1);
+        pos.resize(N);
+        constexpr int kMaxCols = 256;   // one past the longest admissible row
+        int32_t tmp[kMaxCols + 1];      // columns in first-touch order (+1: a non-fresh store at the end)
+        int32_t rank[kMaxCols];
+        std::vector<uint8_t> where;     // per incident element: bit a set where node a is the row's node
         for (int64_t i = lo; i < hi; ++i) {
             const size_t start = out.size();
             const int64_t deg = ip[i + 1] - ip[i];
-            if ((int64_t)hs.size() < deg * S) {
-                hs.resize(deg * S);
-                where.resize(deg);
-            }
+            if ((int64_t)where.size() < deg) where.resize(deg);
             int nused = 0;
             for (int64_t k = 0; k < deg; ++k) {
                 const int64_t ek = inc[ip[i] + k];
                 const int32_t *c = &P.conn[ek * S];
                 const int nen = nen_of(ek);
                 uint32_t mk = 0;
-                for (int a = 0; a < nen; ++a) mk |= (uint32_t)(c[a] == (int32_t)i) << a;
-                where[k] = (uint8_t)mk;
                 for (int a = 0; a < nen; ++a) {
                     const int32_t v = c[a];
-                    uint32_t h = ((uint32_t)v * 2654435761u) >> 23;   // 9 bits
-                    while (table[h] != -1 && table[h] != v) h = (h + 1) & (kSlots - 1);
-                    hs[k * S + a] = (uint16_t)h;
+                    mk |= (uint32_t)(v == (int32_t)i) << a;
                     // branch-free insert (whether a column is new is unpredictable)
-                    const bool fresh = table[h] == -1;
-                    if (fresh & (nused == kSlots / 2)) {   // row longer than any admissible one
+                    const bool fresh = mark[v] != (int32_t)i;
+                    if (fresh & (nused == kMaxCols)) {   // row longer than any admissible one
                         overflow = true;
                         continue;
                     }
-                    table[h] = v;
-                    used[nused] = (uint16_t)h;
+                    mark[v] = (int32_t)i;
                     tmp[nused] = v;
                     nused += fresh;
                 }
+                where[k] = (uint8_t)mk;
             }
             const int n = nused;
             out.resize(start + n);
@@ -317,7 +331,7 @@ static void build_pattern(Plan &P)
                 }
                 for (int x = 0; x < n; ++x) {
                     r[rank[x]] = tmp[x];
-                    posv[used[x]] = (uint8_t)rank[x];
+                    pos[tmp[x]] = (uint8_t)rank[x];
                 }
                 int prev_a = -1;
                 for (int64_t k = 0; k < deg; ++k) {
@@ -331,14 +345,13 @@ static void build_pattern(Plan &P)
                     prev_a = a;
                     if (a == nen) continue;
                     uint8_t *off = &P.elem_off[(size_t)e * OS + (size_t)a * nen];
-                    const uint16_t *hk = &hs[k * S];
-                    for (int q = 0; q < nen; ++q) off[q] = posv[hk[q]];
+                    const int32_t *c = &P.conn[e * S];
+                    for (int q = 0; q < nen; ++q) off[q] = pos[c[q]];
                 }
             } else {
                 std::copy(tmp, tmp + n, r);
                 std::sort(r, r + n);
             }
-            for (int q = 0; q < nused; ++q) table[used[q]] = -1;
         }
     };
     if (nt == 1) {
@@ -492,19 +505,23 @@ static int build_plan_impl(int S, const uint8_t *types, int64_t N, const double 
         };
         const int64_t nchunk = (E + kPlanElemChunk - 1) / kPlanElemChunk;
         std::vector<Chunk> ch(nchunk);
-        parallel_chunks(nchunk, [&](int64_t c) {
+        // a node is in the open block while mark[v] == its id (ids unique per
+        // worker, so nothing is cleared between blocks)
+        const int nw = parallel_workers(nchunk);
+        std::vector<std::vector<int32_t>> &marks = t_scratch.mark;
+        if ((int)marks.size() < nw) marks.resize(nw);
+        std::vector<char> ready(nw, 0);
+        std::vector<int32_t> next_id(nw, 0);
+        parallel_chunks_w(nchunk, [&](int64_t c, int w) {
             Chunk &C = ch[c];
             const int64_t e0 = c * kPlanElemChunk, e1 = std::min(E, e0 + kPlanElemChunk);
-            // the open block's touched nodes: open addressing over 1024 slots
-            // (the LDS budget keeps a block below 450 nodes)
-            constexpr int kSlots = 1024;
-            std::vector<int32_t> key(kSlots, -1);
-            std::vector<int32_t> cur, slots;
-            auto slot_of = [&](int32_t v) {
-                uint32_t h = ((uint32_t)v * 2654435761u) >> 22;
-                while (key[h] != -1 && key[h] != v) h = (h + 1) & (kSlots - 1);
-                return h;
-            };
+            std::vector<int32_t> &mark = marks[w];
+            if (!ready[w]) {
+                mark.assign(N, -1);
+                ready[w] = 1;
+            }
+            int32_t bid = next_id[w]++;
+            std::vector<int32_t> cur;
             int64_t L = 0;
             auto close_block = [&](int64_t e_end) {
                 std::sort(cur.begin(), cur.end());
@@ -514,10 +531,9 @@ static int build_plan_impl(int S, const uint8_t *types, int64_t N, const double 
                 C.img.push_back((int32_t)L);
                 C.max_T = std::max<int>(C.max_T, (int)cur.size());
                 C.max_L = std::max<int>(C.max_L, (int)L);
-                for (uint32_t h : slots) key[h] = -1;
                 cur.clear();
-                slots.clear();
                 L = 0;
+                bid = next_id[w]++;
             };
             int64_t start = e0;
             for (int64_t e = e0; e < e1; ++e) {
@@ -527,7 +543,7 @@ static int build_plan_impl(int S, const uint8_t *types, int64_t N, const double 
                 int64_t newL = 0;
                 for (int a = 0; a < nen; ++a) {
                     const int32_t v = ce[a];
-                    if (key[slot_of(v)] != v) {
+                    if (mark[v] != bid) {
                         bool dup = false;
                         for (int b = 0; b < a; ++b) dup |= (ce[b] == v);
                         if (!dup) {
@@ -543,15 +559,13 @@ static int build_plan_impl(int S, const uint8_t *types, int64_t N, const double 
                 }
                 for (int a = 0; a < nen; ++a) {
                     const int32_t v = ce[a];
-                    const uint32_t h = slot_of(v);
-                    if (key[h] != v) {
-                        key[h] = v;
-                        slots.push_back(h);
+                    if (mark[v] != bid) {
+                        mark[v] = bid;
                         cur.push_back(v);
                         L += P.rowptr[v + 1] - P.rowptr[v];
                     }
                 }
-                if (lds_bytes((int64_t)cur.size(), L) > kLdsBudget || (int)cur.size() >= kSlots / 2) {
+                if (lds_bytes((int64_t)cur.size(), L) > kLdsBudget) {
                     C.too_big = true;
                     return;
                 }

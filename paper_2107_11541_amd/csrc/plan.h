@@ -105,6 +105,10 @@ constexpr size_t kPlanScratchKeep = (size_t)256 << 20;
 // Runs f(c) for every c in [0, n) on up to host_threads() threads (chunks
 // handed out in increasing order; f must only write chunk c's results).
 void parallel_chunks(int64_t n, const std::function<void(int64_t)> &f);
+// The same with the worker's index w in [0, parallel_workers(n)) passed as
+// f(c, w), for per-worker scratch arrays.
+int parallel_workers(int64_t n);
+void parallel_chunks_w(int64_t n, const std::function<void(int64_t, int)> &f);
 
 // Row-owner plan of the 3x3-block momentum operator (rowplan.cpp): tasks =
 // (element, row) pairs ordered by row, then element; whole rows packed into
