@@ -445,69 +445,6 @@ fe_status mesh_commit(fe_mesh_s *m, MeshImage &I, hipStream_t stream)
     return s;
 }
 
-size_t MeshImage::host_bytes() const
-{
-    MeshImage &I = const_cast<MeshImage &>(*this);
-    DevMesh d = I.d;
-    AsmStatus *st = nullptr;
-    size_t total = 0;
-    for_each_array(I, d, &st, [&](void **, const void *src, size_t b) {
-        if (src) total += DevArena::round(b ? b : 1);
-    });
-    return total;
-}
-
-fe_status mesh_commit_pinned(fe_mesh_s *m, MeshImage &I, hipStream_t stream, char *pinned, size_t cap)
-{
-    m->dm = I.d;
-    // one device block for every array (256-byte granules, the order of
-    // for_each_array), the arrays with host data packed in the same order
-    // into the pinned buffer
-    struct Piece {
-        void **dst;
-        const void *src;
-        size_t bytes, dev_off, host_off;
-    };
-    std::vector<Piece> pieces;
-    size_t dev = 0, host = 0;
-    for_each_array(I, m->dm, &m->status, [&](void **dst, const void *src, size_t bytes) {
-        pieces.push_back(Piece{dst, src, bytes, dev, host});
-        dev += DevArena::round(bytes ? bytes : 1);
-        if (src) host += DevArena::round(bytes ? bytes : 1);
-    });
-    if (host > cap) return fail(m->ctx, FE_EINVAL, "internal: pinned staging smaller than the mesh image");
-    char *base = nullptr;
-    fe_status s = mesh_alloc(m, (void **)&base, dev);
-    if (s != FE_OK) return s;
-    for (const Piece &p : pieces) *p.dst = base + p.dev_off;
-    // host copies in 8 MiB pieces on the host threads, then one transfer per
-    // contiguous run of arrays with host data
-    constexpr size_t kPiece = (size_t)8 << 20;
-    std::vector<std::pair<size_t, size_t>> work;   // (piece, offset in it)
-    for (size_t k = 0; k < pieces.size(); ++k)
-        if (pieces[k].src)
-            for (size_t o = 0; o < pieces[k].bytes; o += kPiece) work.emplace_back(k, o);
-    parallel_chunks((int64_t)work.size(), [&](int64_t w) {
-        const Piece &p = pieces[work[w].first];
-        const size_t o = work[w].second, n = std::min(kPiece, p.bytes - o);
-        memcpy(pinned + p.host_off + o, (const char *)p.src + o, n);
-    });
-    size_t k = 0;
-    while (k < pieces.size()) {
-        if (!pieces[k].src) {
-            ++k;
-            continue;
-        }
-        size_t k1 = k;
-        while (k1 + 1 < pieces.size() && pieces[k1 + 1].src) ++k1;
-        const size_t len = pieces[k1].dev_off + pieces[k1].bytes - pieces[k].dev_off;
-        HIPCALL(m->ctx, hipMemcpyAsync(base + pieces[k].dev_off, pinned + pieces[k].host_off, len,
-                                       hipMemcpyHostToDevice, stream));
-        k = k1 + 1;
-    }
-    return FE_OK;
-}
-
 size_t cg_bytes(int64_t n, int max_iter)
 {
     const int cap = std::max(max_iter + 2, 256);

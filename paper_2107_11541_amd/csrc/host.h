@@ -112,8 +112,6 @@ struct MeshImage {
     DevMesh d;                 // sizes filled, device pointers null
     // Device bytes of the mesh arrays (256-byte granules), without CG work.
     size_t device_bytes() const;
-    // Bytes of the arrays with host data, in the same granules.
-    size_t host_bytes() const;
     // Empties the image for the next mesh, keeping its host arrays' capacity.
     void clear();
 };
@@ -130,11 +128,6 @@ int mesh_prepare(int stride, const uint8_t *types, int64_t n_nodes, const double
 // Allocates (from m->arena or hipMalloc) and queues the copies of img on
 // `stream`.  img must stay alive until the copies have completed.
 fe_status mesh_commit(fe_mesh_s *m, MeshImage &img, hipStream_t stream);
-// The same through a pinned host buffer of cap >= img.host_bytes() bytes:
-// every array in one device block, the host data copied into the buffer on
-// the host threads and transferred in one copy per run of arrays.  The
-// buffer must stay untouched until the copies queued on stream complete.
-fe_status mesh_commit_pinned(fe_mesh_s *m, MeshImage &img, hipStream_t stream, char *pinned, size_t cap);
 // Device memory of m (through the arena when it has one).
 fe_status mesh_alloc(fe_mesh_s *m, void **p, size_t bytes);
 void mesh_release(fe_mesh_s *m);

@@ -91,18 +91,6 @@ struct fe_server_s {
     std::vector<double *> stage;                     // per-slot pinned staging for x and mom_rhs
     std::vector<size_t> stage_cap;
     hipEvent_t poll_ev = nullptr;
-    // Pinned upload staging (two, used in turn): admission copies a planned
-    // image and its fields into one on the host threads, then transfers it
-    // with a few large copies.  An upload from pageable memory went through
-    // the runtime's own staging on the dispatcher thread (~5 ms per request
-    // of the serving stream, most of the saturated run).
-    struct PinStage {
-        char *buf = nullptr;
-        size_t cap = 0;
-        hipEvent_t ev = nullptr;   // recorded after the transfers out of buf
-        bool pending = false;
-    } pin[2];
-    int pin_next = 0;
 
     std::mutex mu;
     std::condition_variable cv_plan, cv_work, cv_done;
@@ -277,28 +265,7 @@ fe_status admit(fe_server_s *S, Job *j)
         fail(c, FE_EDEVICE, "could not allocate pinned host staging for the results");
         return FE_EDEVICE;
     }
-    // the image and the fields through the next pinned stage (pageable
-    // uploads if it cannot be had)
-    fe_server_s::PinStage &ps = S->pin[S->pin_next];
-    S->pin_next ^= 1;
-    const size_t img_host = j->img->host_bytes();
-    const size_t need = img_host + DevArena::round(j->fields.size() * sizeof(double));
-    if (ps.pending) {
-        (void)hipEventSynchronize(ps.ev);
-        ps.pending = false;
-    }
-    if (ps.cap < need && ps.ev) {
-        if (ps.buf) (void)hipHostFree(ps.buf);
-        ps.buf = nullptr;
-        ps.cap = 0;
-        const size_t cap = need + need / 4;   // some room for growth
-        if (hipHostMalloc((void **)&ps.buf, cap, hipHostMallocDefault) == hipSuccess) ps.cap = cap;
-        else ps.buf = nullptr;
-    }
-    const bool pinned = ps.cap >= need;
-    fe_status s = pinned ? mesh_commit_pinned(m, *j->img, S->stream, ps.buf, ps.cap)
-                         : mesh_commit(m, *j->img, S->stream);
-    if (pinned && hipEventRecord(ps.ev, S->stream) == hipSuccess) ps.pending = true;
+    fe_status s = mesh_commit(m, *j->img, S->stream);
     if (s == FE_OK) s = ensure_cg(m, q.max_iter, false);
     double **bufs[] = {&j->vals_m, &j->rhs_m, &j->vals_p, &j->rhs_p, &j->fields_d, &j->x_d};
     const size_t sizes[] = {(size_t)nnz, (size_t)3 * N, (size_t)nnz, (size_t)N, (size_t)5 * N, (size_t)N};
@@ -311,22 +278,8 @@ fe_status admit(fe_server_s *S, Job *j)
     }
     CGWork &w = m->cg;
     w.flags = S->flags_d + 4 * j->slot;   // polled with every other slot's flags in one copy
-    if (pinned) {
-        // after the image's region of the stage (its transfers are queued
-        // before this one on the same stream)
-        char *fs = ps.buf + img_host;
-        const size_t fb = j->fields.size() * sizeof(double);
-        constexpr size_t kPiece = (size_t)8 << 20;
-        parallel_chunks((int64_t)((fb + kPiece - 1) / kPiece), [&](int64_t w) {
-            const size_t o = (size_t)w * kPiece;
-            memcpy(fs + o, (const char *)j->fields.data() + o, std::min(kPiece, fb - o));
-        });
-        HIPCALL(c, hipMemcpyAsync(j->fields_d, fs, fb, hipMemcpyHostToDevice, S->stream));
-        if (hipEventRecord(ps.ev, S->stream) == hipSuccess) ps.pending = true;
-    } else {
-        HIPCALL(c, hipMemcpyAsync(j->fields_d, j->fields.data(), j->fields.size() * sizeof(double),
-                                  hipMemcpyHostToDevice, S->stream));
-    }
+    HIPCALL(c, hipMemcpyAsync(j->fields_d, j->fields.data(), j->fields.size() * sizeof(double), hipMemcpyHostToDevice,
+                              S->stream));
     fe_fields fm{};
     fm.op = FE_OP_MOMENTUM;
     fm.dt = q.dt;
@@ -637,14 +590,10 @@ fe_status fe_serve_create(fe_ctx c, size_t hbm_budget, int32_t max_slots, int32_
         if (S->flags_h) (void)hipHostFree(S->flags_h);
         if (S->res_h) (void)hipHostFree(S->res_h);
         if (S->poll_ev) (void)hipEventDestroy(S->poll_ev);
-        for (auto &ps : S->pin)
-            if (ps.ev) (void)hipEventDestroy(ps.ev);
         if (S->stream) (void)hipStreamDestroy(S->stream);
     };
     bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&S->poll_ev, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&S->pin[0].ev, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&S->pin[1].ev, hipEventDisableTiming) == hipSuccess &&
               hipMalloc((void **)&S->arena_base, hbm_budget) == hipSuccess &&
               hipMalloc((void **)&S->jobs_d, kMaxBatch * sizeof(BatchJob)) == hipSuccess &&
               hipMalloc((void **)&S->flags_d, kMaxBatch * 4 * sizeof(int32_t)) == hipSuccess &&
@@ -755,10 +704,6 @@ void fe_serve_destroy(fe_server S)
     (void)hipHostFree(S->flags_h);
     (void)hipHostFree(S->res_h);
     (void)hipEventDestroy(S->poll_ev);
-    for (auto &ps : S->pin) {
-        if (ps.buf) (void)hipHostFree(ps.buf);
-        if (ps.ev) (void)hipEventDestroy(ps.ev);
-    }
     (void)hipStreamDestroy(S->stream);
     delete S;
 }
