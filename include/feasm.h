@@ -235,6 +235,7 @@ typedef struct {
     int32_t outer_iterations;  /* refinement steps (mixed); 1 for FE_FP64 */
     double rel_residual;       /* ||r||/||b|| from the recurrence (FP64 outer residual in mixed) */
     double true_rel_residual;  /* ||b - A x||/||b|| recomputed in FP64 */
+    int32_t symmetric_spmv;    /* 1: the FP64 iterations ran the symmetric SpMV (see fe_cg_solve), else 0 */
 } fe_cg_info;
 
 /*
@@ -243,8 +244,16 @@ typedef struct {
  * ||r||_2 <= rtol ||b||_2; rtol <= 0 runs exactly max_iter iterations and
  * returns FE_OK.  FE_MIXED runs FP32 Jacobi-PCG on an FP32 copy of the
  * matrix inside FP64 iterative refinement (residual and norms in FP64).
- * Returns FE_ENOCONV (x written) at max_iter, FE_EBREAKDOWN on p.Ap <= 0 or
- * non-finite scalars.  info may be NULL.
+ * FE_FP64 iterations use a symmetric SpMV when the matrix is symmetric:
+ * each pair a_ij, a_ji whose rows fall in one SpMV row block is read once,
+ * from the upper entry.  The call checks every such pair first (|a_ij -
+ * a_ji| <= 2^-40 max(|a_ij|, |a_ji|, sqrt|a_ii a_jj|), both finite) and
+ * otherwise runs the general SpMV; info->symmetric_spmv says which ran.  The first FP64 solve
+ * on a mesh builds the symmetric map on the host and keeps it, with a
+ * packed copy of the values, on the device (about 16 bytes per nonzero).
+ * The two SpMVs round differently; the true residual is always computed
+ * with `values` as given.  Returns FE_ENOCONV (x written) at max_iter,
+ * FE_EBREAKDOWN on p.Ap <= 0 or non-finite scalars.  info may be NULL.
  */
 fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, double *x, double rtol,
                       int32_t max_iter, fe_precision prec, fe_cg_info *info);
@@ -252,9 +261,11 @@ fe_status fe_cg_solve(fe_mesh mesh, const double *values, const double *rhs, dou
 /*
  * Allocation-free FP64 Jacobi-PCG, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
- * forbid hipMalloc.  Same solve, arguments, errors and results as
- * fe_cg_solve(..., FE_FP64, ...) (bitwise: same kernels, same launch
- * shapes), but the work vectors r, z, p, q, D^-1, the residual, the partial
+ * forbid hipMalloc.  Same solve, arguments and errors as
+ * fe_cg_solve(..., FE_FP64, ...) with the general SpMV (the symmetric one
+ * needs the packed values, which would need an allocation): results agree
+ * with fe_cg_solve's to rounding, and are bitwise its results whenever
+ * fe_cg_solve runs the general SpMV too.  The work vectors r, z, p, q, D^-1, the residual, the partial
  * sums, the per-iteration scalars and the stop word live in one fixed device
  * area of FE_NOALLOC_BYTES per device (a static device array, held from the
  * first fe_ctx_create on that device until the process ends) instead of
@@ -380,10 +391,10 @@ fe_status fe_fractional_step(fe_mesh mesh, double dt, const double *rho, const d
  *      request's arena space is returned for the next admission.
  * A request's numbers do not depend on the other requests in flight: its
  * work-group counts and summation orders are the ones of a request served
- * alone (and of fe_cg_solve on the same system, the mesh uploaded with
- * FE_UPLOAD_COLOURED: served meshes are assembled by coloured element
+ * alone (and of fe_cg_solve_noalloc on the same system, the mesh uploaded
+ * with FE_UPLOAD_COLOURED: served meshes are assembled by coloured element
  * blocks, since the owner plan's host time exceeds the assembly time it saves
- * for a mesh assembled once).
+ * for a mesh assembled once; the batched PCG runs the general SpMV).
  *
  * Host arrays of a request are borrowed from fe_serve_submit until the
  * request is reported done; they must stay valid and unchanged until then.

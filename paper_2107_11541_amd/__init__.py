@@ -444,7 +444,8 @@ def cg_solve(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_iter: int 
     st = mesh.ctx.lib.fe_cg_solve(mesh.h, _ptr(values), _ptr(rhs), _ptr(x), float(rtol), int(max_iter),
                                   precision, C.byref(info))
     out = {"status": st, "iterations": info.iterations, "outer_iterations": info.outer_iterations,
-           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual}
+           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual,
+           "symmetric_spmv": bool(info.symmetric_spmv)}
     if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):
         raise FeError(st, mesh.ctx.error())
     return x, out
@@ -464,7 +465,8 @@ def cg_solve_noalloc(mesh: Mesh, values, rhs, x=None, rtol: float = 1e-8, max_it
     st = mesh.ctx.lib.fe_cg_solve_noalloc(mesh.h, _ptr(values), _ptr(rhs), _ptr(x), float(rtol), int(max_iter),
                                           C.byref(info))
     out = {"status": st, "iterations": info.iterations, "outer_iterations": info.outer_iterations,
-           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual}
+           "rel_residual": info.rel_residual, "true_rel_residual": info.true_rel_residual,
+           "symmetric_spmv": bool(info.symmetric_spmv)}
     if st != capi.FE_OK and (raise_on_noconv or st != capi.FE_ENOCONV):
         raise FeError(st, mesh.ctx.error())
     return x, out

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libfeasm.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("FEASM_ARCH", "gfx950")
 
-SOURCES = ["asm_kernels.hip", "solver_kernels.hip", "feasm.cpp", "plan.cpp", "rowplan.cpp", "serve.cpp"]
+SOURCES = ["asm_kernels.hip", "solver_kernels.hip", "feasm.cpp", "plan.cpp", "rowplan.cpp", "serve.cpp", "symmap.cpp"]
 HEADERS = ["internal.h", "plan.h"]
 
 # -packed-fp32-ops: no packed FP32 VALU instructions are generated.

@@ -36,7 +36,7 @@ class AsmInfo(C.Structure):
 
 class CGInfo(C.Structure):
     _fields_ = [("iterations", i32), ("outer_iterations", i32), ("rel_residual", dbl),
-                ("true_rel_residual", dbl)]
+                ("true_rel_residual", dbl), ("symmetric_spmv", i32)]
 
 
 class MeshDesc(C.Structure):

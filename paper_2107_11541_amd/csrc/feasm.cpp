@@ -424,6 +424,7 @@ void mesh_release(fe_mesh_s *m)
     }
     m->allocs.clear();
     m->cg = CGWork();
+    m->sym = fe_mesh_s::SymState();
     m->step_work = nullptr;
     m->scalar_work = nullptr;
     m->wall = DevWall();
@@ -629,7 +630,8 @@ fe_status pcg_graph_launch(fe_mesh_s *m, const T *vals, T *x)
 {
     fe_ctx_s *c = m->ctx;
     fe_mesh_s::PcgGraph &g = m->graph[sizeof(T) == 4 ? 1 : 0];
-    if (!(g.exec && g.vals == vals && g.x == x && g.hist == m->cg.hist)) {
+    const void *sym = sizeof(T) == 8 ? (const void *)m->cg.sym.vals : nullptr;
+    if (!(g.exec && g.vals == vals && g.x == x && g.hist == m->cg.hist && g.sym == sym)) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         g = fe_mesh_s::PcgGraph();
         hipGraph_t graph = nullptr;
@@ -650,6 +652,7 @@ fe_status pcg_graph_launch(fe_mesh_s *m, const T *vals, T *x)
         g.vals = vals;
         g.x = x;
         g.hist = m->cg.hist;
+        g.sym = sym;
     }
     HIPCALL(c, hipGraphLaunch(g.exec, c->stream));
     return FE_OK;
@@ -704,15 +707,94 @@ fe_status run_pcg(fe_mesh_s *m, CGWork &w, const T *vals, const T *b, T *x, doub
     return FE_OK;
 }
 
+// The symmetric SpMV map of the mesh's pattern, built on the host from the
+// device pattern and uploaded on first use.  A pattern without one (not
+// structurally symmetric) leaves state -1: its solves use the general SpMV.
+static fe_status ensure_sym(fe_mesh_s *m)
+{
+    fe_mesh_s::SymState &Y = m->sym;
+    if (Y.state != 0) return FE_OK;
+    fe_ctx_s *c = m->ctx;
+    const DevMesh &d = m->dm;
+    std::vector<int32_t> rp(d.N + 1), ci(d.nnz);
+    HIPCALL(c, hipMemcpy(rp.data(), d.rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(ci.data(), d.colidx, ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    SymMap S;
+    std::string err;
+    if (build_sym_map(d.N, rp.data(), ci.data(), S, err) != 0) {
+        Y.state = -1;
+        return FE_OK;
+    }
+    fe_mesh_s::SymState N;
+    fe_status s = FE_OK;
+    auto up = [&](void **dst, const void *src, size_t bytes) {
+        if (s != FE_OK) return;
+        if ((s = mesh_alloc(m, dst, bytes)) != FE_OK) return;
+        const hipError_t e = src && bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice)
+                                          : hipMemset(*dst, 0, bytes);
+        if (e != hipSuccess) s = fail(c, FE_EDEVICE, "symmetric SpMV map upload: %s", hipGetErrorString(e));
+    };
+    void *desc = nullptr, *roff = nullptr, *lidx = nullptr, *mir = nullptr, *cols = nullptr, *vals = nullptr;
+    up(&desc, S.desc.data(), S.desc.size() * sizeof(int32_t));
+    up(&roff, S.roff.data(), S.roff.size() * sizeof(uint32_t));
+    up(&lidx, S.lidx.data(), S.lidx.size());
+    up(&mir, S.mir.data(), S.mir.size() * sizeof(uint32_t));
+    up(&cols, S.cols.data(), std::max<size_t>(S.cols.size(), 1) * sizeof(int32_t));
+    up((void **)&N.dst, S.dst.data(), std::max<size_t>(S.dst.size(), 1) * sizeof(int32_t));
+    up(&vals, nullptr, ((size_t)S.n_packed + 4) * sizeof(double));   // zeros: the padding stays 0
+    up((void **)&N.bad, nullptr, sizeof(int32_t));
+    if (s != FE_OK) {
+        void *ps[] = {desc, roff, lidx, mir, cols, N.dst, vals, N.bad};
+        for (void *q : ps) mesh_free_ptr(m, q);
+        return s;
+    }
+    N.map.desc = (const int4 *)desc;
+    N.map.roff = (const uint32_t *)roff;
+    N.map.lidx = (const uint8_t *)lidx;
+    N.map.mir = (const uint32_t *)mir;
+    N.map.cols = (const int32_t *)cols;
+    N.map.vals = (const double *)vals;
+    N.map.nrb = S.nrb;
+    N.map.nt = spmv_map(d).nt;
+    N.n_packed = S.n_packed;
+    N.state = 1;
+    Y = N;
+    return FE_OK;
+}
+
+// Chooses the SpMV of an FP64 solve of `values` on w: the symmetric one when
+// the mesh has its map and every mirrored pair of values agrees (see
+// launch_sym_pack; the packed copy then holds the stored entry of each
+// pair), else the general one.  Synchronises the stream.
+static fe_status select_sym(fe_mesh_s *m, CGWork &w, const double *values)
+{
+    fe_ctx_s *c = m->ctx;
+    w.sym = SymSpmv();
+    fe_status s = ensure_sym(m);
+    if (s != FE_OK || m->sym.state != 1) return s;
+    fe_mesh_s::SymState &Y = m->sym;
+    HIPCALL(c, launch_sym_pack(m->dm, Y.dst, values, const_cast<double *>(Y.map.vals), Y.bad, c->stream));
+    int32_t *hf = (int32_t *)c->host;
+    HIPCALL(c, hipMemcpyAsync(hf, Y.bad, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c)) != FE_OK) return s;
+    if (hf[0] == 0) w.sym = Y.map;
+    return FE_OK;
+}
+
 // FP64 Jacobi-PCG on the work buffers w: fills the iteration count and the
 // recursive residual of inf, and the outcome of the solve in result
-// (FE_OK, FE_ENOCONV or FE_EBREAKDOWN).
+// (FE_OK, FE_ENOCONV or FE_EBREAKDOWN).  use_sym: run the symmetric SpMV
+// when the matrix allows it (select_sym), else the general one.
 fe_status pcg_fp64(fe_mesh_s *m, CGWork &w, const double *values, const double *rhs, double *x, double rtol,
-                   int max_iter, bool allow_graphs, fe_cg_info &inf, fe_status &result)
+                   int max_iter, bool allow_graphs, fe_cg_info &inf, fe_status &result, bool use_sym)
 {
     fe_ctx_s *c = m->ctx;
     int32_t fl[4];
-    fe_status s = run_pcg<double>(m, w, values, rhs, x, rtol, max_iter, false, fl, allow_graphs);
+    fe_status s = use_sym ? select_sym(m, w, values) : FE_OK;
+    if (s != FE_OK) return s;
+    s = run_pcg<double>(m, w, values, rhs, x, rtol, max_iter, false, fl, allow_graphs);
+    inf.symmetric_spmv = w.sym.vals ? 1 : 0;
+    w.sym = SymSpmv();
     if (s != FE_OK) return s;
     const int it = fl[2];
     double hv[2];
@@ -1108,7 +1190,7 @@ fe_status fe_cg_solve(fe_mesh m, const double *values, const double *rhs, double
     fe_cg_info inf{};
     fe_status result = FE_OK;
     if (prec == FE_FP64) {
-        if ((s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, true, inf, result)) != FE_OK) return s;
+        if ((s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, true, inf, result, true)) != FE_OK) return s;
     } else {
         HIPCALL(c, cast_f64_f32(d.nnz, values, w.v32, c->stream));
         int used = 0, outer = 0;
@@ -1174,7 +1256,7 @@ fe_status fe_cg_solve_noalloc(fe_mesh m, const double *values, const double *rhs
     noalloc_layout(base, m->dm.N, max_iter, w);
     fe_cg_info inf{};
     fe_status result = FE_OK;
-    fe_status s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, false, inf, result);
+    fe_status s = pcg_fp64(m, w, values, rhs, x, rtol, max_iter, false, inf, result, false);
     if (s != FE_OK) return s;
     return pcg_finish(m, w, values, rhs, x, max_iter, inf, result, info);
 }

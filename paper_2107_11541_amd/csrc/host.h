@@ -84,8 +84,17 @@ struct fe_mesh_s {
     // recorded with
     struct PcgGraph {
         hipGraphExec_t exec = nullptr;
-        const void *vals = nullptr, *x = nullptr, *hist = nullptr;
+        const void *vals = nullptr, *x = nullptr, *hist = nullptr, *sym = nullptr;
     } graph[2];
+    // the symmetric PCG SpMV's map (built on the first FP64 solve; state 0:
+    // not built, 1: built, -1: the pattern has none) and its packed values
+    struct SymState {
+        int state = 0;
+        feasm::SymSpmv map;      // vals: the packed array
+        int32_t *dst = nullptr;  // [nnz]
+        int32_t *bad = nullptr;  // the symmetric-pair check word
+        int64_t n_packed = 0;
+    } sym;
 };
 
 namespace feasm {

@@ -101,6 +101,25 @@ inline SpmvMap spmv_map(const DevMesh &m, int elem_bytes = 8)
     return SpmvMap{m.spmv_desc, m.spmv_roff, m.spmv_lidx, m.spmv_cols, m.colidx, m.spmv_nrb, m.nnz, nt};
 }
 
+// The symmetric PCG SpMV (see SymMap in plan.h): the map's device arrays and
+// the packed values it reads (vals == nullptr: the general SpMV runs).
+struct SymSpmv {
+    const int4 *desc = nullptr;
+    const uint32_t *roff = nullptr;
+    const uint8_t *lidx = nullptr;
+    const uint32_t *mir = nullptr;
+    const int32_t *cols = nullptr;
+    const double *vals = nullptr;
+    int64_t nrb = 0;
+    int nt = 0;              // nontemporal value loads, as SpmvMap::nt
+};
+// Packs the FP64 values of the mesh pattern's entries for the symmetric SpMV
+// (dst: the map's per-entry destinations) and sets *bad to 1 when a mirror
+// entry a_ij differs from the stored a_ji by more than 2^-40 max(|a_ij|,
+// |a_ji|, sqrt|a_ii a_jj|) (or either is not finite).  *bad is set to 0 first.
+hipError_t launch_sym_pack(const DevMesh &m, const int32_t *dst, const double *vals, double *packed, int32_t *bad,
+                           hipStream_t s);
+
 // Wall faces of a mesh (boundary assembly of the wall model): face node
 // counts and connectivity (mesh numbering, unused slots repeat slot 0), the
 // wall nodes with, for each, its (face, slot) entries in ascending order,
@@ -179,6 +198,7 @@ struct CGWork {
     int64_t v32_cap = 0;
     double *d64 = nullptr;               // FP64 outer residual
     size_t bytes = 0;
+    SymSpmv sym;                         // FP64 iterations: the symmetric SpMV when sym.vals is set
 };
 
 constexpr int kPartDoubles = 8192;

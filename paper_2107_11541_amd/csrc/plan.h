@@ -172,6 +172,44 @@ int build_owner_plan(const Plan &P, OwnerPlan &O, std::string &err);
 // element's node b; nodes 0-3 of the rotated element are face f.
 extern const int kHexFaceRot[6][8];
 
+// Row blocks of the symmetric PCG SpMV (Section 5.2's matrix-vector product
+// on an SPD matrix).  A block is a run of consecutive rows r0..r1-1, built
+// like the general SpMV's blocks.  Of each pair of entries (i, j), (j, i)
+// with both rows in the block, only the upper one (j > i) is stored; the
+// lower one is a mirror entry that reads the stored value.  Per block:
+//   * <= kSymRows rows, <= kSymStored stored entries, <= kSymMirrors mirror
+//     entries, <= kSymCols columns in its column set;
+//   * the column set lists the block's own rows first (slot r - r0), then
+//     its other columns in first-touch order;
+//   * desc[4 b .. 4 b + 3] = {first row, first stored entry in the packed
+//     value array, first mirror word, first column of the set}; b = nrb is
+//     the end sentinel;
+//   * roff[first row + b + i] (i = 0..rows) = offset of row i's stored
+//     entries from the block's first | offset of its mirrors from the
+//     block's first mirror << 16;
+//   * lidx: one set slot per packed entry (parallel to the packed values);
+//   * mir: two 16-bit mirror entries per word, each the window position of
+//     the stored value (first stored entry's position modulo 4 plus its
+//     index in the block; 10 bits) | the mirrored row minus the first row
+//     << 10 (6 bits); a block's mirrors start at an even index;
+//   * dst[e] for each CSR entry e: its packed position, or -1 - the CSR
+//     position of the stored entry it mirrors.
+// Packed positions of stored entries follow CSR order with the mirrors left
+// out; each row chunk (kPlanRowChunk rows) starts at a multiple of 4.
+constexpr int kSymRows = 64, kSymStored = 1021, kSymMirrors = 512, kSymCols = 256;
+struct SymMap {
+    int64_t nrb = 0, n_packed = 0, n_mirror_words = 0;
+    std::vector<int32_t> desc;    // [nrb + 1][4]
+    std::vector<uint32_t> roff;   // [N + nrb]
+    std::vector<uint8_t> lidx;    // [n_packed + 4]
+    std::vector<uint32_t> mir;    // [n_mirror_words + 1]
+    std::vector<int32_t> cols;
+    std::vector<int32_t> dst;     // [nnz]
+};
+// 0, or FE_EBADMESH when the pattern is not structurally symmetric or a row
+// does not fit a block (err says which).
+int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMap &S, std::string &err);
+
 // Number of worker threads used by the host preprocessing.
 int host_threads();
 // Caps host_threads() for the calling thread (0: no cap); planner threads

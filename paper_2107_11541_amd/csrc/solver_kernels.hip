@@ -21,6 +21,7 @@
 //     alpha / beta without a grid-wide barrier;
 //   * CG scalars stay on the device; the host polls a flag word.
 #include "internal.h"
+#include "plan.h"
 
 namespace feasm {
 
@@ -765,6 +766,182 @@ __global__ void __launch_bounds__(kTB) k_cg_spmv_pq(SpmvMap sm, const int4 *__re
     cg_spmv_pq_step<T, VEC, NT>(sm, desc, vals, p, q, part, flags, blockIdx.x, gridDim.x);
 }
 
+// The PCG's SpMV on its symmetric matrix: the CSR-stream form above on the
+// row blocks of the symmetric map (SymMap in plan.h).  A block's window of
+// packed values holds its stored entries only; each lower entry (i, j) with
+// both rows in the block (a mirror) reads the stored (j, i) from LDS, so the
+// value stream shrinks by the block-internal lower triangle (~20 % of the
+// entries of a HEX08 Poisson matrix).  The set's first slots are the block's
+// own rows, so a mirror names its column by its row offset.  Loads, the
+// one-block-ahead prefetch and the fixed summation order follow spmv_stream:
+// thread t owns window entries 4t..4t+3, column t of the set and mirror
+// word t; the four threads of a row add its stored products and then its
+// mirror products in two interleaved partial sums and a fixed shuffle.
+// Returns this group's share of p . q.
+template <bool NT>
+__device__ inline double spmv_sym_stream(const SymSpmv &sm, int wg, int G, const double *__restrict__ p,
+                                         double *__restrict__ q, const int32_t *done_flags)
+{
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    const int ngrp = G / kXcds;
+    const int xcd = wg % kXcds, slot = wg / kXcds;
+    const int64_t nrb = sm.nrb;
+    const int64_t share = (nrb + kXcds - 1) / kXcds;
+    const int64_t lo = (int64_t)xcd * share, hi = lo + share < nrb ? lo + share : nrb;
+    int64_t blk = lo + slot;
+    if (blk >= hi) return acc;                   // uniform over the group
+    __shared__ double vs[kStreamNnz];            // the window's values, masked to the block
+    __shared__ double xs[kSpmvBlockCols];        // the gathered column set
+    __shared__ uint32_t lw[kStreamNnz / 4];      // set slots of the window entries
+    __shared__ uint32_t mw[kSymMirrors / 2];     // mirror entries, two per word
+    __shared__ uint32_t rps[kStreamRows + 1];    // row starts: stored | mirrors << 16
+    uint32_t li, mword, ro;
+    int cc, r0, nrows, nz, shift;
+    double v[4];
+    // fetch(b, d0, d1, real): issue block b's loads (descriptor pair read
+    // beforehand); real == false touches one chunk only (see spmv_stream)
+    auto fetch = [&](int64_t b, const int4 d0, const int4 d1, bool real) {
+        r0 = d0.x;
+        nrows = d1.x - d0.x;
+        nz = d1.y - d0.y;
+        const int64_t a0 = (int64_t)d0.y & ~(int64_t)3;
+        shift = d0.y - (int)a0;
+        const int chunks = real ? (shift + nz + 3) / 4 : 1;
+        const int t = tid < chunks ? tid : chunks - 1;
+        li = *(const uint32_t *)(sm.lidx + a0 + 4 * t);
+        const v2d *pv = (const v2d *)(sm.vals + a0 + 4 * (int64_t)t);
+        v2d pa, pb;
+        if constexpr (NT) {
+            pa = __builtin_nontemporal_load(pv);
+            pb = __builtin_nontemporal_load(pv + 1);
+        } else {
+            pa = pv[0];
+            pb = pv[1];
+        }
+        v[0] = pa.x;
+        v[1] = pa.y;
+        v[2] = pb.x;
+        v[3] = pb.y;
+        const int ncol = d1.w - d0.w;
+        cc = sm.cols[d0.w + (tid < ncol ? tid : ncol - 1)];
+        const int nmw = d1.z - d0.z;
+        mword = sm.mir[d0.z + (tid < nmw ? tid : 0)];
+        ro = sm.roff[(int64_t)r0 + b + (tid < nrows ? tid : nrows)];
+    };
+    fetch(blk, sm.desc[blk], sm.desc[blk + 1], true);
+    if (done_flags && wg_done(done_flags)) return acc;
+    const int row = tid / kTPR, sub = tid % kTPR;
+    for (;;) {
+        const int cr0 = r0, cn = nrows, cnz = nz, csh = shift;
+        if (tid <= cn) rps[tid] = ro;
+        const int64_t next = blk + ngrp;
+        const bool more = next < hi;
+        const int64_t nb = more ? next : blk;
+        const int4 n0 = sm.desc[nb], n1 = sm.desc[nb + 1];
+        double vv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * tid + j;
+            vv[j] = (w >= csh && w < csh + cnz) ? v[j] : 0.0;
+        }
+        const uint32_t cli = li, cmw = mword;
+        const double xc = p[cc];
+        const double wrow = p[cr0 + (row < cn ? row : cn - 1)];
+        fetch(nb, n0, n1, more);
+        // keep every load of the next block ahead of the first wait on the gathers
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vs[4 * tid + j] = vv[j];
+        lw[tid] = cli;
+        xs[tid] = xc;
+        mw[tid] = cmw;
+        __syncthreads();
+        auto term = [&](int e) { return mul_rn(vs[e], xs[(lw[e >> 2] >> (8 * (e & 3))) & 0xffu]); };
+        auto mterm = [&](int m) {
+            const uint32_t w = (mw[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+            return mul_rn(vs[w & 1023u], xs[w >> 10]);
+        };
+        double s = 0.0, s1 = 0.0;
+        if (row < cn) {
+            const uint32_t a = rps[row], e = rps[row + 1];
+            const int q1 = csh + (int)(e & 0xffffu);
+            int k = csh + (int)(a & 0xffffu) + sub;
+            for (; k + kTPR < q1; k += 2 * kTPR) {
+                s += term(k);
+                s1 += term(k + kTPR);
+            }
+            if (k < q1) s += term(k);
+            const int m1 = (int)(e >> 16);
+            int m = (int)(a >> 16) + sub;
+            for (; m + kTPR < m1; m += 2 * kTPR) {
+                s += mterm(m);
+                s1 += mterm(m + kTPR);
+            }
+            if (m < m1) s += mterm(m);
+        }
+        s += s1;
+        s += __shfl_xor(s, 1, kTPR);
+        s += __shfl_xor(s, 2, kTPR);
+        if (sub == 0 && row < cn) {
+            q[cr0 + row] = s;
+            acc += wrow * s;
+        }
+        if (!more) break;
+        __syncthreads();
+        blk = next;
+    }
+    return acc;
+}
+
+// Iteration k, first step on the symmetric map: q = A p and the partial p . q
+// (advances the iteration counter like k_cg_spmv_pq).
+template <bool NT>
+__global__ void __launch_bounds__(kTB) k_cg_spmv_sym(SymSpmv sm, const double *__restrict__ p,
+                                                     double *__restrict__ q, double *__restrict__ part,
+                                                     int32_t *flags)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_flag(flags + 3, load_flag(flags + 3) + 1);
+    __shared__ double sh[4];
+    double acc = spmv_sym_stream<NT>(sm, blockIdx.x, gridDim.x, p, q, flags);
+    acc = wg_sum(acc, sh);
+    if (threadIdx.x == 0) part[kPartPQ + blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(kTB) k_set_i32(int32_t *p, int v)
+{
+    if (threadIdx.x == 0) store_flag(p, v);
+}
+
+// packed[dst[e]] = vals[e] for stored entries; a mirror entry e = (i, j)
+// (dst[e] < 0) compares its value with the stored (j, i) at CSR position
+// -1 - dst[e], on the scale of the larger of the two and sqrt|a_ii a_jj|
+// (the bound of an off-diagonal entry of an SPD matrix, which keeps an entry
+// summed to nearly zero from failing the check on rounding alone)
+__global__ void __launch_bounds__(kTB) k_sym_pack(int64_t nnz, const int32_t *__restrict__ dst,
+                                                  const int32_t *__restrict__ colidx,
+                                                  const int32_t *__restrict__ diagpos,
+                                                  const double *__restrict__ vals, double *__restrict__ packed,
+                                                  int32_t *bad)
+{
+    bool ok = true;
+    for (int64_t e = (int64_t)blockIdx.x * kTB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kTB) {
+        const int32_t d = dst[e];
+        const double a = vals[e];
+        if (d >= 0) {
+            packed[d] = a;
+        } else {
+            const int64_t t = -1 - (int64_t)d;
+            const double b = vals[t];
+            const int32_t pi = diagpos[colidx[t]], pj = diagpos[colidx[e]];
+            const double dd = pi >= 0 && pj >= 0 ? sqrt(fabs(vals[pi] * vals[pj])) : 0.0;
+            const double m = fmax(fmax(fabs(a), fabs(b)), dd);
+            ok = ok && isfinite(a) && isfinite(b) && fabs(a - b) <= 0x1p-40 * m;
+        }
+    }
+    if (!ok) store_flag(bad, 1);
+}
+
 template <class T>
 __global__ void __launch_bounds__(kTB) k_cg_update_xr(int64_t n, T *r, T *z, const T *q, const T *dinv, double *part,
                                                       int nb_spmv, double *hist, int32_t *flags)
@@ -871,6 +1048,16 @@ hipError_t init_spmv_grid(int device)
     return hipSuccess;
 }
 
+hipError_t launch_sym_pack(const DevMesh &m, const int32_t *dst, const double *vals, double *packed, int32_t *bad,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(kTB), 0, s, bad, 0);
+    if (m.nnz > 0)
+        hipLaunchKernelGGL(k_sym_pack, dim3(stream_blocks(m.nnz)), dim3(kTB), 0, s, m.nnz, dst, m.colidx, m.diagpos,
+                           vals, packed, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmv(const DevMesh &m, const double *vals, const double *x, double *y, hipStream_t s)
 {
     return spmv_dispatch<double>(m, s, vals, x, y);
@@ -973,6 +1160,16 @@ hipError_t cg_spmv_pq(const DevMesh &m, const T *vals, CGWork &w, int, hipStream
 {
     const T *p = sizeof(T) == 8 ? (const T *)w.p : (const T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
+    if constexpr (sizeof(T) == 8) {
+        if (w.sym.vals) {
+            const dim3 grid(spmv_blocks(w.sym.nrb)), block(kTB);
+            if (w.sym.nt)
+                hipLaunchKernelGGL((k_cg_spmv_sym<true>), grid, block, 0, s, w.sym, p, q, w.part, w.flags);
+            else
+                hipLaunchKernelGGL((k_cg_spmv_sym<false>), grid, block, 0, s, w.sym, p, q, w.part, w.flags);
+            return hipGetLastError();
+        }
+    }
     const SpmvMap sm = spmv_map(m, sizeof(T));
     const dim3 grid(spmv_blocks(m.spmv_nrb)), block(kTB);
     const int4 *desc = (const int4 *)m.spmv_desc;
@@ -994,8 +1191,10 @@ hipError_t cg_updates(const DevMesh &m, T *x, CGWork &w, int k, hipStream_t s)
     T *p = sizeof(T) == 8 ? (T *)w.p : (T *)w.p32;
     T *q = sizeof(T) == 8 ? (T *)w.q : (T *)w.q32;
     T *dinv = sizeof(T) == 8 ? (T *)w.dinv : (T *)w.dinv32;
+    // the partial p . q sums of the SpMV launch that ran (one per work-group)
+    const int nb_spmv = sizeof(T) == 8 && w.sym.vals ? spmv_blocks(w.sym.nrb) : spmv_blocks(m.spmv_nrb);
     hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(w.nb), dim3(kTB), 0, s, n, r, z, (const T *)q, (const T *)dinv,
-                       w.part, spmv_blocks(m.spmv_nrb), w.hist, w.flags);
+                       w.part, nb_spmv, w.hist, w.flags);
     hipLaunchKernelGGL((k_cg_update_p<T>), dim3(w.nb), dim3(kTB), 0, s, n, x, (const T *)z, p, w.part, w.nb, w.hist,
                        (const double *)(w.hist + 4 * w.hist_cap), w.flags);
     return hipGetLastError();

@@ -1,4 +1,4 @@
-// plan_check.cpp -- runs the host planner (csrc/plan.cpp, csrc/rowplan.cpp)
+// plan_check.cpp -- runs the host planner (csrc/plan.cpp, rowplan.cpp, symmap.cpp)
 // under AddressSanitizer / UndefinedBehaviorSanitizer on small meshes of every
 // kind, renumbered and not, and checks a few of its invariants.  Test
 // infrastructure: built and run by tests/test_sanitizers_cpu.py.
@@ -19,6 +19,73 @@ static int fails = 0;
             ++fails;                                                \
         }                                                           \
     } while (0)
+
+// The symmetric SpMV map of a pattern: y = A x through the map, read the way
+// the kernel reads it, equals the CSR product, for integer values and x
+// (exact in double); every block within its limits.
+static void check_sym_map(const Plan &P)
+{
+    SymMap S;
+    std::string err;
+    const int st = build_sym_map(P.N, P.rowptr.data(), P.colidx.data(), S, err);
+    CHECK(st == 0);
+    if (st != 0) {
+        fprintf(stderr, "build_sym_map: %s\n", err.c_str());
+        return;
+    }
+    auto aval = [&](int64_t i, int64_t j) {
+        const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+        return (double)(1 + (lo * 7 + hi * 13) % 17);
+    };
+    std::vector<double> x((size_t)P.N), ycsr((size_t)P.N, 0.0), ysym((size_t)P.N, 0.0);
+    for (int64_t i = 0; i < P.N; ++i) x[(size_t)i] = (double)(i % 11) - 5.0;
+    for (int64_t i = 0; i < P.N; ++i)
+        for (int32_t q = P.rowptr[i]; q < P.rowptr[i + 1]; ++q) ycsr[(size_t)i] += aval(i, P.colidx[q]) * x[P.colidx[q]];
+    CHECK(S.lidx.size() == (size_t)S.n_packed + 4 && S.dst.size() == (size_t)P.nnz);
+    std::vector<double> packed((size_t)S.n_packed + 4, 0.0);
+    int64_t stored = 0;
+    for (int64_t i = 0; i < P.N; ++i)
+        for (int32_t q = P.rowptr[i]; q < P.rowptr[i + 1]; ++q) {
+            const int32_t d = S.dst[(size_t)q];
+            if (d >= 0) {
+                CHECK(d < S.n_packed);
+                packed[(size_t)d] = aval(i, P.colidx[q]);
+                ++stored;
+            } else {
+                const int64_t pq = -1 - (int64_t)d;   // the stored transpose
+                CHECK(pq >= 0 && pq < P.nnz && S.dst[(size_t)pq] >= 0 && P.colidx[pq] == (int32_t)i);
+            }
+        }
+    for (int64_t b = 0; b < S.nrb; ++b) {
+        const int32_t *d0 = &S.desc[(size_t)b * 4], *d1 = d0 + 4;
+        const int64_t r0 = d0[0], R = d1[0] - d0[0], a0 = d0[1] & ~3, shift = d0[1] - a0, nz = d1[1] - d0[1];
+        const int64_t nsetc = d1[3] - d0[3], nmw = d1[2] - d0[2];
+        CHECK(R >= 1 && R <= kSymRows && shift + nz <= 1024 && nmw <= kSymMirrors / 2 && nsetc <= kSymCols);
+        for (int64_t i = 0; i < R; ++i) CHECK(S.cols[(size_t)(d0[3] + i)] == (int32_t)(r0 + i));
+        for (int64_t i = 0; i < R; ++i) {
+            const uint32_t ro = S.roff[(size_t)(r0 + b + i)], ro1 = S.roff[(size_t)(r0 + b + i + 1)];
+            double y = 0.0;
+            for (uint32_t s = ro & 0xffffu; s < (ro1 & 0xffffu); ++s) {
+                const int64_t pos = shift + s;
+                CHECK(pos < 1024 && (int64_t)s < nz);
+                const int slot = S.lidx[(size_t)(a0 + pos)];
+                CHECK(slot < nsetc);
+                y += packed[(size_t)(a0 + pos)] * x[S.cols[(size_t)(d0[3] + slot)]];
+            }
+            for (uint32_t m = ro >> 16; m < (ro1 >> 16); ++m) {
+                CHECK((int64_t)m < 2 * nmw);
+                const uint32_t w = (S.mir[(size_t)d0[2] + m / 2] >> (16 * (m & 1))) & 0xffffu;
+                const int64_t pos = w & 1023u, ro_row = w >> 10;
+                CHECK(pos >= shift && pos < shift + nz && ro_row < i);
+                y += packed[(size_t)(a0 + pos)] * x[S.cols[(size_t)(d0[3] + ro_row)]];
+            }
+            ysym[(size_t)(r0 + i)] = y;
+        }
+    }
+    CHECK(S.nrb == 0 || S.desc[(size_t)S.nrb * 4] == (int32_t)P.N);
+    CHECK(ysym == ycsr);
+    CHECK(stored <= P.nnz && (P.N == 0 || stored < P.nnz));
+}
 
 int main()
 {
@@ -59,6 +126,7 @@ int main()
                     }
                     CHECK(r == m.n_nodes && t == (int64_t)O.tk_elem.size());
                 }
+                check_sym_map(P);
                 san_free(&m);
             }
     // a plan does not depend on the number of host threads that built it:
@@ -84,6 +152,25 @@ int main()
         // no block crosses an element chunk boundary
         for (size_t b = 0; b + 1 < A.blk_elem_ptr.size(); ++b)
             CHECK(A.blk_elem_ptr[b] / kPlanElemChunk == (A.blk_elem_ptr[b + 1] - 1) / kPlanElemChunk);
+        san_free(&m);
+    }
+    // the symmetric SpMV map over more than one row chunk, built with 1 and
+    // with 4 threads
+    {
+        SanMesh m = san_cube(32, 0);
+        CHECK(m.n_nodes > kPlanRowChunk);
+        Plan P;
+        std::string err;
+        CHECK(build_plan(m.stride, m.types, m.n_nodes, m.coords, m.n_elems, m.conn, true, P, err) == 0);
+        check_sym_map(P);
+        SymMap S1, S4;
+        set_thread_budget(1);
+        CHECK(build_sym_map(P.N, P.rowptr.data(), P.colidx.data(), S1, err) == 0);
+        set_thread_budget(4);
+        CHECK(build_sym_map(P.N, P.rowptr.data(), P.colidx.data(), S4, err) == 0);
+        set_thread_budget(0);
+        CHECK(S1.nrb == S4.nrb && S1.n_packed == S4.n_packed && S1.desc == S4.desc && S1.roff == S4.roff &&
+              S1.lidx == S4.lidx && S1.mir == S4.mir && S1.cols == S4.cols && S1.dst == S4.dst);
         san_free(&m);
     }
     // a plan object reused for another mesh (the serving runtime's images)

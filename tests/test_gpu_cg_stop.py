@@ -85,7 +85,8 @@ def test_converged_solve_equals_fixed_iteration_solve(fe_ctx, n, rtol):
 def test_served_batch_beyond_residency_equals_plain_api(fe_ctx):
     """Six 56^3..64^3 requests in one server: their batched update launches
     carry ~3000 work-groups of 256 threads, more than the 2048 a 256-CU GPU
-    holds at once.  Each served x must be bitwise the plain API's."""
+    holds at once.  Each served x must be bitwise the plain API's solve
+    with the general SpMV (fe_cg_solve_noalloc)."""
     fe = _fe()
     import torch
     sides = (64, 56, 60, 64, 58, 62)
@@ -104,7 +105,7 @@ def test_served_batch_beyond_residency_equals_plain_api(fe_ctx):
         mesh = fe.Mesh(fe_ctx, HEX, c.coords, c.conn, c.dirichlet, coloured=True)   # the served form
         L, f = _poisson(fe, mesh, c)
         x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
-        x, info = fe.cg_solve(mesh, L, f, x=x, rtol=1e-8, max_iter=20000)
+        x, info = fe.cg_solve_noalloc(mesh, L, f, x=x, rtol=1e-8, max_iter=20000)
         xu = host(mesh.to_user(x))
         mesh.close()
         print(c.name, "served", r["iterations"], "plain", info["iterations"], flush=True)

@@ -406,6 +406,7 @@ def test_pcg_fixed_iterations_follow_the_oracle(fe_ctx):
     mesh, L, f = poisson_gpu(fe_ctx, case)
     x, info = fe.cg_solve(mesh, L, f, rtol=0.0, max_iter=12)
     assert info["status"] == 0 and info["iterations"] == 12
+    assert info["symmetric_spmv"]   # the Poisson matrix is symmetric: the symmetric SpMV ran
     rp, ci, Lr, fr = poisson_oracle(case)
     xo, st, it, rr, tr = oracle.pcg(rp, ci, Lr, fr, rtol=0.0, max_iter=12)
     assert it == 12

@@ -5,7 +5,8 @@ pressure solve over many independent meshes.
 A served request must give what the same request gives alone: bitwise the
 same solution and iteration count, because its work-group counts and
 summation orders do not depend on the other requests in a batch, and
-bitwise what the plain fe_cg_solve path gives for the same system.  Against
+bitwise what the plain API's general-SpMV solve (fe_cg_solve_noalloc)
+gives for the same system.  Against
 the FP64 oracle: the momentum right-hand side to 1e-12 and the pressure
 solution to the CG bound (both solved to rtol 1e-10).
 """
@@ -101,10 +102,13 @@ def test_served_alone_equals_served_in_a_mix(fe_ctx):
 
 
 def test_served_equals_plain_api(fe_ctx):
-    """The batched kernels and the one-system PCG give bitwise the same x."""
+    """The batched kernels and the one-system PCG with the general SpMV
+    (fe_cg_solve_noalloc) give bitwise the same x; fe_cg_solve, which runs
+    the symmetric SpMV on this matrix, agrees to rounding."""
     fe = _fe()
     import torch
     from tests.gpu_helpers import dev, host
+    from tests.gpu_helpers import rel
     case = _case(9, 400)
     srv = fe.Server(fe_ctx, hbm_budget=1 << 30, max_slots=2, host_threads=1)
     served = srv.wait(_submit(srv, case, rtol=1e-9))
@@ -114,11 +118,16 @@ def test_served_equals_plain_api(fe_ctx):
     L, f, _ = fe.assemble(mesh, fe.POISSON, case.dt, u, rho)
     fe.apply_dirichlet(mesh, L, f)
     x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
-    x, info = fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-9, max_iter=5000)
+    x, info = fe.cg_solve_noalloc(mesh, L[0], f[0], x=x, rtol=1e-9, max_iter=5000)
     xu = host(mesh.to_user(x))
+    xs, infos = fe.cg_solve(mesh, L[0], f[0], rtol=1e-9, max_iter=5000)
+    xsu = host(mesh.to_user(xs))
     mesh.close()
     assert served["iterations"] == info["iterations"]
     assert np.array_equal(served["x"], xu)
+    assert infos["symmetric_spmv"] and not info["symmetric_spmv"]
+    assert abs(infos["iterations"] - info["iterations"]) <= 2
+    assert rel(xsu, xu) <= 1e-7
 
 
 def test_bad_element_fails_only_its_request(fe_ctx):
@@ -173,8 +182,9 @@ def test_many_requests_small_arena(fe_ctx):
 
 def test_hybrid_and_prism_requests_in_a_mix(fe_ctx):
     """Hybrid (all four types) and prism meshes served in one batch with
-    hexahedral ones: each equals the plain API on the same mesh bitwise and
-    the oracle's pressure to the CG bound."""
+    hexahedral ones: each equals the plain API's general-SpMV solve
+    (fe_cg_solve_noalloc) on the same mesh bitwise and the oracle's pressure
+    to the CG bound."""
     fe = _fe()
     import torch
     from tests.gpu_helpers import dev, host, make_mesh
@@ -199,7 +209,7 @@ def test_hybrid_and_prism_requests_in_a_mix(fe_ctx):
         L, f, _ = fe.assemble(mesh, fe.POISSON, case.dt, u, rho)
         fe.apply_dirichlet(mesh, L, f)
         x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
-        x, info = fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-10, max_iter=5000)
+        x, info = fe.cg_solve_noalloc(mesh, L[0], f[0], x=x, rtol=1e-10, max_iter=5000)
         xu = host(mesh.to_user(x))
         mesh.close()
         assert r["iterations"] == info["iterations"]

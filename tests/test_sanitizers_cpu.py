@@ -28,7 +28,8 @@ def _run(cmd, tmp_path, name):
 def test_planner_under_asan_ubsan(tmp_path):
     csrc = os.path.join(ROOT, "paper_2107_11541_amd", "csrc")
     cmd = ["g++", "-std=c++17", "-pthread", *FLAGS, "-I", os.path.join(ROOT, "include"),
-           os.path.join(SAN, "plan_check.cpp"), os.path.join(csrc, "plan.cpp"), os.path.join(csrc, "rowplan.cpp")]
+           os.path.join(SAN, "plan_check.cpp"), os.path.join(csrc, "plan.cpp"), os.path.join(csrc, "rowplan.cpp"),
+           os.path.join(csrc, "symmap.cpp")]
     out = _run(cmd, tmp_path, "plan_check")
     assert "0 failed checks" in out
 
