@@ -117,16 +117,16 @@ def poisson_bytes(nnz, n, conn_entries):
     return n * 56 + 4 * conn_entries + nnz * 8 + n * 8
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of the dominant kernel from the committed PMC summary
-    of this workload (profiles/k_cg_spmv_pq_<workload>.md).
+    of this workload (profiles/<kernel>_<workload>.md).
 
     The summary records a hash of the solver kernel sources; once they have
     changed the counters describe another kernel and the figure is dropped
     (None), as it is for any workload the counters were not taken on.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_cg_spmv_pq_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     try:
         text = open(path).read()
     except OSError:
@@ -138,7 +138,8 @@ def measured_traffic(workload):
                                                "source_sha256"):
             k, v = ln.split(":", 1)
             kv[k] = v.strip()
-    if kv.get("traffic_workload") != workload or "traffic_bytes_per_launch" not in kv:
+    if kv.get("traffic_workload") != workload or kv.get("traffic_kernel") != kernel or \
+            "traffic_bytes_per_launch" not in kv:
         return None
     h = hashlib.sha256()
     for rel in ("solver_kernels.hip", "internal.h"):
@@ -149,15 +150,19 @@ def measured_traffic(workload):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline_entry(workload, algo_bytes, avg_us, launches):
+def roofline_entry(workload, algo_bytes, avg_us, launches, symmetric):
     """The dominant kernel against the HBM roofline: achieved = its
-    algorithmic bytes per launch over its average launch time; beside it the
-    real HBM rate, the counted bytes per launch over the same time, while the
-    counters describe the kernel as built (else null)."""
+    algorithmic bytes per launch (those of the CSR product it computes) over
+    its average launch time; beside it the real HBM rate, the counted bytes
+    per launch over the same time, while the counters describe the kernel as
+    built (else null).  symmetric: the PCG ran the symmetric SpMV."""
+    kernel = "k_cg_spmv_sym" if symmetric else "k_cg_spmv_pq"
     achieved = algo_bytes / (avg_us * 1e-6) / 1e9
-    traffic = measured_traffic(workload)
+    traffic = measured_traffic(workload, kernel)
     real = traffic / (avg_us * 1e-6) / 1e9 if traffic else None
-    return {"bound": "hbm", "kernel": "k_cg_spmv_pq (CSR SpMV fused with p.Ap)",
+    label = ("k_cg_spmv_sym (CSR SpMV, in-block symmetric pairs read once, fused with p.Ap)" if symmetric
+             else "k_cg_spmv_pq (CSR SpMV fused with p.Ap)")
+    return {"bound": "hbm", "kernel": label,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "real_hbm_gbs": real, "real_frac": real / HBM_PEAK_GBS if real else None,
             "algorithmic_bytes_per_launch": algo_bytes, "avg_launch_us": avg_us, "launches": launches}
@@ -711,7 +716,7 @@ def main():
         "config": {"workload": wl, "elements": E, "nodes": N, "nnz": nnz, "cg_iterations": CG_ITERS,
                    "blocks": info["n_blocks"], "colours": info["n_colors"],
                    "elements_by_nodes_per_element": type_counts},
-        "roofline": roofline_entry(args.workload, sb, spmv_us, n_spmv),
+        "roofline": roofline_entry(args.workload, sb, spmv_us, n_spmv, last["cg"]["symmetric_spmv"]),
         "breakdown": {
             "assembly_ms_per_step": ms_asm / prof_steps,
             "momentum_assembly_ms": ms_mom, "poisson_assembly_ms": ms_poi,
@@ -722,6 +727,7 @@ def main():
             "momentum_mixed_vs_fp64": mixed_err,
             "assembly_roofline": assembly_roofline(args.workload, E, ms_mom, ms_poi, ms_mix),
             "dirichlet_ms": ms_dir / max(n_dir, 1),
+            "cg_symmetric_spmv": cg["symmetric_spmv"],
             "cg_spmv_us": spmv_us, "cg_update_us": ms_upd / max(n_upd, 1) * 1e3,
             "cg_iteration_effective_gbs": (sb + 88 * N) / ((spmv_us + ms_upd / max(n_upd, 1) * 1e3) * 1e-6) / 1e9,
             "cg_rel_residual_after_200": cg["rel_residual"], "cg_true_rel_residual": cg["true_rel_residual"],

@@ -917,15 +917,26 @@ __global__ void __launch_bounds__(kTB) k_set_i32(int32_t *p, int v)
 // (dst[e] < 0) compares its value with the stored (j, i) at CSR position
 // -1 - dst[e], on the scale of the larger of the two and sqrt|a_ii a_jj|
 // (the bound of an off-diagonal entry of an SPD matrix, which keeps an entry
-// summed to nearly zero from failing the check on rounding alone)
+// summed to nearly zero from failing the check on rounding alone).
+// Work-group b takes a contiguous chunk of kPackChunk entries, the chunks of
+// one XCD consecutive (groups are dispatched round-robin over the XCDs): the
+// partner and the diagonals of a mirror lie within its row block, so their
+// lines are in the L2 of the XCD that streams the block.  One chunk per group
+// keeps many groups in flight for the dependent loads of the check.
+constexpr int kPackChunk = 16 * kTB;
 __global__ void __launch_bounds__(kTB) k_sym_pack(int64_t nnz, const int32_t *__restrict__ dst,
                                                   const int32_t *__restrict__ colidx,
                                                   const int32_t *__restrict__ diagpos,
                                                   const double *__restrict__ vals, double *__restrict__ packed,
                                                   int32_t *bad)
 {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t q = G / kXcds, rem = G % kXcds, x = b % kXcds;
+    const int64_t chunk = x * q + (x < rem ? x : rem) + b / kXcds;
+    const int64_t e0 = chunk * kPackChunk, e1 = e0 + kPackChunk < nnz ? e0 + kPackChunk : nnz;
     bool ok = true;
-    for (int64_t e = (int64_t)blockIdx.x * kTB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kTB) {
+#pragma unroll 4
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kTB) {
         const int32_t d = dst[e];
         const double a = vals[e];
         if (d >= 0) {
@@ -1053,8 +1064,8 @@ hipError_t launch_sym_pack(const DevMesh &m, const int32_t *dst, const double *v
 {
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(kTB), 0, s, bad, 0);
     if (m.nnz > 0)
-        hipLaunchKernelGGL(k_sym_pack, dim3(stream_blocks(m.nnz)), dim3(kTB), 0, s, m.nnz, dst, m.colidx, m.diagpos,
-                           vals, packed, bad);
+        hipLaunchKernelGGL(k_sym_pack, dim3((unsigned)((m.nnz + kPackChunk - 1) / kPackChunk)), dim3(kTB), 0, s,
+                           m.nnz, dst, m.colidx, m.diagpos, vals, packed, bad);
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = ("solver_kernels.hip", "internal.h")
 
 
+K = "k_cg_spmv_sym"
+
+
 def _fake_root(tmp_path, workload, sha=None, bytes_=123456789):
     csrc = tmp_path / "paper_2107_11541_amd" / "csrc"
     csrc.mkdir(parents=True)
@@ -24,8 +27,8 @@ def _fake_root(tmp_path, workload, sha=None, bytes_=123456789):
         shutil.copy(os.path.join(ROOT, "paper_2107_11541_amd", "csrc", name), csrc / name)
         h.update((csrc / name).read_bytes())
     (tmp_path / "profiles").mkdir()
-    (tmp_path / "profiles" / f"k_cg_spmv_pq_{workload}.md").write_text(
-        "# summary\n\n    traffic_kernel: k_cg_spmv_pq\n"
+    (tmp_path / "profiles" / f"{K}_{workload}.md").write_text(
+        f"# summary\n\n    traffic_kernel: {K}\n"
         f"    traffic_workload: {workload}\n    traffic_bytes_per_launch: {bytes_}\n"
         f"    source_sha256: {sha or h.hexdigest()}\n")
     return tmp_path
@@ -33,26 +36,26 @@ def _fake_root(tmp_path, workload, sha=None, bytes_=123456789):
 
 def test_traffic_read_for_its_workload(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(_fake_root(tmp_path, "hex128")))
-    assert bench.measured_traffic("hex128") == 123456789.0
-    assert bench.measured_traffic("hybrid128") is None     # no summary for it
+    assert bench.measured_traffic("hex128", K) == 123456789.0
+    assert bench.measured_traffic("hybrid128", K) is None     # no summary for it
+    assert bench.measured_traffic("hex128", "k_cg_spmv_pq") is None     # nor for the other kernel
 
 
 def test_traffic_dropped_when_sources_changed(tmp_path, monkeypatch):
     root = _fake_root(tmp_path, "hybrid128")
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.measured_traffic("hybrid128") == 123456789.0
+    assert bench.measured_traffic("hybrid128", K) == 123456789.0
     with open(root / "paper_2107_11541_amd" / "csrc" / "internal.h", "a") as fh:
         fh.write("\n// edited\n")
-    assert bench.measured_traffic("hybrid128") is None
+    assert bench.measured_traffic("hybrid128", K) is None
 
 
 def test_traffic_dropped_for_another_workload_or_hash(tmp_path, monkeypatch):
     root = _fake_root(tmp_path, "hex128", sha="0" * 64)
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.measured_traffic("hex128") is None
-    (root / "profiles" / "k_cg_spmv_pq_tet128.md").write_text(
-        (root / "profiles" / "k_cg_spmv_pq_hex128.md").read_text())
-    assert bench.measured_traffic("tet128") is None     # records another workload
+    assert bench.measured_traffic("hex128", K) is None
+    (root / "profiles" / f"{K}_tet128.md").write_text((root / "profiles" / f"{K}_hex128.md").read_text())
+    assert bench.measured_traffic("tet128", K) is None     # records another workload
 
 
 def test_more_than_one_gpu_is_refused():
@@ -67,11 +70,11 @@ def test_committed_traffic_summaries_name_their_workload():
     # positive byte count and a full hash
     import glob
     import re
-    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_cg_spmv_pq_*.md")))
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_cg_spmv_*_*.md")))
     assert paths
     for p in paths:
-        wl = re.match(r"k_cg_spmv_pq_(.+)\.md$", os.path.basename(p)).group(1)
+        kern, wl = re.match(r"(k_cg_spmv_(?:sym|pq))_(.+)\.md$", os.path.basename(p)).groups()
         kv = dict(ln.strip().split(": ", 1) for ln in open(p) if re.match(r"\s+(traffic_\w+|source_sha256): ", ln))
-        assert kv["traffic_workload"] == wl and kv["traffic_kernel"] == "k_cg_spmv_pq"
+        assert kv["traffic_workload"] == wl and kv["traffic_kernel"] == kern
         assert float(kv["traffic_bytes_per_launch"]) > 0
         assert re.fullmatch(r"[0-9a-f]{64}", kv["source_sha256"])
