@@ -25,6 +25,7 @@
 // Precision: FP64, or (mixed) FP32 Gauss-point products and elemental sums
 // with the Jacobian, det J, J^-1 and the CSR accumulation in FP64.
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 #include "internal.h"
@@ -502,18 +503,18 @@ __device__ __forceinline__ void gauss_loop(const Geo<EL> &GE, const double *nd, 
 
 // One work-group = one block of <= 64 elements = W waves.  Lane l computes
 // rows [a0, a0 + RA) of element l mod 64 with a0 = (l / 64) * RA.
-// The block body of every assembly and element-vector pass.  FORM >= 0
-// fixes the residual pass's operator variants at compile time; -1 reads them
-// from the arguments.
+// The block body of every assembly and element-vector pass: block
+// color_blk[blk_offset + wg] of the launch.  FORM >= 0 fixes the residual
+// pass's operator variants at compile time; -1 reads them from the arguments.
 template <class EL, int OP, class Q, int FORM>
-__device__ __forceinline__ void assemble_block(const KArgs &k)
+__device__ __forceinline__ void assemble_block(const KArgs &k, int wg)
 {
     constexpr int NEN = EL::NEN, NG = EL::NG, W = Split<EL>::W, RA = NEN / W, NT = 64 * W;
     constexpr int NF = OpTraits<OP>::NF, NRHS = OpTraits<OP>::NRHS;
     constexpr bool VEC = OP >= OP_RES;       // element-vector pass: no row image
     extern __shared__ double lds[];
 
-    const int blk = k.color_blk[k.blk_offset + blockIdx.x];
+    const int blk = k.color_blk[k.blk_offset + wg];
     const int e0 = k.blk_elem_ptr[blk], ne = k.blk_elem_ptr[blk + 1] - e0;
     const int n0 = k.blk_node_ptr[blk], T = k.blk_node_ptr[blk + 1] - n0;
     const int tid = threadIdx.x;
@@ -697,7 +698,31 @@ __device__ __forceinline__ void assemble_block(const KArgs &k)
 template <class EL, int OP, class Q>
 __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
 {
-    assemble_block<EL, OP, Q, -1>(k);
+    assemble_block<EL, OP, Q, -1>(k, blockIdx.x);
+}
+
+// Batched coloured assembly (the serving runtime): one launch runs the same
+// (colour, type) launch of several meshes.  Work-group w belongs to entry j
+// with wgs[j] <= w < wgs[j + 1] (a handful of entries: a linear scan); the
+// entry's kernel arguments are ks[slot[j]], its blocks color_blk[first[j] +
+// w - wgs[j]].  Each block runs the code of k_assemble, so a mesh's results
+// do not depend on what shares the launch.
+struct AsmBatch {
+    int n;
+    int slot[kMaxBatch];
+    int first[kMaxBatch];
+    int wgs[kMaxBatch + 1];
+};
+static_assert(sizeof(KArgs) <= kKArgsBytes, "the device table's slot size");
+
+template <class EL, int OP>
+__global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_bat_assemble(const KArgs *__restrict__ ks, AsmBatch B)
+{
+    int j = 0;
+    while (j + 1 < B.n && (int)blockIdx.x >= B.wgs[j + 1]) ++j;
+    // read in place (its blk_offset is 0): a copy would hold every field live
+    const KArgs &k = *(const KArgs *)((const char *)ks + (size_t)B.slot[j] * kKArgsBytes);
+    assemble_block<EL, OP, double, -1>(k, B.first[j] + (int)blockIdx.x - B.wgs[j]);
 }
 
 // The momentum residual pass with its operator variants (FE_FORM_* bits)
@@ -705,7 +730,7 @@ __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_assemble(KArgs k)
 template <class EL, int FORM>
 __global__ void __launch_bounds__(64 * Split<EL>::W, 2) k_residual(KArgs k)
 {
-    assemble_block<EL, OP_RES, double, FORM>(k);
+    assemble_block<EL, OP_RES, double, FORM>(k, blockIdx.x);
 }
 
 // ---- owner assembly of the matrix operators ---------------------------------
@@ -1365,10 +1390,12 @@ hipError_t launch_wall_traction(const DevMesh &m, const DevWall &w, const double
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
+namespace {
+
+// The coloured kernels' arguments for one operator pass.
+KArgs make_kargs(const AsmArgs &a)
 {
     const DevMesh &m = *a.m;
-    if (a.op < 0 || a.op >= kNumOps) return hipErrorInvalidValue;
     KArgs k{};
     k.X = m.X;
     k.blk_elem_ptr = m.blk_elem_ptr;
@@ -1400,6 +1427,78 @@ hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
     k.blk_bad = (long long *)(k.blk_mindet + nstat);
     k.off_stride = m.off_stride;
     k.form = a.form;
+    return k;
+}
+
+template <class EL>
+void launch_bat(int op, const AsmBatch &B, const KArgs *ks, size_t lds, hipStream_t s)
+{
+    if (op == OP_MOM)
+        hipLaunchKernelGGL((k_bat_assemble<EL, OP_MOM>), dim3(B.wgs[B.n]), dim3(64 * Split<EL>::W), lds, s, ks, B);
+    else
+        hipLaunchKernelGGL((k_bat_assemble<EL, OP_POI>), dim3(B.wgs[B.n]), dim3(64 * Split<EL>::W), lds, s, ks, B);
+}
+
+}  // namespace
+
+void fill_kargs(const AsmArgs &a, void *out)
+{
+    const KArgs k = make_kargs(a);
+    memset(out, 0, kKArgsBytes);
+    memcpy(out, &k, sizeof(KArgs));
+}
+
+hipError_t launch_assemble_batch(const AsmArgs *a, const int *slot, int n, const void *kargs_d, hipStream_t s)
+{
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    const int op = a[0].op;
+    if (op != OP_MOM && op != OP_POI) return hipErrorInvalidValue;
+    size_t nl = 0;
+    for (int i = 0; i < n; ++i) {
+        if (a[i].op != op || a[i].m->own_G > 0) return hipErrorInvalidValue;
+        nl = std::max(nl, a[i].m->launches.size());
+    }
+    const KArgs *ks = (const KArgs *)kargs_d;
+    // launch li of every mesh, one launch per element type; launch li + 1
+    // after it, so each mesh keeps its own colour order
+    for (size_t li = 0; li < nl; ++li) {
+        for (int nen : {8, 6, 5, 4}) {
+            AsmBatch B{};
+            size_t lds = 0;
+            for (int i = 0; i < n; ++i) {
+                const std::vector<AsmLaunch> &Ls = a[i].m->launches;
+                if (li >= Ls.size() || Ls[li].nen != nen || Ls[li].count == 0) continue;
+                B.slot[B.n] = slot[i];
+                B.first[B.n] = Ls[li].first;
+                B.wgs[B.n + 1] = B.wgs[B.n] + Ls[li].count;
+                lds = std::max(lds, Ls[li].lds[op]);
+                ++B.n;
+            }
+            if (B.n == 0) continue;
+            switch (nen) {
+            case 8: launch_bat<Hex>(op, B, ks, lds, s); break;
+            case 6: launch_bat<Pen>(op, B, ks, lds, s); break;
+            case 5: launch_bat<Pyr>(op, B, ks, lds, s); break;
+            default: launch_bat<Tet>(op, B, ks, lds, s); break;
+            }
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
+    }
+    // each mesh's status word from its per-block scratch (as launch_assemble)
+    for (int i = 0; i < n; ++i) {
+        const KArgs k = make_kargs(a[i]);
+        hipLaunchKernelGGL(k_asm_status, dim3(1), dim3(kStatusThreads), 0, s, k.blk_mindet, k.blk_bad, a[i].m->nblk,
+                           a[i].status_out ? a[i].status_out : a[i].status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s)
+{
+    const DevMesh &m = *a.m;
+    if (a.op < 0 || a.op >= kNumOps) return hipErrorInvalidValue;
+    KArgs k = make_kargs(a);
     if (a.op < OP_RES && m.own_G > 0) {
         // matrix operators of a single-type mesh: the owner assembly, one launch
         OArgs o{};

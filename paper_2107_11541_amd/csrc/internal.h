@@ -145,6 +145,9 @@ struct AsmStatus {
     long long first_bad;                // smallest mesh element index with det J <= 0
 };
 
+// Systems (serving slots) one batched launch may cover.
+constexpr int kMaxBatch = 32;
+
 struct AsmArgs {
     const DevMesh *m;
     int op;                  // fe_operator, or kOpResidual / kOpGradient / kOpDivergence
@@ -160,6 +163,15 @@ struct AsmArgs {
 
 // Launchers (asm_kernels.hip).
 hipError_t launch_assemble(const AsmArgs &a, bool mixed, hipStream_t s);
+// Batched coloured assembly of one operator (MOMENTUM or POISSON, FP64) over
+// n meshes that carry the coloured plan only (the serving runtime): launch li
+// of every mesh's (colour, type) list runs as one launch per element type,
+// launch li + 1 after it, then each mesh's status word.  Request i's kernel
+// arguments must sit in the device table kargs_d at slot[i] * kKArgsBytes,
+// written from fill_kargs(a[i]) before the launches run.
+constexpr size_t kKArgsBytes = 256;
+void fill_kargs(const AsmArgs &a, void *out);   // out: kKArgsBytes bytes
+hipError_t launch_assemble_batch(const AsmArgs *a, const int *slot, int n, const void *kargs_d, hipStream_t s);
 
 // Device copy of the row-owner plan of the 3x3-block momentum operator
 // (plan.h RowPlan), built on the first block assembly of a mesh.
@@ -251,7 +263,7 @@ struct BatchJob {
     int nb_spmv, nb_vec;
     int vec;                     // 16-byte SpMV loads (vals aligned, nnz >= 4)
 };
-constexpr int kMaxBatch = 32;
+
 struct BatchList {
     int n;                       // systems in this launch
     int slot[kMaxBatch];         // index into the BatchJob table

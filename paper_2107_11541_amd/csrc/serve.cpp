@@ -9,6 +9,8 @@
 //     fe_mesh_upload preprocessing, on one to four threads per mesh);
 //   * places every admitted request in one pre-allocated device arena
 //     (admission by footprint; no hipMalloc per request);
+//   * assembles the requests admitted in one pass together: one launch per
+//     (colour, type) launch index and element type over all of them;
 //   * advances all admitted requests' PCG iterations together, three
 //     launches per iteration whatever the number of requests, and polls
 //     their device-side stop flags asynchronously (one small copy per poll);
@@ -86,6 +88,7 @@ struct fe_server_s {
     std::unique_ptr<DevArena> arena;
     int max_slots = 0;
     BatchJob *jobs_d = nullptr, *jobs_h = nullptr;   // per-slot system descriptions
+    char *kargs_d = nullptr, *kargs_h = nullptr;     // per-slot assembly arguments (momentum, Poisson)
     int32_t *flags_d = nullptr, *flags_h = nullptr;  // per-slot PCG flag words (4 ints)
     double *res_d = nullptr, *res_h = nullptr;       // per-slot read-back area
     std::vector<double *> stage;                     // per-slot pinned staging for x and mom_rhs
@@ -242,8 +245,28 @@ fe_status ensure_stage(fe_server_s *S, int slot, size_t doubles)
     return FE_OK;
 }
 
-// Allocates the request's device memory, uploads it and queues assembly,
-// Dirichlet elimination and the PCG set-up.  On failure every allocation is
+// The assembly arguments of an admitted request (FP64, coloured plan).
+AsmArgs job_asm_args(Job *j, int op)
+{
+    fe_mesh_s *m = j->mesh;
+    const int64_t N = m->dm.N;
+    AsmArgs a{};
+    a.m = &m->dm;
+    a.op = op;
+    a.dt = j->desc.dt;
+    a.u = j->fields_d;
+    a.rho = j->fields_d + 3 * N;
+    a.mu = j->fields_d + 4 * N;
+    a.status = m->status;
+    a.values = op == FE_OP_MOMENTUM ? j->vals_m : j->vals_p;
+    a.rhs = op == FE_OP_MOMENTUM ? j->rhs_m : j->rhs_p;
+    return a;
+}
+
+// Allocates an admitted request's device memory, uploads its mesh and
+// fields and writes its assembly arguments; the assemblies, the Dirichlet
+// elimination and the PCG set-up follow with the other admissions of the
+// pass (assemble_admitted, admit_finish).  On failure every allocation is
 // returned and the status says why (FE_ENOMEM: try again later).
 fe_status admit(fe_server_s *S, Job *j)
 {
@@ -280,16 +303,46 @@ fe_status admit(fe_server_s *S, Job *j)
     w.flags = S->flags_d + 4 * j->slot;   // polled with every other slot's flags in one copy
     HIPCALL(c, hipMemcpyAsync(j->fields_d, j->fields.data(), j->fields.size() * sizeof(double), hipMemcpyHostToDevice,
                               S->stream));
-    fe_fields fm{};
-    fm.op = FE_OP_MOMENTUM;
-    fm.dt = q.dt;
-    fm.u = j->fields_d;
-    fm.rho = j->fields_d + 3 * N;
-    fm.mu = j->fields_d + 4 * N;
-    if ((s = assemble_queue(m, &fm, FE_FP64, j->vals_m, j->rhs_m, S->stream)) != FE_OK) return s;
-    fe_fields fp = fm;
-    fp.op = FE_OP_POISSON;
-    if ((s = assemble_queue(m, &fp, FE_FP64, j->vals_p, j->rhs_p, S->stream)) != FE_OK) return s;
+    // the two assemblies run batched with the other admissions of this pass
+    // (assemble_admitted); their kernel arguments go to this slot's entries
+    char *kh = S->kargs_h + (size_t)2 * j->slot * kKArgsBytes;
+    fill_kargs(job_asm_args(j, FE_OP_MOMENTUM), kh);
+    fill_kargs(job_asm_args(j, FE_OP_POISSON), kh + kKArgsBytes);
+    HIPCALL(c, hipMemcpyAsync(S->kargs_d + (size_t)2 * j->slot * kKArgsBytes, kh, 2 * kKArgsBytes,
+                              hipMemcpyHostToDevice, S->stream));
+    return FE_OK;
+}
+
+// The momentum and Poisson assemblies of the requests admitted in one
+// dispatcher pass: one launch per (colour, type) launch index and element
+// type over all of them, each request's blocks running the code of its own
+// coloured launch (its results do not depend on the batch).
+fe_status assemble_admitted(fe_server_s *S, const std::vector<Job *> &js)
+{
+    fe_ctx_s *c = &S->sctx;
+    AsmArgs a[kMaxBatch];
+    int slot[kMaxBatch];
+    const int n = (int)js.size();
+    if (n < 1 || n > kMaxBatch) return fail(c, FE_EINVAL, "internal: %d admissions in one pass", n);
+    for (int o = 0; o < 2; ++o) {
+        for (int i = 0; i < n; ++i) {
+            a[i] = job_asm_args(js[i], o == 0 ? FE_OP_MOMENTUM : FE_OP_POISSON);
+            slot[i] = 2 * js[i]->slot + o;
+        }
+        HIPCALL(c, launch_assemble_batch(a, slot, n, S->kargs_d, S->stream));
+    }
+    return FE_OK;
+}
+
+// After the assemblies: the Dirichlet elimination, the PCG set-up and the
+// request's entry in the batched PCG's table.
+fe_status admit_finish(fe_server_s *S, Job *j)
+{
+    fe_ctx_s *c = &S->sctx;
+    const fe_job &q = j->desc;
+    fe_mesh_s *m = j->mesh;
+    const int64_t N = m->dm.N, nnz = m->dm.nnz;
+    CGWork &w = m->cg;
     HIPCALL(c, launch_dirichlet(m->dm, j->vals_p, j->rhs_p, nullptr, S->stream));
     HIPCALL(c, cg_setup<double>(m->dm, j->vals_p, j->rhs_p, j->x_d, w, q.rtol, S->stream, true));
     BatchJob &b = S->jobs_h[j->slot];
@@ -435,6 +488,7 @@ void dispatcher_main(fe_server_s *S)
         // passed by later ones: each admission past it counts, and after
         // kMaxBypass of them nothing behind it is admitted until it fits
         std::vector<Job *> passed;   // requests of this pass that did not fit
+        std::vector<Job *> fresh;    // admitted in this pass: assembled together below
         for (size_t i = 0; i < S->ready.size() && !S->free_slots.empty();) {
             Job *j = S->ready[i];
             if (j->bytes > S->arena->free_bytes()) {
@@ -462,11 +516,29 @@ void dispatcher_main(fe_server_s *S)
                 complete(j);
                 continue;
             }
-            j->phase = kRunning;
             j->t_admitted = Clock::now();
-            j->k = 0;
-            S->active.push_back(j);
+            fresh.push_back(j);
             for (Job *p : passed) ++p->skipped;   // j was admitted ahead of them
+        }
+        if (!fresh.empty()) {
+            lk.unlock();
+            std::vector<fe_status> st(fresh.size(), assemble_admitted(S, fresh));
+            for (size_t i = 0; i < fresh.size(); ++i)
+                if (st[i] == FE_OK) st[i] = admit_finish(S, fresh[i]);
+            lk.lock();
+            for (size_t i = 0; i < fresh.size(); ++i) {
+                Job *j = fresh[i];
+                if (st[i] != FE_OK) {
+                    lk.unlock();
+                    fail_job(S, j, st[i], S->sctx.err);
+                    lk.lock();
+                    complete(j);
+                    continue;
+                }
+                j->phase = kRunning;
+                j->k = 0;
+                S->active.push_back(j);
+            }
         }
         // 3. idle?
         if (S->active.empty()) {
@@ -587,6 +659,8 @@ fe_status fe_serve_create(fe_ctx c, size_t hbm_budget, int32_t max_slots, int32_
         if (S->flags_d) (void)hipFree(S->flags_d);
         if (S->res_d) (void)hipFree(S->res_d);
         if (S->jobs_h) (void)hipHostFree(S->jobs_h);
+        if (S->kargs_d) (void)hipFree(S->kargs_d);
+        if (S->kargs_h) (void)hipHostFree(S->kargs_h);
         if (S->flags_h) (void)hipHostFree(S->flags_h);
         if (S->res_h) (void)hipHostFree(S->res_h);
         if (S->poll_ev) (void)hipEventDestroy(S->poll_ev);
@@ -599,6 +673,8 @@ fe_status fe_serve_create(fe_ctx c, size_t hbm_budget, int32_t max_slots, int32_
               hipMalloc((void **)&S->flags_d, kMaxBatch * 4 * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void **)&S->res_d, kMaxBatch * kResDoubles * sizeof(double)) == hipSuccess &&
               hipHostMalloc((void **)&S->jobs_h, kMaxBatch * sizeof(BatchJob), hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void **)&S->kargs_d, 2 * kMaxBatch * kKArgsBytes) == hipSuccess &&
+              hipHostMalloc((void **)&S->kargs_h, 2 * kMaxBatch * kKArgsBytes, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void **)&S->flags_h, kMaxBatch * 4 * sizeof(int32_t), hipHostMallocDefault) ==
                   hipSuccess &&
               hipHostMalloc((void **)&S->res_h, kMaxBatch * kResDoubles * sizeof(double), hipHostMallocDefault) ==
@@ -608,6 +684,7 @@ fe_status fe_serve_create(fe_ctx c, size_t hbm_budget, int32_t max_slots, int32_
         return fail(c, FE_ENOMEM, "serve: could not allocate the arena (%zu bytes) or its tables", hbm_budget);
     }
     memset(S->jobs_h, 0, kMaxBatch * sizeof(BatchJob));
+    memset(S->kargs_h, 0, 2 * kMaxBatch * kKArgsBytes);
     S->sctx.device = c->device;
     S->sctx.stream = S->stream;
     memset(S->flags_h, 0, kMaxBatch * 4 * sizeof(int32_t));
@@ -701,6 +778,8 @@ void fe_serve_destroy(fe_server S)
     (void)hipFree(S->flags_d);
     (void)hipFree(S->res_d);
     (void)hipHostFree(S->jobs_h);
+    (void)hipFree(S->kargs_d);
+    (void)hipHostFree(S->kargs_h);
     (void)hipHostFree(S->flags_h);
     (void)hipHostFree(S->res_h);
     (void)hipEventDestroy(S->poll_ev);
