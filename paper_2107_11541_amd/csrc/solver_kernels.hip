@@ -847,7 +847,6 @@ __device__ inline double spmv_sym_stream(const SymSpmv &sm, int wg, int G, const
         }
         const uint32_t cli = li, cmw = mword;
         const double xc = p[cc];
-        const double wrow = p[cr0 + (row < cn ? row : cn - 1)];
         fetch(nb, n0, n1, more);
         // keep every load of the next block ahead of the first wait on the gathers
         __builtin_amdgcn_sched_barrier(0);
@@ -885,7 +884,7 @@ __device__ inline double spmv_sym_stream(const SymSpmv &sm, int wg, int G, const
         s += __shfl_xor(s, 2, kTPR);
         if (sub == 0 && row < cn) {
             q[cr0 + row] = s;
-            acc += wrow * s;
+            acc += xs[row] * s;   // p[first row + row]: the set's own-row slot
         }
         if (!more) break;
         __syncthreads();
