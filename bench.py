@@ -448,7 +448,8 @@ def cfg4_measure(n, reps):
     solves, xs = {}, {}
     for name, prec in (("fp64_pcg", fe.FP64), ("mixed_ir", fe.MIXED)):
         # untimed warm-up: the first solve of a precision allocates its work
-        # vectors (and, mixed, the FP32 value copy) and records its iteration
+        # vectors (and, mixed, the FP32 value copy), builds the symmetric
+        # SpMV's map (first solve on the mesh) and records its iteration
         # graph; a time-stepping code pays that once
         x = torch.zeros(N, dtype=torch.float64, device=dev)
         fe.cg_solve(mesh, L[0], f[0], x=x, rtol=1e-8, max_iter=16, precision=prec, raise_on_noconv=False)
