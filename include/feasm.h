@@ -248,9 +248,10 @@ typedef struct {
  * each pair a_ij, a_ji whose rows fall in one SpMV row block is read once,
  * from the upper entry.  The call checks every such pair first (|a_ij -
  * a_ji| <= 2^-40 max(|a_ij|, |a_ji|, sqrt|a_ii a_jj|), both finite) and
- * otherwise runs the general SpMV; info->symmetric_spmv says which ran.  The first FP64 solve
- * on a mesh builds the symmetric map on the host and keeps it, with a
- * packed copy of the values, on the device (about 12 bytes per nonzero).
+ * otherwise runs the general SpMV; info->symmetric_spmv says which ran.
+ * The first FP64 solve on a mesh builds the symmetric map on the host and
+ * keeps it, with a packed copy of the values, on the device (about 12
+ * bytes per nonzero).
  * The two SpMVs round differently; the true residual is always computed
  * with `values` as given.  Returns FE_ENOCONV (x written) at max_iter,
  * FE_EBREAKDOWN on p.Ap <= 0 or non-finite scalars.  info may be NULL.
