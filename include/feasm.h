@@ -251,7 +251,7 @@ typedef struct {
  * otherwise runs the general SpMV; info->symmetric_spmv says which ran.
  * The first FP64 solve on a mesh builds the symmetric map on the host and
  * keeps it, with a packed copy of the values, on the device (about 12
- * bytes per nonzero).
+ * bytes per nonzero; without room for them the general SpMV runs).
  * The two SpMVs round differently; the true residual is always computed
  * with `values` as given.  Returns FE_ENOCONV (x written) at max_iter,
  * FE_EBREAKDOWN on p.Ap <= 0 or non-finite scalars.  info may be NULL.

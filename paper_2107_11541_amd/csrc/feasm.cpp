@@ -709,7 +709,8 @@ fe_status run_pcg(fe_mesh_s *m, CGWork &w, const T *vals, const T *b, T *x, doub
 
 // The symmetric SpMV map of the mesh's pattern, built on the host from the
 // device pattern and uploaded on first use.  A pattern without one (not
-// structurally symmetric) leaves state -1: its solves use the general SpMV.
+// structurally symmetric), or a device without room for it, leaves state -1:
+// the mesh's solves use the general SpMV.
 static fe_status ensure_sym(fe_mesh_s *m)
 {
     fe_mesh_s::SymState &Y = m->sym;
@@ -746,7 +747,9 @@ static fe_status ensure_sym(fe_mesh_s *m)
     if (s != FE_OK) {
         void *ps[] = {desc, roff, lidx, mir, cols, N.dst, vals, N.bad};
         for (void *q : ps) mesh_free_ptr(m, q);
-        return s;
+        if (s != FE_ENOMEM) return s;
+        Y.state = -1;   // no room for the map: this mesh's solves use the general SpMV
+        return FE_OK;
     }
     N.map.desc = (const int4 *)desc;
     N.map.roff = (const uint32_t *)roff;
