@@ -543,14 +543,14 @@ struct ProfScope {
     {
         if (c->profiling) {
             hipEvent_t e = prof_event(c, slot);
-            if (e) hipEventRecord(e, c->stream);
+            if (e) (void)hipEventRecord(e, c->stream);   // a failed bracket only loses a timing
         }
     }
     ~ProfScope()
     {
         if (c->profiling) {
             hipEvent_t e = prof_event(c, slot);
-            if (e) hipEventRecord(e, c->stream);
+            if (e) (void)hipEventRecord(e, c->stream);
         }
     }
 };
