@@ -266,8 +266,10 @@ def serve_measure(nreq, slots, threads, budget_gb, modes=("saturated", "load0.8"
     RTOL = 1e-8
 
     def run_plain(c):
-        # a mesh assembled once: the coloured blocks (no owner plan to build)
-        mesh = fe.Mesh(ctx, c.elem_type, c.coords, c.conn, c.dirichlet, renumber=True, coloured=True)
+        # a mesh assembled and solved once: the coloured blocks (no owner plan
+        # to build) and the general SpMV (no symmetric map to build), as served
+        mesh = fe.Mesh(ctx, c.elem_type, c.coords, c.conn, c.dirichlet, renumber=True, coloured=True,
+                       symmetric_spmv=False)
         u = mesh.to_mesh(torch.as_tensor(c.u, device="cuda"))
         rho = mesh.to_mesh(torch.as_tensor(c.rho, device="cuda"))
         mu = mesh.to_mesh(torch.as_tensor(c.mu, device="cuda"))

@@ -60,6 +60,10 @@ typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_oper
 #define FE_UPLOAD_COLOURED 2u   /* single-type meshes: assemble the matrix operators with the coloured
                                  * element blocks (the serving runtime's form, and always that of hybrid
                                  * meshes) instead of the owner groups; the two agree to rounding order */
+#define FE_UPLOAD_GENERAL_SPMV 4u   /* fe_cg_solve runs the general SpMV on this mesh and never builds
+                                     * the symmetric one's map: for a mesh solved once or a few times,
+                                     * where building the map on the host (~6 ns per nonzero on 8
+                                     * threads) costs more than the solves save (see fe_cg_solve) */
 
 typedef struct fe_ctx_s *fe_ctx;
 typedef struct fe_mesh_s *fe_mesh;

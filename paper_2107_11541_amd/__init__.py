@@ -129,11 +129,12 @@ class Mesh:
     """A preprocessed, device-resident mesh (fe_mesh_upload)."""
 
     def __init__(self, ctx: Context, elem_type: int, coords, conn, dirichlet=None, renumber: bool = True,
-                 types=None, coloured: bool = False):
+                 types=None, coloured: bool = False, symmetric_spmv: bool = True):
         """elem_type: HEX08, PEN06, PYR05, TET04 (conn [E, nen]) or HYBRID with
         types [E] node counts and conn [E, 8] (fe_mesh_upload_mixed).
         coloured: HEX08 matrix assembly by coloured element blocks (the
-        serving runtime's form) instead of owner groups."""
+        serving runtime's form) instead of owner groups.
+        symmetric_spmv=False: FE_UPLOAD_GENERAL_SPMV (a mesh solved once)."""
         self.ctx = ctx
         lib = ctx.lib
         coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -145,7 +146,8 @@ class Mesh:
             raise ValueError("types are given exactly for a HYBRID mesh")
         d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.int32)
         nd, dp = (0, None) if d is None else (d.shape[0], d.ctypes.data)
-        flags = (FE_UPLOAD_RENUMBER if renumber else 0) | (capi.FE_UPLOAD_COLOURED if coloured else 0)
+        flags = ((FE_UPLOAD_RENUMBER if renumber else 0) | (capi.FE_UPLOAD_COLOURED if coloured else 0) |
+                 (0 if symmetric_spmv else capi.FE_UPLOAD_GENERAL_SPMV))
         h = C.c_void_p()
         if types is None:
             st = lib.fe_mesh_upload(ctx.h, elem_type, coords.shape[0], coords.ctypes.data, conn.shape[0],

@@ -15,6 +15,7 @@ FE_FP64, FE_MIXED = 0, 1
 FE_OP_MOMENTUM, FE_OP_SCALAR, FE_OP_POISSON = 0, 1, 2
 FE_UPLOAD_RENUMBER = 1
 FE_UPLOAD_COLOURED = 2
+FE_UPLOAD_GENERAL_SPMV = 4
 FE_FORM_FULL_STRESS, FE_FORM_EMAC = 1, 2
 
 P = C.c_void_p

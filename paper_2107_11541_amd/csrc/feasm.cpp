@@ -955,6 +955,7 @@ static fe_status mesh_upload(fe_ctx c, int stride, const uint8_t *types, int64_t
     m->conn_m = std::move(img->P.conn);
     m->etype_m = std::move(img->P.etype);
     m->stride_m = img->P.nen;
+    if (flags & FE_UPLOAD_GENERAL_SPMV) m->sym.state = -1;   // never build the symmetric map
     c->meshes.push_back(m);
     *out = m;
     return FE_OK;

@@ -144,3 +144,27 @@ def test_symmetric_spmv_at_full_size(fe_ctx):
     assert rel(host(xs), host(xg)) <= 1e-11
     assert abs(info_s["rel_residual"] - info_g["rel_residual"]) <= 1e-11 * info_g["rel_residual"]
     mesh.close()
+
+
+def test_upload_flag_keeps_the_general_spmv(fe_ctx):
+    """FE_UPLOAD_GENERAL_SPMV (a mesh solved once): fe_cg_solve runs the general
+    SpMV and builds no symmetric map, bitwise the allocation-free solve."""
+    import torch
+    import paper_2107_11541_amd as fe
+    c = meshgen.make_case(10, meshgen.HEX08, 0.15, case_id=66, shuffle=True)
+    mesh = fe.Mesh(fe_ctx, c.nen, c.coords, c.conn, c.dirichlet, symmetric_spmv=False)
+    u, rho = mesh.to_mesh(dev(c.u)), mesh.to_mesh(dev(c.rho))
+    L, f, _ = fe.assemble(mesh, fe.POISSON, c.dt, u, rho)
+    fe.apply_dirichlet(mesh, L, f)
+    L, f = L[0].contiguous(), f[0].contiguous()
+    bytes0 = mesh.info()["device_bytes"]
+    x, info = fe.cg_solve(mesh, L, f, rtol=1e-10, max_iter=5000)
+    xn, infon = fe.cg_solve_noalloc(mesh, L, f, rtol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and not info["symmetric_spmv"]
+    assert info["iterations"] == infon["iterations"] and torch.equal(x, xn)
+    # the solve allocated its work vectors (the reported bytes count them
+    # ~twice: ~96 B per node) but no map (~12 B per nonzero, ~300 B per node)
+    grown = mesh.info()["device_bytes"] - bytes0
+    assert grown < 128 * mesh.n_nodes + (1 << 20)
+    mesh.close()
