@@ -62,7 +62,7 @@ typedef enum { FE_OP_MOMENTUM = 0, FE_OP_SCALAR = 1, FE_OP_POISSON = 2 } fe_oper
                                  * meshes) instead of the owner groups; the two agree to rounding order */
 #define FE_UPLOAD_GENERAL_SPMV 4u   /* fe_cg_solve runs the general SpMV on this mesh and never builds
                                      * the symmetric one's map: for a mesh solved once or a few times,
-                                     * where building the map on the host (~6 ns per nonzero on 8
+                                     * where building the map on the host (~3 ns per nonzero on 8
                                      * threads) costs more than the solves save (see fe_cg_solve) */
 
 typedef struct fe_ctx_s *fe_ctx;
@@ -254,7 +254,7 @@ typedef struct {
  * a_ji| <= 2^-40 max(|a_ij|, |a_ji|, sqrt|a_ii a_jj|), both finite) and
  * otherwise runs the general SpMV; info->symmetric_spmv says which ran.
  * The first FP64 solve on a mesh builds the symmetric map on the host and
- * keeps it, with a packed copy of the values, on the device (about 12
+ * keeps it, with a packed copy of the values, on the device (about 8
  * bytes per nonzero; without room for them the general SpMV runs).
  * The two SpMVs round differently; the true residual is always computed
  * with `values` as given.  Returns FE_ENOCONV (x written) at max_iter,

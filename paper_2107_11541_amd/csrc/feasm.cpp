@@ -741,11 +741,11 @@ static fe_status ensure_sym(fe_mesh_s *m)
     up(&lidx, S.lidx.data(), S.lidx.size());
     up(&mir, S.mir.data(), S.mir.size() * sizeof(uint32_t));
     up(&cols, S.cols.data(), std::max<size_t>(S.cols.size(), 1) * sizeof(int32_t));
-    up((void **)&N.dst, S.dst.data(), std::max<size_t>(S.dst.size(), 1) * sizeof(int32_t));
+    up((void **)&N.mstart, S.mstart.data(), std::max<size_t>(S.mstart.size(), 1));
     up(&vals, nullptr, ((size_t)S.n_packed + 4) * sizeof(double));   // zeros: the padding stays 0
     up((void **)&N.bad, nullptr, sizeof(int32_t));
     if (s != FE_OK) {
-        void *ps[] = {desc, roff, lidx, mir, cols, N.dst, vals, N.bad};
+        void *ps[] = {desc, roff, lidx, mir, cols, N.mstart, vals, N.bad};
         for (void *q : ps) mesh_free_ptr(m, q);
         if (s != FE_ENOMEM) return s;
         Y.state = -1;   // no room for the map: this mesh's solves use the general SpMV
@@ -776,7 +776,7 @@ static fe_status select_sym(fe_mesh_s *m, CGWork &w, const double *values)
     fe_status s = ensure_sym(m);
     if (s != FE_OK || m->sym.state != 1) return s;
     fe_mesh_s::SymState &Y = m->sym;
-    HIPCALL(c, launch_sym_pack(m->dm, Y.dst, values, const_cast<double *>(Y.map.vals), Y.bad, c->stream));
+    HIPCALL(c, launch_sym_pack(m->dm, Y.map, Y.mstart, values, const_cast<double *>(Y.map.vals), Y.bad, c->stream));
     int32_t *hf = (int32_t *)c->host;
     HIPCALL(c, hipMemcpyAsync(hf, Y.bad, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     if ((s = sync(c)) != FE_OK) return s;

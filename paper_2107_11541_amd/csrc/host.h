@@ -91,7 +91,7 @@ struct fe_mesh_s {
     struct SymState {
         int state = 0;
         feasm::SymSpmv map;      // vals: the packed array
-        int32_t *dst = nullptr;  // [nnz]
+        uint8_t *mstart = nullptr;   // [n_nodes] per-row mirror-run starts
         int32_t *bad = nullptr;  // the symmetric-pair check word
         int64_t n_packed = 0;
     } sym;

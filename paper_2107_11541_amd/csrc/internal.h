@@ -114,11 +114,12 @@ struct SymSpmv {
     int nt = 0;              // nontemporal value loads, as SpmvMap::nt
 };
 // Packs the FP64 values of the mesh pattern's entries for the symmetric SpMV
-// (dst: the map's per-entry destinations) and sets *bad to 1 when a mirror
-// entry a_ij differs from the stored a_ji by more than 2^-40 max(|a_ij|,
-// |a_ji|, sqrt|a_ii a_jj|) (or either is not finite).  *bad is set to 0 first.
-hipError_t launch_sym_pack(const DevMesh &m, const int32_t *dst, const double *vals, double *packed, int32_t *bad,
-                           hipStream_t s);
+// map (mstart: its per-row mirror-run starts) and sets *bad to 1 when a
+// mirror entry a_ij differs from the stored a_ji by more than 2^-40
+// max(|a_ij|, |a_ji|, sqrt|a_ii a_jj|) (or either is not finite).  *bad is
+// set to 0 first.
+hipError_t launch_sym_pack(const DevMesh &m, const SymSpmv &map, const uint8_t *mstart, const double *vals,
+                           double *packed, int32_t *bad, hipStream_t s);
 
 // Wall faces of a mesh (boundary assembly of the wall model): face node
 // counts and connectivity (mesh numbering, unused slots repeat slot 0), the

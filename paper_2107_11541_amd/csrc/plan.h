@@ -192,8 +192,11 @@ extern const int kHexFaceRot[6][8];
 //     the stored value (first stored entry's position modulo 4 plus its
 //     index in the block; 10 bits) | the mirrored row minus the first row
 //     << 10 (6 bits); a block's mirrors start at an even index;
-//   * dst[e] for each CSR entry e: its packed position, or -1 - the CSR
-//     position of the stored entry it mirrors.
+//   * mstart[i]: the position in row i of its first mirror.  Rows are
+//     sorted, so a row's mirrors (columns r0 .. i-1) are one run of its
+//     entries; the packed position of entry k of row i is the block's first
+//     stored entry + row i's stored offset + k, less the run's length when
+//     k is past the run.
 // Packed positions of stored entries follow CSR order with the mirrors left
 // out; each row chunk (kPlanRowChunk rows) starts at a multiple of 4.
 constexpr int kSymRows = 64, kSymStored = 1021, kSymMirrors = 512, kSymCols = 256;
@@ -204,10 +207,10 @@ struct SymMap {
     std::vector<uint8_t> lidx;    // [n_packed + 4]
     std::vector<uint32_t> mir;    // [n_mirror_words + 1]
     std::vector<int32_t> cols;
-    std::vector<int32_t> dst;     // [nnz]
+    std::vector<uint8_t> mstart;  // [N]
 };
-// 0, or FE_EBADMESH when the pattern is not structurally symmetric or a row
-// does not fit a block (err says which).
+// 0, or FE_EBADMESH when the pattern is not structurally symmetric, a row is
+// not sorted or does not fit a block (err says which).
 int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMap &S, std::string &err);
 
 // Number of worker threads used by the host preprocessing.

@@ -912,42 +912,57 @@ __global__ void __launch_bounds__(kTB) k_set_i32(int32_t *p, int v)
     if (threadIdx.x == 0) store_flag(p, v);
 }
 
-// packed[dst[e]] = vals[e] for stored entries; a mirror entry e = (i, j)
-// (dst[e] < 0) compares its value with the stored (j, i) at CSR position
-// -1 - dst[e], on the scale of the larger of the two and sqrt|a_ii a_jj|
-// (the bound of an off-diagonal entry of an SPD matrix, which keeps an entry
-// summed to nearly zero from failing the check on rounding alone).
-// Work-group b takes a contiguous chunk of kPackChunk entries, the chunks of
-// one XCD consecutive (groups are dispatched round-robin over the XCDs): the
-// partner and the diagonals of a mirror lie within its row block, so their
-// lines are in the L2 of the XCD that streams the block.  One chunk per group
-// keeps many groups in flight for the dependent loads of the check.
-constexpr int kPackChunk = 16 * kTB;
-__global__ void __launch_bounds__(kTB) k_sym_pack(int64_t nnz, const int32_t *__restrict__ dst,
-                                                  const int32_t *__restrict__ colidx,
+// Packs a matrix for the symmetric SpMV: one work-group per row block, four
+// threads per row as in the SpMV.  Each row's stored entries go to their
+// window positions in LDS (its mirror run left out, mstart); after a barrier
+// the window is copied to the packed array in one coalesced pass (rows hold
+// ~22 stored entries: written row by row they would leave partial lines), and
+// each mirror entry (i, j) compares its
+// value with the stored (j, i) it replaces, on the scale of the larger of the
+// two and sqrt|a_ii a_jj| (the bound of an off-diagonal entry of an SPD
+// matrix, which keeps an entry summed to nearly zero from failing the check
+// on rounding alone).
+__global__ void __launch_bounds__(kTB) k_sym_pack(SymSpmv sm, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ diagpos,
+                                                  const uint8_t *__restrict__ mstart,
                                                   const double *__restrict__ vals, double *__restrict__ packed,
                                                   int32_t *bad)
 {
-    const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t q = G / kXcds, rem = G % kXcds, x = b % kXcds;
-    const int64_t chunk = x * q + (x < rem ? x : rem) + b / kXcds;
-    const int64_t e0 = chunk * kPackChunk, e1 = e0 + kPackChunk < nnz ? e0 + kPackChunk : nnz;
+    __shared__ double win[kStreamNnz];
+    const int tid = threadIdx.x, row = tid / kTPR, sub = tid % kTPR;
+    const uint16_t *__restrict__ mir16 = (const uint16_t *)sm.mir;
     bool ok = true;
-#pragma unroll 4
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kTB) {
-        const int32_t d = dst[e];
-        const double a = vals[e];
-        if (d >= 0) {
-            packed[d] = a;
-        } else {
-            const int64_t t = -1 - (int64_t)d;
-            const double b = vals[t];
-            const int32_t pi = diagpos[colidx[t]], pj = diagpos[colidx[e]];
-            const double dd = pi >= 0 && pj >= 0 ? sqrt(fabs(vals[pi] * vals[pj])) : 0.0;
-            const double m = fmax(fmax(fabs(a), fabs(b)), dd);
-            ok = ok && isfinite(a) && isfinite(b) && fabs(a - b) <= 0x1p-40 * m;
+    for (int64_t b = blockIdx.x; b < sm.nrb; b += gridDim.x) {
+        const int4 d0 = sm.desc[b], d1 = sm.desc[b + 1];
+        const int r0 = d0.x, R = d1.x - d0.x, shift = d0.y & 3;
+        const int ns = (int)(sm.roff[(int64_t)r0 + b + R] & 0xffffu);   // the block's stored entries
+        int64_t p0 = 0;
+        int ms = 0, ml = 0, mo = 0;
+        if (row < R) {
+            const uint32_t ro = sm.roff[(int64_t)r0 + b + row], ro1 = sm.roff[(int64_t)r0 + b + row + 1];
+            const int so = (int)(ro & 0xffffu), len = rowptr[r0 + row + 1] - rowptr[r0 + row];
+            mo = (int)(ro >> 16);
+            ml = (int)(ro1 >> 16) - mo;
+            ms = mstart[r0 + row];
+            p0 = rowptr[r0 + row];
+            for (int k = sub; k < len; k += kTPR) {
+                if (k >= ms && k < ms + ml) continue;   // a mirror: checked below
+                win[shift + so + (k < ms ? k : k - ml)] = vals[p0 + k];
+            }
         }
+        __syncthreads();
+        for (int t = tid; t < ns; t += kTB) packed[(int64_t)d0.y + t] = win[shift + t];
+        if (row < R) {
+            for (int m = sub; m < ml; m += kTPR) {
+                const double a = vals[p0 + ms + m];
+                const uint32_t w = mir16[2 * (int64_t)d0.z + mo + m];
+                const double t = win[w & 1023u];
+                const double dd = sqrt(fabs(vals[diagpos[r0 + row]] * vals[diagpos[r0 + (int)(w >> 10)]]));
+                const double mx = fmax(fmax(fabs(a), fabs(t)), dd);
+                ok = ok && isfinite(a) && isfinite(t) && fabs(a - t) <= 0x1p-40 * mx;
+            }
+        }
+        __syncthreads();
     }
     if (!ok) store_flag(bad, 1);
 }
@@ -1058,13 +1073,15 @@ hipError_t init_spmv_grid(int device)
     return hipSuccess;
 }
 
-hipError_t launch_sym_pack(const DevMesh &m, const int32_t *dst, const double *vals, double *packed, int32_t *bad,
-                           hipStream_t s)
+hipError_t launch_sym_pack(const DevMesh &m, const SymSpmv &map, const uint8_t *mstart, const double *vals,
+                           double *packed, int32_t *bad, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(kTB), 0, s, bad, 0);
-    if (m.nnz > 0)
-        hipLaunchKernelGGL(k_sym_pack, dim3((unsigned)((m.nnz + kPackChunk - 1) / kPackChunk)), dim3(kTB), 0, s,
-                           m.nnz, dst, m.colidx, m.diagpos, vals, packed, bad);
+    if (map.nrb > 0) {
+        const unsigned grid = (unsigned)(map.nrb < (1 << 20) ? map.nrb : (1 << 20));
+        hipLaunchKernelGGL(k_sym_pack, dim3(grid), dim3(kTB), 0, s, map, m.rowptr, m.diagpos, mstart, vals, packed,
+                           bad);
+    }
     return hipGetLastError();
 }
 

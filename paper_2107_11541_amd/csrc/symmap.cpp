@@ -42,8 +42,7 @@ int64_t find_in_row(const int32_t *rowptr, const int32_t *colidx, int64_t c, int
 
 int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMap &S, std::string &err)
 {
-    const int64_t nnz = rowptr[N];
-    S.dst.assign((size_t)nnz, 0);
+    S.mstart.assign((size_t)N, 0);
     const int64_t nch = (N + kPlanRowChunk - 1) / kPlanRowChunk;
     std::vector<SymChunk> ch((size_t)nch);
     const int nw = parallel_workers(nch);
@@ -107,9 +106,17 @@ int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMa
             int32_t ns = 0, nm = 0;
             for (int64_t i = r; i < r1; ++i) {
                 C.roff.push_back((uint32_t)ns | (uint32_t)nm << 16);
+                S.mstart[(size_t)i] = (uint8_t)(rowptr[i + 1] - rowptr[i]);   // no mirror: the row's end
+                bool run = false;
                 for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
                     const int32_t v = colidx[q];
+                    if (q > rowptr[i] && v <= colidx[q - 1]) {
+                        C.err = "row " + std::to_string(i) + " is not sorted";
+                        return;
+                    }
                     if (v >= r && v < i) {
+                        if (!run) S.mstart[(size_t)i] = (uint8_t)(q - rowptr[i]);
+                        run = true;
                         // mirror of (v, i), stored earlier in row v (i > v)
                         const int64_t pq = find_in_row(rowptr, colidx, v, (int32_t)i);
                         if (pq < 0) {
@@ -119,7 +126,6 @@ int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMa
                         }
                         const int32_t k = C.sidx[(size_t)(pq - p0)];
                         C.mir.push_back((uint16_t)((shift + k) | (int32_t)(v - r) << 10));
-                        S.dst[(size_t)q] = (int32_t)(-1 - pq);
                         ++nm;
                         continue;
                     }
@@ -136,7 +142,6 @@ int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMa
                     }
                     C.sidx[(size_t)(q - p0)] = ns;
                     C.lidx.push_back((uint8_t)sl);
-                    S.dst[(size_t)q] = (int32_t)(packed + ns);   // chunk-local until the bases are known
                     ++ns;
                 }
             }
@@ -189,9 +194,6 @@ int build_sym_map(int64_t N, const int32_t *rowptr, const int32_t *colidx, SymMa
         for (size_t k = 0; k < C.mir.size(); k += 2)
             S.mir[(size_t)wb[c] + k / 2] = (uint32_t)C.mir[k] | (uint32_t)C.mir[k + 1] << 16;
         std::copy(C.cols.begin(), C.cols.end(), S.cols.begin() + cb[c]);
-        const int64_t R1 = std::min<int64_t>(N, R0 + kPlanRowChunk);
-        for (int64_t q = rowptr[R0]; q < rowptr[R1]; ++q)
-            if (S.dst[(size_t)q] >= 0) S.dst[(size_t)q] += (int32_t)pb[c];
     });
     int32_t *d = &S.desc[(size_t)S.nrb * 4];
     d[0] = (int32_t)N;

@@ -41,21 +41,34 @@ static void check_sym_map(const Plan &P)
     for (int64_t i = 0; i < P.N; ++i) x[(size_t)i] = (double)(i % 11) - 5.0;
     for (int64_t i = 0; i < P.N; ++i)
         for (int32_t q = P.rowptr[i]; q < P.rowptr[i + 1]; ++q) ycsr[(size_t)i] += aval(i, P.colidx[q]) * x[P.colidx[q]];
-    CHECK(S.lidx.size() == (size_t)S.n_packed + 4 && S.dst.size() == (size_t)P.nnz);
+    CHECK(S.lidx.size() == (size_t)S.n_packed + 4 && S.mstart.size() == (size_t)P.N);
+    // the device pack, row by row: entry k of row i goes to the block's first
+    // stored entry + the row's stored offset + k, less the mirror run's
+    // length past the run; every mirror's window value is its transpose
     std::vector<double> packed((size_t)S.n_packed + 4, 0.0);
+    std::vector<char> hit((size_t)S.n_packed + 4, 0);
     int64_t stored = 0;
-    for (int64_t i = 0; i < P.N; ++i)
-        for (int32_t q = P.rowptr[i]; q < P.rowptr[i + 1]; ++q) {
-            const int32_t d = S.dst[(size_t)q];
-            if (d >= 0) {
-                CHECK(d < S.n_packed);
-                packed[(size_t)d] = aval(i, P.colidx[q]);
+    for (int64_t b = 0; b < S.nrb; ++b) {
+        const int32_t *d0 = &S.desc[(size_t)b * 4], *d1 = d0 + 4;
+        const int64_t r0 = d0[0], R = d1[0] - d0[0];
+        for (int64_t i = 0; i < R; ++i) {
+            const int64_t row = r0 + i, len = P.rowptr[row + 1] - P.rowptr[row];
+            const uint32_t ro = S.roff[(size_t)(r0 + b + i)], ro1 = S.roff[(size_t)(r0 + b + i + 1)];
+            const int64_t so = ro & 0xffffu, ml = (int64_t)(ro1 >> 16) - (int64_t)(ro >> 16), ms = S.mstart[(size_t)row];
+            CHECK(ms + ml <= len && (int64_t)(ro1 & 0xffffu) - so == len - ml);
+            for (int64_t k = 0; k < len; ++k) {
+                const int32_t col = P.colidx[P.rowptr[row] + k];
+                const bool mirror = k >= ms && k < ms + ml;
+                CHECK(mirror == (col >= r0 && col < row));
+                if (mirror) continue;
+                const int64_t d = d0[1] + so + (k < ms ? k : k - ml);
+                CHECK(d >= 0 && d < S.n_packed && !hit[(size_t)d]);
+                hit[(size_t)d] = 1;
+                packed[(size_t)d] = aval(row, col);
                 ++stored;
-            } else {
-                const int64_t pq = -1 - (int64_t)d;   // the stored transpose
-                CHECK(pq >= 0 && pq < P.nnz && S.dst[(size_t)pq] >= 0 && P.colidx[pq] == (int32_t)i);
             }
         }
+    }
     for (int64_t b = 0; b < S.nrb; ++b) {
         const int32_t *d0 = &S.desc[(size_t)b * 4], *d1 = d0 + 4;
         const int64_t r0 = d0[0], R = d1[0] - d0[0], a0 = d0[1] & ~3, shift = d0[1] - a0, nz = d1[1] - d0[1];
@@ -170,7 +183,7 @@ int main()
         CHECK(build_sym_map(P.N, P.rowptr.data(), P.colidx.data(), S4, err) == 0);
         set_thread_budget(0);
         CHECK(S1.nrb == S4.nrb && S1.n_packed == S4.n_packed && S1.desc == S4.desc && S1.roff == S4.roff &&
-              S1.lidx == S4.lidx && S1.mir == S4.mir && S1.cols == S4.cols && S1.dst == S4.dst);
+              S1.lidx == S4.lidx && S1.mir == S4.mir && S1.cols == S4.cols && S1.mstart == S4.mstart);
         san_free(&m);
     }
     // a plan object reused for another mesh (the serving runtime's images)
